@@ -1,0 +1,157 @@
+"""The CPU oracle against results fixed by mathematics (no GPU needed)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import pins
+import wdgen
+
+
+def _ok(res):
+    ok, detail = res
+    assert bool(ok), detail
+
+
+def test_gamma_algebra():
+    _ok(pins.gamma_algebra())
+
+
+def test_links_unitary_det_one_and_generator_scale():
+    dims = (4, 4, 4, 4)
+    U = wdgen.gauge_field(dims, 0.5, 1001).reshape(-1, 3, 3)
+    eye = np.eye(3)
+    assert np.max(np.abs(np.conj(np.swapaxes(U, -1, -2)) @ U - eye)) <= 1e-14
+    assert np.max(np.abs(np.linalg.det(U) - 1)) <= 1e-14
+    # H = sum h_a lambda_a / 2 with h_a ~ N(0,1): E[tr H^2] = 8 * (1/2) = 4
+    rng = np.random.default_rng(5)
+    h = rng.standard_normal((200000, 8))
+    H = np.einsum("na,aij->nij", h, wdgen.gell_mann()) / 2
+    trH2 = np.real(np.einsum("nij,nji->n", H, H))
+    assert abs(trH2.mean() - 4.0) < 5 * trH2.std() / math.sqrt(len(trH2))
+    # determinism of the generator: same seed, same field
+    assert np.array_equal(wdgen.gauge_field(dims, 0.5, 7), wdgen.gauge_field(dims, 0.5, 7))
+
+
+@pytest.mark.parametrize("dims,m0,t_sign", [
+    ((2, 2, 2, 2), 0.1, -1), ((4, 4, 4, 4), 0.1, -1), ((4, 6, 2, 8), 0.1, +1),
+    ((3, 5, 4, 6), 0.02, -1), ((14, 14, 14, 14), 0.05, -1), ((16, 16, 16, 32), 0.02, -1)])
+def test_free_plane_waves(dims, m0, t_sign):
+    n = 1 if dims[0] >= 14 else 3
+    _ok(pins.free_plane_waves(dims, m0, t_sign, n_waves=n))
+
+
+def test_free_spectrum_2x4_exact():
+    _ok(pins.free_spectrum_2x4(0.1))
+    _ok(pins.free_spectrum_2x4(0.37))
+
+
+def test_gamma5_hermiticity():
+    _ok(pins.gamma5_hermiticity())
+    _ok(pins.gamma5_hermiticity(dims=(2, 2, 2, 2), seed=3))
+
+
+def test_adjoint_is_conjugate_transpose_dense():
+    dims = (2, 2, 2, 2)
+    U = wdgen.gauge_field(dims, 0.8, 99)
+    D = oracle.dense(U, dims, 0.1)
+    Dd = oracle.dense(U, dims, 0.1, dagger=True)
+    assert np.max(np.abs(Dd - D.conj().T)) <= 1e-15
+    assert D.shape == (12 * 16, 12 * 16)   # the matrix dimension is 12 V (Sec. 1)
+
+
+def test_gauge_covariance():
+    _ok(pins.gauge_covariance())
+
+
+def test_norm_bounds():
+    _ok(pins.norm_bounds())
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (2, 2, 4, 4)])
+def test_cg_matches_dense_solve(dims):
+    _ok(pins.dense_solve(dims=dims))
+
+
+def test_cg_matches_dense_solve_4x4():
+    _ok(pins.dense_solve(dims=(4, 4, 4, 4), m0=0.1, eps=0.3, seed=1001))
+
+
+def test_cgnr_matches_dense_solve():
+    _ok(pins.dense_solve(form=1))
+
+
+def test_cg_matches_free_fft_solution():
+    _ok(pins.free_fft_solve())
+
+
+def test_cg_matches_pure_gauge_solution():
+    _ok(pins.pure_gauge_solve())
+
+
+def test_cgne_error_monotone():
+    _ok(pins.cgne_error_monotone())
+
+
+def test_cg_zero_source_and_exact_guess():
+    dims = (4, 4, 4, 4)
+    U = wdgen.gauge_field(dims, 0.3, 1001)
+    x, it, res, st = oracle.cg(U, np.zeros((1,) + wdgen.lattice_shape(dims) + (4, 3)), dims, 0.1)
+    assert it == [0] and st == [0] and not np.any(x)
+    eta = wdgen.gaussian_source(dims, 1, 2001)
+    x, it, res, st = oracle.cg(U, eta, dims, 0.1)
+    x2, it2, res2, st2 = oracle.cg(U, eta, dims, 0.1, x0=x)
+    assert it2 == [0] and st2 == [0] and np.array_equal(x, x2)
+
+
+def test_cg_max_iter_reports_not_converged():
+    dims = (4, 4, 4, 4)
+    U = wdgen.gauge_field(dims, 0.3, 1001)
+    eta = wdgen.gaussian_source(dims, 1, 2001)
+    x, it, res, st = oracle.cg(U, eta, dims, 0.1, max_iter=5)
+    assert st == [1] and it == [5] and res[0] > 1e-10
+
+
+def test_coo_format_matches_operator():
+    """The coordinate-format matrix (Sec. 2) built term by term in NumPy agrees
+    with the C operator; 49 stored entries per row (duplicates on 2^4 kept)."""
+    for dims in [(2, 2, 2, 2), (4, 4, 4, 4), (2, 3, 4, 5)]:
+        V = wdgen.volume(dims)
+        U = wdgen.gauge_field(dims, 0.6, 5)
+        psi = wdgen.gaussian_source(dims, 1, 6)[0]
+        for dag in (False, True):
+            val, row, col = oracle.coo(U, dims, 0.07, dagger=dag)
+            assert len(val) == 588 * V
+            got = oracle.coo_matvec(val, row, col, psi.ravel(), 12 * V)
+            want = oracle.dirac(U, psi, dims, 0.07, dagger=dag).ravel()
+            assert np.linalg.norm(got - want) <= 1e-14 * np.linalg.norm(want)
+
+
+def test_fp16n_encoding():
+    rng = np.random.default_rng(3)
+    v = (rng.standard_normal((5, 64, 4, 3)) + 1j * rng.standard_normal((5, 64, 4, 3))) * 10.0
+    v32 = v.astype(np.complex64)
+    codes, norms = oracle.fp16n_encode(v32)
+    assert codes.dtype == np.float16 and norms.dtype == np.float32
+    assert codes.shape == (5, 64, 24) and norms.shape == (5, 64)
+    # the largest component of each site is coded as +-1 exactly
+    assert np.all(np.max(np.abs(codes.astype(np.float32)), axis=-1) == 1.0)
+    dec = oracle.fp16n_decode(codes, norms)
+    err = np.abs(dec - v32).reshape(5, 64, 12)
+    # half has 11 significant bits: |code - q| <= 2^-12 for |q| <= 1, times norm
+    assert np.all(err.real <= norms[..., None] * 2.0 ** -11 * 1.0001)
+    # all-zero site -> norm 0, codes 0
+    z = np.zeros((1, 2, 4, 3), dtype=np.complex64)
+    z[0, 1, 2, 1] = 0.5 + 0.25j
+    c, n = oracle.fp16n_encode(z)
+    assert n[0, 0] == 0 and not np.any(c[0, 0])
+    assert n[0, 1] == 0.5 and c[0, 1, 14] == 1.0 and c[0, 1, 15] == 0.5
+    # ties round to even: 1 + 2^-11 sits halfway between 1 and 1 + 2^-10
+    t = np.zeros((1, 1, 4, 3), dtype=np.complex64)
+    t[0, 0, 0, 0] = 2.0
+    t[0, 0, 0, 1] = 2.0 * (1 + 2.0 ** -11)  # becomes the norm
+    t[0, 0, 0, 2] = 1.0 + 2.0 ** -11
+    c, n = oracle.fp16n_encode(t)
+    q = np.float32(1.0 + 2.0 ** -11) / np.float32(2.0 * (1 + 2.0 ** -11))
+    assert c[0, 0, 4] == np.float16(q)
