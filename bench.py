@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark: multi-right-hand-side mixed-precision CG for the Wilson-Dirac
+operator on one MI355X (arXiv 2111.14958, the CG of Sec. 2 on Eq. (1)).
+
+Workload (one step = one full batched solve, every step of the hot path):
+  14^4 lattice, antiperiodic time boundary, m0 = 0.05, links exp(i 0.5 H),
+  16 right-hand sides (12 spin-colour point sources at the origin, 4 complex
+  Gaussian sources), FP32 inner CG with FP64 reliable updates every 50
+  iterations, stop at true relative residual 1e-10 (FP64).  Inputs (links,
+  sources) are resident in HBM before the timed region; the links are packed
+  once (gauge setup), sources are packed inside every solve.
+
+Prints ONE JSON line: value = right-hand-side solves per second.  Beside it:
+the plain FP64 CG on the same GPU (the "mixed vs FP64" ratio), the roofline of
+the dominant kernel measured with HIP events (the library's profiling mode),
+the stand-alone operator bandwidth, a device copy ceiling and the CPU oracle.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "dslash GB/s (% HBM peak); CG solves/s at res 1e-10, mixed vs FP64"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-iters", type=int, default=150,
+                    help="oracle CG iterations timed for the CPU baseline sample")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(independent solves would shard by request, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2111_14958_amd as wd
+    import wdgen
+
+    if not os.path.exists(wd.LIB_PATH):
+        from paper_2111_14958_amd import build
+        build.build()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    arch, ncu = wd.device_info(0)
+
+    cfg = wdgen.CONFIGS["c3_14x4_16rhs"]
+    dims, m0, tol = cfg["dims"], cfg["m0"], cfg["tol"]
+    nrhs = cfg["n_point"] + cfg["n_gauss"]
+    V = wdgen.volume(dims)
+    log("generating inputs", dims, nrhs)
+    U = wdgen.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
+    src = wdgen.mixed_sources(dims, cfg["n_point"], cfg["n_gauss"], cfg["src_seed"])
+    dU = torch.from_numpy(U).to(dev)
+    dsrc = torch.from_numpy(src).to(dev)
+    g = wd.Gauge(dU, dims, -1)
+    sol = torch.zeros_like(dsrc)
+
+    p_mixed = wd.cg_default_params(tol=tol, inner=wd.F32, reliable_every=50)
+    p_fp64 = wd.cg_default_params(tol=tol, inner=wd.F64, reliable_every=0)
+    ws = torch.empty(max(wd.cg_workspace_bytes(g, nrhs, p_mixed),
+                         wd.cg_workspace_bytes(g, nrhs, p_fp64)), dtype=torch.uint8, device=dev)
+
+    def solve(params):
+        x, reps, rc = wd.cg_solve_batch(g, m0, dsrc, sol=sol, params=params, ws=ws)
+        return reps, rc
+
+    # ------------------------------------------------------------- timed: mixed
+    log("warmup", args.warmup)
+    for _ in range(args.warmup):
+        solve(p_mixed)
+    torch.cuda.synchronize()
+    log("timed", args.steps, "steps")
+    t0 = time.perf_counter()
+    all_reps = []
+    for _ in range(args.steps):
+        reps, rc = solve(p_mixed)
+        all_reps.append((reps, rc))
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t0
+    ok = all(rc == wd.WD_OK and all(r["status"] == 0 and r["true_rel_res"] <= tol for r in reps)
+             for reps, rc in all_reps)
+    reps_mixed = all_reps[-1][0]
+    x_mixed = sol.clone()
+    value = nrhs * args.steps / t_mixed
+    log(f"mixed: {value:.2f} solves/s, iters {[r['iters'] for r in reps_mixed]}")
+
+    # ------------------------------------------------------------- FP64 beside
+    solve(p_fp64)  # warm the graph
+    torch.cuda.synchronize()
+    n64 = max(1, min(args.steps, 2))
+    t0 = time.perf_counter()
+    for _ in range(n64):
+        reps64, rc64 = solve(p_fp64)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    fp64_value = nrhs * n64 / t64
+    x64 = sol.clone()
+    diff = (x_mixed - x64).reshape(nrhs, -1)
+    err_vs_fp64 = (diff.norm(dim=1) / x64.reshape(nrhs, -1).norm(dim=1)).max().item()
+    log(f"fp64: {fp64_value:.2f} solves/s, iters {[r['iters'] for r in reps64]}")
+
+    # ------------------------------------------- FP16-storage inner (context)
+    p16 = wd.cg_default_params(tol=tol, inner=wd.F16N, reliable_every=50)
+    solve(p16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps16, rc16 = solve(p16)
+    torch.cuda.synchronize()
+    f16_value = nrhs / (time.perf_counter() - t0)
+    err16 = ((sol - x64).reshape(nrhs, -1).norm(dim=1) / x64.reshape(nrhs, -1).norm(dim=1)).max().item()
+
+    # ------------------------------------ roofline of the dominant CG kernel
+    wd.profile_reset()
+    wd.profile_enable(True)
+    solve(p_mixed)
+    torch.cuda.synchronize()
+    wd.profile_enable(False)
+    prof = wd.profile_read()
+    dom_name = max(prof, key=lambda k: prof[k]["total_ms"])
+    dom = prof[dom_name]
+    dom_gbps = dom["bytes_total"] / (dom["total_ms"] * 1e-3) / 1e9
+    kernel_symbol = {"cg_phaseA": "k_phaseA<P32,NR>", "cg_phaseB": "k_phaseB<P32,NR>",
+                     "cg_phaseC": "k_phaseC<P32>"}[dom_name]
+    per_launch = {k: {"launches": v["launches"],
+                      "avg_us": 1e3 * v["total_ms"] / max(v["launches"], 1),
+                      "GBps": v["bytes_total"] / max(v["total_ms"], 1e-12) / 1e6}
+                  for k, v in prof.items()}
+
+    # ------------------------------------------ stand-alone operator, 16 rhs
+    dslash = {}
+    for prec, name in ((wd.F32, "f32"), (wd.F64, "f64"), (wd.F16N, "f16n")):
+        pin = wd.pack_spinor(g, dsrc, prec)
+        pout = wd.empty_packed(g, prec, nrhs)
+        for _ in range(3):
+            wd.dslash(g, m0, pin, prec, packed=True, nrhs=nrhs, out=pout)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps_n = 50
+        e0.record()
+        for _ in range(reps_n):
+            wd.dslash(g, m0, pin, prec, packed=True, nrhs=nrhs, out=pout)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps_n
+        link = {wd.F64: 576, wd.F32: 288, wd.F16N: 144}[prec]
+        spin = {wd.F64: 192, wd.F32: 96, wd.F16N: 52}[prec]
+        alg = V * (link + 2 * nrhs * spin)
+        dslash[name] = {"us": us, "GBps": alg / (us * 1e-6) / 1e9,
+                        "GFLOPs": 1368.0 * V * nrhs / (us * 1e-6) / 1e9,
+                        "frac_hbm": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
+        del pin, pout
+
+    # ----------------------------------------------------- copy ceiling
+    a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * a.numel() * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+
+    # ----------------------------------------------------- CPU oracle baseline
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        i_g = cfg["n_point"]   # first Gaussian source
+        iters_needed = reps64[i_g]["iters"]
+        n_it = min(args.cpu_iters, iters_needed)
+        log(f"cpu oracle: {n_it} CG iterations on one 14^4 field")
+        t0 = time.perf_counter()
+        oracle.cg(U, src[i_g:i_g + 1], dims, m0, tol=1e-300, max_iter=n_it)
+        t_cpu = time.perf_counter() - t0
+        per_iter = t_cpu / n_it
+        cpu = {"value": 1.0 / (per_iter * iters_needed), "unit": "solves/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"FP64 C oracle CG (single thread) on 1 Gaussian field of this 14^4 "
+                         f"workload: {n_it} iterations timed ({t_cpu:.1f} s), scaled to the "
+                         f"{iters_needed} iterations the FP64 solve needs",
+               "seconds": t_cpu}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_mixed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "wilson-dirac cg 14^4 x 16 rhs (12 point + 4 gaussian), m0 0.05, "
+                               "eps 0.5, tol 1e-10, fp32 inner + fp64 reliable updates every 50",
+                   "lattice": list(dims), "nrhs": nrhs, "global_batch": nrhs,
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "kernel": kernel_symbol, "achieved": dom_gbps,
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": dom_gbps / HBM_PEAK_GBPS,
+                     "traffic": None},
+        "cpu_baseline": cpu,
+        "details": {
+            "device": f"{arch} ({ncu} CUs)",
+            "all_solves_converged": ok,
+            "max_true_rel_res": max(r["true_rel_res"] for r in reps_mixed),
+            "iters_mixed": [r["iters"] for r in reps_mixed],
+            "reliable_updates": [r["reliable_updates"] for r in reps_mixed],
+            "fp64_solves_per_s": fp64_value,
+            "mixed_vs_fp64": value / fp64_value,
+            "iters_fp64": [r["iters"] for r in reps64],
+            "mixed_err_vs_fp64_solution": err_vs_fp64,
+            "f16n_solves_per_s": f16_value,
+            "f16n_all_converged": rc16 == wd.WD_OK,
+            "f16n_err_vs_fp64_solution": err16,
+            "cg_kernels": per_launch,
+            "dslash_16rhs": dslash,
+            "copy_GBps": copy_gbps,
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

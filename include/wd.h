@@ -1,0 +1,261 @@
+/*
+ * wd.h -- C ABI of libwd, a Wilson-Dirac conjugate-gradient library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the lattice-QCD linear system D psi = eta of Eq. (1) of
+ * arXiv 2111.14958 (Sec. 1): D is the Wilson-Dirac operator acting on fields
+ * with 3 colours and 4 spins per lattice site (12 complex numbers per site).
+ * It solves by conjugate gradient on the normal equations, as in Sec. 2: CG on
+ * D D^dagger chi = eta, then psi = D^dagger chi, the multiplication by
+ * D^dagger being folded into the iteration (psi is updated directly).
+ *
+ * Operator convention (Wilson parameter r = 1, bare mass m0):
+ *   D psi(x) = (4 + m0) psi(x)
+ *              - 1/2 sum_mu [ (1 - gamma_mu) U_mu(x) s psi(x + mu)
+ *                           + (1 + gamma_mu) U_mu(x - mu)^dagger s psi(x - mu) ]
+ * with s = t_sign for a hop in t that wraps around the lattice, else 1.
+ * Gamma matrices in the DeGrand-Rossi chiral basis, gamma5 = diag(1,1,-1,-1).
+ * D^dagger = gamma5 D gamma5 (gamma5-hermiticity, Sec. 2) exchanges the two
+ * projectors.
+ *
+ * Canonical (user) layouts, C order, complex128 = (double re, double im):
+ *   gauge   U[t][z][y][x][mu][a][b]     mu = 0..3 is x, y, z, t; U_mu(x) is the
+ *                                       link x -> x + mu, (U psi)_a = sum_b U_ab psi_b
+ *   spinor  psi[rhs][t][z][y][x][spin][colour]
+ * dims are (Lx, Ly, Lz, Lt); site = x + Lx*(y + Ly*(z + Lz*t)).
+ *
+ * Packed (internal, structure-of-arrays) spinor layouts, used when a call
+ * passes WD_PACKED; V = number of sites, component k = 3*spin + colour:
+ *   WD_F64   double2 [rhs][12][V]          element (k, site) = component k
+ *   WD_F32   float4  [rhs][6][V]           chunk j = components 2j, 2j+1 as (re,im,re,im)
+ *   WD_F16N  16-byte [rhs][3][V] codes, then float [rhs][V] norms, in one buffer:
+ *            chunk j = 8 halves = components 4j..4j+3 as (re,im) pairs; value =
+ *            norm * code; norm = max |real or imaginary part| over the site's 24
+ *            numbers (FP32), code = half(v / norm) (FP32 quotient, then
+ *            round-to-nearest-even to half); an all-zero site has norm 0.
+ *
+ * Memory ownership: every pointer argument named *_dev is device memory owned by
+ * the caller (for example a PyTorch tensor); the library never frees it.  A
+ * wd_gauge owns the packed link copies it allocates until wd_gauge_destroy.
+ * A server owns nothing but what it carves out of the caller's arena.
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ * wd_dslash* and the pack functions are asynchronous on that stream.
+ * wd_cg_solve* enqueue their work on that stream and return once the solution
+ * and the reports are final (they synchronise the stream).
+ *
+ * Errors: functions return WD_OK (0) or a negative code; wd_strerror gives the
+ * text, wd_last_error_detail the detail of the most recent failure on the
+ * calling thread.  No function aborts the process.
+ */
+#ifndef WD_H
+#define WD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    WD_OK = 0,
+    WD_EINVAL = -1,      /* bad dimensions, null pointer, nrhs, tolerance, flags    */
+    WD_ENODEV = -2,      /* no gfx950 device visible                                */
+    WD_EHIP = -3,        /* HIP runtime error (detail string has the runtime text)  */
+    WD_ENOMEM = -4,      /* workspace too small or device allocation failed         */
+    WD_ENOTCONV = -5,    /* max_iter reached before the true residual met tol       */
+    WD_EBREAKDOWN = -6,  /* NaN/Inf or <q,q> <= 0 inside CG                         */
+    WD_ETOOBIG = -7,     /* request larger than the server arena                    */
+    WD_ENOTFOUND = -8    /* unknown server ticket                                   */
+};
+
+typedef enum { WD_F64 = 0, WD_F32 = 1, WD_F16N = 2 } wd_prec;
+
+/* flags of wd_dslash / wd_dslash_dag */
+#define WD_PACKED 1u     /* in/out are in the packed layout of `prec` (see above) */
+
+/* ------------------------------------------------------------------ library */
+int         wd_version(void);                 /* 10000*major + 100*minor + patch  */
+const char *wd_strerror(int code);
+const char *wd_last_error_detail(void);       /* thread-local, "" when none        */
+/* name of device `device` (gcnArchName) and its compute-unit count; WD_ENODEV
+ * when the device is not gfx950 */
+int wd_device_info(int device, char *arch, size_t arch_len, int32_t *num_cu);
+
+/* ------------------------------------------------------------------ gauge field */
+typedef struct wd_gauge wd_gauge;
+
+#define WD_GAUGE_F64  (1u << WD_F64)
+#define WD_GAUGE_F32  (1u << WD_F32)
+#define WD_GAUGE_F16  (1u << WD_F16N)
+
+/* Pack the canonical complex128 links U_dev (dims, see above) into device-resident
+ * copies in the precisions of prec_mask (the FP64 copy is always made: the solver
+ * uses it for true residuals).  t_sign is -1 (antiperiodic time boundary) or +1.
+ * Lower-precision copies are rounded to nearest even (FP16 via FP32).
+ * Synchronises `stream` before returning; U_dev may be freed afterwards. */
+int wd_gauge_create(const int32_t dims[4], int32_t t_sign, const void *U_dev,
+                    uint32_t prec_mask, void *stream, wd_gauge **out);
+int wd_gauge_destroy(wd_gauge *g);
+/* dims[4], t_sign, sites and the precision mask of a gauge handle */
+int wd_gauge_info(const wd_gauge *g, int32_t dims[4], int32_t *t_sign, int64_t *sites,
+                  uint32_t *prec_mask);
+
+/* --------------------------------------------------------- spinor conversion */
+/* bytes of a packed spinor buffer holding nrhs fields of the gauge's lattice */
+size_t wd_spinor_bytes(const wd_gauge *g, int32_t prec, int32_t nrhs);
+/* canonical complex128 [nrhs][V][12] -> packed `prec` layout (RNE rounding) */
+int wd_pack_spinor(const wd_gauge *g, int32_t prec, const void *in_dev, void *out_dev,
+                   int32_t nrhs, void *stream);
+/* packed `prec` layout -> canonical complex128 */
+int wd_unpack_spinor(const wd_gauge *g, int32_t prec, const void *in_dev, void *out_dev,
+                     int32_t nrhs, void *stream);
+
+/* ----------------------------------------------------------------- operator */
+/* out = D in (wd_dslash) or out = D^dagger in (wd_dslash_dag) for nrhs fields,
+ * Eq. (1) with the convention above; arithmetic in the precision `prec`
+ * (WD_F16N: half storage with per-site norms, FP32 arithmetic).  With
+ * WD_PACKED the buffers are in the packed layout of `prec`; otherwise they are
+ * canonical complex128 and the call packs / unpacks through stream-ordered
+ * temporary buffers.  The gauge handle must hold the links in `prec`.
+ * in and out must not overlap.  Asynchronous on `stream`. */
+int wd_dslash(const wd_gauge *g, double m0, int32_t prec, const void *in_dev, void *out_dev,
+              int32_t nrhs, uint32_t flags, void *stream);
+int wd_dslash_dag(const wd_gauge *g, double m0, int32_t prec, const void *in_dev,
+                  void *out_dev, int32_t nrhs, uint32_t flags, void *stream);
+
+/* -------------------------------------------------------------- CG solvers */
+typedef struct {
+    double  tol;            /* target |eta - D x| / |eta| (true residual, FP64), > 0   */
+    int32_t max_iter;       /* CG iterations per right-hand side                        */
+    int32_t reliable_every; /* inner iterations between reliable updates; 0 = only when
+                               the iterated residual reaches tol                         */
+    int32_t inner;          /* wd_prec of the inner iteration                           */
+    int32_t use_x0;         /* 1: sol_dev holds the initial guess on entry              */
+    int32_t persistent;     /* 0: one kernel per CG phase, 1: one persistent kernel per
+                               chunk with grid barriers, -1: library default             */
+    int32_t chunk;          /* CG iterations per graph replay, 0 = library default     */
+} wd_cg_params;
+
+typedef struct {
+    int32_t status;           /* WD_OK, WD_ENOTCONV or WD_EBREAKDOWN                    */
+    int32_t iters;            /* CG iterations performed                                */
+    int32_t reliable_updates; /* true-residual recomputations, the final one included   */
+    int32_t reserved;
+    double  true_rel_res;     /* |eta - D x| / |eta|, recomputed in FP64 at the end    */
+    double  iter_rel_res;     /* last recursively updated residual / |eta|             */
+    double  seconds;          /* wall time of the whole call                           */
+} wd_cg_report;
+
+/* tol 1e-10, max_iter 20000, reliable_every 50, inner WD_F32, use_x0 0,
+ * persistent -1, chunk 0 */
+void   wd_cg_default_params(wd_cg_params *p);
+/* device workspace a solve of nrhs fields on g's lattice needs, in bytes */
+size_t wd_cg_workspace_bytes(const wd_gauge *g, int32_t nrhs, const wd_cg_params *p);
+
+/* Solve D x = eta for one field (src/sol canonical complex128 [V][12]).
+ * ws_dev: caller-owned device workspace of at least wd_cg_workspace_bytes.
+ * The inner iteration runs in p->inner precision; the solution is accumulated
+ * in FP64 and every reliable update recomputes eta - D x with the FP64 links.
+ * Returns WD_OK when the FP64 true residual is <= tol, else the first failing
+ * per-field status.  Synchronises `stream`. */
+int wd_cg_solve(const wd_gauge *g, double m0, const void *src_dev, void *sol_dev,
+                const wd_cg_params *p, void *ws_dev, size_t ws_bytes, wd_cg_report *rep,
+                void *stream);
+/* The same for nrhs fields that share the links (src/sol [nrhs][V][12]); one
+ * report per field.  All fields advance in the same kernels, each with its own
+ * CG scalars; converged fields stop doing work. */
+int wd_cg_solve_batch(const wd_gauge *g, double m0, const void *src_dev, void *sol_dev,
+                      int32_t nrhs, const wd_cg_params *p, void *ws_dev, size_t ws_bytes,
+                      wd_cg_report *reps, void *stream);
+
+/* --------------------------------------------------------------- autotuner */
+typedef struct {
+    int32_t block;        /* threads per block                                   */
+    int32_t rhs_per_thread;
+    int32_t xcd_remap;    /* 1: tiles mapped to XCDs in contiguous ranges        */
+    int32_t reserved;
+    double  us;           /* median time of one application, microseconds        */
+    double  gbps;         /* algorithmic bytes / time                             */
+} wd_tune_result;
+
+/* Time every candidate launch shape of the operator for (g, prec, nrhs, dagger)
+ * on scratch data, reject candidates whose output differs from the reference
+ * shape, and store the fastest in the in-process table (and in the cache file
+ * named by WD_TUNE_CACHE, if set).  Later calls with the same key use it.
+ * Synchronises `stream`. */
+int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger,
+                   wd_tune_result *best, void *stream);
+/* the launch shape currently used for the key (tuned or default) */
+int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger,
+                   wd_tune_result *cfg);
+
+/* --------------------------------------------------------------- profiling */
+/* Per-kernel statistics of CG solves.  While profiling is on, wd_cg_solve*
+ * launch the kernels of each chunk one by one (instead of replaying the chunk
+ * graph) and bracket every phase-A/B/C launch with HIP events on the solve's
+ * stream; bytes_total sums the algorithmic bytes of those launches (links once,
+ * every spinor of every active right-hand side once per read or write).
+ * Meant for measurement runs: it adds a host synchronisation per iteration. */
+typedef struct {
+    char    name[32];       /* "cg_phaseA" (q = D^dagger p), "cg_phaseB" (D q + updates),
+                               "cg_phaseC" (p = r + beta p)                              */
+    int64_t launches;
+    double  total_ms;       /* summed event time                                    */
+    double  bytes_total;    /* summed algorithmic bytes                             */
+} wd_kernel_stat;
+
+int wd_profile_enable(int32_t on);                       /* process-wide switch   */
+int wd_profile_reset(void);
+/* copy up to max_n entries into out, *n = number of entries available */
+int wd_profile_read(wd_kernel_stat *out, int32_t max_n, int32_t *n);
+
+/* ----------------------------------------------------------------- serving */
+typedef struct wd_server wd_server;
+
+typedef struct {
+    void   *arena_dev;     /* caller-owned device memory the server carves from       */
+    size_t  arena_bytes;
+    int32_t max_slots;     /* requests resident on the device at once (<= 64)         */
+    int32_t chunk;         /* CG iterations per scheduling step (0 = default 25)     */
+    int32_t device;        /* HIP device ordinal                                      */
+    int32_t reserved;
+} wd_serve_config;
+
+typedef struct {
+    int32_t     dims[4];
+    int32_t     t_sign;
+    int32_t     nrhs;
+    double      m0;
+    const void *gauge_dev;  /* canonical complex128 links; read during admission     */
+    const void *src_dev;    /* canonical complex128 [nrhs][V][12]; read at admission */
+    void       *sol_dev;    /* canonical complex128 [nrhs][V][12]; written at retire */
+    wd_cg_params params;    /* inner must be WD_F32 or WD_F64                         */
+} wd_request;
+
+typedef struct {
+    uint64_t submitted, admitted, completed;
+    uint64_t steps;             /* scheduling steps run                           */
+    uint64_t arena_high_water;  /* largest number of arena bytes in use           */
+    int32_t  active, pending;
+} wd_serve_stats;
+
+/* Device bytes a request occupies in the arena while it is resident. */
+size_t wd_serve_footprint(const wd_request *req);
+/* Start the scheduler thread.  The arena is used as a first-fit heap. */
+int wd_serve_create(const wd_serve_config *cfg, wd_server **out);
+/* Queue a request; returns at once.  WD_ETOOBIG if it can never fit the arena.
+ * The caller keeps gauge_dev/src_dev/sol_dev alive until the ticket is done. */
+int wd_serve_submit(wd_server *s, const wd_request *req, uint64_t *ticket);
+/* *done = 1 and reps[nrhs] filled once the request is finished, else *done = 0.
+ * Thread-safe, non-blocking.  The per-field seconds are submit -> done. */
+int wd_serve_poll(wd_server *s, uint64_t ticket, wd_cg_report *reps, int32_t *done);
+int wd_serve_stats_get(wd_server *s, wd_serve_stats *st);
+/* Finish the requests already admitted, drop the pending ones, stop the thread. */
+int wd_serve_destroy(wd_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WD_H */

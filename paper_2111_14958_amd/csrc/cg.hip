@@ -1,0 +1,600 @@
+// Conjugate gradient on the normal equations (arXiv 2111.14958, Sec. 2):
+// kernels of the phases, the hipGraph that replays a chunk of iterations, and
+// the solve driver behind wd_cg_solve / wd_cg_solve_batch.
+//
+// A solve runs
+//   init   eta64 <- src, x64 <- x0 or 0, x_lo <- 0, scalars <- host record,
+//          N (|eta|^2), R2 (r = eta - D x64, true-residual test), C (p = r)
+//   chunk  K x [A, B, C], then R1 (x64 += x_lo), R2, C, summary   (one graph)
+// and replays the chunk graph until no right-hand side is active, reading back
+// one counter per replay.
+#include <string.h>
+
+#include <atomic>
+#include <chrono>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "cg_core.h"
+#include "cg_host.h"
+
+namespace wd {
+
+// ------------------------------------------------------------------ kernels
+#define WD_KERNEL_PROLOGUE(K)                                                  \
+    const int b_ = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x; \
+    const Prob &pr = probs[find_prob(probs, nprob, K, b_)];                    \
+    const int t_ = b_ - pr.t0[K];
+
+template <int P, int NR>
+__global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KA)
+    phaseA_tile<P, NR>(pr, t_);
+    if (ticket_last(pr.ticket, pr.nt[KA])) {
+        phaseA_finish(pr);
+        if (threadIdx.x == 0) *pr.ticket = 0;
+    }
+}
+
+template <int P, int NR>
+__global__ __launch_bounds__(256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KB)
+    phaseB_tile<P, NR>(pr, t_);
+    if (ticket_last(pr.ticket, pr.nt[KB])) {
+        phaseB_finish(pr);
+        if (threadIdx.x == 0) *pr.ticket = 0;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_phaseC(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KC)
+    phaseC_tile<P>(pr, t_);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_ru1(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KR1)
+    ru1_tile<P>(pr, t_);
+}
+
+template <int P, int NR>
+__global__ __launch_bounds__(256) void k_ru2(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KR2)
+    ru2_tile<P, NR>(pr, t_);
+    if (ticket_last(pr.ticket, pr.nt[KR2])) {
+        ru2_finish(pr);
+        if (threadIdx.x == 0) *pr.ticket = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_norm(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KN)
+    norm_tile(pr, t_);
+    if (ticket_last(pr.ticket, pr.nt[KN])) {
+        norm_finish(pr);
+        if (threadIdx.x == 0) *pr.ticket = 0;
+    }
+}
+
+// out[0] = right-hand sides still active or frozen over all problems,
+// out[1] = the persistent kernel's abort flag (0 when there is none)
+__global__ void k_summary(const Prob *__restrict__ probs, int nprob, int *out, const int *abort_flag) {
+    if (threadIdx.x != 0) return;
+    int live = 0;
+    for (int j = 0; j < nprob; ++j)
+        for (int i = 0; i < probs[j].nrhs; ++i) {
+            const int st = probs[j].sc[i].state;
+            live += (st == ST_ACTIVE || st == ST_FROZEN);
+        }
+    out[0] = live;
+    out[1] = abort_flag ? *abort_flag : 0;
+}
+
+// x_lo <- 0 (a fill kernel rather than a memset, so it can sit in a graph)
+__global__ void k_zero(uint4 *p, size_t n16) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0, 0, 0, 0);
+}
+
+// ------------------------------------------------------------- launchers
+template <int P>
+static void launch_A(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    if (nr == 1) hipLaunchKernelGGL((k_phaseA<P, 1>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else if (nr == 2) hipLaunchKernelGGL((k_phaseA<P, 2>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else hipLaunchKernelGGL((k_phaseA<P, 4>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+}
+template <int P>
+static void launch_B(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    if (nr == 1) hipLaunchKernelGGL((k_phaseB<P, 1>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else if (nr == 2) hipLaunchKernelGGL((k_phaseB<P, 2>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else hipLaunchKernelGGL((k_phaseB<P, 4>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+}
+template <int P>
+static void launch_R2(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    if (nr == 1) hipLaunchKernelGGL((k_ru2<P, 1>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else hipLaunchKernelGGL((k_ru2<P, 2>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+}
+
+void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob) {
+    const KindShape &k = ls.k[kind];
+    if (k.grid <= 0) return;
+    switch (kind) {
+    case KA:
+        if (inner == P64) launch_A<P64>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
+        else if (inner == P32) launch_A<P32>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
+        else launch_A<P16>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
+        break;
+    case KB:
+        if (inner == P64) launch_B<P64>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
+        else if (inner == P32) launch_B<P32>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
+        else launch_B<P16>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
+        break;
+    case KC:
+        if (inner == P64) hipLaunchKernelGGL(k_phaseC<P64>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
+        else if (inner == P32) hipLaunchKernelGGL(k_phaseC<P32>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
+        else hipLaunchKernelGGL(k_phaseC<P16>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
+        break;
+    case KR1:
+        if (inner == P64) hipLaunchKernelGGL(k_ru1<P64>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
+        else if (inner == P32) hipLaunchKernelGGL(k_ru1<P32>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
+        else hipLaunchKernelGGL(k_ru1<P16>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
+        break;
+    case KR2:
+        if (inner == P64) launch_R2<P64>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
+        else if (inner == P32) launch_R2<P32>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
+        else launch_R2<P16>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
+        break;
+    case KN:
+        hipLaunchKernelGGL(k_norm, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
+        break;
+    }
+}
+
+void launch_summary(hipStream_t st, const Prob *d, int nprob, int *out, const int *abort_flag) {
+    hipLaunchKernelGGL(k_summary, dim3(1), dim3(64), 0, st, d, nprob, out, abort_flag);
+}
+
+void launch_zero(void *p, size_t bytes, hipStream_t st) {
+    const size_t n16 = bytes / 16;
+    const int grid = (int)std::min<size_t>((n16 + 255) / 256, 4096);
+    if (grid > 0) hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, st, (uint4 *)p, n16);
+}
+
+// ------------------------------------------------------------- host plan
+static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+WsLayout ws_layout(int64_t V, int nrhs, int inner) {
+    WsLayout L;
+    size_t o = 0;
+    L.prob = o; o += al256(sizeof(Prob));
+    L.scal = o; o += al256(sizeof(Scal) * nrhs);
+    L.ticket = o; o += 256;
+    L.summary = o; o += 256;
+    L.part = o; o += al256((size_t)((V + 63) / 64) * nrhs * sizeof(double));
+    L.eta64 = o; o += al256(spinor_bytes(WD_F64, V, nrhs));
+    L.x64 = o; o += al256(spinor_bytes(WD_F64, V, nrhs));
+    const int xp = inner == WD_F16N ? WD_F32 : inner;
+    L.xlo = o; o += al256(spinor_bytes(xp, V, nrhs));
+    L.r = o; o += al256(spinor_bytes(inner, V, nrhs));
+    L.p = o; o += al256(spinor_bytes(inner, V, nrhs));
+    L.q = o; o += al256(spinor_bytes(inner, V, nrhs));
+    L.total = o;
+    return L;
+}
+
+// Launch shapes of every kernel kind for one problem (tiles start at 0).
+void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr) {
+    const int V = (int)g->V;
+    ShapeKey ka{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, inner, nrhs, 1};
+    ShapeKey kb = ka;
+    kb.dag = 0;
+    ShapeKey kr = kb;
+    kr.prec = WD_F64;
+    Shape sa = shape_lookup(ka), sb = shape_lookup(kb), sr = shape_lookup(kr);
+    if (sr.nr > 2) sr.nr = 2;
+    const Shape *st[NKIND] = {&sa, &sb, nullptr, nullptr, &sr, nullptr};
+    for (int k = 0; k < NKIND; ++k) {
+        KindShape &ks = ls.k[k];
+        if (st[k]) {
+            ks.block = st[k]->block;
+            ks.nr = st[k]->nr;
+            ks.remap = st[k]->remap;
+        } else {
+            ks.block = 256;
+            ks.nr = 1;
+            ks.remap = 0;
+        }
+        pr.nsb[k] = (V + ks.block - 1) / ks.block;
+        pr.ng[k] = (nrhs + ks.nr - 1) / ks.nr;
+        pr.t0[k] = 0;
+        pr.nt[k] = pr.nsb[k] * pr.ng[k];
+        ks.grid = pr.nt[k];
+    }
+}
+
+// Fill the problem record of a solve whose workspace starts at ws.
+void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_params &p,
+               char *ws, const WsLayout &L) {
+    pr.g = make_geom(g);
+    pr.diag = 4.0 + m0;
+    pr.tol2 = p.tol * p.tol;
+    pr.nrhs = nrhs;
+    pr.max_iter = p.max_iter;
+    pr.ru_every = p.reliable_every;
+    pr.pad0 = 0;
+    pr.U_lo = g->U[p.inner];
+    pr.U64 = g->U[WD_F64];
+    pr.x_lo = ws + L.xlo;
+    pr.r = ws + L.r;
+    pr.p = ws + L.p;
+    pr.q = ws + L.q;
+    pr.x64 = ws + L.x64;
+    pr.eta64 = ws + L.eta64;
+    pr.part = (double *)(ws + L.part);
+    pr.ticket = (unsigned *)(ws + L.ticket);
+    pr.sc = (Scal *)(ws + L.scal);
+}
+
+void init_scalars(std::vector<Scal> &sc, int nrhs) {
+    sc.assign(nrhs, Scal());
+    for (auto &c : sc) {
+        memset(&c, 0, sizeof(c));
+        c.rho = 1.0;
+        c.rho_old = 1.0;
+        c.state = ST_FROZEN;   // the first reliable update computes r = eta - D x0
+        c.restart = 1;
+    }
+}
+
+// ------------------------------------------------------------ graph cache
+struct GraphKey {
+    const void *ws;
+    int dims[4], nrhs, inner, K, persistent;
+    int shp[NKIND][4];
+    bool operator<(const GraphKey &o) const { return memcmp(this, &o, sizeof(*this)) < 0; }
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+
+static std::mutex g_graph_mu;
+static std::map<GraphKey, GraphEntry> g_graphs;
+static uint64_t g_graph_clock = 0;
+static std::map<int, hipStream_t> g_capture_streams;
+
+static hipStream_t capture_stream() {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    auto it = g_capture_streams.find(dev);
+    if (it != g_capture_streams.end()) return it->second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    g_capture_streams[dev] = s;
+    return s;
+}
+
+// Graph of one chunk: K iterations, then the reliable update and the summary.
+// `record` enqueues the kernels of the chunk on the capture stream.
+template <typename F>
+static int get_graph(const GraphKey &key, F record, hipGraphExec_t *out) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it != g_graphs.end()) {
+        it->second.last_use = ++g_graph_clock;
+        *out = it->second.exec;
+        return WD_OK;
+    }
+    if (g_graphs.size() >= 32) {   // evict the least recently used
+        auto victim = g_graphs.begin();
+        for (auto j = g_graphs.begin(); j != g_graphs.end(); ++j)
+            if (j->second.last_use < victim->second.last_use) victim = j;
+        (void)hipGraphExecDestroy(victim->second.exec);
+        (void)hipGraphDestroy(victim->second.graph);
+        g_graphs.erase(victim);
+    }
+    hipStream_t cs = capture_stream();
+    WD_CHECK(cs, WD_EHIP, "could not create the capture stream");
+    WD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    record(cs);
+    GraphEntry e;
+    hipError_t err = hipStreamEndCapture(cs, &e.graph);
+    if (err != hipSuccess) return fail(WD_EHIP, "graph capture failed: %s", hipGetErrorString(err));
+    err = hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+        (void)hipGraphDestroy(e.graph);
+        return fail(WD_EHIP, "graph instantiation failed: %s", hipGetErrorString(err));
+    }
+    e.last_use = ++g_graph_clock;
+    g_graphs[key] = e;
+    *out = e.exec;
+    return WD_OK;
+}
+
+static int status_of(int st) {
+    switch (st) {
+    case ST_DONE: return WD_OK;
+    case ST_BREAKDOWN: return WD_EBREAKDOWN;
+    default: return WD_ENOTCONV;
+    }
+}
+
+// ------------------------------------------------------------- profiling
+static std::atomic<int> g_prof_on{0};
+static std::mutex g_prof_mu;
+struct ProfEntry {
+    int64_t launches = 0;
+    double ms = 0, bytes = 0;
+};
+static ProfEntry g_prof[3];   // phases A, B, C
+static const char *g_prof_names[3] = {"cg_phaseA", "cg_phaseB", "cg_phaseC"};
+
+static int count_states(const std::vector<Scal> &sc, bool need_pending) {
+    int n = 0;
+    for (const Scal &c : sc) n += (c.state == ST_ACTIVE && (!need_pending || c.pending_p));
+    return n;
+}
+
+// One chunk launched kernel by kernel with events around phases A, B, C.
+static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *dprob, int K,
+                          int nrhs, int64_t V, void *dscal) {
+    hipEvent_t ev[4];
+    for (auto &e : ev) WD_HIP(hipEventCreate(&e));
+    std::vector<Scal> sc(nrhs);
+    const double G = (double)link_bytes(inner, V);
+    const double S = (double)spinor_bytes(inner, V, 1);
+    const double SX = (double)spinor_bytes(inner == WD_F16N ? WD_F32 : inner, V, 1);
+    int rc = WD_OK;
+    for (int it = 0; it < K && !rc; ++it) {
+        if (hipMemcpyAsync(sc.data(), dscal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) { rc = fail(WD_EHIP, "profiling copy failed"); break; }
+        const int nact = count_states(sc, false);
+        hipEventRecord(ev[0], st);
+        launch_kind(KA, inner, ls, st, dprob, 1);
+        hipEventRecord(ev[1], st);
+        launch_kind(KB, inner, ls, st, dprob, 1);
+        hipEventRecord(ev[2], st);
+        launch_kind(KC, inner, ls, st, dprob, 1);
+        hipEventRecord(ev[3], st);
+        if (hipEventSynchronize(ev[3]) != hipSuccess) { rc = fail(WD_EHIP, "profiling sync failed"); break; }
+        if (hipMemcpyAsync(sc.data(), dscal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) { rc = fail(WD_EHIP, "profiling copy failed"); break; }
+        const int nc = count_states(sc, true);
+        float ms[3];
+        for (int k = 0; k < 3; ++k) hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]);
+        const double bytes[3] = {G + nact * 2.0 * S, G + nact * (3.0 * S + 2.0 * SX), nc * 3.0 * S};
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        for (int k = 0; k < 3; ++k) {
+            if (k < 2 && nact == 0) continue;
+            if (k == 2 && nc == 0) continue;
+            g_prof[k].launches += 1;
+            g_prof[k].ms += ms[k];
+            g_prof[k].bytes += bytes[k];
+        }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    return rc;
+}
+
+// The solve driver shared by wd_cg_solve and wd_cg_solve_batch.
+int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, const wd_cg_params &p,
+           void *ws, size_t ws_bytes, wd_cg_report *reps, hipStream_t st) {
+    const auto t_start = std::chrono::steady_clock::now();
+    const int64_t V = g->V;
+    const WsLayout L = ws_layout(V, nrhs, p.inner);
+    WD_CHECK(ws_bytes >= L.total, WD_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+    char *w = (char *)ws;
+    Prob hp;
+    memset(&hp, 0, sizeof(hp));
+    fill_prob(hp, g, m0, nrhs, p, w, L);
+    LaunchSet ls;
+    plan_shapes(g, nrhs, p.inner, ls, hp);
+    const Prob *dprob = (const Prob *)(w + L.prob);
+    int *dsum = (int *)(w + L.summary);
+
+    const int K = p.chunk > 0 ? p.chunk : (p.reliable_every > 0 ? p.reliable_every : 50);
+    const int persistent = p.persistent == 1 ? 1 : 0;
+
+    // upload the problem record and the initial scalars
+    std::vector<Scal> sc;
+    init_scalars(sc, nrhs);
+    WD_HIP(hipMemcpyAsync((void *)dprob, &hp, sizeof(hp), hipMemcpyHostToDevice, st));
+    WD_HIP(hipMemcpyAsync(w + L.scal, sc.data(), sizeof(Scal) * nrhs, hipMemcpyHostToDevice, st));
+    WD_HIP(hipMemsetAsync(w + L.ticket, 0, 256, st));
+    // fields
+    int rc = launch_pack_spinor(WD_F64, src, w + L.eta64, (int)V, nrhs, st);
+    if (rc) return rc;
+    if (p.use_x0) rc = launch_pack_spinor(WD_F64, sol, w + L.x64, (int)V, nrhs, st);
+    else launch_zero(w + L.x64, spinor_bytes(WD_F64, V, nrhs), st);
+    if (rc) return rc;
+    launch_zero(w + L.xlo, spinor_bytes(p.inner == WD_F16N ? WD_F32 : p.inner, V, nrhs), st);
+    // |eta|, first true residual, p = r
+    launch_kind(KN, p.inner, ls, st, dprob, 1);
+    launch_kind(KR2, p.inner, ls, st, dprob, 1);
+    launch_kind(KC, p.inner, ls, st, dprob, 1);
+    const int *dabort = persistent ? (const int *)(w + L.ticket + 128) : nullptr;
+    launch_summary(st, dprob, 1, dsum, dabort);
+    WD_HIP(hipGetLastError());
+
+    GraphKey key;
+    memset(&key, 0, sizeof(key));
+    key.ws = ws;
+    for (int d = 0; d < 4; ++d) key.dims[d] = g->dims[d];
+    key.nrhs = nrhs;
+    key.inner = p.inner;
+    key.K = K;
+    key.persistent = persistent;
+    for (int k = 0; k < NKIND; ++k) {
+        key.shp[k][0] = ls.k[k].block;
+        key.shp[k][1] = ls.k[k].nr;
+        key.shp[k][2] = ls.k[k].remap;
+        key.shp[k][3] = ls.k[k].grid;
+    }
+    hipGraphExec_t exec = nullptr;
+    int rec_rc = WD_OK;
+    rc = get_graph(key, [&](hipStream_t cs) {
+        if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, K, w + L.ticket + 64);
+        else
+            for (int it = 0; it < K; ++it) {
+                launch_kind(KA, p.inner, ls, cs, dprob, 1);
+                launch_kind(KB, p.inner, ls, cs, dprob, 1);
+                launch_kind(KC, p.inner, ls, cs, dprob, 1);
+            }
+        launch_kind(KR1, p.inner, ls, cs, dprob, 1);
+        launch_kind(KR2, p.inner, ls, cs, dprob, 1);
+        launch_kind(KC, p.inner, ls, cs, dprob, 1);
+        launch_summary(cs, dprob, 1, dsum, dabort);
+    }, &exec);
+    if (rc) return rc;
+    if (rec_rc) return rec_rc;
+
+    int *hsum = nullptr;
+    WD_HIP(hipHostMalloc((void **)&hsum, 64, hipHostMallocDefault));
+    WD_HIP(hipMemcpyAsync(hsum, dsum, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    WD_HIP(hipStreamSynchronize(st));
+    // every chunk either converges a field or spends K iterations of it
+    const int max_chunks = p.max_iter / K + 2 * (p.max_iter / (K * 4) + 4);
+    const bool prof = g_prof_on.load() != 0 && !persistent;
+    for (int c = 0; c < max_chunks && hsum[0] > 0; ++c) {
+        hipError_t e = hipSuccess;
+        if (prof) {
+            rc = profiled_chunk(p.inner, ls, st, dprob, K, nrhs, V, w + L.scal);
+            if (rc) {
+                (void)hipHostFree(hsum);
+                return rc;
+            }
+            launch_kind(KR1, p.inner, ls, st, dprob, 1);
+            launch_kind(KR2, p.inner, ls, st, dprob, 1);
+            launch_kind(KC, p.inner, ls, st, dprob, 1);
+            launch_summary(st, dprob, 1, dsum, dabort);
+        } else {
+            e = hipGraphLaunch(exec, st);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(hsum, dsum, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            (void)hipHostFree(hsum);
+            return fail(WD_EHIP, "chunk replay failed: %s", hipGetErrorString(e));
+        }
+        if (persistent && hsum[1] != 0) {
+            (void)hipHostFree(hsum);
+            return fail(WD_EHIP, "persistent kernel grid barrier timed out");
+        }
+    }
+    (void)hipHostFree(hsum);
+    // solution out, scalars back
+    rc = launch_unpack_spinor(WD_F64, w + L.x64, sol, (int)V, nrhs, st);
+    if (rc) return rc;
+    WD_HIP(hipMemcpyAsync(sc.data(), w + L.scal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st));
+    WD_HIP(hipStreamSynchronize(st));
+    int first_bad = WD_OK;
+    for (int i = 0; i < nrhs; ++i) {
+        if (sc[i].zero_src) WD_HIP(hipMemsetAsync((char *)sol + (size_t)i * V * 192, 0, (size_t)V * 192, st));
+    }
+    WD_HIP(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    for (int i = 0; i < nrhs; ++i) {
+        const Scal &c = sc[i];
+        wd_cg_report &r = reps[i];
+        memset(&r, 0, sizeof(r));
+        r.status = status_of(c.state);
+        r.iters = c.iters;
+        r.reliable_updates = c.n_ru;
+        r.true_rel_res = c.eta2 > 0 ? sqrt(c.true2 / c.eta2) : 0.0;
+        r.iter_rel_res = c.eta2 > 0 ? sqrt(c.rho / c.eta2) : 0.0;
+        r.seconds = secs;
+        if (r.status != WD_OK && first_bad == WD_OK) first_bad = r.status;
+    }
+    if (first_bad != WD_OK)
+        fail(first_bad, "%s", first_bad == WD_EBREAKDOWN ? "a field broke down" : "a field did not converge");
+    return first_bad;
+}
+
+int check_params(const wd_cg_params *p) {
+    WD_CHECK(p, WD_EINVAL, "null params");
+    WD_CHECK(p->tol > 0 && p->tol < 1, WD_EINVAL, "tol %g out of (0, 1)", p->tol);
+    WD_CHECK(p->max_iter >= 1, WD_EINVAL, "max_iter %d < 1", p->max_iter);
+    WD_CHECK(p->reliable_every >= 0, WD_EINVAL, "reliable_every %d < 0", p->reliable_every);
+    WD_CHECK(p->inner >= 0 && p->inner <= 2, WD_EINVAL, "unknown inner precision %d", p->inner);
+    WD_CHECK(p->chunk >= 0 && p->chunk <= 1000, WD_EINVAL, "chunk %d out of range", p->chunk);
+    WD_CHECK(p->persistent >= -1 && p->persistent <= 1, WD_EINVAL, "persistent %d", p->persistent);
+    return WD_OK;
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+void wd_cg_default_params(wd_cg_params *p) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->tol = 1e-10;
+    p->max_iter = 20000;
+    p->reliable_every = 50;
+    p->inner = WD_F32;
+    p->use_x0 = 0;
+    p->persistent = -1;
+    p->chunk = 0;
+}
+
+size_t wd_cg_workspace_bytes(const wd_gauge *g, int32_t nrhs, const wd_cg_params *p) {
+    if (!g || !p || nrhs < 1 || nrhs > MAX_RHS || p->inner < 0 || p->inner > 2) return 0;
+    return ws_layout(g->V, nrhs, p->inner).total;
+}
+
+int wd_cg_solve_batch(const wd_gauge *g, double m0, const void *src, void *sol, int32_t nrhs,
+                      const wd_cg_params *p, void *ws, size_t ws_bytes, wd_cg_report *reps, void *stream) {
+    clear_error();
+    WD_CHECK(g && src && sol && ws && reps, WD_EINVAL, "null argument");
+    WD_CHECK(nrhs >= 1 && nrhs <= MAX_RHS, WD_EINVAL, "nrhs %d out of range 1..%d", nrhs, MAX_RHS);
+    WD_CHECK(m0 > -4.0 && m0 < 1e6, WD_EINVAL, "m0 %g out of range", m0);
+    int rc = check_params(p);
+    if (rc) return rc;
+    WD_CHECK(g->U[p->inner], WD_EINVAL, "gauge handle holds no links in precision %d", p->inner);
+    WD_CHECK(src != sol, WD_EINVAL, "src and sol must not overlap");
+    rc = require_gfx950();
+    if (rc) return rc;
+    return cg_run(g, m0, src, sol, nrhs, *p, ws, ws_bytes, reps, (hipStream_t)stream);
+}
+
+int wd_cg_solve(const wd_gauge *g, double m0, const void *src, void *sol, const wd_cg_params *p,
+                void *ws, size_t ws_bytes, wd_cg_report *rep, void *stream) {
+    return wd_cg_solve_batch(g, m0, src, sol, 1, p, ws, ws_bytes, rep, stream);
+}
+
+int wd_profile_enable(int32_t on) {
+    clear_error();
+    g_prof_on.store(on ? 1 : 0);
+    return WD_OK;
+}
+
+int wd_profile_reset(void) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &e : g_prof) e = ProfEntry();
+    return WD_OK;
+}
+
+int wd_profile_read(wd_kernel_stat *out, int32_t max_n, int32_t *n) {
+    clear_error();
+    WD_CHECK(n && (out || max_n == 0), WD_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    *n = 3;
+    for (int k = 0; k < 3 && k < max_n; ++k) {
+        memset(&out[k], 0, sizeof(out[k]));
+        strncpy(out[k].name, g_prof_names[k], sizeof(out[k].name) - 1);
+        out[k].launches = g_prof[k].launches;
+        out[k].total_ms = g_prof[k].ms;
+        out[k].bytes_total = g_prof[k].bytes;
+    }
+    return WD_OK;
+}
+
+}  // extern "C"

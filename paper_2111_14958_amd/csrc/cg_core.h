@@ -1,0 +1,428 @@
+// Device side of the conjugate-gradient solver (arXiv 2111.14958, Sec. 2).
+//
+// The paper's CG on D D^dagger chi = eta, psi = D^dagger chi, is carried in the
+// solution space (x = D^dagger chi):
+//     q = D^dagger p;  alpha = rho / |q|^2;  x += alpha q;  r -= alpha D q;
+//     rho' = |r|^2;    beta = rho' / rho;    p = r + beta p
+// so r is the residual of D x = eta itself.  One iteration is three phases:
+//     A  q = D^dagger p                     + partial sums of |q|^2   -> alpha
+//     B  t = D q, r -= alpha t, x += alpha q + partial sums of |r|^2   -> beta
+//     C  p = r + beta p
+// Every scalar lives in device memory, one record per right-hand side; the
+// last block of a phase (an atomic ticket) sums the per-block partials in a
+// fixed order and updates the scalars, so nothing returns to the host inside
+// an iteration and reductions are bitwise reproducible.
+//
+// Mixed precision: p, q, r and x_lo are stored in the inner precision (FP16N
+// keeps x_lo in FP32).  A reliable update (R1, R2) accumulates x64 += x_lo and
+// recomputes r = eta - D x64 with FP64 links and FP64 arithmetic; the solve
+// ends only when that true residual satisfies |r| <= tol |eta|.
+#pragma once
+
+#include "wd_device.h"
+
+namespace wd {
+
+// per right-hand-side state
+enum : int { ST_ACTIVE = 0, ST_FROZEN = 1, ST_DONE = 2, ST_BREAKDOWN = 3, ST_NOTCONV = 4 };
+// kernel kinds: phase A, phase B, phase C, reliable update R1 (x64 += x_lo),
+// reliable update R2 (r = eta - D x64), source norm N
+enum : int { KA = 0, KB = 1, KC = 2, KR1 = 3, KR2 = 4, KN = 5, NKIND = 6 };
+
+struct alignas(16) Scal {
+    double rho;       // |r|^2 of the current residual
+    double rho_old;   // previous rho, for beta
+    double alpha, beta, sigma;
+    double eta2;      // |eta|^2
+    double stop2;     // (tol |eta|)^2
+    double true2;     // last true residual |eta - D x64|^2
+    int state;        // ST_*
+    int iters;        // CG iterations done
+    int since_ru;     // iterations since the last reliable update
+    int n_ru;         // reliable updates done
+    int pending_p;    // 1: phase C must rebuild p for this rhs
+    int restart;      // 1: the next direction is p = r
+    int zero_src;     // 1: eta == 0, the solution is 0
+    int pad;
+};
+
+struct alignas(16) Prob {
+    Geom g;
+    double diag;      // 4 + m0
+    double tol2;
+    int nrhs, max_iter, ru_every, pad0;
+    int nsb[NKIND];   // site blocks per kernel kind
+    int ng[NKIND];    // rhs groups per kernel kind
+    int t0[NKIND];    // first tile of this problem in a grouped launch
+    int nt[NKIND];    // tiles of this problem
+    const void *U_lo; // links in the inner precision
+    const void *U64;  // FP64 links
+    void *x_lo, *r, *p, *q;   // inner-precision vectors (x_lo: FP32 for FP16N)
+    void *x64, *eta64;        // FP64 packed vectors
+    double *part;             // [nsb][nrhs] partial sums of the current phase
+    unsigned *ticket;         // block counter of the current phase (self-resetting)
+    Scal *sc;                 // [nrhs]
+};
+
+// precision x_lo is stored in
+template <int P> struct XPrec { static constexpr int value = P; };
+template <> struct XPrec<P16> { static constexpr int value = P32; };
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Sum v[j] over the block in a fixed order; result valid on thread 0.
+template <int NR>
+__device__ __forceinline__ void block_sum(double v[NR]) {
+    __shared__ double red[4][NR];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) v[j] = wave_sum(v[j]);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < NR; ++j) red[w][j] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            double s = 0;
+            for (int k = 0; k < nw; ++k) s += red[k][j];
+            v[j] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// After thread 0 has written this block's partials: count the block in the
+// problem's ticket; returns true (in every thread) for the last block of the
+// phase, which then sees every other block's partials.
+__device__ __forceinline__ bool ticket_last(unsigned *ticket, unsigned total) {
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned t = atomicAdd(ticket, 1u);
+        last = (t == total - 1);
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+// Fixed-order sum over site blocks of partial column i; valid on thread 0.
+__device__ __forceinline__ double sum_partials(const Prob &pr, int nsb, int i) {
+    double s[1] = {0.0};
+    for (int b = threadIdx.x; b < nsb; b += blockDim.x) s[0] += pr.part[(size_t)b * pr.nrhs + i];
+    block_sum<1>(s);
+    return s[0];
+}
+
+__device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < 1e300; }
+
+// which problem of a grouped launch owns global tile b of kind K
+__device__ __forceinline__ int find_prob(const Prob *probs, int nprob, int K, int b) {
+    int j = 0;
+    while (j + 1 < nprob && b >= probs[j + 1].t0[K]) ++j;
+    return j;
+}
+
+// bit j set: rhs rhs0 + j is in state `want`
+template <int NR>
+__device__ __forceinline__ unsigned rhs_mask(const Prob &pr, int rhs0, int want) {
+    unsigned m = 0;
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+        if (rhs0 + j < pr.nrhs && pr.sc[rhs0 + j].state == want) m |= 1u << j;
+    return m;
+}
+
+// ------------------------------------------------------------------ phase A
+// q = D^dagger p for active rhs; partial |q|^2 (of the stored q)
+template <int P, int NR>
+__device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
+    typedef typename real_of<P>::type R;
+    const int ng = pr.ng[KA];
+    const int sb = t / ng, grp = t - sb * ng;
+    const int s = sb * blockDim.x + threadIdx.x;
+    const int rhs0 = grp * NR;
+    const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
+    double part[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) part[j] = 0.0;
+    const Geom g = pr.g;
+    if (act && s < g.V) {
+        FieldPtr fp{pr.p, g.V, pr.nrhs}, fq{pr.q, g.V, pr.nrhs};
+        const void *U = pr.U_lo;
+        cx<R> acc[NR][12];
+        hopping<P, true, NR>(g, s, U, fp, rhs0, act, acc);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            if (act >> j & 1) {
+                cx<R> self[12], o[12];
+                Spinor<P>::load(fp, rhs0 + j, s, self);
+                wilson_finish<R>((R)pr.diag, self, acc[j], o);
+                Spinor<P>::store(fq, rhs0 + j, s, o);
+                double n = 0;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) n += (double)norm2(o[k]);
+                part[j] = n;
+            }
+        }
+    }
+    if (act) {
+        block_sum<NR>(part);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+                if (act >> j & 1) pr.part[(size_t)sb * pr.nrhs + rhs0 + j] = part[j];
+    }
+}
+
+__device__ __forceinline__ void phaseA_finish(const Prob &pr) {
+    for (int i = 0; i < pr.nrhs; ++i) {
+        Scal &c = pr.sc[i];
+        const int st = c.state;   // uniform
+        if (st == ST_ACTIVE) {
+            const double sigma = sum_partials(pr, pr.nsb[KA], i);
+            if (threadIdx.x == 0) {
+                c.sigma = sigma;
+                if (!finite_pos(sigma)) c.state = ST_BREAKDOWN;
+                else c.alpha = c.rho / sigma;
+            }
+        }
+        if (threadIdx.x == 0) {
+            c.pending_p = 0;
+            c.restart = 0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ phase B
+// t = D q; r -= alpha t; x_lo += alpha q(s); partial |r|^2 (of the stored r)
+template <int P, int NR>
+__device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
+    typedef typename real_of<P>::type R;
+    constexpr int XP = XPrec<P>::value;
+    typedef typename real_of<XP>::type RX;
+    const int ng = pr.ng[KB];
+    const int sb = t / ng, grp = t - sb * ng;
+    const int s = sb * blockDim.x + threadIdx.x;
+    const int rhs0 = grp * NR;
+    const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
+    double part[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) part[j] = 0.0;
+    const Geom g = pr.g;
+    if (act && s < g.V) {
+        FieldPtr fq{pr.q, g.V, pr.nrhs}, fr{pr.r, g.V, pr.nrhs}, fx{pr.x_lo, g.V, pr.nrhs};
+        const void *U = pr.U_lo;
+        cx<R> acc[NR][12];
+        hopping<P, false, NR>(g, s, U, fq, rhs0, act, acc);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            if (act >> j & 1) {
+                const R a = (R)pr.sc[rhs0 + j].alpha;
+                cx<R> q[12], o[12], r[12];
+                Spinor<P>::load(fq, rhs0 + j, s, q);
+                wilson_finish<R>((R)pr.diag, q, acc[j], o);
+                Spinor<P>::load(fr, rhs0 + j, s, r);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) r[k] = {r[k].re - a * o[k].re, r[k].im - a * o[k].im};
+                Spinor<P>::store(fr, rhs0 + j, s, r);
+                double n = 0;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) n += (double)norm2(r[k]);
+                part[j] = n;
+                cx<RX> x[12];
+                Spinor<XP>::load(fx, rhs0 + j, s, x);
+                const RX ax = (RX)pr.sc[rhs0 + j].alpha;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) x[k] = {x[k].re + ax * (RX)q[k].re, x[k].im + ax * (RX)q[k].im};
+                Spinor<XP>::store(fx, rhs0 + j, s, x);
+            }
+        }
+    }
+    if (act) {
+        block_sum<NR>(part);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+                if (act >> j & 1) pr.part[(size_t)sb * pr.nrhs + rhs0 + j] = part[j];
+    }
+}
+
+__device__ __forceinline__ void phaseB_finish(const Prob &pr) {
+    for (int i = 0; i < pr.nrhs; ++i) {
+        Scal &c = pr.sc[i];
+        if (c.state != ST_ACTIVE) continue;   // uniform
+        const double rho = sum_partials(pr, pr.nsb[KB], i);
+        if (threadIdx.x == 0) {
+            c.rho_old = c.rho;
+            c.rho = rho;
+            c.beta = rho / c.rho_old;
+            c.iters += 1;
+            c.since_ru += 1;
+            if (!(rho < 1e300)) c.state = ST_BREAKDOWN;   // NaN or Inf
+            else if (rho <= c.stop2 || c.iters >= pr.max_iter ||
+                     (pr.ru_every > 0 && c.since_ru >= pr.ru_every))
+                c.state = ST_FROZEN;                       // wants a reliable update
+            else c.pending_p = 1;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ phase C
+// p = r + beta p (or p = r after a restart), streaming, tile = (site block, rhs)
+template <int P>
+__device__ __forceinline__ void phaseC_tile(const Prob &pr, int t) {
+    typedef typename real_of<P>::type R;
+    const int sb = t / pr.nrhs, i = t - sb * pr.nrhs;
+    const int s = sb * blockDim.x + threadIdx.x;
+    const Scal &c = pr.sc[i];
+    if (c.state != ST_ACTIVE || !c.pending_p || s >= pr.g.V) return;
+    FieldPtr fr{pr.r, pr.g.V, pr.nrhs}, fp{pr.p, pr.g.V, pr.nrhs};
+    cx<R> r[12], p[12];
+    Spinor<P>::load(fr, i, s, r);
+    if (!c.restart) {
+        const R b = (R)c.beta;
+        Spinor<P>::load(fp, i, s, p);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) r[k] = {r[k].re + b * p[k].re, r[k].im + b * p[k].im};
+    }
+    Spinor<P>::store(fp, i, s, r);
+}
+
+// ------------------------------------------------------- reliable update R1
+// x64 += x_lo; x_lo = 0   (rhs that are frozen)
+template <int P>
+__device__ __forceinline__ void ru1_tile(const Prob &pr, int t) {
+    constexpr int XP = XPrec<P>::value;
+    typedef typename real_of<XP>::type RX;
+    const int sb = t / pr.nrhs, i = t - sb * pr.nrhs;
+    const int s = sb * blockDim.x + threadIdx.x;
+    if (pr.sc[i].state != ST_FROZEN || s >= pr.g.V) return;
+    FieldPtr fx{pr.x_lo, pr.g.V, pr.nrhs}, f64{pr.x64, pr.g.V, pr.nrhs};
+    cx<RX> xl[12];
+    cx<double> x[12];
+    Spinor<XP>::load(fx, i, s, xl);
+    Spinor<P64>::load(f64, i, s, x);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        x[k] = {x[k].re + (double)xl[k].re, x[k].im + (double)xl[k].im};
+        xl[k] = {RX(0), RX(0)};
+    }
+    Spinor<P64>::store(f64, i, s, x);
+    Spinor<XP>::store(fx, i, s, xl);
+}
+
+// ------------------------------------------------------- reliable update R2
+// r = eta - D x64 in FP64 with FP64 links; r_lo = r rounded to the inner
+// precision; partial |r|^2 in FP64 (frozen rhs)
+template <int P, int NR>
+__device__ __forceinline__ void ru2_tile(const Prob &pr, int t) {
+    typedef typename real_of<P>::type R;
+    const int ng = pr.ng[KR2];
+    const int sb = t / ng, grp = t - sb * ng;
+    const int s = sb * blockDim.x + threadIdx.x;
+    const int rhs0 = grp * NR;
+    const unsigned act = rhs_mask<NR>(pr, rhs0, ST_FROZEN);
+    double part[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) part[j] = 0.0;
+    const Geom g = pr.g;
+    if (act && s < g.V) {
+        FieldPtr fx{pr.x64, g.V, pr.nrhs}, fe{pr.eta64, g.V, pr.nrhs}, fr{pr.r, g.V, pr.nrhs};
+        const void *U = pr.U64;
+        cx<double> acc[NR][12];
+        hopping<P64, false, NR>(g, s, U, fx, rhs0, act, acc);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            if (act >> j & 1) {
+                cx<double> x[12], e[12], o[12];
+                Spinor<P64>::load(fx, rhs0 + j, s, x);
+                wilson_finish<double>(pr.diag, x, acc[j], o);
+                Spinor<P64>::load(fe, rhs0 + j, s, e);
+                cx<R> rl[12];
+                double n = 0;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    const cx<double> d = e[k] - o[k];
+                    n += norm2(d);
+                    rl[k] = {(R)d.re, (R)d.im};
+                }
+                Spinor<P>::store(fr, rhs0 + j, s, rl);
+                part[j] = n;
+            }
+        }
+    }
+    if (act) {
+        block_sum<NR>(part);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+                if (act >> j & 1) pr.part[(size_t)sb * pr.nrhs + rhs0 + j] = part[j];
+    }
+}
+
+__device__ __forceinline__ void ru2_finish(const Prob &pr) {
+    for (int i = 0; i < pr.nrhs; ++i) {
+        Scal &c = pr.sc[i];
+        if (c.state != ST_FROZEN) {
+            if (threadIdx.x == 0) c.pending_p = 0;
+            continue;
+        }
+        const double r2 = sum_partials(pr, pr.nsb[KR2], i);
+        if (threadIdx.x == 0) {
+            c.true2 = r2;
+            c.n_ru += 1;
+            c.since_ru = 0;
+            c.pending_p = 0;
+            if (r2 <= c.stop2) c.state = ST_DONE;
+            else if (!(r2 < 1e300)) c.state = ST_BREAKDOWN;
+            else if (c.iters >= pr.max_iter) c.state = ST_NOTCONV;
+            else {
+                // Continue from the true residual.  beta stays the value of the
+                // last iteration (iterated |r|^2 over its predecessor); forming it
+                // from the true |r|^2 instead stalls when the stored residual has
+                // drifted far from the true one (FP16 storage).
+                c.rho = r2;
+                c.state = ST_ACTIVE;
+                c.pending_p = 1;
+            }
+        }
+    }
+}
+
+// -------------------------------------------------------- source norm |eta|^2
+__device__ __forceinline__ void norm_tile(const Prob &pr, int t) {
+    const int sb = t / pr.nrhs, i = t - sb * pr.nrhs;
+    const int s = sb * blockDim.x + threadIdx.x;
+    double part[1] = {0.0};
+    if (s < pr.g.V) {
+        FieldPtr fe{pr.eta64, pr.g.V, pr.nrhs};
+        cx<double> e[12];
+        Spinor<P64>::load(fe, i, s, e);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) part[0] += norm2(e[k]);
+    }
+    block_sum<1>(part);
+    if (threadIdx.x == 0) pr.part[(size_t)sb * pr.nrhs + i] = part[0];
+}
+
+__device__ __forceinline__ void norm_finish(const Prob &pr) {
+    for (int i = 0; i < pr.nrhs; ++i) {
+        const double e2 = sum_partials(pr, pr.nsb[KN], i);
+        if (threadIdx.x == 0) {
+            Scal &c = pr.sc[i];
+            c.eta2 = e2;
+            c.stop2 = pr.tol2 * e2;
+            if (e2 == 0.0) { c.state = ST_DONE; c.zero_src = 1; c.true2 = 0.0; }
+            else if (!(e2 < 1e300)) c.state = ST_BREAKDOWN;
+        }
+    }
+}
+
+}  // namespace wd

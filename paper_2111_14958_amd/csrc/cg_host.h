@@ -1,0 +1,37 @@
+// Host-side pieces of the CG solver shared by the batch solver and the server.
+#pragma once
+
+#include <vector>
+
+#include "cg_core.h"
+#include "wd_host.h"
+
+namespace wd {
+
+struct KindShape {
+    int block = 256, nr = 1, remap = 0, grid = 0;
+};
+struct LaunchSet {
+    KindShape k[NKIND];
+};
+
+// Byte offsets of the pieces of a solve workspace.
+struct WsLayout {
+    size_t prob, scal, ticket, summary, part, eta64, x64, xlo, r, p, q, total;
+};
+
+WsLayout ws_layout(int64_t V, int nrhs, int inner);
+void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr);
+void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_params &p, char *ws,
+               const WsLayout &L);
+void init_scalars(std::vector<Scal> &sc, int nrhs);
+void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob);
+void launch_summary(hipStream_t st, const Prob *d, int nprob, int *out, const int *abort_flag);
+void launch_zero(void *p, size_t bytes, hipStream_t st);
+int check_params(const wd_cg_params *p);
+// Record one persistent chunk kernel (K iterations of phases A, B, C with grid
+// barriers) on `st`; `bar` is 256 bytes of device scratch for the barrier.
+int record_persistent_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob,
+                            int K, void *bar);
+
+}  // namespace wd

@@ -1,0 +1,128 @@
+// The Wilson-Dirac operator D and its adjoint (Eq. (1), Sec. 1; D^dagger by
+// gamma5-hermiticity, Sec. 2) as a matrix-free stencil on packed fields.
+//
+// One thread computes one lattice site for NR right-hand sides, so each link
+// is loaded once per NR fields.  A block covers `block` consecutive sites of one
+// group of NR right-hand sides; tiles are ordered site-block-major, group-minor,
+// and optionally remapped so each XCD sweeps one contiguous slab of sites.
+#include "wd_device.h"
+#include "wd_host.h"
+
+namespace wd {
+
+template <int P, bool DAG, int NR>
+__global__ __launch_bounds__(256) void k_dslash(Geom g, double diag, const void *__restrict__ U,
+                                                FieldPtr in, FieldPtr out, int ngroups, int remap) {
+    typedef typename real_of<P>::type R;
+    const int b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int sb = b / ngroups, grp = b - sb * ngroups;
+    const int s = sb * blockDim.x + threadIdx.x;
+    if (s >= g.V) return;
+    const int rhs0 = grp * NR;
+    const int nact = min(NR, in.nrhs - rhs0);
+    const unsigned act = (1u << nact) - 1u;
+    cx<R> acc[NR][12];
+    hopping<P, DAG, NR>(g, s, U, in, rhs0, act, acc);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (act >> j & 1) {
+            cx<R> self[12], o[12];
+            Spinor<P>::load(in, rhs0 + j, s, self);
+            wilson_finish<R>((R)diag, self, acc[j], o);
+            Spinor<P>::store(out, rhs0 + j, s, o);
+        }
+    }
+}
+
+template <int P, bool DAG>
+static void launch_nr(int nr, dim3 grid, dim3 block, hipStream_t st, const Geom &g, double diag,
+                      const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap) {
+    switch (nr) {
+    case 1: hipLaunchKernelGGL((k_dslash<P, DAG, 1>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap); break;
+    case 2: hipLaunchKernelGGL((k_dslash<P, DAG, 2>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap); break;
+    default: hipLaunchKernelGGL((k_dslash<P, DAG, 4>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap); break;
+    }
+}
+
+Geom make_geom(const wd_gauge *gg) {
+    Geom g;
+    for (int d = 0; d < 4; ++d) g.L[d] = gg->dims[d];
+    g.S[0] = 1;
+    g.S[1] = g.L[0];
+    g.S[2] = g.L[0] * g.L[1];
+    g.S[3] = g.L[0] * g.L[1] * g.L[2];
+    g.V = (int)gg->V;
+    g.tsign = gg->tsign;
+    return g;
+}
+
+int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void *in, void *out,
+                  int nrhs, const Shape &sh, hipStream_t st) {
+    const Geom g = make_geom(gg);
+    const int nr = (sh.nr == 1 || sh.nr == 2 || sh.nr == 4) ? sh.nr : 1;
+    const int blk = (sh.block == 64 || sh.block == 128 || sh.block == 256) ? sh.block : 256;
+    const int ngroups = (nrhs + nr - 1) / nr;
+    const int nsb = (g.V + blk - 1) / blk;
+    const dim3 grid(nsb * ngroups), block(blk);
+    FieldPtr fi{(void *)in, g.V, nrhs}, fo{out, g.V, nrhs};
+    const void *U = gg->U[prec];
+    const double diag = 4.0 + m0;
+    switch (prec * 2 + (dag ? 1 : 0)) {
+    case 0: launch_nr<P64, false>(nr, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    case 1: launch_nr<P64, true>(nr, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    case 2: launch_nr<P32, false>(nr, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    case 3: launch_nr<P32, true>(nr, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    case 4: launch_nr<P16, false>(nr, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    case 5: launch_nr<P16, true>(nr, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    default: return fail(WD_EINVAL, "unknown precision %d", prec);
+    }
+    WD_HIP(hipGetLastError());
+    return WD_OK;
+}
+
+static int dslash_entry(const wd_gauge *g, double m0, int32_t prec, const void *in, void *out,
+                        int32_t nrhs, uint32_t flags, void *stream, bool dag) {
+    clear_error();
+    WD_CHECK(g && in && out, WD_EINVAL, "null argument");
+    WD_CHECK(prec >= 0 && prec <= 2, WD_EINVAL, "unknown precision %d", prec);
+    WD_CHECK(nrhs >= 1 && nrhs <= MAX_RHS, WD_EINVAL, "nrhs %d out of range 1..%d", nrhs, MAX_RHS);
+    WD_CHECK((flags & ~WD_PACKED) == 0, WD_EINVAL, "unknown flags 0x%x", flags);
+    WD_CHECK(g->U[prec] != nullptr, WD_EINVAL, "gauge handle holds no links in precision %d", prec);
+    WD_CHECK(in != out, WD_EINVAL, "in and out must not overlap");
+    WD_CHECK(m0 == m0, WD_EINVAL, "m0 is NaN");
+    int rc = require_gfx950();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    ShapeKey key{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, prec, nrhs, dag ? 1 : 0};
+    const Shape sh = shape_lookup(key);
+    if (flags & WD_PACKED) return launch_dslash(g, m0, prec, dag, in, out, nrhs, sh, st);
+
+    // canonical complex128 in/out: pack, apply, unpack through temporaries
+    const size_t nb = spinor_bytes(prec, g->V, nrhs);
+    void *a = nullptr, *b = nullptr;
+    WD_HIP(hipMallocAsync(&a, nb, st));
+    hipError_t e = hipMallocAsync(&b, nb, st);
+    if (e != hipSuccess) {
+        hipFreeAsync(a, st);
+        return fail(WD_ENOMEM, "hipMallocAsync: %s", hipGetErrorString(e));
+    }
+    rc = launch_pack_spinor(prec, in, a, (int)g->V, nrhs, st);
+    if (!rc) rc = launch_dslash(g, m0, prec, dag, a, b, nrhs, sh, st);
+    if (!rc) rc = launch_unpack_spinor(prec, b, out, (int)g->V, nrhs, st);
+    hipFreeAsync(a, st);
+    hipFreeAsync(b, st);
+    return rc;
+}
+
+}  // namespace wd
+
+extern "C" {
+int wd_dslash(const wd_gauge *g, double m0, int32_t prec, const void *in_dev, void *out_dev,
+              int32_t nrhs, uint32_t flags, void *stream) {
+    return wd::dslash_entry(g, m0, prec, in_dev, out_dev, nrhs, flags, stream, false);
+}
+int wd_dslash_dag(const wd_gauge *g, double m0, int32_t prec, const void *in_dev, void *out_dev,
+                  int32_t nrhs, uint32_t flags, void *stream) {
+    return wd::dslash_entry(g, m0, prec, in_dev, out_dev, nrhs, flags, stream, true);
+}
+}

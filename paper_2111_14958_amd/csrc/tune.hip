@@ -1,0 +1,240 @@
+// Launch-shape table and autotuner.
+//
+// The paper tunes the SYCL workgroup size of its CG kernels per device
+// (Sec. 3.1, Fig. 1).  Here the equivalent knobs of the operator kernel are the
+// block size, the number of right-hand sides each thread carries (link reuse
+// against register pressure) and the XCD-contiguous tile order.  Candidates are
+// timed on scratch fields with HIP events; a candidate must reproduce the
+// reference shape's output bit for bit (the per-site arithmetic does not depend
+// on the shape) or it is rejected.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "wd_device.h"
+#include "wd_host.h"
+
+namespace wd {
+
+bool ShapeKey::operator<(const ShapeKey &o) const {
+    for (int d = 0; d < 4; ++d)
+        if (L[d] != o.L[d]) return L[d] < o.L[d];
+    if (prec != o.prec) return prec < o.prec;
+    if (nrhs != o.nrhs) return nrhs < o.nrhs;
+    return dag < o.dag;
+}
+
+static std::mutex g_mu;
+static std::map<ShapeKey, std::pair<Shape, double>> g_table;
+static bool g_loaded = false;
+
+Shape default_shape(int prec, int nrhs) {
+    Shape s;
+    s.block = 256;
+    s.remap = 1;
+    s.nr = (prec == WD_F64) ? 1 : (nrhs >= 2 ? 2 : 1);
+    return s;
+}
+
+static void load_cache_locked() {
+    if (g_loaded) return;
+    g_loaded = true;
+    const char *path = getenv("WD_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        ShapeKey k;
+        Shape s;
+        double us = 0;
+        if (sscanf(line, "gfx950 %d %d %d %d %d %d %d %d %d %d %lf", &k.L[0], &k.L[1], &k.L[2], &k.L[3],
+                   &k.prec, &k.nrhs, &k.dag, &s.block, &s.nr, &s.remap, &us) == 11)
+            g_table[k] = {s, us};
+    }
+    fclose(f);
+}
+
+Shape shape_lookup(const ShapeKey &k) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_cache_locked();
+    auto it = g_table.find(k);
+    if (it != g_table.end()) return it->second.first;
+    return default_shape(k.prec, k.nrhs);
+}
+
+void shape_store(const ShapeKey &k, const Shape &s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    load_cache_locked();
+    g_table[k] = {s, 0.0};
+}
+
+static void append_cache(const ShapeKey &k, const Shape &s, double us) {
+    const char *path = getenv("WD_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "gfx950 %d %d %d %d %d %d %d %d %d %d %.3f\n", k.L[0], k.L[1], k.L[2], k.L[3], k.prec,
+            k.nrhs, k.dag, s.block, s.nr, s.remap, us);
+    fclose(f);
+}
+
+// Deterministic scratch data: a counter hash mapped to [-1, 1).
+__device__ __forceinline__ float hash_unit(uint32_t i) {
+    i ^= i >> 16; i *= 0x7feb352du; i ^= i >> 15; i *= 0x846ca68bu; i ^= i >> 16;
+    return (float)(i >> 8) * (2.0f / 16777216.0f) - 1.0f;
+}
+
+// Fill a packed spinor buffer with valid data of precision P.
+template <int P>
+__global__ void k_fill(void *buf, int V, int nrhs, uint32_t seed) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= V) return;
+    typedef typename real_of<P>::type R;
+    cx<R> v[12];
+    for (int k = 0; k < 12; ++k) {
+        const uint32_t base = seed + 24u * ((uint32_t)r * (uint32_t)V + (uint32_t)s) + 2u * k;
+        v[k] = {(R)hash_unit(base), (R)hash_unit(base + 1)};
+    }
+    FieldPtr f{buf, V, nrhs};
+    Spinor<P>::store(f, r, s, v);
+}
+
+static int fill_spinor(int prec, void *buf, int V, int nrhs, hipStream_t st) {
+    dim3 grid((V + 255) / 256, nrhs);
+    if (prec == WD_F64) hipLaunchKernelGGL(k_fill<P64>, grid, dim3(256), 0, st, buf, V, nrhs, 12345u);
+    if (prec == WD_F32) hipLaunchKernelGGL(k_fill<P32>, grid, dim3(256), 0, st, buf, V, nrhs, 12345u);
+    if (prec == WD_F16N) hipLaunchKernelGGL(k_fill<P16>, grid, dim3(256), 0, st, buf, V, nrhs, 12345u);
+    WD_HIP(hipGetLastError());
+    return WD_OK;
+}
+
+static double algorithmic_bytes(int prec, int64_t V, int nrhs) {
+    return (double)link_bytes(prec, V) + 2.0 * (double)spinor_bytes(prec, V, nrhs);
+}
+
+// Time `reps` launches of one shape; returns the median in microseconds.
+static int time_shape(const wd_gauge *g, int prec, bool dag, const void *in, void *out, int nrhs,
+                      const Shape &sh, hipStream_t st, int reps, double *median_us) {
+    hipEvent_t e0, e1;
+    WD_HIP(hipEventCreate(&e0));
+    WD_HIP(hipEventCreate(&e1));
+    std::vector<double> t;
+    int rc = WD_OK;
+    for (int w = 0; w < 2 && !rc; ++w) rc = launch_dslash(g, 0.1, prec, dag, in, out, nrhs, sh, st);
+    for (int i = 0; i < reps && !rc; ++i) {
+        hipEventRecord(e0, st);
+        rc = launch_dslash(g, 0.1, prec, dag, in, out, nrhs, sh, st);
+        hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = fail(WD_EHIP, "event sync failed");
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        t.push_back(ms * 1000.0);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    std::sort(t.begin(), t.end());
+    *median_us = t[t.size() / 2];
+    return WD_OK;
+}
+
+}  // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, wd_tune_result *cfg) {
+    clear_error();
+    WD_CHECK(g && cfg, WD_EINVAL, "null argument");
+    ShapeKey k{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, prec, nrhs, dagger ? 1 : 0};
+    Shape s = shape_lookup(k);
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->block = s.block;
+    cfg->rhs_per_thread = s.nr;
+    cfg->xcd_remap = s.remap;
+    return WD_OK;
+}
+
+int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, wd_tune_result *best,
+                   void *stream) {
+    clear_error();
+    WD_CHECK(g, WD_EINVAL, "null gauge");
+    WD_CHECK(prec >= 0 && prec <= 2 && g->U[prec], WD_EINVAL, "gauge holds no links in precision %d", prec);
+    WD_CHECK(nrhs >= 1 && nrhs <= MAX_RHS, WD_EINVAL, "nrhs %d out of range", nrhs);
+    int rc = require_gfx950();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int V = (int)g->V;
+    const size_t nb = spinor_bytes(prec, V, nrhs);
+    void *in = nullptr, *ref = nullptr, *out = nullptr;
+    WD_HIP(hipMalloc(&in, nb));
+    if (hipMalloc(&ref, nb) != hipSuccess || hipMalloc(&out, nb) != hipSuccess) {
+        hipFree(in);
+        if (ref) hipFree(ref);
+        return fail(WD_ENOMEM, "autotuner scratch allocation failed");
+    }
+    std::vector<unsigned char> h_ref(nb), h_out(nb);
+    const bool dag = dagger != 0;
+    Shape refshape;
+    refshape.block = 256;
+    refshape.nr = 1;
+    refshape.remap = 0;
+    Shape bestshape = refshape;
+    double best_us = 1e30;
+    rc = fill_spinor(prec, in, V, nrhs, st);
+    if (!rc) rc = launch_dslash(g, 0.1, prec, dag, in, ref, nrhs, refshape, st);
+    if (!rc && hipMemcpyAsync(h_ref.data(), ref, nb, hipMemcpyDeviceToHost, st) != hipSuccess)
+        rc = fail(WD_EHIP, "copy of reference output failed");
+    if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(WD_EHIP, "stream sync failed");
+    const int blocks[3] = {64, 128, 256};
+    const int nrs[3] = {1, 2, 4};
+    for (int bi = 0; bi < 3 && !rc; ++bi)
+        for (int ni = 0; ni < 3 && !rc; ++ni)
+            for (int remap = 0; remap < 2 && !rc; ++remap) {
+                Shape s;
+                s.block = blocks[bi];
+                s.nr = nrs[ni];
+                s.remap = remap;
+                if (s.nr > 1 && s.nr > nrhs) continue;
+                if (prec == WD_F64 && s.nr > 2) continue;
+                hipMemsetAsync(out, 0, nb, st);
+                rc = launch_dslash(g, 0.1, prec, dag, in, out, nrhs, s, st);
+                if (rc) break;
+                if (hipMemcpyAsync(h_out.data(), out, nb, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess) {
+                    rc = fail(WD_EHIP, "copy of candidate output failed");
+                    break;
+                }
+                if (memcmp(h_out.data(), h_ref.data(), nb) != 0) continue;   // rejected
+                double us = 0;
+                rc = time_shape(g, prec, dag, in, out, nrhs, s, st, 10, &us);
+                if (!rc && us < best_us) { best_us = us; bestshape = s; }
+            }
+    hipFree(in);
+    hipFree(ref);
+    hipFree(out);
+    if (rc) return rc;
+    ShapeKey k{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, prec, nrhs, dagger ? 1 : 0};
+    shape_store(k, bestshape);
+    append_cache(k, bestshape, best_us);
+    if (best) {
+        memset(best, 0, sizeof(*best));
+        best->block = bestshape.block;
+        best->rhs_per_thread = bestshape.nr;
+        best->xcd_remap = bestshape.remap;
+        best->us = best_us;
+        best->gbps = algorithmic_bytes(prec, V, nrhs) / (best_us * 1e-6) / 1e9;
+    }
+    return WD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,347 @@
+// Device-side building blocks of libwd: complex arithmetic, lattice geometry,
+// packed field accessors in three storage precisions, and the spin-projected
+// Wilson hopping term of Eq. (1) (arXiv 2111.14958, Sec. 1).
+//
+// Storage precisions:
+//   P64  FP64 links and spinors, FP64 arithmetic
+//   P32  FP32 links and spinors, FP32 arithmetic
+//   P16  FP16 links, FP16 spinors with one FP32 norm per site, FP32 arithmetic
+//
+// Packed layouts (structure of arrays, sites fastest, so that the 64 lanes of a
+// wavefront read 64 consecutive sites with one wide load per component chunk):
+//   spinor P64  double2 [rhs][12][V]
+//          P32  float4  [rhs][6][V]      (two complex components per float4)
+//          P16  half8   [rhs][3][V]      (four complex components per 16 bytes)
+//               + float [rhs][V] norms after the codes of all rhs
+//   links  P64  double2 [mu][9][V]       (U_mu(x)[a][b] at index 3a+b)
+//          P32  float2  [mu][9][V]
+//          P16  half2   [mu][9][V]
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wd {
+
+enum : int { P64 = 0, P32 = 1, P16 = 2 };
+
+typedef _Float16 h16;
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef _Float16 half8v __attribute__((ext_vector_type(8)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// Field pointers handed to kernels through device-side records are generic
+// pointers; accessing them through the global address space lets the compiler
+// emit global (not flat) loads and stores.
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(void *p) { return (gptr<T>)p; }
+template <typename T> __device__ __forceinline__ gptr<const T> as_global(const void *p) { return (gptr<const T>)p; }
+
+template <int P> struct real_of { typedef float type; };
+template <> struct real_of<P64> { typedef double type; };
+
+template <typename R> struct cx { R re, im; };
+
+template <typename R> __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator-(cx<R> a) { return {-a.re, -a.im}; }
+template <typename R> __device__ __forceinline__ cx<R> operator*(R s, cx<R> a) { return {s * a.re, s * a.im}; }
+template <typename R> __device__ __forceinline__ cx<R> times_i(cx<R> a) { return {-a.im, a.re}; }
+template <typename R> __device__ __forceinline__ cx<R> times_mi(cx<R> a) { return {a.im, -a.re}; }
+// a * b
+template <typename R> __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename R> __device__ __forceinline__ cx<R> cjmul(cx<R> a, cx<R> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; }
+
+// ------------------------------------------------------------------ geometry
+struct Geom {
+    int L[4];     // Lx, Ly, Lz, Lt
+    int S[4];     // strides 1, Lx, Lx*Ly, Lx*Ly*Lz
+    int V;        // sites
+    int tsign;    // -1 antiperiodic in t, +1 periodic
+};
+
+__device__ __forceinline__ void site_coords(const Geom &g, int s, int c[4]) {
+    int r = s;
+    c[0] = r % g.L[0]; r /= g.L[0];
+    c[1] = r % g.L[1]; r /= g.L[1];
+    c[2] = r % g.L[2];
+    c[3] = r / g.L[2];
+}
+
+// ------------------------------------------------------------- spinor views
+// Base pointer of a packed field holding nrhs right-hand sides on V sites.
+struct FieldPtr {
+    void *p;
+    int V;
+    int nrhs;
+};
+
+template <int P> struct Spinor;
+
+template <> struct Spinor<P64> {
+    typedef double R;
+    static constexpr int BYTES_PER_SITE = 192;
+    __device__ static __forceinline__ void load(const FieldPtr &f, int r, int s, cx<R> o[12]) {
+        gptr<const d2v> d = as_global<d2v>((const void *)f.p) + (size_t)r * 12 * f.V + s;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) { d2v v = d[k * f.V]; o[k] = {v.x, v.y}; }
+    }
+    __device__ static __forceinline__ void store(const FieldPtr &f, int r, int s, const cx<R> o[12]) {
+        gptr<d2v> d = as_global<d2v>(f.p) + (size_t)r * 12 * f.V + s;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) d[k * f.V] = d2v{o[k].re, o[k].im};
+    }
+};
+
+template <> struct Spinor<P32> {
+    typedef float R;
+    static constexpr int BYTES_PER_SITE = 96;
+    __device__ static __forceinline__ void load(const FieldPtr &f, int r, int s, cx<R> o[12]) {
+        gptr<const f4v> d = as_global<f4v>((const void *)f.p) + (size_t)r * 6 * f.V + s;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            f4v v = d[j * f.V];
+            o[2 * j] = {v.x, v.y};
+            o[2 * j + 1] = {v.z, v.w};
+        }
+    }
+    __device__ static __forceinline__ void store(const FieldPtr &f, int r, int s, const cx<R> o[12]) {
+        gptr<f4v> d = as_global<f4v>(f.p) + (size_t)r * 6 * f.V + s;
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+            d[j * f.V] = f4v{o[2 * j].re, o[2 * j].im, o[2 * j + 1].re, o[2 * j + 1].im};
+    }
+};
+
+template <> struct Spinor<P16> {
+    typedef float R;
+    static constexpr int BYTES_PER_SITE = 52;
+    __device__ static __forceinline__ gptr<float> norms(const FieldPtr &f) {
+        return (gptr<float>)(as_global<half8v>(f.p) + (size_t)f.nrhs * 3 * f.V);
+    }
+    __device__ static __forceinline__ void load(const FieldPtr &f, int r, int s, cx<R> o[12]) {
+        gptr<const half8v> d = as_global<half8v>((const void *)f.p) + (size_t)r * 3 * f.V + s;
+        const float n = norms(f)[(size_t)r * f.V + s];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            half8v v = d[j * f.V];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o[4 * j + k] = {n * (float)v[2 * k], n * (float)v[2 * k + 1]};
+        }
+    }
+    // Quantise: norm = max |re|,|im| over the site; code = half(v / norm), the
+    // FP32 quotient rounded to nearest even.  Returns the stored values in o.
+    __device__ static __forceinline__ void store(const FieldPtr &f, int r, int s, cx<R> o[12]) {
+        float n = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) n = fmaxf(n, fmaxf(fabsf(o[k].re), fabsf(o[k].im)));
+        gptr<half8v> d = as_global<half8v>(f.p) + (size_t)r * 3 * f.V + s;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            half8v v;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float a = n > 0.f ? o[4 * j + k].re / n : 0.f;
+                float b = n > 0.f ? o[4 * j + k].im / n : 0.f;
+                v[2 * k] = (h16)a;
+                v[2 * k + 1] = (h16)b;
+                o[4 * j + k] = {n * (float)v[2 * k], n * (float)v[2 * k + 1]};
+            }
+            d[j * f.V] = v;
+        }
+        norms(f)[(size_t)r * f.V + s] = n;
+    }
+};
+
+// --------------------------------------------------------------- link views
+template <int P> struct Link;
+
+template <> struct Link<P64> {
+    typedef double R;
+    static constexpr int BYTES_PER_LINK = 144;
+    __device__ static __forceinline__ void load(const void *U, int V, int mu, int s, cx<R> u[9]) {
+        gptr<const d2v> d = as_global<d2v>(U) + (size_t)mu * 9 * V + s;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) { d2v v = d[k * V]; u[k] = {v.x, v.y}; }
+    }
+};
+template <> struct Link<P32> {
+    typedef float R;
+    static constexpr int BYTES_PER_LINK = 72;
+    __device__ static __forceinline__ void load(const void *U, int V, int mu, int s, cx<R> u[9]) {
+        gptr<const f2v> d = as_global<f2v>(U) + (size_t)mu * 9 * V + s;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) { f2v v = d[k * V]; u[k] = {v.x, v.y}; }
+    }
+};
+template <> struct Link<P16> {
+    typedef float R;
+    static constexpr int BYTES_PER_LINK = 36;
+    __device__ static __forceinline__ void load(const void *U, int V, int mu, int s, cx<R> u[9]) {
+        gptr<const half2v> d = as_global<half2v>(U) + (size_t)mu * 9 * V + s;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) { half2v v = d[k * V]; u[k] = {(float)v.x, (float)v.y}; }
+    }
+};
+
+// ------------------------------------------------- spin projection, Eq. (1)
+// In the DeGrand-Rossi basis gamma_mu = [[0, B_mu], [B_mu^dagger, 0]] with
+// B_x = i sigma_1, B_y = -i sigma_2, B_z = i sigma_3, B_t = 1.  For a spinor
+// psi = (u; d) (spins 0,1 | 2,3):
+//   (1 + S gamma_mu) psi = (h ; S B_mu^dagger h),   h = u + S B_mu d,   S = +-1.
+// The colour link commutes with the spin structure, so a hop multiplies only
+// the two-spin half spinor h by the link and rebuilds the lower spins after.
+
+// h = u + S * B_mu d  (h: 2 spins x 3 colours)
+template <int MU, int S, typename R>
+__device__ __forceinline__ void project(const cx<R> p[12], cx<R> h[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cx<R> d0 = p[6 + c], d1 = p[9 + c];
+        cx<R> b0, b1;
+        if constexpr (MU == 0) { b0 = times_i(d1); b1 = times_i(d0); }
+        else if constexpr (MU == 1) { b0 = -d1; b1 = d0; }
+        else if constexpr (MU == 2) { b0 = times_i(d0); b1 = times_mi(d1); }
+        else { b0 = d0; b1 = d1; }
+        if constexpr (S > 0) { h[c] = p[c] + b0; h[3 + c] = p[3 + c] + b1; }
+        else { h[c] = p[c] - b0; h[3 + c] = p[3 + c] - b1; }
+    }
+}
+
+// acc_upper += w, acc_lower += S * B_mu^dagger w
+template <int MU, int S, typename R>
+__device__ __forceinline__ void accumulate(const cx<R> w[6], cx<R> acc[12]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cx<R> w0 = w[c], w1 = w[3 + c];
+        acc[c] = acc[c] + w0;
+        acc[3 + c] = acc[3 + c] + w1;
+        cx<R> l0, l1;
+        if constexpr (MU == 0) { l0 = times_mi(w1); l1 = times_mi(w0); }
+        else if constexpr (MU == 1) { l0 = w1; l1 = -w0; }
+        else if constexpr (MU == 2) { l0 = times_mi(w0); l1 = times_i(w1); }
+        else { l0 = w0; l1 = w1; }
+        if constexpr (S > 0) { acc[6 + c] = acc[6 + c] + l0; acc[9 + c] = acc[9 + c] + l1; }
+        else { acc[6 + c] = acc[6 + c] - l0; acc[9 + c] = acc[9 + c] - l1; }
+    }
+}
+
+// w = U h   (per spin component)
+template <typename R>
+__device__ __forceinline__ void link_mul(const cx<R> u[9], const cx<R> h[6], cx<R> w[6]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            w[3 * sp + a] = cmul(u[3 * a], h[3 * sp]) + cmul(u[3 * a + 1], h[3 * sp + 1]) +
+                            cmul(u[3 * a + 2], h[3 * sp + 2]);
+}
+
+// w = U^dagger h
+template <typename R>
+__device__ __forceinline__ void link_adj_mul(const cx<R> u[9], const cx<R> h[6], cx<R> w[6]) {
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            w[3 * sp + a] = cjmul(u[a], h[3 * sp]) + cjmul(u[3 + a], h[3 * sp + 1]) +
+                            cjmul(u[6 + a], h[3 * sp + 2]);
+}
+
+template <int MU> struct IntC { static constexpr int value = MU; };
+
+// Hopping sum of Eq. (1) at site s for NR right-hand sides of field `in`
+// starting at rhs0 (only those whose bit is set in `act` are touched):
+//   acc = sum_mu [ (1 + SF gamma_mu) U_mu(s) psi(s+mu) + (1 + SB gamma_mu) U_mu(s-mu)^dag psi(s-mu) ]
+// with SF = -1, SB = +1 for D and SF = +1, SB = -1 for D^dagger, and the
+// boundary sign on hops in t that wrap around.  Each link is loaded once and
+// applied to all NR right-hand sides.
+template <int P, bool DAG, int NR>
+__device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, const FieldPtr &in,
+                                        int rhs0, unsigned act, cx<typename real_of<P>::type> acc[NR][12]) {
+    typedef typename real_of<P>::type R;
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    int c[4];
+    site_coords(g, s, c);
+#pragma unroll
+    for (int j = 0; j < NR; ++j)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[j][k] = {R(0), R(0)};
+
+    // One hop at a time.  Each hop's load addresses pass through empty asm
+    // statements that also consume every accumulator of the previous hop, so
+    // the compiler cannot
+    // hoist the loads of all eight hops ahead of the arithmetic (it treats the
+    // field loads as unclobbered and would otherwise do so, exhausting the
+    // register file: FP64 needs 36 registers per link and 48 per neighbour
+    // spinor, and the kernel spills to scratch).  Latency is hidden by
+    // occupancy instead.
+    auto hop = [&](auto muc, auto fwdc) {
+        constexpr int MU = decltype(muc)::value;
+        constexpr bool FWD = decltype(fwdc)::value != 0;
+        constexpr int S = FWD ? SF : SB;
+        const bool wrap = FWD ? (c[MU] == g.L[MU] - 1) : (c[MU] == 0);
+        int nb = FWD ? (wrap ? s - (g.L[MU] - 1) * g.S[MU] : s + g.S[MU])
+                     : (wrap ? s + (g.L[MU] - 1) * g.S[MU] : s - g.S[MU]);
+        int ls = FWD ? s : nb;
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+#pragma unroll
+            for (int k = 0; k < 12; ++k)
+                asm volatile("" : "+v"(nb), "+v"(ls) : "v"(acc[j][k].re), "v"(acc[j][k].im));
+        const bool neg = (MU == 3) && wrap && g.tsign < 0;
+        cx<R> u[9];
+        Link<P>::load(U, g.V, MU, ls, u);
+#pragma unroll
+        for (int j = 0; j < NR; ++j) {
+            if (act >> j & 1) {
+                cx<R> p[12], h[6], w[6];
+                Spinor<P>::load(in, rhs0 + j, nb, p);
+                project<MU, S>(p, h);
+                if (neg) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) h[k] = -h[k];
+                }
+                if constexpr (FWD) link_mul(u, h, w);
+                else link_adj_mul(u, h, w);
+                accumulate<MU, S>(w, acc[j]);
+            }
+        }
+    };
+    hop(IntC<0>{}, IntC<1>{});
+    hop(IntC<0>{}, IntC<0>{});
+    hop(IntC<1>{}, IntC<1>{});
+    hop(IntC<1>{}, IntC<0>{});
+    hop(IntC<2>{}, IntC<1>{});
+    hop(IntC<2>{}, IntC<0>{});
+    hop(IntC<3>{}, IntC<1>{});
+    hop(IntC<3>{}, IntC<0>{});
+}
+
+// Apply D (or D^dagger): o = diag * psi(s) - 1/2 acc, with diag = 4 + m0.
+template <typename R>
+__device__ __forceinline__ void wilson_finish(R diag, const cx<R> self[12], const cx<R> acc[12], cx<R> o[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k)
+        o[k] = {diag * self[k].re - R(0.5) * acc[k].re, diag * self[k].im - R(0.5) * acc[k].im};
+}
+
+// Blocks are handed to the 8 XCDs round robin (block b runs on XCD b % 8).
+// Remap so that each XCD works on one contiguous range of tiles: lattice
+// neighbours then share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    const int xcd = b & 7, idx = b >> 3;
+    const int per = n >> 3, rem = n & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
+}  // namespace wd

@@ -1,0 +1,77 @@
+// Host-side internals of libwd: error reporting, the gauge handle, launch
+// shapes and the launch helpers shared by the translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+
+#include "wd.h"
+#include "wd_device.h"
+
+namespace wd {
+
+// Record a failure for wd_last_error_detail (thread-local) and return `code`.
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+#define WD_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return ::wd::fail(WD_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                              __FILE__, __LINE__);                                         \
+    } while (0)
+
+#define WD_CHECK(cond, code, ...)                   \
+    do {                                            \
+        if (!(cond)) return ::wd::fail(code, __VA_ARGS__); \
+    } while (0)
+
+// Largest supported lattice (keeps every per-field offset in 32 bits).
+constexpr int64_t MAX_SITES = int64_t(1) << 26;
+constexpr int MAX_RHS = 64;
+
+// Verify that the current device is a gfx950; caches the answer per device.
+int require_gfx950(int *num_cu = nullptr);
+
+size_t spinor_bytes(int prec, int64_t V, int nrhs);
+size_t link_bytes(int prec, int64_t V);   // all four directions
+
+// Launch shape of one operator kernel.
+struct Shape {
+    int block = 256;         // threads per block (64, 128 or 256)
+    int nr = 1;              // right-hand sides per thread (1, 2 or 4)
+    int remap = 1;           // XCD-contiguous tile order
+};
+
+// Key of the launch-shape table: lattice, precision, rhs count, dagger.
+struct ShapeKey {
+    int L[4];
+    int prec, nrhs, dag;
+    bool operator<(const ShapeKey &o) const;
+};
+Shape shape_lookup(const ShapeKey &k);      // tuned entry or the default
+void shape_store(const ShapeKey &k, const Shape &s);
+Shape default_shape(int prec, int nrhs);
+
+}  // namespace wd
+
+struct wd_gauge {
+    int dims[4];
+    int tsign;
+    int64_t V;
+    uint32_t mask;
+    int device;
+    void *U[3];     // packed links per precision (device), nullptr when absent
+};
+
+namespace wd {
+Geom make_geom(const wd_gauge *g);
+// Launchers implemented in the .hip units (all asynchronous on `stream`).
+int launch_pack_spinor(int prec, const void *in_c128, void *out, int V, int nrhs, hipStream_t st);
+int launch_unpack_spinor(int prec, const void *in, void *out_c128, int V, int nrhs, hipStream_t st);
+int launch_dslash(const wd_gauge *g, double m0, int prec, bool dag, const void *in, void *out,
+                  int nrhs, const Shape &sh, hipStream_t st);
+}  // namespace wd

@@ -1,0 +1,197 @@
+"""GPU solver parity: wd_cg_solve / wd_cg_solve_batch against the FP64 oracle.
+
+Every returned solution is judged by the oracle's own operator: its true
+relative residual |eta - D x| / |eta| must be <= tol = 1e-10.  Against the
+oracle's CG solution the error is bounded by kappa(D) (tol_gpu + tol_oracle)
+with kappa(D) <= (8 + m0) / m0 (|D| <= 8 + m0, sigma_min(D) >= m0); the
+measured error is asserted below that bound.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2111_14958_amd as wd
+import pins
+import wdgen
+from gpu_util import dev, host, rel, say, field_set
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def kappa(m0):
+    return (8.0 + m0) / m0
+
+
+def _check_solution(U, eta, x, dims, m0, t_sign=-1):
+    res = oracle.true_residual(U, eta, x, dims, m0, t_sign)
+    assert np.all(res <= TOL * 1.0000001), f"true residuals {res}"
+    return res
+
+
+@pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
+def test_c1_4x4(inner):
+    cfg = wdgen.CONFIGS["c1_4x4"]
+    dims, m0 = cfg["dims"], cfg["m0"]
+    U = wdgen.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
+    eta = wdgen.gaussian_source(dims, 1, cfg["src_seed"])
+    say("cg c1", inner)
+    g = wd.Gauge(dev(U), dims)
+    p = wd.cg_default_params(inner=inner, reliable_every=0 if inner == wd.F64 else 50)
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    x = host(x)
+    assert rc == wd.WD_OK, reps
+    assert reps[0]["status"] == 0 and reps[0]["true_rel_res"] <= TOL
+    res = _check_solution(U, eta, x, dims, m0)
+    # the library's own FP64 true residual agrees with the oracle's
+    assert abs(reps[0]["true_rel_res"] - res[0]) <= 1e-3 * TOL + 1e-6 * res[0]
+    xo, it, ro, st = oracle.cg(U, eta, dims, m0, tol=TOL)
+    assert rel(x, xo) <= kappa(m0) * 2 * TOL
+    # and against the dense LAPACK solution of the 4^4 system
+    D = oracle.dense(U, dims, m0)
+    xs = np.linalg.solve(D, eta.ravel())
+    assert rel(x.ravel(), xs) <= kappa(m0) * TOL
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (12, 12, 12, 12), (14, 14, 14, 14)],
+                         ids=["8^4", "12^4", "14^4"])
+@pytest.mark.parametrize("inner", [wd.F64, wd.F32], ids=["f64", "f32"])
+def test_c2_single_rhs(dims, inner):
+    m0, eps = 0.05, 0.5
+    U = wdgen.gauge_field(dims, eps, 1002)
+    eta = wdgen.gaussian_source(dims, 1, 2002)
+    say("cg c2", dims, inner)
+    g = wd.Gauge(dev(U), dims)
+    p = wd.cg_default_params(inner=inner, reliable_every=0 if inner == wd.F64 else 50)
+    x, reps, rc = wd.cg_solve(g, m0, dev(eta[0]), params=p)
+    assert rc == wd.WD_OK, reps
+    x = host(x)[None]
+    _check_solution(U, eta, x, dims, m0)
+    if dims == (8, 8, 8, 8):
+        xo = oracle.cg(U, eta, dims, m0, tol=TOL)[0]
+        assert rel(x, xo) <= kappa(m0) * 2 * TOL
+
+
+def test_free_field_matches_fft_solution():
+    dims, m0 = (8, 8, 8, 8), 0.05
+    U = wdgen.unit_gauge(dims)
+    eta = wdgen.gaussian_source(dims, 1, 5)
+    say("cg free field")
+    g = wd.Gauge(dev(U), dims)
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=wd.cg_default_params(inner=wd.F32))
+    assert rc == wd.WD_OK
+    gam = [oracle.gamma(mu) for mu in range(4)]
+    xs = pins.free_solve_fft(eta[0], dims, m0, -1, gam)
+    assert rel(host(x)[0], xs) <= kappa(m0) * TOL
+
+
+def test_pure_gauge_matches_rotated_free_solution():
+    dims, m0 = (4, 4, 4, 8), 0.1
+    Om = wdgen.site_matrices(dims, 2.0, 61)
+    U = wdgen.pure_gauge(Om)
+    eta = wdgen.gaussian_source(dims, 1, 62)
+    say("cg pure gauge")
+    g = wd.Gauge(dev(U), dims)
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=wd.cg_default_params(inner=wd.F64))
+    assert rc == wd.WD_OK
+    gam = [oracle.gamma(mu) for mu in range(4)]
+    xs = wdgen.apply_site_matrix(
+        Om, pins.free_solve_fft(wdgen.apply_site_matrix(Om, eta[0], dagger=True), dims, m0, -1, gam))
+    assert rel(host(x)[0], xs) <= kappa(m0) * TOL
+
+
+@pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
+def test_batch_mixed_sources_8x4(inner):
+    """12 point sources + 4 Gaussian ones sharing one gauge field (smaller volume)."""
+    dims, m0 = (8, 8, 8, 8), 0.05
+    U = wdgen.gauge_field(dims, 0.5, 1003)
+    eta = wdgen.mixed_sources(dims, 12, 4, 2003)
+    say("cg batch 16 rhs", inner)
+    g = wd.Gauge(dev(U), dims)
+    p = wd.cg_default_params(inner=inner, reliable_every=0 if inner == wd.F64 else 50)
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    assert rc == wd.WD_OK, reps
+    assert all(r["status"] == 0 for r in reps)
+    x = host(x)
+    _check_solution(U, eta, x, dims, m0)
+    # each field agrees with the oracle's CG solution of that field
+    for i in (0, 7, 13):
+        xo = oracle.cg(U, eta[i:i + 1], dims, m0, tol=TOL)[0]
+        assert rel(x[i:i + 1], xo) <= kappa(m0) * 2 * TOL
+
+
+def test_batch_equals_single_solves():
+    dims, m0 = (6, 6, 6, 6), 0.1
+    U = wdgen.gauge_field(dims, 0.5, 71)
+    eta = wdgen.gaussian_source(dims, 3, 72)
+    g = wd.Gauge(dev(U), dims)
+    p = wd.cg_default_params(inner=wd.F32)
+    say("batch vs single")
+    xb, rb, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    assert rc == wd.WD_OK
+    xb = host(xb)
+    for i in range(3):
+        xi, ri, rc = wd.cg_solve(g, m0, dev(eta[i]), params=p)
+        assert rc == wd.WD_OK
+        # same kernels, same per-field arithmetic and reduction order
+        assert rel(host(xi), xb[i]) <= kappa(m0) * 2 * TOL
+        assert ri["iters"] == rb[i]["iters"]
+
+
+def test_initial_guess_zero_source_and_max_iter():
+    dims, m0 = (4, 4, 4, 4), 0.1
+    U = wdgen.gauge_field(dims, 0.3, 1001)
+    eta = wdgen.gaussian_source(dims, 2, 2001)
+    eta[1] = 0.0
+    g = wd.Gauge(dev(U), dims)
+    say("cg edge cases")
+    p = wd.cg_default_params(inner=wd.F64, reliable_every=0)
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    assert rc == wd.WD_OK
+    assert reps[1]["iters"] == 0 and reps[1]["true_rel_res"] == 0.0
+    assert not np.any(host(x)[1])
+    # warm start from the solution: done without an iteration
+    p.use_x0 = 1
+    x2, reps2, rc = wd.cg_solve_batch(g, m0, dev(eta), sol=x.clone(), params=p)
+    assert rc == wd.WD_OK and reps2[0]["iters"] == 0 and reps2[0]["reliable_updates"] == 1
+    # too few iterations
+    p = wd.cg_default_params(inner=wd.F64, reliable_every=0, max_iter=5)
+    x3, reps3, rc = wd.cg_solve_batch(g, m0, dev(eta[:1]), params=p, raise_on_error=False)
+    assert rc == wd.WD_ENOTCONV and reps3[0]["status"] == wd.WD_ENOTCONV
+    assert reps3[0]["iters"] == 5 and reps3[0]["true_rel_res"] > TOL
+
+
+def test_nan_source_breaks_down():
+    dims, m0 = (4, 4, 4, 4), 0.1
+    U = wdgen.gauge_field(dims, 0.3, 1001)
+    eta = wdgen.gaussian_source(dims, 2, 2001)
+    eta[0, 0, 0, 0, 0, 0, 0] = np.nan
+    g = wd.Gauge(dev(U), dims)
+    say("cg nan source")
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=wd.cg_default_params(), raise_on_error=False)
+    assert rc == wd.WD_EBREAKDOWN
+    assert reps[0]["status"] == wd.WD_EBREAKDOWN and reps[1]["status"] == wd.WD_OK
+
+
+def test_workspace_too_small():
+    dims = (4, 4, 4, 4)
+    U = wdgen.gauge_field(dims, 0.3, 1001)
+    eta = wdgen.gaussian_source(dims, 1, 2001)
+    g = wd.Gauge(dev(U), dims)
+    import torch
+    say("cg small workspace")
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    sol = torch.zeros_like(dev(eta))
+    rep = (wd.CGReport * 1)()
+    p = wd.cg_default_params()
+    import ctypes
+    rc = wd.lib().wd_cg_solve_batch(g.handle, 0.1, ctypes.c_void_p(dev(eta).data_ptr()),
+                                    ctypes.c_void_p(sol.data_ptr()), 1, ctypes.byref(p),
+                                    ctypes.c_void_p(ws.data_ptr()), 1024, rep, None)
+    assert rc == wd.WD_ENOMEM
