@@ -406,6 +406,9 @@ class Server:
         return int(lib().wd_serve_footprint(ctypes.byref(req)))
 
     def submit(self, req: Request, keep=None) -> Ticket:
+        """Queue a request.  The server reads the fields on its own stream, so
+        the caller's stream is synchronised first (the fields must be ready)."""
+        _torch().cuda.current_stream().synchronize()
         t = ctypes.c_uint64()
         _check(lib().wd_serve_submit(self.handle, ctypes.byref(req), ctypes.byref(t)),
                "wd_serve_submit")

@@ -215,6 +215,24 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
     }
 }
 
+// The persistent kernel runs phases A, B and C with one block shape.
+void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner) {
+    const int blk = ls.k[KB].block;
+    int nr = ls.k[KB].nr;
+    if (inner == WD_F64 && nr > 2) nr = 2;
+    const int kinds[3] = {KA, KB, KC};
+    for (int k : kinds) {
+        KindShape &ks = ls.k[k];
+        ks.block = blk;
+        ks.nr = (k == KC) ? 1 : nr;
+        ks.remap = 0;
+        pr.nsb[k] = (int)((V + blk - 1) / blk);
+        pr.ng[k] = (k == KC) ? nrhs : (nrhs + nr - 1) / nr;
+        pr.nt[k] = pr.nsb[k] * pr.ng[k];
+        ks.grid = pr.nt[k];
+    }
+}
+
 // Fill the problem record of a solve whose workspace starts at ws.
 void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_params &p,
                char *ws, const WsLayout &L) {
@@ -316,7 +334,7 @@ static int get_graph(const GraphKey &key, F record, hipGraphExec_t *out) {
     return WD_OK;
 }
 
-static int status_of(int st) {
+int cg_status_of(int st) {
     switch (st) {
     case ST_DONE: return WD_OK;
     case ST_BREAKDOWN: return WD_EBREAKDOWN;
@@ -399,6 +417,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
 
     const int K = p.chunk > 0 ? p.chunk : (p.reliable_every > 0 ? p.reliable_every : 50);
     const int persistent = p.persistent == 1 ? 1 : 0;
+    if (persistent) plan_persistent(ls, hp, V, nrhs, p.inner);
 
     // upload the problem record and the initial scalars
     std::vector<Scal> sc;
@@ -502,7 +521,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
         const Scal &c = sc[i];
         wd_cg_report &r = reps[i];
         memset(&r, 0, sizeof(r));
-        r.status = status_of(c.state);
+        r.status = cg_status_of(c.state);
         r.iters = c.iters;
         r.reliable_updates = c.n_ru;
         r.true_rel_res = c.eta2 > 0 ? sqrt(c.true2 / c.eta2) : 0.0;

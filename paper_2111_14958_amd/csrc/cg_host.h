@@ -22,6 +22,7 @@ struct WsLayout {
 
 WsLayout ws_layout(int64_t V, int nrhs, int inner);
 void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr);
+void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner);
 void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_params &p, char *ws,
                const WsLayout &L);
 void init_scalars(std::vector<Scal> &sc, int nrhs);
@@ -29,6 +30,7 @@ void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const
 void launch_summary(hipStream_t st, const Prob *d, int nprob, int *out, const int *abort_flag);
 void launch_zero(void *p, size_t bytes, hipStream_t st);
 int check_params(const wd_cg_params *p);
+int cg_status_of(int state);
 // Record one persistent chunk kernel (K iterations of phases A, B, C with grid
 // barriers) on `st`; `bar` is 256 bytes of device scratch for the barrier.
 int record_persistent_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob,

@@ -118,6 +118,18 @@ __global__ void k_unpack_spinor(const void *__restrict__ in, double2 *__restrict
     for (int k = 0; k < 12; ++k) dst[k] = make_double2((double)v[k].re, (double)v[k].im);
 }
 
+int launch_pack_links(int prec, const void *in, void *out, int V, hipStream_t st) {
+    const int blocks = (V + 255) / 256;
+    switch (prec) {
+    case WD_F64: hipLaunchKernelGGL(k_pack_links<P64>, dim3(blocks), dim3(256), 0, st, (const double2 *)in, out, V); break;
+    case WD_F32: hipLaunchKernelGGL(k_pack_links<P32>, dim3(blocks), dim3(256), 0, st, (const double2 *)in, out, V); break;
+    case WD_F16N: hipLaunchKernelGGL(k_pack_links<P16>, dim3(blocks), dim3(256), 0, st, (const double2 *)in, out, V); break;
+    default: return fail(WD_EINVAL, "unknown precision %d", prec);
+    }
+    WD_HIP(hipGetLastError());
+    return WD_OK;
+}
+
 int launch_pack_spinor(int prec, const void *in, void *out, int V, int nrhs, hipStream_t st) {
     dim3 grid((V + 255) / 256, nrhs);
     switch (prec) {
@@ -216,10 +228,7 @@ int wd_gauge_create(const int32_t dims[4], int32_t t_sign, const void *U_dev, ui
             delete g;
             return fail(WD_ENOMEM, "hipMalloc of %zu link bytes: %s", link_bytes(p, V), hipGetErrorString(e));
         }
-        const int blocks = (int)((V + 255) / 256);
-        if (p == WD_F64) hipLaunchKernelGGL(k_pack_links<P64>, dim3(blocks), dim3(256), 0, st, (const double2 *)U_dev, g->U[p], (int)V);
-        if (p == WD_F32) hipLaunchKernelGGL(k_pack_links<P32>, dim3(blocks), dim3(256), 0, st, (const double2 *)U_dev, g->U[p], (int)V);
-        if (p == WD_F16N) hipLaunchKernelGGL(k_pack_links<P16>, dim3(blocks), dim3(256), 0, st, (const double2 *)U_dev, g->U[p], (int)V);
+        launch_pack_links(p, U_dev, g->U[p], (int)V, st);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -1,8 +1,157 @@
-// Persistent chunk kernel (placeholder until the grid-barrier kernel lands).
+// Persistent CG chunk kernel: K iterations of phases A, B and C (the CG of
+// arXiv 2111.14958, Sec. 2, carried in the solution space) in one launch.
+//
+// The grid is sized so that every block is resident at once (occupancy x CU
+// count).  Blocks sweep the tiles of a phase, XCD by XCD in contiguous ranges,
+// then meet at a grid barrier.  The last block to arrive performs the phase's
+// fixed-order reduction (alpha or beta and the convergence tests) and releases
+// the others, so a CG iteration costs three grid-wide synchronisations and no
+// kernel launches.  Every wait is bounded: a block that waits longer than the
+// limit sets an abort flag, every other waiter sees it and exits, and the host
+// reports the failure; no wave can spin forever.
 #include "cg_host.h"
 
 namespace wd {
-int record_persistent_chunk(int, const LaunchSet &, hipStream_t, const Prob *, int, int, void *) {
-    return fail(WD_EINVAL, "persistent CG kernel not available in this build");
+
+struct Barrier {
+    unsigned *count;   // arrivals, monotonic within a launch
+    unsigned *gen;     // released barrier generations
+    int *abort;        // set when a wait exceeded its limit
+    unsigned long long limit;   // wall-clock ticks a block may wait
+};
+
+// Arrive at barrier number e; true (in every thread) for the last block.
+__device__ __forceinline__ bool bar_arrive(const Barrier &b, unsigned nblk, unsigned e) {
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned old = atomicAdd(b.count, 1u);
+        last = (old + 1 == nblk * (e + 1));
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
 }
+
+__device__ __forceinline__ void bar_release(const Barrier &b, unsigned e) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_store(b.gen, e + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Wait for barrier e to be released; returns nonzero if the launch aborted.
+__device__ __forceinline__ int bar_wait(const Barrier &b, unsigned e) {
+    __shared__ int aborted;
+    if (threadIdx.x == 0) {
+        const unsigned long long t0 = wall_clock64();
+        int ab = 0;
+        while (__hip_atomic_load(b.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < e + 1) {
+            if (__hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ab = 1; break; }
+            if (wall_clock64() - t0 > b.limit) {
+                __hip_atomic_store(b.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ab = 1;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __threadfence();
+        aborted = ab;
+    }
+    __syncthreads();
+    return aborted;
+}
+
+// Tiles of one phase for this block: the XCD of block b (b mod 8) owns the
+// contiguous range [x nt / 8, (x+1) nt / 8); its blocks stride through it.
+#define FOR_MY_TILES(nt, t)                                                       \
+    const int x_ = blockIdx.x & 7, i_ = blockIdx.x >> 3, per_ = gridDim.x >> 3;  \
+    const int lo_ = (int)(((long long)(nt) * x_) / 8), hi_ = (int)(((long long)(nt) * (x_ + 1)) / 8); \
+    for (int t = lo_ + i_; t < hi_; t += per_)
+
+template <int P, int NR>
+__global__ __launch_bounds__(256) void k_persistent(const Prob *__restrict__ probs, int K, Barrier b) {
+    const Prob &pr = probs[0];
+    const unsigned nblk = gridDim.x;
+    unsigned e = 0;
+    for (int it = 0; it < K; ++it) {
+        {   // phase A
+            FOR_MY_TILES(pr.nt[KA], t) phaseA_tile<P, NR>(pr, t);
+        }
+        if (bar_arrive(b, nblk, e)) {
+            phaseA_finish(pr);
+            bar_release(b, e);
+        } else if (bar_wait(b, e)) {
+            return;
+        }
+        ++e;
+        {   // phase B
+            FOR_MY_TILES(pr.nt[KB], t) phaseB_tile<P, NR>(pr, t);
+        }
+        if (bar_arrive(b, nblk, e)) {
+            phaseB_finish(pr);
+            bar_release(b, e);
+        } else if (bar_wait(b, e)) {
+            return;
+        }
+        ++e;
+        {   // phase C
+            FOR_MY_TILES(pr.nt[KC], t) phaseC_tile<P>(pr, t);
+        }
+        if (bar_arrive(b, nblk, e)) bar_release(b, e);
+        else if (bar_wait(b, e)) return;
+        ++e;
+    }
+}
+
+__global__ void k_bar_reset(unsigned *p) {
+    if (threadIdx.x < 32) p[threadIdx.x] = 0u;   // count, gen, abort (128 bytes)
+}
+
+template <int P, int NR>
+static int launch_persistent(int blk, hipStream_t st, const Prob *d, int K, void *bar, int max_tiles) {
+    int dev = 0, ncu = 0, per_cu = 0, khz = 0;
+    WD_HIP(hipGetDevice(&dev));
+    WD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    WD_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    WD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<P, NR>, blk, 0));
+    WD_CHECK(per_cu >= 1, WD_EHIP, "persistent kernel does not fit a compute unit");
+    int nblk = per_cu * ncu;
+    if (nblk > max_tiles) nblk = max_tiles;
+    nblk &= ~7;   // whole XCD rounds
+    if (nblk < 8) nblk = 8;
+    Barrier b;
+    b.count = (unsigned *)bar;
+    b.gen = (unsigned *)((char *)bar + 32);
+    b.abort = (int *)((char *)bar + 64);
+    b.limit = (unsigned long long)khz * 1000ull * 2ull;   // two seconds
+    hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, st, (unsigned *)bar);
+    hipLaunchKernelGGL((k_persistent<P, NR>), dim3(nblk), dim3(blk), 0, st, d, K, b);
+    WD_HIP(hipGetLastError());
+    return WD_OK;
+}
+
+int record_persistent_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob,
+                            int K, void *bar) {
+    WD_CHECK(nprob == 1, WD_EINVAL, "the persistent kernel serves one problem");
+    const KindShape &ka = ls.k[KA], &kb = ls.k[KB], &kc = ls.k[KC];
+    WD_CHECK(ka.block == kb.block && ka.block == kc.block && ka.nr == kb.nr, WD_EINVAL,
+             "persistent kernel needs one block shape for phases A, B and C");
+    const int max_tiles = std::max(ka.grid, std::max(kb.grid, kc.grid));
+    const int blk = ka.block;
+    switch (inner * 4 + ka.nr) {
+    case P64 * 4 + 1: return launch_persistent<P64, 1>(blk, st, d, K, bar, max_tiles);
+    case P64 * 4 + 2: return launch_persistent<P64, 2>(blk, st, d, K, bar, max_tiles);
+    case P32 * 4 + 1: return launch_persistent<P32, 1>(blk, st, d, K, bar, max_tiles);
+    case P32 * 4 + 2: return launch_persistent<P32, 2>(blk, st, d, K, bar, max_tiles);
+    case P32 * 4 + 4: return launch_persistent<P32, 4>(blk, st, d, K, bar, max_tiles);
+    case P16 * 4 + 1: return launch_persistent<P16, 1>(blk, st, d, K, bar, max_tiles);
+    case P16 * 4 + 2: return launch_persistent<P16, 2>(blk, st, d, K, bar, max_tiles);
+    case P16 * 4 + 4: return launch_persistent<P16, 4>(blk, st, d, K, bar, max_tiles);
+    }
+    return fail(WD_EINVAL, "no persistent kernel for precision %d with %d rhs per thread", inner, ka.nr);
+}
+
 }  // namespace wd

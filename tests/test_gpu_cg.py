@@ -195,3 +195,24 @@ def test_workspace_too_small():
                                     ctypes.c_void_p(sol.data_ptr()), 1, ctypes.byref(p),
                                     ctypes.c_void_p(ws.data_ptr()), 1024, rep, None)
     assert rc == wd.WD_ENOMEM
+
+
+@pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
+def test_persistent_kernel_matches_oracle(inner):
+    """One persistent launch per chunk (grid barriers) gives a converged solution
+    that the oracle accepts, agreeing with the kernel-per-phase path."""
+    dims, m0 = (8, 8, 8, 8), 0.05
+    U = wdgen.gauge_field(dims, 0.5, 1003)
+    eta = wdgen.mixed_sources(dims, 3, 2, 2003)
+    say("cg persistent", inner)
+    g = wd.Gauge(dev(U), dims)
+    ru = 0 if inner == wd.F64 else 50
+    p = wd.cg_default_params(inner=inner, reliable_every=ru, persistent=1)
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    assert rc == wd.WD_OK, reps
+    x = host(x)
+    _check_solution(U, eta, x, dims, m0)
+    p0 = wd.cg_default_params(inner=inner, reliable_every=ru, persistent=0)
+    x0, reps0, rc0 = wd.cg_solve_batch(g, m0, dev(eta), params=p0)
+    assert rc0 == wd.WD_OK
+    assert rel(x, host(x0)) <= kappa(m0) * 2 * TOL

@@ -1,0 +1,122 @@
+"""Serving: continuous batching of solves of different lattices on one GPU.
+
+Checks that every result is accepted by the oracle (true residual <= 1e-10),
+that each result is bit-for-bit the same alone and in a mix (the per-field
+arithmetic of a grouped launch does not depend on the other requests), that
+admission never exceeds the arena, and the error paths."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2111_14958_amd as wd
+import wdgen
+from gpu_util import dev, host, say
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def _requests():
+    rng = np.random.default_rng(10_000)
+    vols = [(4, 4, 4, 4), (6, 6, 6, 6), (4, 4, 6, 8), (8, 8, 8, 8), (6, 4, 4, 6)]
+    out = []
+    for i in range(7):
+        dims = vols[i % len(vols)]
+        nrhs = int(rng.integers(1, 4))
+        m0 = float(rng.uniform(0.05, 0.2))
+        U = wdgen.gauge_field(dims, 0.5, 10_000 + i)
+        src = wdgen.gaussian_source(dims, nrhs, 60_000 + i)
+        inner = wd.F64 if i % 3 == 2 else wd.F32
+        out.append(dict(dims=dims, nrhs=nrhs, m0=m0, U=U, src=src, inner=inner))
+    return out
+
+
+def _run(reqs, arena_bytes, max_slots=8, chunk=10):
+    import torch
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    srv = wd.Server(arena, max_slots=max_slots, chunk=chunk)
+    tickets, keep = [], []
+    for r in reqs:
+        dU, dsrc = dev(r["U"]), dev(r["src"])
+        sol = torch.zeros_like(dsrc)
+        p = wd.cg_default_params(inner=r["inner"], reliable_every=0 if r["inner"] == wd.F64 else 50)
+        req = wd.Server.request(r["dims"], r["nrhs"], r["m0"], dU, dsrc, sol, p)
+        tickets.append(srv.submit(req, keep=(dU, dsrc, sol)))
+        keep.append(sol)
+    reps = [None] * len(reqs)
+    t0 = time.time()
+    while any(r is None for r in reps):
+        for i, t in enumerate(tickets):
+            if reps[i] is None:
+                reps[i] = srv.poll(t)
+        assert time.time() - t0 < 100, "server did not finish"
+        time.sleep(0.002)
+    st = srv.stats()
+    srv.close()
+    return [host(s) for s in keep], reps, st
+
+
+def test_serve_mix_matches_oracle_and_alone():
+    reqs = _requests()
+    say("serve mix", len(reqs))
+    xs, reps, st = _run(reqs, 256 << 20)
+    assert st["completed"] == len(reqs) and st["submitted"] == len(reqs)
+    for r, x, rep in zip(reqs, xs, reps):
+        assert all(e["status"] == 0 for e in rep), rep
+        res = oracle.true_residual(r["U"], r["src"], x, r["dims"], r["m0"])
+        assert np.all(res <= TOL * 1.0000001), res
+    # each request alone gives the identical bits
+    for i in (0, 3, 5):
+        say("serve alone", i)
+        xa, repa, _ = _run([reqs[i]], 64 << 20)
+        assert np.array_equal(xa[0], xs[i])
+        assert [e["iters"] for e in repa[0]] == [e["iters"] for e in reps[i]]
+
+
+def test_serve_admission_respects_arena():
+    reqs = _requests()[:5]
+    fps = []
+    for r in reqs:
+        p = wd.cg_default_params(inner=r["inner"])
+        req = wd.Request()
+        req.dims[:] = list(r["dims"])
+        req.t_sign, req.nrhs, req.m0 = -1, r["nrhs"], r["m0"]
+        req.gauge_dev = req.src_dev = 1
+        req.sol_dev = 2
+        req.params = p
+        fps.append(wd.Server.footprint(req))
+    assert all(f > 0 for f in fps)
+    table = 3 * ((256 * 8 + 255) // 256 * 256)   # request tables, see wd_serve_create
+    arena = table + max(fps) + min(fps) + 4096      # room for about two requests at once
+    say("serve small arena", arena)
+    xs, reps, st = _run(reqs, arena, max_slots=8)
+    assert st["arena_high_water"] <= arena
+    assert st["completed"] == len(reqs)
+    for r, x, rep in zip(reqs, xs, reps):
+        assert all(e["status"] == 0 for e in rep)
+        assert np.all(oracle.true_residual(r["U"], r["src"], x, r["dims"], r["m0"]) <= TOL * 1.0000001)
+
+
+def test_serve_errors():
+    import torch
+    arena = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    srv = wd.Server(arena, max_slots=2)
+    dims = (16, 16, 16, 16)
+    U = torch.zeros((16, 16, 16, 16, 4, 3, 3), dtype=torch.complex128, device="cuda")
+    src = torch.zeros((1, 16, 16, 16, 16, 4, 3), dtype=torch.complex128, device="cuda")
+    sol = torch.zeros_like(src)
+    req = wd.Server.request(dims, 1, 0.1, U, src, sol)
+    say("serve errors")
+    with pytest.raises(wd.WDError) as e:
+        srv.submit(req)
+    assert e.value.code == wd.WD_ETOOBIG
+    with pytest.raises(wd.WDError) as e:
+        srv.poll(wd.Ticket(12345, 1))
+    assert e.value.code == wd.WD_ENOTFOUND
+    bad = wd.Server.request(dims, 1, 0.1, U, src, sol, wd.cg_default_params(inner=wd.F16N))
+    with pytest.raises(wd.WDError) as e:
+        srv.submit(bad)
+    assert e.value.code == wd.WD_EINVAL
+    srv.close()
