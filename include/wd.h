@@ -175,6 +175,9 @@ typedef struct {
     int32_t block;        /* threads per block                                   */
     int32_t rhs_per_thread;
     int32_t xcd_remap;    /* 1: tiles mapped to XCDs in contiguous ranges        */
+    int32_t hop_order;    /* 1: hops one at a time, 2: a direction's two hops together,
+                             0: compiler order                                    */
+    int32_t rhs_loop;     /* rhs groups one block handles one after the other    */
     int32_t reserved;
     double  us;           /* median time of one application, microseconds        */
     double  gbps;         /* algorithmic bytes / time                             */

@@ -68,7 +68,8 @@ class CGReport(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("rhs_per_thread", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32), ("hop_order", ctypes.c_int32),
+                ("rhs_loop", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("us", ctypes.c_double), ("gbps", ctypes.c_double)]
 
 

@@ -188,11 +188,13 @@ WsLayout ws_layout(int64_t V, int nrhs, int inner) {
 // Launch shapes of every kernel kind for one problem (tiles start at 0).
 void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr) {
     const int V = (int)g->V;
-    ShapeKey ka{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, inner, nrhs, 1};
+    ShapeKey ka{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, inner, nrhs, 1, FAM_CG_A};
     ShapeKey kb = ka;
     kb.dag = 0;
+    kb.fam = FAM_CG_B;
     ShapeKey kr = kb;
     kr.prec = WD_F64;
+    kr.fam = FAM_CG_R;
     Shape sa = shape_lookup(ka), sb = shape_lookup(kb), sr = shape_lookup(kr);
     if (sr.nr > 2) sr.nr = 2;
     const Shape *st[NKIND] = {&sa, &sb, nullptr, nullptr, &sr, nullptr};
@@ -352,47 +354,62 @@ struct ProfEntry {
 static ProfEntry g_prof[3];   // phases A, B, C
 static const char *g_prof_names[3] = {"cg_phaseA", "cg_phaseB", "cg_phaseC"};
 
-static int count_states(const std::vector<Scal> &sc, bool need_pending) {
-    int n = 0;
-    for (const Scal &c : sc) n += (c.state == ST_ACTIVE && (!need_pending || c.pending_p));
-    return n;
-}
-
-// One chunk launched kernel by kernel with events around phases A, B, C.
+// One chunk launched kernel by kernel, back to back, with events around
+// every phase-A/B/C launch.  The number of fields that iterated in each
+// launch is recovered after the chunk from the per-field iteration counters:
+// an active field iterates without gaps from the start of the chunk until it
+// freezes, so field i took part in iteration j of the chunk iff j < d_i, where
+// d_i is its iteration count advance over the chunk (and skipped phase C of
+// the iteration in which it froze).
 static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *dprob, int K,
                           int nrhs, int64_t V, void *dscal) {
-    hipEvent_t ev[4];
+    std::vector<hipEvent_t> ev(3 * K + 1);
     for (auto &e : ev) WD_HIP(hipEventCreate(&e));
-    std::vector<Scal> sc(nrhs);
+    std::vector<Scal> before(nrhs), after(nrhs);
     const double G = (double)link_bytes(inner, V);
     const double S = (double)spinor_bytes(inner, V, 1);
     const double SX = (double)spinor_bytes(inner == WD_F16N ? WD_F32 : inner, V, 1);
     int rc = WD_OK;
-    for (int it = 0; it < K && !rc; ++it) {
-        if (hipMemcpyAsync(sc.data(), dscal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) { rc = fail(WD_EHIP, "profiling copy failed"); break; }
-        const int nact = count_states(sc, false);
+    if (hipMemcpyAsync(before.data(), dscal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        rc = fail(WD_EHIP, "profiling copy failed");
+    if (!rc) {
         hipEventRecord(ev[0], st);
-        launch_kind(KA, inner, ls, st, dprob, 1);
-        hipEventRecord(ev[1], st);
-        launch_kind(KB, inner, ls, st, dprob, 1);
-        hipEventRecord(ev[2], st);
-        launch_kind(KC, inner, ls, st, dprob, 1);
-        hipEventRecord(ev[3], st);
-        if (hipEventSynchronize(ev[3]) != hipSuccess) { rc = fail(WD_EHIP, "profiling sync failed"); break; }
-        if (hipMemcpyAsync(sc.data(), dscal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) { rc = fail(WD_EHIP, "profiling copy failed"); break; }
-        const int nc = count_states(sc, true);
-        float ms[3];
-        for (int k = 0; k < 3; ++k) hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]);
-        const double bytes[3] = {G + nact * 2.0 * S, G + nact * (3.0 * S + 2.0 * SX), nc * 3.0 * S};
+        for (int it = 0; it < K; ++it) {
+            launch_kind(KA, inner, ls, st, dprob, 1);
+            hipEventRecord(ev[3 * it + 1], st);
+            launch_kind(KB, inner, ls, st, dprob, 1);
+            hipEventRecord(ev[3 * it + 2], st);
+            launch_kind(KC, inner, ls, st, dprob, 1);
+            hipEventRecord(ev[3 * it + 3], st);
+        }
+        if (hipMemcpyAsync(after.data(), dscal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(WD_EHIP, "profiling copy failed");
+    }
+    if (!rc) {
+        std::vector<int> d(nrhs), froze(nrhs);
+        for (int i = 0; i < nrhs; ++i) {
+            d[i] = after[i].iters - before[i].iters;
+            froze[i] = (d[i] > 0 && after[i].state != ST_ACTIVE) ? 1 : 0;
+        }
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        for (int k = 0; k < 3; ++k) {
-            if (k < 2 && nact == 0) continue;
-            if (k == 2 && nc == 0) continue;
-            g_prof[k].launches += 1;
-            g_prof[k].ms += ms[k];
-            g_prof[k].bytes += bytes[k];
+        for (int it = 0; it < K; ++it) {
+            int nact = 0, nc = 0;
+            for (int i = 0; i < nrhs; ++i) {
+                nact += it < d[i];
+                nc += it < d[i] - froze[i];
+            }
+            const double bytes[3] = {G + nact * 2.0 * S, G + nact * (3.0 * S + 2.0 * SX), nc * 3.0 * S};
+            const int cnt[3] = {nact, nact, nc};
+            for (int k = 0; k < 3; ++k) {
+                if (cnt[k] == 0) continue;
+                float ms = 0;
+                hipEventElapsedTime(&ms, ev[3 * it + k], ev[3 * it + k + 1]);
+                g_prof[k].launches += 1;
+                g_prof[k].ms += ms;
+                g_prof[k].bytes += bytes[k];
+            }
         }
     }
     for (auto &e : ev) (void)hipEventDestroy(e);

@@ -5,43 +5,62 @@
 // is loaded once per NR fields.  A block covers `block` consecutive sites of one
 // group of NR right-hand sides; tiles are ordered site-block-major, group-minor,
 // and optionally remapped so each XCD sweeps one contiguous slab of sites.
+#include <algorithm>
+
 #include "wd_device.h"
 #include "wd_host.h"
 
 namespace wd {
 
-template <int P, bool DAG, int NR>
+template <int P, bool DAG, int NR, int ORD>
 __global__ __launch_bounds__(256) void k_dslash(Geom g, double diag, const void *__restrict__ U,
-                                                FieldPtr in, FieldPtr out, int ngroups, int remap) {
+                                                FieldPtr in, FieldPtr out, int ngroups, int remap, int rloop) {
     typedef typename real_of<P>::type R;
+    // tile = (site block, group of rloop consecutive rhs groups); the block
+    // handles its rhs groups one after the other, so fewer distinct fields are
+    // in flight per XCD at a time
+    const int nouter = (ngroups + rloop - 1) / rloop;
     const int b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int sb = b / ngroups, grp = b - sb * ngroups;
+    const int sb = b / nouter, go = b - sb * nouter;
     const int s = sb * blockDim.x + threadIdx.x;
     if (s >= g.V) return;
-    const int rhs0 = grp * NR;
-    const int nact = min(NR, in.nrhs - rhs0);
-    const unsigned act = (1u << nact) - 1u;
-    cx<R> acc[NR][12];
-    hopping<P, DAG, NR>(g, s, U, in, rhs0, act, acc);
+    for (int gi = 0; gi < rloop; ++gi) {
+        const int grp = go * rloop + gi;
+        if (grp >= ngroups) break;
+        const int rhs0 = grp * NR;
+        const int nact = min(NR, in.nrhs - rhs0);
+        const unsigned act = (1u << nact) - 1u;
+        cx<R> acc[NR][12];
+        hopping<P, DAG, NR, ORD>(g, s, U, in, rhs0, act, acc);
 #pragma unroll
-    for (int j = 0; j < NR; ++j) {
-        if (act >> j & 1) {
-            cx<R> self[12], o[12];
-            Spinor<P>::load(in, rhs0 + j, s, self);
-            wilson_finish<R>((R)diag, self, acc[j], o);
-            Spinor<P>::store(out, rhs0 + j, s, o);
+        for (int j = 0; j < NR; ++j) {
+            if (act >> j & 1) {
+                cx<R> self[12], o[12];
+                Spinor<P>::load(in, rhs0 + j, s, self);
+                wilson_finish<R>((R)diag, self, acc[j], o);
+                Spinor<P>::store(out, rhs0 + j, s, o);
+            }
         }
     }
 }
 
-template <int P, bool DAG>
-static void launch_nr(int nr, dim3 grid, dim3 block, hipStream_t st, const Geom &g, double diag,
-                      const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap) {
+template <int P, bool DAG, int ORD>
+static void launch_nr_o(int nr, dim3 grid, dim3 block, hipStream_t st, const Geom &g, double diag,
+                        const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int rl) {
     switch (nr) {
-    case 1: hipLaunchKernelGGL((k_dslash<P, DAG, 1>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap); break;
-    case 2: hipLaunchKernelGGL((k_dslash<P, DAG, 2>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap); break;
-    default: hipLaunchKernelGGL((k_dslash<P, DAG, 4>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap); break;
+    case 1: hipLaunchKernelGGL((k_dslash<P, DAG, 1, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl); break;
+    case 2: hipLaunchKernelGGL((k_dslash<P, DAG, 2, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl); break;
+    default: hipLaunchKernelGGL((k_dslash<P, DAG, 4, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl); break;
     }
+}
+
+template <int P, bool DAG>
+static void launch_nr(int nr, int ordered, int rl, dim3 grid, dim3 block, hipStream_t st, const Geom &g, double diag,
+                      const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap) {
+    if (ordered == 1) launch_nr_o<P, DAG, 1>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
+    else if (ordered == 2) launch_nr_o<P, DAG, 2>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
+    else if (ordered == 3) launch_nr_o<P, DAG, 3>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
+    else launch_nr_o<P, DAG, 0>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
 }
 
 Geom make_geom(const wd_gauge *gg) {
@@ -62,18 +81,19 @@ int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void 
     const int nr = (sh.nr == 1 || sh.nr == 2 || sh.nr == 4) ? sh.nr : 1;
     const int blk = (sh.block == 64 || sh.block == 128 || sh.block == 256) ? sh.block : 256;
     const int ngroups = (nrhs + nr - 1) / nr;
+    const int rl = sh.rloop >= 1 ? std::min(sh.rloop, ngroups) : 1;
     const int nsb = (g.V + blk - 1) / blk;
-    const dim3 grid(nsb * ngroups), block(blk);
+    const dim3 grid(nsb * ((ngroups + rl - 1) / rl)), block(blk);
     FieldPtr fi{(void *)in, g.V, nrhs}, fo{out, g.V, nrhs};
     const void *U = gg->U[prec];
     const double diag = 4.0 + m0;
     switch (prec * 2 + (dag ? 1 : 0)) {
-    case 0: launch_nr<P64, false>(nr, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
-    case 1: launch_nr<P64, true>(nr, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
-    case 2: launch_nr<P32, false>(nr, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
-    case 3: launch_nr<P32, true>(nr, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
-    case 4: launch_nr<P16, false>(nr, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
-    case 5: launch_nr<P16, true>(nr, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    case 0: launch_nr<P64, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    case 1: launch_nr<P64, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    case 2: launch_nr<P32, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    case 3: launch_nr<P32, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    case 4: launch_nr<P16, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    case 5: launch_nr<P16, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
     default: return fail(WD_EINVAL, "unknown precision %d", prec);
     }
     WD_HIP(hipGetLastError());

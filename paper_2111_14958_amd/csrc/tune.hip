@@ -27,18 +27,30 @@ bool ShapeKey::operator<(const ShapeKey &o) const {
         if (L[d] != o.L[d]) return L[d] < o.L[d];
     if (prec != o.prec) return prec < o.prec;
     if (nrhs != o.nrhs) return nrhs < o.nrhs;
-    return dag < o.dag;
+    if (dag != o.dag) return dag < o.dag;
+    return fam < o.fam;
 }
 
 static std::mutex g_mu;
 static std::map<ShapeKey, std::pair<Shape, double>> g_table;
 static bool g_loaded = false;
 
-Shape default_shape(int prec, int nrhs) {
+// Untuned shapes.  Operator kernel: one rhs per thread (fewest registers,
+// highest occupancy; the measured best on gfx950 for 14^4 x 16 rhs).  CG phase
+// kernels: two rhs per thread in FP32 / FP16N (the link loads are shared, which
+// matters more with the extra streams of the fused updates), one in FP64.
+Shape default_shape(int prec, int nrhs, int fam) {
     Shape s;
-    s.block = 256;
     s.remap = 1;
-    s.nr = (prec == WD_F64) ? 1 : (nrhs >= 2 ? 2 : 1);
+    s.ordered = 1;
+    s.rloop = 1;
+    if (fam == FAM_DSLASH) {
+        s.block = 128;
+        s.nr = 1;
+    } else {
+        s.block = 256;
+        s.nr = (prec == WD_F64 || nrhs < 2) ? 1 : 2;
+    }
     return s;
 }
 
@@ -54,8 +66,8 @@ static void load_cache_locked() {
         ShapeKey k;
         Shape s;
         double us = 0;
-        if (sscanf(line, "gfx950 %d %d %d %d %d %d %d %d %d %d %lf", &k.L[0], &k.L[1], &k.L[2], &k.L[3],
-                   &k.prec, &k.nrhs, &k.dag, &s.block, &s.nr, &s.remap, &us) == 11)
+        if (sscanf(line, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %lf", &k.L[0], &k.L[1], &k.L[2], &k.L[3],
+                   &k.prec, &k.nrhs, &k.dag, &s.block, &s.nr, &s.remap, &s.ordered, &s.rloop, &us) == 13)
             g_table[k] = {s, us};
     }
     fclose(f);
@@ -66,7 +78,7 @@ Shape shape_lookup(const ShapeKey &k) {
     load_cache_locked();
     auto it = g_table.find(k);
     if (it != g_table.end()) return it->second.first;
-    return default_shape(k.prec, k.nrhs);
+    return default_shape(k.prec, k.nrhs, k.fam);
 }
 
 void shape_store(const ShapeKey &k, const Shape &s) {
@@ -80,8 +92,8 @@ static void append_cache(const ShapeKey &k, const Shape &s, double us) {
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "gfx950 %d %d %d %d %d %d %d %d %d %d %.3f\n", k.L[0], k.L[1], k.L[2], k.L[3], k.prec,
-            k.nrhs, k.dag, s.block, s.nr, s.remap, us);
+    fprintf(f, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %.3f\n", k.L[0], k.L[1], k.L[2], k.L[3], k.prec,
+            k.nrhs, k.dag, s.block, s.nr, s.remap, s.ordered, s.rloop, us);
     fclose(f);
 }
 
@@ -161,6 +173,8 @@ int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     cfg->block = s.block;
     cfg->rhs_per_thread = s.nr;
     cfg->xcd_remap = s.remap;
+    cfg->hop_order = s.ordered;
+    cfg->rhs_loop = s.rloop;
     return WD_OK;
 }
 
@@ -188,6 +202,8 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     refshape.block = 256;
     refshape.nr = 1;
     refshape.remap = 0;
+    refshape.ordered = 1;
+    refshape.rloop = 1;
     Shape bestshape = refshape;
     double best_us = 1e30;
     rc = fill_spinor(prec, in, V, nrhs, st);
@@ -197,13 +213,19 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = fail(WD_EHIP, "stream sync failed");
     const int blocks[3] = {64, 128, 256};
     const int nrs[3] = {1, 2, 4};
+    const bool verbose = getenv("WD_TUNE_VERBOSE") != nullptr;
+    const int rloops[3] = {1, 2, 4};
     for (int bi = 0; bi < 3 && !rc; ++bi)
         for (int ni = 0; ni < 3 && !rc; ++ni)
-            for (int remap = 0; remap < 2 && !rc; ++remap) {
+            for (int cand = 0; cand < 24 && !rc; ++cand) {
                 Shape s;
                 s.block = blocks[bi];
                 s.nr = nrs[ni];
-                s.remap = remap;
+                s.remap = cand & 1;
+                s.ordered = (cand >> 1) % 4;      // 0 free, 1 per hop, 2 per direction, 3 pipelined
+                s.rloop = rloops[cand / 8];
+                const int ngroups = (nrhs + s.nr - 1) / s.nr;
+                if (s.rloop > 1 && s.rloop > ngroups) continue;
                 if (s.nr > 1 && s.nr > nrhs) continue;
                 if (prec == WD_F64 && s.nr > 2) continue;
                 hipMemsetAsync(out, 0, nb, st);
@@ -214,9 +236,17 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
                     rc = fail(WD_EHIP, "copy of candidate output failed");
                     break;
                 }
-                if (memcmp(h_out.data(), h_ref.data(), nb) != 0) continue;   // rejected
+                if (memcmp(h_out.data(), h_ref.data(), nb) != 0) {   // rejected
+                    if (verbose) fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d: output differs, rejected\n",
+                                         s.block, s.nr, s.remap, s.ordered, s.rloop);
+                    continue;
+                }
                 double us = 0;
                 rc = time_shape(g, prec, dag, in, out, nrhs, s, st, 10, &us);
+                if (verbose && !rc)
+                    fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d: %.2f us, %.0f GB/s\n",
+                            s.block, s.nr, s.remap, s.ordered, s.rloop, us,
+                            algorithmic_bytes(prec, V, nrhs) / (us * 1e-6) / 1e9);
                 if (!rc && us < best_us) { best_us = us; bestshape = s; }
             }
     hipFree(in);
@@ -231,6 +261,8 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
         best->block = bestshape.block;
         best->rhs_per_thread = bestshape.nr;
         best->xcd_remap = bestshape.remap;
+        best->hop_order = bestshape.ordered;
+        best->rhs_loop = bestshape.rloop;
         best->us = best_us;
         best->gbps = algorithmic_bytes(prec, V, nrhs) / (best_us * 1e-6) / 1e9;
     }

@@ -264,7 +264,7 @@ template <int MU> struct IntC { static constexpr int value = MU; };
 // with SF = -1, SB = +1 for D and SF = +1, SB = -1 for D^dagger, and the
 // boundary sign on hops in t that wrap around.  Each link is loaded once and
 // applied to all NR right-hand sides.
-template <int P, bool DAG, int NR>
+template <int P, bool DAG, int NR, int ORDERED = 1>
 __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, const FieldPtr &in,
                                         int rhs0, unsigned act, cx<typename real_of<P>::type> acc[NR][12]) {
     typedef typename real_of<P>::type R;
@@ -277,30 +277,50 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[j][k] = {R(0), R(0)};
 
-    // One hop at a time.  Each hop's load addresses pass through empty asm
+    // ORDERED (1): one hop at a time.  Each hop's load addresses pass through empty asm
     // statements that also consume every accumulator of the previous hop, so
     // the compiler cannot
     // hoist the loads of all eight hops ahead of the arithmetic (it treats the
     // field loads as unclobbered and would otherwise do so, exhausting the
     // register file: FP64 needs 36 registers per link and 48 per neighbour
     // spinor, and the kernel spills to scratch).  Latency is hidden by
-    // occupancy instead.
-    auto hop = [&](auto muc, auto fwdc) {
-        constexpr int MU = decltype(muc)::value;
-        constexpr bool FWD = decltype(fwdc)::value != 0;
-        constexpr int S = FWD ? SF : SB;
-        const bool wrap = FWD ? (c[MU] == g.L[MU] - 1) : (c[MU] == 0);
-        int nb = FWD ? (wrap ? s - (g.L[MU] - 1) * g.S[MU] : s + g.S[MU])
-                     : (wrap ? s + (g.L[MU] - 1) * g.S[MU] : s - g.S[MU]);
-        int ls = FWD ? s : nb;
+    // occupancy instead.  Unordered, the compiler schedules freely (kept for
+    // the operator kernel, where the autotuner may prefer it).
+    // make the index values depend on every accumulator (no instructions)
+    auto after_acc = [&](int &a, int &b) {
 #pragma unroll
         for (int j = 0; j < NR; ++j)
 #pragma unroll
             for (int k = 0; k < 12; ++k)
-                asm volatile("" : "+v"(nb), "+v"(ls) : "v"(acc[j][k].re), "v"(acc[j][k].im));
+                asm volatile("" : "+v"(a), "+v"(b) : "v"(acc[j][k].re), "v"(acc[j][k].im));
+    };
+    // neighbour and link-site index of every hop h = 2 mu + (backward ? 1 : 0)
+    int nbi[8], lsi[8];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        nbi[2 * mu] = c[mu] == g.L[mu] - 1 ? s - (g.L[mu] - 1) * g.S[mu] : s + g.S[mu];
+        nbi[2 * mu + 1] = c[mu] == 0 ? s + (g.L[mu] - 1) * g.S[mu] : s - g.S[mu];
+        lsi[2 * mu] = s;
+        lsi[2 * mu + 1] = nbi[2 * mu + 1];
+    }
+    auto hop = [&](auto hc) {
+        constexpr int H = decltype(hc)::value;
+        constexpr int MU = H / 2;
+        constexpr bool FWD = (H % 2) == 0;
+        constexpr int S = FWD ? SF : SB;
+        // ORDERED 1: this hop's loads wait for every earlier hop's arithmetic.
+        // ORDERED 2: a direction's two hops are issued together.
+        // ORDERED 3: software pipeline, the loads of hop H+1 are released as soon
+        //            as hop H-1's arithmetic is done (two hops in flight).
+        if constexpr (ORDERED == 1) after_acc(nbi[H], lsi[H]);
+        if constexpr (ORDERED == 2 && FWD) after_acc(nbi[H], lsi[H]);
+        if constexpr (ORDERED == 2 && FWD) after_acc(nbi[H + 1], lsi[H + 1]);
+        if constexpr (ORDERED == 3 && H + 1 < 8) after_acc(nbi[H + 1], lsi[H + 1]);
+        const int nb = nbi[H];
+        const bool wrap = FWD ? (c[MU] == g.L[MU] - 1) : (c[MU] == 0);
         const bool neg = (MU == 3) && wrap && g.tsign < 0;
         cx<R> u[9];
-        Link<P>::load(U, g.V, MU, ls, u);
+        Link<P>::load(U, g.V, MU, lsi[H], u);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
@@ -317,14 +337,14 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
             }
         }
     };
-    hop(IntC<0>{}, IntC<1>{});
-    hop(IntC<0>{}, IntC<0>{});
-    hop(IntC<1>{}, IntC<1>{});
-    hop(IntC<1>{}, IntC<0>{});
-    hop(IntC<2>{}, IntC<1>{});
-    hop(IntC<2>{}, IntC<0>{});
-    hop(IntC<3>{}, IntC<1>{});
-    hop(IntC<3>{}, IntC<0>{});
+    hop(IntC<0>{});
+    hop(IntC<1>{});
+    hop(IntC<2>{});
+    hop(IntC<3>{});
+    hop(IntC<4>{});
+    hop(IntC<5>{});
+    hop(IntC<6>{});
+    hop(IntC<7>{});
 }
 
 // Apply D (or D^dagger): o = diag * psi(s) - 1/2 acc, with diag = 4 + m0.

@@ -44,17 +44,23 @@ struct Shape {
     int block = 256;         // threads per block (64, 128 or 256)
     int nr = 1;              // right-hand sides per thread (1, 2 or 4)
     int remap = 1;           // XCD-contiguous tile order
+    int ordered = 1;         // hops issued one at a time (see hopping())
+    int rloop = 1;           // rhs groups a block handles one after the other
 };
 
-// Key of the launch-shape table: lattice, precision, rhs count, dagger.
+// Key of the launch-shape table: lattice, precision, rhs count, dagger, and
+// the kernel family (operator kernel, or one of the CG phase kernels, whose
+// fused epilogues move more data per site and prefer other shapes).
+enum : int { FAM_DSLASH = 0, FAM_CG_A = 1, FAM_CG_B = 2, FAM_CG_R = 3 };
 struct ShapeKey {
     int L[4];
     int prec, nrhs, dag;
+    int fam = FAM_DSLASH;
     bool operator<(const ShapeKey &o) const;
 };
 Shape shape_lookup(const ShapeKey &k);      // tuned entry or the default
 void shape_store(const ShapeKey &k, const Shape &s);
-Shape default_shape(int prec, int nrhs);
+Shape default_shape(int prec, int nrhs, int fam = FAM_DSLASH);
 
 }  // namespace wd
 
