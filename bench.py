@@ -169,6 +169,31 @@ def main():
                         "frac_hbm": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
         del pin, pout
 
+    # ------------------------- the paper's coordinate-format operator (Sec. 2)
+    coo = {}
+    x1 = dsrc[cfg["n_point"]:cfg["n_point"] + 1].reshape(1, -1).contiguous()
+    for prec, name in ((wd.F64, "f64"), (wd.F32, "f32")):
+        c = wd.Coo(g, m0, prec)
+        xin = x1 if prec == wd.F64 else x1.to(torch.complex64)
+        yout = torch.empty_like(xin)
+        for _ in range(3):
+            c.spmv(xin, out=yout)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            c.spmv(xin, out=yout)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / 20
+        vb = 16 if prec == wd.F64 else 8
+        alg = c.nnz * (vb + 4) + 2 * c.rows * vb     # Val, Col, in, out
+        coo[name] = {"us": us, "GBps": alg / (us * 1e-6) / 1e9,
+                     "GFLOPs_useful": 1368.0 * V / (us * 1e-6) / 1e9,
+                     "GFLOPs_executed": 8.0 * c.nnz / (us * 1e-6) / 1e9,
+                     "bytes_per_site": alg / V, "nnz": c.nnz}
+        c.close()
+
     # ----------------------------------------------------- copy ceiling
     a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     b = torch.empty_like(a)
@@ -239,6 +264,7 @@ def main():
             "f16n_err_vs_fp64_solution": err16,
             "cg_kernels": per_launch,
             "dslash_16rhs": dslash,
+            "coo_spmv_1rhs": coo,
             "copy_GBps": copy_gbps,
         },
     }

@@ -125,6 +125,27 @@ int wd_dslash(const wd_gauge *g, double m0, int32_t prec, const void *in_dev, vo
 int wd_dslash_dag(const wd_gauge *g, double m0, int32_t prec, const void *in_dev,
                   void *out_dev, int32_t nrhs, uint32_t flags, void *stream);
 
+/* ------------------------------------------- coordinate-format operator */
+/* The operator stored explicitly as in Sec. 2 of the paper: arrays Val, Row,
+ * Col of the non-zero entries of D (or D^dagger), 49 per row (the diagonal,
+ * then per direction x, y, z, t the 6 forward and 6 backward entries), rows
+ * r = 12 site + 3 spin + colour stored one after the other; duplicate entries
+ * of extent-2 lattices are kept.  Built on the device from the gauge handle's
+ * FP64 links; prec is WD_F64 (complex128 values) or WD_F32 (complex64).
+ * Row and Col are int32.  The handle owns the arrays (nnz*(16 or 8) + nnz*8
+ * bytes). */
+typedef struct wd_coo wd_coo;
+int wd_coo_create(const wd_gauge *g, double m0, int32_t prec, int32_t dagger, void *stream,
+                  wd_coo **out);
+int wd_coo_destroy(wd_coo *h);
+int wd_coo_info(const wd_coo *h, int64_t *nnz, int64_t *rows, size_t *bytes);
+/* copy Val, Row, Col into caller buffers (device) */
+int wd_coo_export(const wd_coo *h, void *val_dev, void *row_dev, void *col_dev, void *stream);
+/* out[Row[k]] += Val[k] * in[Col[k]] for nrhs vectors of 12 V complex numbers
+ * (canonical layout, complex128 for WD_F64, complex64 for WD_F32); out is
+ * overwritten.  Asynchronous on `stream`. */
+int wd_coo_spmv(const wd_coo *h, const void *in_dev, void *out_dev, int32_t nrhs, void *stream);
+
 /* -------------------------------------------------------------- CG solvers */
 typedef struct {
     double  tol;            /* target |eta - D x| / |eta| (true residual, FP64), > 0   */
@@ -193,6 +214,25 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
 /* the launch shape currently used for the key (tuned or default) */
 int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger,
                    wd_tune_result *cfg);
+
+/* kernel families of the shape table */
+#define WD_FAMILY_DSLASH 0   /* wd_dslash / wd_dslash_dag                       */
+#define WD_FAMILY_CG_A   1   /* CG phase A: q = D^dagger p and |q|^2           */
+#define WD_FAMILY_CG_B   2   /* CG phase B: D q, r and x updates, |r|^2        */
+#define WD_FAMILY_CG_R   3   /* reliable update r = eta - D x (FP64)           */
+/* Set the launch shape of one kernel family for (g's lattice, prec, nrhs,
+ * dagger) by hand -- e.g. to sweep the block size of the whole CG as the paper
+ * does for its workgroup size (Sec. 3.1, Fig. 1).  block in {64,128,256},
+ * rhs_per_thread in {1,2,4}, hop_order 0..4, rhs_loop >= 1. */
+int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, int32_t family,
+                 const wd_tune_result *shape);
+
+/* A HIP stream (default priority) whose kernels may run only on n_cu compute
+ * units (CU-mask bits 0..n_cu-1), for the paper's speedup-versus-compute-units
+ * study (Sec. 3.1, Fig. 2).  Use it with kernel-per-phase CG solves (the
+ * persistent kernel needs every compute unit). */
+int wd_stream_create_cu_limited(int32_t n_cu, void **stream);
+int wd_stream_destroy(void *stream);
 
 /* --------------------------------------------------------------- profiling */
 /* Per-kernel statistics of CG solves.  While profiling is on, wd_cg_solve*

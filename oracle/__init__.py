@@ -10,6 +10,7 @@ Functions and the passages they follow (arXiv 2111.14958):
   dirac, dirac_dag      -- Eq. (1) with the Wilson-Dirac operator; D^dagger from
                            gamma5-hermiticity (Sec. 2)
   cg                    -- CG on the normal equations (Sec. 2, CG algorithm)
+  bicgstab              -- BiCGSTAB on D (one of the other Krylov methods, Sec. 1)
   coo                   -- the coordinate (Val, Row, Col) storage of D (Sec. 2)
   coo_matvec            -- the coordinate-format product out[Row] += Val*in[Col]
   dense                 -- D as a dense matrix, column by column from `dirac`
@@ -52,6 +53,9 @@ def _bind(lib):
     lib.oracle_cg.restype = ctypes.c_int
     lib.oracle_gamma.argtypes = [ctypes.c_int, P]
     lib.oracle_gamma.restype = None
+    lib.oracle_bicgstab.argtypes = [P, P, ctypes.c_int, ctypes.c_double, P, P, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_int, P, P]
+    lib.oracle_bicgstab.restype = ctypes.c_int
     return lib
 
 
@@ -166,6 +170,34 @@ def cg(U, eta, dims, m0: float, tol: float = 1e-10, max_iter: int = 20000,
             traces.append(tr[: it.value].copy())
     out = (xs.reshape(shape), iters, res, st)
     return out + (traces,) if trace else out
+
+
+def bicgstab(U, eta, dims, m0: float, tol: float = 1e-10, max_iter: int = 20000,
+             t_sign: int = -1, x0=None, lib=None):
+    """Solve D x = eta by BiCGSTAB on D itself (Sec. 1 lists it), one field at a time.
+    Returns (x, iters[list], true_rel_res[list], status[list])."""
+    U, eta, V = _check(U, eta, dims)
+    shape = eta.shape
+    flat = eta.reshape(-1, V * 12)
+    xs = np.zeros_like(flat)
+    if x0 is not None:
+        xs[:] = np.asarray(x0, dtype=np.complex128).reshape(flat.shape)
+    d = _dims_arr(dims)
+    lib = lib or _load()
+    iters, res, st = [], [], []
+    for i in range(flat.shape[0]):
+        e = np.ascontiguousarray(flat[i])
+        x = np.ascontiguousarray(xs[i])
+        it = ctypes.c_int(0)
+        rr = ctypes.c_double(0.0)
+        s = lib.oracle_bicgstab(_ptr(U), _ptr(d), int(t_sign), float(m0), _ptr(e), _ptr(x),
+                                1 if x0 is not None else 0, float(tol), int(max_iter),
+                                ctypes.byref(it), ctypes.byref(rr))
+        xs[i] = x
+        iters.append(it.value)
+        res.append(rr.value)
+        st.append(s)
+    return xs.reshape(shape), iters, res, st
 
 
 def dense(U, dims, m0: float, t_sign: int = -1, dagger: bool = False, lib=None) -> np.ndarray:

@@ -17,7 +17,8 @@
  *    space: x = D^dagger chi, so the update psi += alpha p of the paper becomes
  *    x += alpha D^dagger p, and the residual r = eta - D x is the residual of
  *    D psi = eta itself;
- *  - optionally CG on D^dagger D x = D^dagger eta (CGNR), the other normal form.
+ *  - optionally CG on D^dagger D x = D^dagger eta (CGNR), the other normal form;
+ *  - BiCGSTAB directly on D, one of the other Krylov methods of Sec. 1.
  *
  * Conventions (the paper is silent on them):
  *  D psi(x) = (4 + m0) psi(x)
@@ -264,6 +265,72 @@ int oracle_cg(const cplx *U, const int L[4], int t_sign, double m0,
     *iters_out = it;
     *true_rel_res = sqrt(norm2(r, n)) / eta_norm;
     free(r); free(p); free(q); free(t); free(rh);
+    return status;
+}
+
+/*
+ * BiCGSTAB (van der Vorst, 1992) directly on D psi = eta -- one of the other
+ * Krylov methods the paper lists (Sec. 1).  Shadow residual r_hat = r_0.
+ * Stops when |r| <= tol |eta| holds for the recursive residual and then for
+ * the recomputed true residual (otherwise continues from the true one).
+ * Returns 0 on convergence, 1 at max_iter, 2 on breakdown (rho or <r_hat, v>
+ * or <t, t> zero / not finite).
+ */
+int oracle_bicgstab(const cplx *U, const int L[4], int t_sign, double m0,
+                    const cplx *eta, cplx *x, int use_x0, double tol, int max_iter,
+                    int *iters_out, double *true_rel_res)
+{
+    const long n = 12L * L[0] * L[1] * L[2] * L[3];
+    cplx *r = malloc(sizeof(cplx) * n), *rh = malloc(sizeof(cplx) * n);
+    cplx *p = calloc(n, sizeof(cplx)), *v = calloc(n, sizeof(cplx));
+    cplx *sv = malloc(sizeof(cplx) * n), *t = malloc(sizeof(cplx) * n);
+    int status = 1, it = 0;
+    const double eta_norm = sqrt(norm2(eta, n));
+    if (!use_x0) memset(x, 0, sizeof(cplx) * n);
+    if (eta_norm == 0.0) {
+        memset(x, 0, sizeof(cplx) * n);
+        *iters_out = 0;
+        *true_rel_res = 0.0;
+        free(r); free(rh); free(p); free(v); free(sv); free(t);
+        return 0;
+    }
+    const double stop = tol * eta_norm;
+    residual(U, L, t_sign, m0, eta, x, r, t, n);
+    if (sqrt(norm2(r, n)) <= stop) {
+        max_iter = 0;
+        status = 0;
+    }
+    memcpy(rh, r, sizeof(cplx) * n);
+    cplx rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    while (it < max_iter) {
+        const cplx rho = dotc(rh, r, n);
+        if (rho == 0 || !isfinite(creal(rho)) || !isfinite(cimag(rho))) { status = 2; break; }
+        const cplx beta = (rho / rho_old) * (alpha / omega);
+        for (long i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        oracle_dirac(U, L, t_sign, m0, p, v, 0);               /* v = D p          */
+        const cplx rhv = dotc(rh, v, n);
+        if (rhv == 0 || !isfinite(creal(rhv))) { status = 2; break; }
+        alpha = rho / rhv;
+        for (long i = 0; i < n; ++i) sv[i] = r[i] - alpha * v[i];
+        oracle_dirac(U, L, t_sign, m0, sv, t, 0);              /* t = D s          */
+        const double tt = norm2(t, n);
+        if (!(tt > 0.0) || !isfinite(tt)) { status = 2; break; }
+        omega = dotc(t, sv, n) / tt;
+        for (long i = 0; i < n; ++i) {
+            x[i] += alpha * p[i] + omega * sv[i];
+            r[i] = sv[i] - omega * t[i];
+        }
+        rho_old = rho;
+        ++it;
+        if (sqrt(norm2(r, n)) <= stop) {
+            residual(U, L, t_sign, m0, eta, x, r, t, n);
+            if (sqrt(norm2(r, n)) <= stop) { status = 0; break; }
+        }
+    }
+    residual(U, L, t_sign, m0, eta, x, r, t, n);
+    *iters_out = it;
+    *true_rel_res = sqrt(norm2(r, n)) / eta_norm;
+    free(r); free(rh); free(p); free(v); free(sv); free(t);
     return status;
 }
 

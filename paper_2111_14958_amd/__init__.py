@@ -32,8 +32,10 @@ EXPORTS = [
     "wd_gauge_create", "wd_gauge_destroy", "wd_gauge_info",
     "wd_spinor_bytes", "wd_pack_spinor", "wd_unpack_spinor",
     "wd_dslash", "wd_dslash_dag",
+    "wd_coo_create", "wd_coo_destroy", "wd_coo_info", "wd_coo_export", "wd_coo_spmv",
     "wd_cg_default_params", "wd_cg_workspace_bytes", "wd_cg_solve", "wd_cg_solve_batch",
-    "wd_tune_dslash", "wd_tune_lookup",
+    "wd_tune_dslash", "wd_tune_lookup", "wd_shape_set",
+    "wd_stream_create_cu_limited", "wd_stream_destroy",
     "wd_profile_enable", "wd_profile_reset", "wd_profile_read",
     "wd_serve_footprint", "wd_serve_create", "wd_serve_submit", "wd_serve_poll",
     "wd_serve_stats_get", "wd_serve_destroy",
@@ -125,6 +127,12 @@ def lib():
             "wd_unpack_spinor": ([P, I32, P, P, I32, P], ctypes.c_int),
             "wd_dslash": ([P, D, I32, P, P, I32, U32, P], ctypes.c_int),
             "wd_dslash_dag": ([P, D, I32, P, P, I32, U32, P], ctypes.c_int),
+            "wd_coo_create": ([P, D, I32, I32, P, ctypes.POINTER(P)], ctypes.c_int),
+            "wd_coo_destroy": ([P], ctypes.c_int),
+            "wd_coo_info": ([P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                             ctypes.POINTER(SZ)], ctypes.c_int),
+            "wd_coo_export": ([P, P, P, P, P], ctypes.c_int),
+            "wd_coo_spmv": ([P, P, P, I32, P], ctypes.c_int),
             "wd_cg_default_params": ([ctypes.POINTER(CGParams)], None),
             "wd_cg_workspace_bytes": ([P, I32, ctypes.POINTER(CGParams)], SZ),
             "wd_cg_solve": ([P, D, P, P, ctypes.POINTER(CGParams), P, SZ,
@@ -133,6 +141,9 @@ def lib():
                                    ctypes.POINTER(CGReport), P], ctypes.c_int),
             "wd_tune_dslash": ([P, I32, I32, I32, ctypes.POINTER(TuneResult), P], ctypes.c_int),
             "wd_tune_lookup": ([P, I32, I32, I32, ctypes.POINTER(TuneResult)], ctypes.c_int),
+            "wd_shape_set": ([P, I32, I32, I32, I32, ctypes.POINTER(TuneResult)], ctypes.c_int),
+            "wd_stream_create_cu_limited": ([I32, ctypes.POINTER(P)], ctypes.c_int),
+            "wd_stream_destroy": ([P], ctypes.c_int),
             "wd_profile_enable": ([I32], ctypes.c_int),
             "wd_profile_reset": ([], ctypes.c_int),
             "wd_profile_read": ([ctypes.POINTER(KernelStat), I32, ctypes.POINTER(I32)], ctypes.c_int),
@@ -279,6 +290,50 @@ def dslash(g: Gauge, m0: float, psi, prec: int = F64, dagger: bool = False,
     return out
 
 
+class Coo:
+    """D (or D^dagger) in the coordinate format of Sec. 2 (wd_coo_*)."""
+
+    def __init__(self, g: Gauge, m0: float, prec: int = F64, dagger: bool = False):
+        h = ctypes.c_void_p()
+        _check(lib().wd_coo_create(g.handle, float(m0), prec, 1 if dagger else 0, _stream(),
+                                   ctypes.byref(h)), "wd_coo_create")
+        self.handle, self.prec, self.sites = h, prec, g.sites
+        nnz, rows, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+        _check(lib().wd_coo_info(h, ctypes.byref(nnz), ctypes.byref(rows), ctypes.byref(nb)),
+               "wd_coo_info")
+        self.nnz, self.rows, self.bytes = nnz.value, rows.value, nb.value
+
+    def export(self):
+        torch = _torch()
+        vdt = torch.complex128 if self.prec == F64 else torch.complex64
+        val = torch.empty(self.nnz, dtype=vdt, device="cuda")
+        row = torch.empty(self.nnz, dtype=torch.int32, device="cuda")
+        col = torch.empty(self.nnz, dtype=torch.int32, device="cuda")
+        _check(lib().wd_coo_export(self.handle, _ptr(val), _ptr(row), _ptr(col), _stream()),
+               "wd_coo_export")
+        return val, row, col
+
+    def spmv(self, x, out=None):
+        torch = _torch()
+        vdt = torch.complex128 if self.prec == F64 else torch.complex64
+        _require_cuda(x, vdt, "x")
+        nrhs = x.numel() // self.rows
+        out = torch.empty_like(x) if out is None else out
+        _check(lib().wd_coo_spmv(self.handle, _ptr(x), _ptr(out), nrhs, _stream()), "wd_coo_spmv")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().wd_coo_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def cg_default_params(**kw) -> CGParams:
     p = CGParams()
     lib().wd_cg_default_params(ctypes.byref(p))
@@ -347,6 +402,33 @@ def tune_lookup(g: Gauge, prec: int, nrhs: int, dagger: bool = False) -> dict:
     _check(lib().wd_tune_lookup(g.handle, prec, nrhs, 1 if dagger else 0, ctypes.byref(r)),
            "wd_tune_lookup")
     return {f[0]: getattr(r, f[0]) for f in r._fields_ if f[0] != "reserved"}
+
+
+FAMILY_DSLASH, FAMILY_CG_A, FAMILY_CG_B, FAMILY_CG_R = 0, 1, 2, 3
+
+
+def shape_set(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int, block: int,
+              rhs_per_thread: int = 1, xcd_remap: int = 1, hop_order: int = 1, rhs_loop: int = 1):
+    r = TuneResult(block=block, rhs_per_thread=rhs_per_thread, xcd_remap=xcd_remap,
+                   hop_order=hop_order, rhs_loop=rhs_loop)
+    _check(lib().wd_shape_set(g.handle, prec, nrhs, 1 if dagger else 0, family, ctypes.byref(r)),
+           "wd_shape_set")
+
+
+class CULimitedStream:
+    """A torch-usable HIP stream restricted to the first n_cu compute units."""
+
+    def __init__(self, n_cu: int):
+        h = ctypes.c_void_p()
+        _check(lib().wd_stream_create_cu_limited(int(n_cu), ctypes.byref(h)),
+               "wd_stream_create_cu_limited")
+        self.handle = h
+        self.torch_stream = _torch().cuda.ExternalStream(h.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().wd_stream_destroy(self.handle)
+            self.handle = None
 
 
 def profile_enable(on: bool = True):

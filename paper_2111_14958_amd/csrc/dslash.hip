@@ -31,14 +31,30 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, double diag, const void 
         const int nact = min(NR, in.nrhs - rhs0);
         const unsigned act = (1u << nact) - 1u;
         cx<R> acc[NR][12];
-        hopping<P, DAG, NR, ORD>(g, s, U, in, rhs0, act, acc);
+        if constexpr (ORD == 4) {
+            cx<R> self[NR][12];
 #pragma unroll
-        for (int j = 0; j < NR; ++j) {
-            if (act >> j & 1) {
-                cx<R> self[12], o[12];
-                Spinor<P>::load(in, rhs0 + j, s, self);
-                wilson_finish<R>((R)diag, self, acc[j], o);
-                Spinor<P>::store(out, rhs0 + j, s, o);
+            for (int j = 0; j < NR; ++j)
+                if (act >> j & 1) Spinor<P>::load(in, rhs0 + j, s, self[j]);
+            hopping<P, DAG, NR, ORD>(g, s, U, in, rhs0, act, acc, self);
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                if (act >> j & 1) {
+                    cx<R> o[12];
+                    wilson_finish<R>((R)diag, self[j], acc[j], o);
+                    Spinor<P>::store(out, rhs0 + j, s, o);
+                }
+            }
+        } else {
+            hopping<P, DAG, NR, ORD>(g, s, U, in, rhs0, act, acc);
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                if (act >> j & 1) {
+                    cx<R> self[12], o[12];
+                    Spinor<P>::load(in, rhs0 + j, s, self);
+                    wilson_finish<R>((R)diag, self, acc[j], o);
+                    Spinor<P>::store(out, rhs0 + j, s, o);
+                }
             }
         }
     }
@@ -47,10 +63,18 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, double diag, const void 
 template <int P, bool DAG, int ORD>
 static void launch_nr_o(int nr, dim3 grid, dim3 block, hipStream_t st, const Geom &g, double diag,
                         const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int rl) {
-    switch (nr) {
-    case 1: hipLaunchKernelGGL((k_dslash<P, DAG, 1, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl); break;
-    case 2: hipLaunchKernelGGL((k_dslash<P, DAG, 2, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl); break;
-    default: hipLaunchKernelGGL((k_dslash<P, DAG, 4, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl); break;
+    if constexpr (ORD == 4) {
+        // the own spinors of several rhs do not fit in registers: only NR = 1
+        if (nr == 1)
+            hipLaunchKernelGGL((k_dslash<P, DAG, 1, 4>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl);
+        else
+            launch_nr_o<P, DAG, 3>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
+    } else {
+        switch (nr) {
+        case 1: hipLaunchKernelGGL((k_dslash<P, DAG, 1, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl); break;
+        case 2: hipLaunchKernelGGL((k_dslash<P, DAG, 2, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl); break;
+        default: hipLaunchKernelGGL((k_dslash<P, DAG, 4, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl); break;
+        }
     }
 }
 
@@ -60,6 +84,7 @@ static void launch_nr(int nr, int ordered, int rl, dim3 grid, dim3 block, hipStr
     if (ordered == 1) launch_nr_o<P, DAG, 1>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
     else if (ordered == 2) launch_nr_o<P, DAG, 2>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
     else if (ordered == 3) launch_nr_o<P, DAG, 3>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
+    else if (ordered == 4) launch_nr_o<P, DAG, 4>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
     else launch_nr_o<P, DAG, 0>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
 }
 

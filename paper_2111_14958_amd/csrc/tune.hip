@@ -178,6 +178,33 @@ int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     return WD_OK;
 }
 
+int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, int32_t family,
+                 const wd_tune_result *sh) {
+    clear_error();
+    WD_CHECK(g && sh, WD_EINVAL, "null argument");
+    WD_CHECK(prec >= 0 && prec <= 2, WD_EINVAL, "unknown precision %d", prec);
+    WD_CHECK(nrhs >= 1 && nrhs <= MAX_RHS, WD_EINVAL, "nrhs %d out of range", nrhs);
+    WD_CHECK(family >= FAM_DSLASH && family <= FAM_CG_R, WD_EINVAL, "unknown kernel family %d", family);
+    WD_CHECK(sh->block == 64 || sh->block == 128 || sh->block == 256, WD_EINVAL, "block %d", sh->block);
+    WD_CHECK(sh->rhs_per_thread == 1 || sh->rhs_per_thread == 2 || sh->rhs_per_thread == 4, WD_EINVAL,
+             "rhs_per_thread %d", sh->rhs_per_thread);
+    WD_CHECK(sh->hop_order >= 0 && sh->hop_order <= 4 && sh->rhs_loop >= 1, WD_EINVAL, "bad hop order / rhs loop");
+    WD_CHECK(family == FAM_DSLASH || (sh->hop_order == 1 && sh->rhs_loop == 1), WD_EINVAL,
+             "CG kernels always issue hops one at a time, one rhs group per block");
+    WD_CHECK(!(family == FAM_CG_R && sh->rhs_per_thread > 2), WD_EINVAL, "reliable-update kernel takes <= 2 rhs");
+    WD_CHECK(!(prec == WD_F64 && family != FAM_DSLASH && sh->rhs_per_thread > 2), WD_EINVAL,
+             "FP64 CG kernels take <= 2 rhs per thread");
+    ShapeKey k{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, prec, nrhs, dagger ? 1 : 0, family};
+    Shape s;
+    s.block = sh->block;
+    s.nr = sh->rhs_per_thread;
+    s.remap = sh->xcd_remap ? 1 : 0;
+    s.ordered = sh->hop_order;
+    s.rloop = sh->rhs_loop;
+    shape_store(k, s);
+    return WD_OK;
+}
+
 int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, wd_tune_result *best,
                    void *stream) {
     clear_error();
@@ -217,13 +244,15 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     const int rloops[3] = {1, 2, 4};
     for (int bi = 0; bi < 3 && !rc; ++bi)
         for (int ni = 0; ni < 3 && !rc; ++ni)
-            for (int cand = 0; cand < 24 && !rc; ++cand) {
+            for (int cand = 0; cand < 30 && !rc; ++cand) {
                 Shape s;
                 s.block = blocks[bi];
                 s.nr = nrs[ni];
                 s.remap = cand & 1;
-                s.ordered = (cand >> 1) % 4;      // 0 free, 1 per hop, 2 per direction, 3 pipelined
-                s.rloop = rloops[cand / 8];
+                s.ordered = (cand >> 1) % 5;      // 0 free, 1 per hop, 2 per direction, 3 pipelined,
+                                                  // 4 pipelined with the own spinor first
+                s.rloop = rloops[cand / 10];
+                if (s.ordered == 4 && s.nr != 1) continue;
                 const int ngroups = (nrhs + s.nr - 1) / s.nr;
                 if (s.rloop > 1 && s.rloop > ngroups) continue;
                 if (s.nr > 1 && s.nr > nrhs) continue;

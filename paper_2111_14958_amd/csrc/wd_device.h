@@ -266,7 +266,8 @@ template <int MU> struct IntC { static constexpr int value = MU; };
 // applied to all NR right-hand sides.
 template <int P, bool DAG, int NR, int ORDERED = 1>
 __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, const FieldPtr &in,
-                                        int rhs0, unsigned act, cx<typename real_of<P>::type> acc[NR][12]) {
+                                        int rhs0, unsigned act, cx<typename real_of<P>::type> acc[NR][12],
+                                        const cx<typename real_of<P>::type> (*first)[12] = nullptr) {
     typedef typename real_of<P>::type R;
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
@@ -296,6 +297,16 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
     };
     // neighbour and link-site index of every hop h = 2 mu + (backward ? 1 : 0)
     int nbi[8], lsi[8];
+    // ORDERED 4: as 3, and the caller's values `first` (the site's own spinor,
+    // loaded before the call) are in registers before any hop is issued, so
+    // the own-site load and the x/y neighbour loads touch their common cache
+    // lines close together in time
+    auto after_first = [&](int &a) {
+        if (first)
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+                asm volatile("" : "+v"(a) : "v"(first[j][0].re), "v"(first[j][11].im));
+    };
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         nbi[2 * mu] = c[mu] == g.L[mu] - 1 ? s - (g.L[mu] - 1) * g.S[mu] : s + g.S[mu];
@@ -315,7 +326,8 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
         if constexpr (ORDERED == 1) after_acc(nbi[H], lsi[H]);
         if constexpr (ORDERED == 2 && FWD) after_acc(nbi[H], lsi[H]);
         if constexpr (ORDERED == 2 && FWD) after_acc(nbi[H + 1], lsi[H + 1]);
-        if constexpr (ORDERED == 3 && H + 1 < 8) after_acc(nbi[H + 1], lsi[H + 1]);
+        if constexpr ((ORDERED == 3 || ORDERED == 4) && H + 1 < 8) after_acc(nbi[H + 1], lsi[H + 1]);
+        if constexpr (ORDERED == 4 && H == 0) after_first(nbi[0]);
         const int nb = nbi[H];
         const bool wrap = FWD ? (c[MU] == g.L[MU] - 1) : (c[MU] == 0);
         const bool neg = (MU == 3) && wrap && g.tsign < 0;

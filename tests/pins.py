@@ -197,6 +197,28 @@ def dense_solve(dims=(2, 2, 4, 4), m0=0.1, eps=0.5, seed=41, tol=1e-10, lib=None
     return ok, f"status {st[0]} iters {it[0]} res {res[0]:.2e} err {err:.2e} bound {bound:.2e}"
 
 
+def bicgstab_dense_solve(dims=(2, 2, 4, 4), m0=0.1, eps=0.5, seed=43, tol=1e-10, lib=None,
+                         max_iter=5000):
+    U = wdgen.gauge_field(dims, eps, seed)
+    eta = wdgen.gaussian_source(dims, 1, seed + 1)[0]
+    Dm = oracle.dense(U, dims, m0, lib=lib)
+    xs = np.linalg.solve(Dm, eta.ravel()).reshape(eta.shape)
+    x, it, res, st = oracle.bicgstab(U, eta, dims, m0, tol=tol, max_iter=max_iter, lib=lib)
+    err = _rel(x, xs)
+    bound = kappa_bound(m0) * tol
+    ok = st[0] == 0 and res[0] <= tol and err <= bound
+    return ok, f"status {st[0]} iters {it[0]} res {res[0]:.2e} err {err:.2e} bound {bound:.2e}"
+
+
+def bicgstab_free_fft_solve(dims=(8, 8, 8, 8), m0=0.05, seed=53, tol=1e-10, lib=None):
+    U = wdgen.unit_gauge(dims)
+    eta = wdgen.gaussian_source(dims, 1, seed)[0]
+    xs = free_solve_fft(eta, dims, m0, -1, _gammas(None))
+    x, it, res, st = oracle.bicgstab(U, eta, dims, m0, tol=tol, max_iter=5000, lib=lib)
+    err = _rel(x, xs)
+    return st[0] == 0 and err <= kappa_bound(m0) * tol, f"status {st[0]} iters {it[0]} err {err:.2e}"
+
+
 def free_fft_solve(dims=(8, 8, 8, 8), m0=0.05, seed=51, tol=1e-10, lib=None, max_iter=5000):
     U = wdgen.unit_gauge(dims)
     eta = wdgen.gaussian_source(dims, 1, seed)[0]

@@ -36,6 +36,10 @@ MUTANTS = [
     ("CG solution updated with p", "axpy(alpha, q, x, n);", "axpy(alpha, p, x, n);", 0),
     ("CG residual update sign", "axpy(-alpha, t, r, n);", "axpy(alpha, t, r, n);", 0),
     ("CG direction without beta", "p[i] = r[i] + beta * p[i];", "p[i] = r[i];", 0),
+    ("BiCGSTAB residual update sign", "r[i] = sv[i] - omega * t[i];", "r[i] = sv[i] + omega * t[i];", 0),
+    ("BiCGSTAB alpha inverted", "alpha = rho / rhv;", "alpha = rhv / rho;", 0),
+    ("BiCGSTAB x update without omega s", "x[i] += alpha * p[i] + omega * sv[i];",
+     "x[i] += alpha * p[i];", 0),
 ]
 
 
@@ -66,6 +70,7 @@ def _pins(lib):
         "covariance": lambda: pins.gauge_covariance(dims=(4, 4, 4, 6), lib=lib),
         "dense_solve": lambda: pins.dense_solve(dims=(2, 2, 4, 4), lib=lib, max_iter=1000),
         "pure_gauge": lambda: pins.pure_gauge_solve(dims=(4, 4, 4, 8), lib=lib, max_iter=1000),
+        "bicgstab_dense": lambda: pins.bicgstab_dense_solve(dims=(2, 2, 4, 4), lib=lib, max_iter=1000),
     }
     failed = []
     for name, fn in checks.items():

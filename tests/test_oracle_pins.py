@@ -155,3 +155,22 @@ def test_fp16n_encoding():
     c, n = oracle.fp16n_encode(t)
     q = np.float32(1.0 + 2.0 ** -11) / np.float32(2.0 * (1 + 2.0 ** -11))
     assert c[0, 0, 4] == np.float16(q)
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (2, 2, 4, 4), (4, 4, 4, 4)])
+def test_bicgstab_matches_dense_solve(dims):
+    _ok(pins.bicgstab_dense_solve(dims=dims))
+
+
+def test_bicgstab_matches_free_fft_solution():
+    _ok(pins.bicgstab_free_fft_solve())
+
+
+def test_bicgstab_agrees_with_cg():
+    dims, m0 = (6, 6, 6, 6), 0.05
+    U = wdgen.gauge_field(dims, 0.5, 1002)
+    eta = wdgen.gaussian_source(dims, 2, 2002)
+    xb, itb, rb, sb = oracle.bicgstab(U, eta, dims, m0)
+    xc, itc, rc, sc = oracle.cg(U, eta, dims, m0)
+    assert sb == [0, 0] and max(rb) <= 1e-10
+    assert np.linalg.norm(xb - xc) / np.linalg.norm(xc) <= pins.kappa_bound(m0) * 2e-10
