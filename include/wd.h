@@ -157,7 +157,19 @@ typedef struct {
     int32_t persistent;     /* 0: one kernel per CG phase, 1: one persistent kernel per
                                chunk with grid barriers, -1: library default             */
     int32_t chunk;          /* CG iterations per graph replay, 0 = library default     */
+    int32_t method;         /* WD_METHOD_CGNE (default) or WD_METHOD_BICGSTAB           */
+    int32_t reserved;       /* must be 0                                                */
 } wd_cg_params;
+
+/* Krylov method of wd_cg_solve / wd_cg_solve_batch.
+ * WD_METHOD_CGNE: CG on the normal equations D D^dagger chi = eta, x = D^dagger chi
+ *   (Sec. 2, the paper's solver), two operator applications per iteration.
+ * WD_METHOD_BICGSTAB: BiCGSTAB on D x = eta (one of the Krylov methods Sec. 1
+ *   names for the Dirac equation), two applications of D per iteration; a
+ *   reliable update restarts it from the FP64 true residual (shadow residual
+ *   r_hat = r).  Runs without the persistent kernel and without profiling. */
+#define WD_METHOD_CGNE     0
+#define WD_METHOD_BICGSTAB 1
 
 typedef struct {
     int32_t status;           /* WD_OK, WD_ENOTCONV or WD_EBREAKDOWN                    */
@@ -170,7 +182,7 @@ typedef struct {
 } wd_cg_report;
 
 /* tol 1e-10, max_iter 20000, reliable_every 50, inner WD_F32, use_x0 0,
- * persistent -1, chunk 0 */
+ * persistent -1, chunk 0, method WD_METHOD_CGNE */
 void   wd_cg_default_params(wd_cg_params *p);
 /* device workspace a solve of nrhs fields on g's lattice needs, in bytes */
 size_t wd_cg_workspace_bytes(const wd_gauge *g, int32_t nrhs, const wd_cg_params *p);
@@ -227,12 +239,6 @@ int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
 int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, int32_t family,
                  const wd_tune_result *shape);
 
-/* A HIP stream (default priority) whose kernels may run only on n_cu compute
- * units (CU-mask bits 0..n_cu-1), for the paper's speedup-versus-compute-units
- * study (Sec. 3.1, Fig. 2).  Use it with kernel-per-phase CG solves (the
- * persistent kernel needs every compute unit). */
-int wd_stream_create_cu_limited(int32_t n_cu, void **stream);
-int wd_stream_destroy(void *stream);
 
 /* --------------------------------------------------------------- profiling */
 /* Per-kernel statistics of CG solves.  While profiling is on, wd_cg_solve*

@@ -20,6 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwd.so")
 
 F64, F32, F16N = 0, 1, 2
+METHOD_CGNE, METHOD_BICGSTAB = 0, 1
 PACKED = 1
 GAUGE_F64, GAUGE_F32, GAUGE_F16 = 1, 2, 4
 
@@ -35,7 +36,6 @@ EXPORTS = [
     "wd_coo_create", "wd_coo_destroy", "wd_coo_info", "wd_coo_export", "wd_coo_spmv",
     "wd_cg_default_params", "wd_cg_workspace_bytes", "wd_cg_solve", "wd_cg_solve_batch",
     "wd_tune_dslash", "wd_tune_lookup", "wd_shape_set",
-    "wd_stream_create_cu_limited", "wd_stream_destroy",
     "wd_profile_enable", "wd_profile_reset", "wd_profile_read",
     "wd_serve_footprint", "wd_serve_create", "wd_serve_submit", "wd_serve_poll",
     "wd_serve_stats_get", "wd_serve_destroy",
@@ -55,7 +55,8 @@ class CGParams(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("reliable_every", ctypes.c_int32), ("inner", ctypes.c_int32),
                 ("use_x0", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("chunk", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class CGReport(ctypes.Structure):
@@ -142,8 +143,6 @@ def lib():
             "wd_tune_dslash": ([P, I32, I32, I32, ctypes.POINTER(TuneResult), P], ctypes.c_int),
             "wd_tune_lookup": ([P, I32, I32, I32, ctypes.POINTER(TuneResult)], ctypes.c_int),
             "wd_shape_set": ([P, I32, I32, I32, I32, ctypes.POINTER(TuneResult)], ctypes.c_int),
-            "wd_stream_create_cu_limited": ([I32, ctypes.POINTER(P)], ctypes.c_int),
-            "wd_stream_destroy": ([P], ctypes.c_int),
             "wd_profile_enable": ([I32], ctypes.c_int),
             "wd_profile_reset": ([], ctypes.c_int),
             "wd_profile_read": ([ctypes.POINTER(KernelStat), I32, ctypes.POINTER(I32)], ctypes.c_int),
@@ -413,22 +412,6 @@ def shape_set(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int, block: 
                    hop_order=hop_order, rhs_loop=rhs_loop)
     _check(lib().wd_shape_set(g.handle, prec, nrhs, 1 if dagger else 0, family, ctypes.byref(r)),
            "wd_shape_set")
-
-
-class CULimitedStream:
-    """A torch-usable HIP stream restricted to the first n_cu compute units."""
-
-    def __init__(self, n_cu: int):
-        h = ctypes.c_void_p()
-        _check(lib().wd_stream_create_cu_limited(int(n_cu), ctypes.byref(h)),
-               "wd_stream_create_cu_limited")
-        self.handle = h
-        self.torch_stream = _torch().cuda.ExternalStream(h.value)
-
-    def close(self):
-        if getattr(self, "handle", None):
-            lib().wd_stream_destroy(self.handle)
-            self.handle = None
 
 
 def profile_enable(on: bool = True):

@@ -7,7 +7,8 @@
 //          N (|eta|^2), R2 (r = eta - D x64, true-residual test), C (p = r)
 //   chunk  K x [A, B, C], then R1 (x64 += x_lo), R2, C, summary   (one graph)
 // and replays the chunk graph until no right-hand side is active, reading back
-// one counter per replay.
+// one counter per replay.  BiCGSTAB (bicgstab_core.h) uses the same driver with
+// the chunk K x [S1, S2, S3, S4, S5], then R1, R2, summary.
 #include <string.h>
 
 #include <atomic>
@@ -17,7 +18,7 @@
 #include <tuple>
 #include <vector>
 
-#include "cg_core.h"
+#include "bicgstab_core.h"
 #include "cg_host.h"
 
 namespace wd {
@@ -28,20 +29,20 @@ namespace wd {
     const Prob &pr = probs[find_prob(probs, nprob, K, b_)];                    \
     const int t_ = b_ - pr.t0[K];
 
-template <int P, int NR>
+template <int P, int NR, int ORD>
 __global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KA)
-    phaseA_tile<P, NR>(pr, t_);
+    phaseA_tile<P, NR, ORD>(pr, t_);
     if (ticket_last(pr.ticket, pr.nt[KA])) {
         phaseA_finish(pr);
         if (threadIdx.x == 0) *pr.ticket = 0;
     }
 }
 
-template <int P, int NR>
+template <int P, int NR, int ORD>
 __global__ __launch_bounds__(256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KB)
-    phaseB_tile<P, NR>(pr, t_);
+    phaseB_tile<P, NR, ORD>(pr, t_);
     if (ticket_last(pr.ticket, pr.nt[KB])) {
         phaseB_finish(pr);
         if (threadIdx.x == 0) *pr.ticket = 0;
@@ -93,6 +94,41 @@ __global__ void k_summary(const Prob *__restrict__ probs, int nprob, int *out, c
     out[1] = abort_flag ? *abort_flag : 0;
 }
 
+// BiCGSTAB stages (bicgstab_core.h)
+template <int P>
+__global__ __launch_bounds__(256) void k_bi1(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KS1)
+    bi1_tile<P>(pr, t_);
+}
+
+template <int P, int NR, bool S4>
+__global__ __launch_bounds__(256) void k_bi_stencil(const Prob *__restrict__ probs, int nprob, int remap) {
+    constexpr int K = S4 ? KS4 : KS2;
+    WD_KERNEL_PROLOGUE(K)
+    bi_stencil_tile<P, NR, S4>(pr, t_);
+    if (ticket_last(pr.ticket, pr.nt[K])) {
+        if (S4) bi4_finish(pr);
+        else bi2_finish(pr);
+        if (threadIdx.x == 0) *pr.ticket = 0;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_bi3(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KS3)
+    bi3_tile<P>(pr, t_);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_bi5(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KS5)
+    bi5_tile<P>(pr, t_);
+    if (ticket_last(pr.ticket, pr.nt[KS5])) {
+        bi5_finish(pr);
+        if (threadIdx.x == 0) *pr.ticket = 0;
+    }
+}
+
 // x_lo <- 0 (a fill kernel rather than a memset, so it can sit in a graph)
 __global__ void k_zero(uint4 *p, size_t n16) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
@@ -100,17 +136,28 @@ __global__ void k_zero(uint4 *p, size_t n16) {
 }
 
 // ------------------------------------------------------------- launchers
-template <int P>
-static void launch_A(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (nr == 1) hipLaunchKernelGGL((k_phaseA<P, 1>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else if (nr == 2) hipLaunchKernelGGL((k_phaseA<P, 2>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else hipLaunchKernelGGL((k_phaseA<P, 4>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+// hop order 3 (pipelined) or 1 (one hop at a time) for the phase kernels
+template <int P, int ORD>
+static void launch_A_o(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    if (nr == 1) hipLaunchKernelGGL((k_phaseA<P, 1, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else if (nr == 2) hipLaunchKernelGGL((k_phaseA<P, 2, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else hipLaunchKernelGGL((k_phaseA<P, 4, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+}
+template <int P, int ORD>
+static void launch_B_o(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    if (nr == 1) hipLaunchKernelGGL((k_phaseB<P, 1, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else if (nr == 2) hipLaunchKernelGGL((k_phaseB<P, 2, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else hipLaunchKernelGGL((k_phaseB<P, 4, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
 }
 template <int P>
-static void launch_B(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (nr == 1) hipLaunchKernelGGL((k_phaseB<P, 1>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else if (nr == 2) hipLaunchKernelGGL((k_phaseB<P, 2>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else hipLaunchKernelGGL((k_phaseB<P, 4>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+static void launch_A(int nr, int ord, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    if (ord == 3) launch_A_o<P, 3>(nr, grid, blk, st, d, n, remap);
+    else launch_A_o<P, 1>(nr, grid, blk, st, d, n, remap);
+}
+template <int P>
+static void launch_B(int nr, int ord, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    if (ord == 3) launch_B_o<P, 3>(nr, grid, blk, st, d, n, remap);
+    else launch_B_o<P, 1>(nr, grid, blk, st, d, n, remap);
 }
 template <int P>
 static void launch_R2(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
@@ -118,19 +165,36 @@ static void launch_R2(int nr, int grid, int blk, hipStream_t st, const Prob *d, 
     else hipLaunchKernelGGL((k_ru2<P, 2>), dim3(grid), dim3(blk), 0, st, d, n, remap);
 }
 
+template <int P, bool S4>
+static void launch_BS(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    if (nr == 1) hipLaunchKernelGGL((k_bi_stencil<P, 1, S4>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else if (nr == 2) hipLaunchKernelGGL((k_bi_stencil<P, 2, S4>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else hipLaunchKernelGGL((k_bi_stencil<P, 4, S4>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+}
+template <int P>
+static void launch_bicg(int kind, const KindShape &k, hipStream_t st, const Prob *d, int n) {
+    switch (kind) {
+    case KS1: hipLaunchKernelGGL(k_bi1<P>, dim3(k.grid), dim3(k.block), 0, st, d, n, 0); break;
+    case KS2: launch_BS<P, false>(k.nr, k.grid, k.block, st, d, n, k.remap); break;
+    case KS3: hipLaunchKernelGGL(k_bi3<P>, dim3(k.grid), dim3(k.block), 0, st, d, n, 0); break;
+    case KS4: launch_BS<P, true>(k.nr, k.grid, k.block, st, d, n, k.remap); break;
+    case KS5: hipLaunchKernelGGL(k_bi5<P>, dim3(k.grid), dim3(k.block), 0, st, d, n, 0); break;
+    }
+}
+
 void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob) {
     const KindShape &k = ls.k[kind];
     if (k.grid <= 0) return;
     switch (kind) {
     case KA:
-        if (inner == P64) launch_A<P64>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
-        else if (inner == P32) launch_A<P32>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
-        else launch_A<P16>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
+        if (inner == P64) launch_A<P64>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
+        else if (inner == P32) launch_A<P32>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
+        else launch_A<P16>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
         break;
     case KB:
-        if (inner == P64) launch_B<P64>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
-        else if (inner == P32) launch_B<P32>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
-        else launch_B<P16>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
+        if (inner == P64) launch_B<P64>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
+        else if (inner == P32) launch_B<P32>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
+        else launch_B<P16>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
         break;
     case KC:
         if (inner == P64) hipLaunchKernelGGL(k_phaseC<P64>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
@@ -150,6 +214,11 @@ void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const
     case KN:
         hipLaunchKernelGGL(k_norm, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
         break;
+    case KS1: case KS2: case KS3: case KS4: case KS5:
+        if (inner == P64) launch_bicg<P64>(kind, k, st, d, nprob);
+        else if (inner == P32) launch_bicg<P32>(kind, k, st, d, nprob);
+        else launch_bicg<P16>(kind, k, st, d, nprob);
+        break;
     }
 }
 
@@ -166,21 +235,28 @@ void launch_zero(void *p, size_t bytes, hipStream_t st) {
 // ------------------------------------------------------------- host plan
 static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
-WsLayout ws_layout(int64_t V, int nrhs, int inner) {
+WsLayout ws_layout(int64_t V, int nrhs, int inner, int method) {
     WsLayout L;
     size_t o = 0;
     L.prob = o; o += al256(sizeof(Prob));
     L.scal = o; o += al256(sizeof(Scal) * nrhs);
     L.ticket = o; o += 256;
     L.summary = o; o += 256;
-    L.part = o; o += al256((size_t)((V + 63) / 64) * nrhs * sizeof(double));
+    L.part = o; o += al256((size_t)((V + 63) / 64) * nrhs * PSTRIDE * sizeof(double));
     L.eta64 = o; o += al256(spinor_bytes(WD_F64, V, nrhs));
     L.x64 = o; o += al256(spinor_bytes(WD_F64, V, nrhs));
     const int xp = inner == WD_F16N ? WD_F32 : inner;
     L.xlo = o; o += al256(spinor_bytes(xp, V, nrhs));
     L.r = o; o += al256(spinor_bytes(inner, V, nrhs));
     L.p = o; o += al256(spinor_bytes(inner, V, nrhs));
-    L.q = o; o += al256(spinor_bytes(inner, V, nrhs));
+    L.q = o; o += al256(spinor_bytes(inner, V, nrhs));   // BiCGSTAB: v
+    L.bscal = L.rh = L.sv = L.tv = 0;
+    if (method == METHOD_BICGSTAB) {
+        L.bscal = o; o += al256(sizeof(BScal) * nrhs);
+        L.rh = o; o += al256(spinor_bytes(inner, V, nrhs));
+        L.sv = o; o += al256(spinor_bytes(inner, V, nrhs));
+        L.tv = o; o += al256(spinor_bytes(inner, V, nrhs));
+    }
     L.total = o;
     return L;
 }
@@ -197,13 +273,15 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
     kr.fam = FAM_CG_R;
     Shape sa = shape_lookup(ka), sb = shape_lookup(kb), sr = shape_lookup(kr);
     if (sr.nr > 2) sr.nr = 2;
-    const Shape *st[NKIND] = {&sa, &sb, nullptr, nullptr, &sr, nullptr};
+    // stencil kinds: A (D^dagger), B, S2 and S4 (D), R2 (FP64 D); the rest stream
+    const Shape *st[NKIND] = {&sa, &sb, nullptr, nullptr, &sr, nullptr, nullptr, &sb, nullptr, &sb, nullptr};
     for (int k = 0; k < NKIND; ++k) {
         KindShape &ks = ls.k[k];
         if (st[k]) {
             ks.block = st[k]->block;
             ks.nr = st[k]->nr;
             ks.remap = st[k]->remap;
+            ks.ordered = (k == KA || k == KB) && st[k]->ordered == 3 ? 3 : 1;
         } else {
             ks.block = 256;
             ks.nr = 1;
@@ -244,7 +322,7 @@ void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_par
     pr.nrhs = nrhs;
     pr.max_iter = p.max_iter;
     pr.ru_every = p.reliable_every;
-    pr.pad0 = 0;
+    pr.method = p.method;
     pr.U_lo = g->U[p.inner];
     pr.U64 = g->U[WD_F64];
     pr.x_lo = ws + L.xlo;
@@ -256,6 +334,11 @@ void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_par
     pr.part = (double *)(ws + L.part);
     pr.ticket = (unsigned *)(ws + L.ticket);
     pr.sc = (Scal *)(ws + L.scal);
+    pr.v = ws + L.q;
+    pr.rh = L.rh ? ws + L.rh : nullptr;
+    pr.sv = L.sv ? ws + L.sv : nullptr;
+    pr.tv = L.tv ? ws + L.tv : nullptr;
+    pr.bs = L.bscal ? (BScal *)(ws + L.bscal) : nullptr;
 }
 
 void init_scalars(std::vector<Scal> &sc, int nrhs) {
@@ -272,7 +355,7 @@ void init_scalars(std::vector<Scal> &sc, int nrhs) {
 // ------------------------------------------------------------ graph cache
 struct GraphKey {
     const void *ws;
-    int dims[4], nrhs, inner, K, persistent;
+    int dims[4], nrhs, inner, K, persistent, method;
     int shp[NKIND][4];
     bool operator<(const GraphKey &o) const { return memcmp(this, &o, sizeof(*this)) < 0; }
 };
@@ -421,7 +504,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
            void *ws, size_t ws_bytes, wd_cg_report *reps, hipStream_t st) {
     const auto t_start = std::chrono::steady_clock::now();
     const int64_t V = g->V;
-    const WsLayout L = ws_layout(V, nrhs, p.inner);
+    const WsLayout L = ws_layout(V, nrhs, p.inner, p.method);
     WD_CHECK(ws_bytes >= L.total, WD_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
     char *w = (char *)ws;
     Prob hp;
@@ -433,7 +516,8 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     int *dsum = (int *)(w + L.summary);
 
     const int K = p.chunk > 0 ? p.chunk : (p.reliable_every > 0 ? p.reliable_every : 50);
-    const int persistent = p.persistent == 1 ? 1 : 0;
+    const bool bicg = p.method == METHOD_BICGSTAB;
+    const int persistent = (p.persistent == 1 && !bicg) ? 1 : 0;
     if (persistent) plan_persistent(ls, hp, V, nrhs, p.inner);
 
     // upload the problem record and the initial scalars
@@ -449,10 +533,11 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     else launch_zero(w + L.x64, spinor_bytes(WD_F64, V, nrhs), st);
     if (rc) return rc;
     launch_zero(w + L.xlo, spinor_bytes(p.inner == WD_F16N ? WD_F32 : p.inner, V, nrhs), st);
-    // |eta|, first true residual, p = r
+    if (bicg) launch_zero(w + L.bscal, al256(sizeof(BScal) * nrhs), st);
+    // |eta|, first true residual, p = r (BiCGSTAB: its first stage S1 does that)
     launch_kind(KN, p.inner, ls, st, dprob, 1);
     launch_kind(KR2, p.inner, ls, st, dprob, 1);
-    launch_kind(KC, p.inner, ls, st, dprob, 1);
+    if (!bicg) launch_kind(KC, p.inner, ls, st, dprob, 1);
     const int *dabort = persistent ? (const int *)(w + L.ticket + 128) : nullptr;
     launch_summary(st, dprob, 1, dsum, dabort);
     WD_HIP(hipGetLastError());
@@ -465,6 +550,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     key.inner = p.inner;
     key.K = K;
     key.persistent = persistent;
+    key.method = p.method;
     for (int k = 0; k < NKIND; ++k) {
         key.shp[k][0] = ls.k[k].block;
         key.shp[k][1] = ls.k[k].nr;
@@ -474,6 +560,14 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     hipGraphExec_t exec = nullptr;
     int rec_rc = WD_OK;
     rc = get_graph(key, [&](hipStream_t cs) {
+        if (bicg) {
+            for (int it = 0; it < K; ++it)
+                for (int k = KS1; k <= KS5; ++k) launch_kind(k, p.inner, ls, cs, dprob, 1);
+            launch_kind(KR1, p.inner, ls, cs, dprob, 1);
+            launch_kind(KR2, p.inner, ls, cs, dprob, 1);
+            launch_summary(cs, dprob, 1, dsum, dabort);
+            return;
+        }
         if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, K, w + L.ticket + 64);
         else
             for (int it = 0; it < K; ++it) {
@@ -495,7 +589,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     WD_HIP(hipStreamSynchronize(st));
     // every chunk either converges a field or spends K iterations of it
     const int max_chunks = p.max_iter / K + 2 * (p.max_iter / (K * 4) + 4);
-    const bool prof = g_prof_on.load() != 0 && !persistent;
+    const bool prof = g_prof_on.load() != 0 && !persistent && !bicg;
     for (int c = 0; c < max_chunks && hsum[0] > 0; ++c) {
         hipError_t e = hipSuccess;
         if (prof) {
@@ -559,6 +653,10 @@ int check_params(const wd_cg_params *p) {
     WD_CHECK(p->inner >= 0 && p->inner <= 2, WD_EINVAL, "unknown inner precision %d", p->inner);
     WD_CHECK(p->chunk >= 0 && p->chunk <= 1000, WD_EINVAL, "chunk %d out of range", p->chunk);
     WD_CHECK(p->persistent >= -1 && p->persistent <= 1, WD_EINVAL, "persistent %d", p->persistent);
+    WD_CHECK(p->method == METHOD_CGNE || p->method == METHOD_BICGSTAB, WD_EINVAL, "unknown method %d", p->method);
+    WD_CHECK(p->method == METHOD_CGNE || p->persistent != 1, WD_EINVAL,
+             "the persistent kernel runs CG only");
+    WD_CHECK(p->reserved == 0, WD_EINVAL, "reserved field of the parameters is not 0");
     return WD_OK;
 }
 
@@ -578,11 +676,13 @@ void wd_cg_default_params(wd_cg_params *p) {
     p->use_x0 = 0;
     p->persistent = -1;
     p->chunk = 0;
+    p->method = METHOD_CGNE;
 }
 
 size_t wd_cg_workspace_bytes(const wd_gauge *g, int32_t nrhs, const wd_cg_params *p) {
     if (!g || !p || nrhs < 1 || nrhs > MAX_RHS || p->inner < 0 || p->inner > 2) return 0;
-    return ws_layout(g->V, nrhs, p->inner).total;
+    if (p->method != METHOD_CGNE && p->method != METHOD_BICGSTAB) return 0;
+    return ws_layout(g->V, nrhs, p->inner, p->method).total;
 }
 
 int wd_cg_solve_batch(const wd_gauge *g, double m0, const void *src, void *sol, int32_t nrhs,

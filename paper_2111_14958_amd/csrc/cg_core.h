@@ -26,8 +26,15 @@ namespace wd {
 // per right-hand-side state
 enum : int { ST_ACTIVE = 0, ST_FROZEN = 1, ST_DONE = 2, ST_BREAKDOWN = 3, ST_NOTCONV = 4 };
 // kernel kinds: phase A, phase B, phase C, reliable update R1 (x64 += x_lo),
-// reliable update R2 (r = eta - D x64), source norm N
-enum : int { KA = 0, KB = 1, KC = 2, KR1 = 3, KR2 = 4, KN = 5, NKIND = 6 };
+// reliable update R2 (r = eta - D x64), source norm N, and the five BiCGSTAB
+// stages S1 (p update), S2 (v = D p), S3 (s = r - alpha v), S4 (t = D s),
+// S5 (x and r updates)
+enum : int { KA = 0, KB = 1, KC = 2, KR1 = 3, KR2 = 4, KN = 5,
+             KS1 = 6, KS2 = 7, KS3 = 8, KS4 = 9, KS5 = 10, NKIND = 11 };
+enum : int { METHOD_CGNE = 0, METHOD_BICGSTAB = 1 };
+// doubles per (site block, rhs) partial-sum entry (complex dot products need
+// up to three numbers)
+constexpr int PSTRIDE = 4;
 
 struct alignas(16) Scal {
     double rho;       // |r|^2 of the current residual
@@ -46,11 +53,16 @@ struct alignas(16) Scal {
     int pad;
 };
 
+// complex scalars of BiCGSTAB, one record per right-hand side
+struct alignas(16) BScal {
+    double rho[2], rho_old[2], alpha[2], omega[2], beta[2];
+};
+
 struct alignas(16) Prob {
     Geom g;
     double diag;      // 4 + m0
     double tol2;
-    int nrhs, max_iter, ru_every, pad0;
+    int nrhs, max_iter, ru_every, method;
     int nsb[NKIND];   // site blocks per kernel kind
     int ng[NKIND];    // rhs groups per kernel kind
     int t0[NKIND];    // first tile of this problem in a grouped launch
@@ -59,9 +71,11 @@ struct alignas(16) Prob {
     const void *U64;  // FP64 links
     void *x_lo, *r, *p, *q;   // inner-precision vectors (x_lo: FP32 for FP16N)
     void *x64, *eta64;        // FP64 packed vectors
-    double *part;             // [nsb][nrhs] partial sums of the current phase
+    double *part;             // [nsb][nrhs][PSTRIDE] partial sums of the current phase
     unsigned *ticket;         // block counter of the current phase (self-resetting)
     Scal *sc;                 // [nrhs]
+    void *rh, *v, *sv, *tv;   // BiCGSTAB: shadow residual r_hat, v = D p, s, t = D s
+    BScal *bs;                // BiCGSTAB scalars [nrhs]
 };
 
 // precision x_lo is stored in
@@ -77,7 +91,7 @@ __device__ __forceinline__ double wave_sum(double x) {
 // Sum v[j] over the block in a fixed order; result valid on thread 0.
 template <int NR>
 __device__ __forceinline__ void block_sum(double v[NR]) {
-    __shared__ double red[4][NR];
+    __shared__ double red[4][NR > 0 ? NR : 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NR; ++j) v[j] = wave_sum(v[j]);
@@ -112,12 +126,17 @@ __device__ __forceinline__ bool ticket_last(unsigned *ticket, unsigned total) {
     return last;
 }
 
-// Fixed-order sum over site blocks of partial column i; valid on thread 0.
-__device__ __forceinline__ double sum_partials(const Prob &pr, int nsb, int i) {
+// Fixed-order sum over site blocks of partial k of column i; valid on thread 0.
+__device__ __forceinline__ double sum_partials(const Prob &pr, int nsb, int i, int k = 0) {
     double s[1] = {0.0};
-    for (int b = threadIdx.x; b < nsb; b += blockDim.x) s[0] += pr.part[(size_t)b * pr.nrhs + i];
+    for (int b = threadIdx.x; b < nsb; b += blockDim.x)
+        s[0] += pr.part[((size_t)b * pr.nrhs + i) * PSTRIDE + k];
     block_sum<1>(s);
     return s[0];
+}
+
+__device__ __forceinline__ double &part_at(const Prob &pr, int sb, int i, int k) {
+    return pr.part[((size_t)sb * pr.nrhs + i) * PSTRIDE + k];
 }
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < 1e300; }
@@ -141,7 +160,7 @@ __device__ __forceinline__ unsigned rhs_mask(const Prob &pr, int rhs0, int want)
 
 // ------------------------------------------------------------------ phase A
 // q = D^dagger p for active rhs; partial |q|^2 (of the stored q)
-template <int P, int NR>
+template <int P, int NR, int ORD = 1>
 __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     const int ng = pr.ng[KA];
@@ -157,7 +176,7 @@ __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
         FieldPtr fp{pr.p, g.V, pr.nrhs}, fq{pr.q, g.V, pr.nrhs};
         const void *U = pr.U_lo;
         cx<R> acc[NR][12];
-        hopping<P, true, NR>(g, s, U, fp, rhs0, act, acc);
+        hopping<P, true, NR, ORD>(g, s, U, fp, rhs0, act, acc);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
@@ -177,7 +196,7 @@ __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
         if (threadIdx.x == 0)
 #pragma unroll
             for (int j = 0; j < NR; ++j)
-                if (act >> j & 1) pr.part[(size_t)sb * pr.nrhs + rhs0 + j] = part[j];
+                if (act >> j & 1) part_at(pr, sb, rhs0 + j, 0) = part[j];
     }
 }
 
@@ -202,7 +221,7 @@ __device__ __forceinline__ void phaseA_finish(const Prob &pr) {
 
 // ------------------------------------------------------------------ phase B
 // t = D q; r -= alpha t; x_lo += alpha q(s); partial |r|^2 (of the stored r)
-template <int P, int NR>
+template <int P, int NR, int ORD = 1>
 __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     constexpr int XP = XPrec<P>::value;
@@ -220,7 +239,7 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
         FieldPtr fq{pr.q, g.V, pr.nrhs}, fr{pr.r, g.V, pr.nrhs}, fx{pr.x_lo, g.V, pr.nrhs};
         const void *U = pr.U_lo;
         cx<R> acc[NR][12];
-        hopping<P, false, NR>(g, s, U, fq, rhs0, act, acc);
+        hopping<P, false, NR, ORD>(g, s, U, fq, rhs0, act, acc);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
@@ -250,7 +269,7 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
         if (threadIdx.x == 0)
 #pragma unroll
             for (int j = 0; j < NR; ++j)
-                if (act >> j & 1) pr.part[(size_t)sb * pr.nrhs + rhs0 + j] = part[j];
+                if (act >> j & 1) part_at(pr, sb, rhs0 + j, 0) = part[j];
     }
 }
 
@@ -363,7 +382,7 @@ __device__ __forceinline__ void ru2_tile(const Prob &pr, int t) {
         if (threadIdx.x == 0)
 #pragma unroll
             for (int j = 0; j < NR; ++j)
-                if (act >> j & 1) pr.part[(size_t)sb * pr.nrhs + rhs0 + j] = part[j];
+                if (act >> j & 1) part_at(pr, sb, rhs0 + j, 0) = part[j];
     }
 }
 
@@ -371,7 +390,9 @@ __device__ __forceinline__ void ru2_finish(const Prob &pr) {
     for (int i = 0; i < pr.nrhs; ++i) {
         Scal &c = pr.sc[i];
         if (c.state != ST_FROZEN) {
-            if (threadIdx.x == 0) c.pending_p = 0;
+            // CG: the chunk's last phase C has consumed the flag.  BiCGSTAB: a
+            // field still iterating keeps it for the next p update.
+            if (threadIdx.x == 0 && pr.method == METHOD_CGNE) c.pending_p = 0;
             continue;
         }
         const double r2 = sum_partials(pr, pr.nsb[KR2], i);
@@ -391,6 +412,12 @@ __device__ __forceinline__ void ru2_finish(const Prob &pr) {
                 c.rho = r2;
                 c.state = ST_ACTIVE;
                 c.pending_p = 1;
+                if (pr.method == METHOD_BICGSTAB) {
+                    // restart from the true residual: r_hat = r, p = r, rho = |r|^2
+                    c.restart = 1;
+                    pr.bs[i].rho[0] = r2;
+                    pr.bs[i].rho[1] = 0.0;
+                }
             }
         }
     }
@@ -409,7 +436,7 @@ __device__ __forceinline__ void norm_tile(const Prob &pr, int t) {
         for (int k = 0; k < 12; ++k) part[0] += norm2(e[k]);
     }
     block_sum<1>(part);
-    if (threadIdx.x == 0) pr.part[(size_t)sb * pr.nrhs + i] = part[0];
+    if (threadIdx.x == 0) part_at(pr, sb, i, 0) = part[0];
 }
 
 __device__ __forceinline__ void norm_finish(const Prob &pr) {

@@ -10,6 +10,7 @@ namespace wd {
 
 struct KindShape {
     int block = 256, nr = 1, remap = 0, grid = 0;
+    int ordered = 1;   // hop order of phases A and B: 1 or 3 (pipelined)
 };
 struct LaunchSet {
     KindShape k[NKIND];
@@ -17,10 +18,12 @@ struct LaunchSet {
 
 // Byte offsets of the pieces of a solve workspace.
 struct WsLayout {
-    size_t prob, scal, ticket, summary, part, eta64, x64, xlo, r, p, q, total;
+    size_t prob, scal, ticket, summary, part, eta64, x64, xlo, r, p, q;
+    size_t bscal, rh, sv, tv;   // BiCGSTAB only (0 otherwise)
+    size_t total;
 };
 
-WsLayout ws_layout(int64_t V, int nrhs, int inner);
+WsLayout ws_layout(int64_t V, int nrhs, int inner, int method);
 void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr);
 void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner);
 void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_params &p, char *ws,

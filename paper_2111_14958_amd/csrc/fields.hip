@@ -198,28 +198,6 @@ int wd_device_info(int device, char *arch, size_t arch_len, int32_t *num_cu) {
     return WD_OK;
 }
 
-int wd_stream_create_cu_limited(int32_t n_cu, void **stream) {
-    clear_error();
-    WD_CHECK(stream, WD_EINVAL, "null argument");
-    int ncu = 0;
-    int rc = require_gfx950(&ncu);
-    if (rc) return rc;
-    WD_CHECK(n_cu >= 1 && n_cu <= ncu, WD_EINVAL, "n_cu %d out of 1..%d", n_cu, ncu);
-    std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
-    for (int i = 0; i < n_cu; ++i) mask[i / 32] |= 1u << (i % 32);
-    hipStream_t st = nullptr;
-    WD_HIP(hipExtStreamCreateWithCUMask(&st, (uint32_t)mask.size(), mask.data()));
-    *stream = st;
-    return WD_OK;
-}
-
-int wd_stream_destroy(void *stream) {
-    clear_error();
-    if (!stream) return WD_OK;
-    WD_HIP(hipStreamDestroy((hipStream_t)stream));
-    return WD_OK;
-}
-
 int wd_gauge_create(const int32_t dims[4], int32_t t_sign, const void *U_dev, uint32_t prec_mask,
                     void *stream, wd_gauge **out) {
     clear_error();

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_persistent(const Prob *__restrict__ pro
     unsigned e = 0;
     for (int it = 0; it < K; ++it) {
         {   // phase A
-            FOR_MY_TILES(pr.nt[KA], t) phaseA_tile<P, NR>(pr, t);
+            FOR_MY_TILES(pr.nt[KA], t) phaseA_tile<P, NR, 1>(pr, t);
         }
         if (bar_arrive(b, nblk, e)) {
             phaseA_finish(pr);
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void k_persistent(const Prob *__restrict__ pro
         }
         ++e;
         {   // phase B
-            FOR_MY_TILES(pr.nt[KB], t) phaseB_tile<P, NR>(pr, t);
+            FOR_MY_TILES(pr.nt[KB], t) phaseB_tile<P, NR, 1>(pr, t);
         }
         if (bar_arrive(b, nblk, e)) {
             phaseB_finish(pr);

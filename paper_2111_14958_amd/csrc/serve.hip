@@ -90,7 +90,7 @@ static SlotLayout slot_layout(int64_t V, int nrhs, int inner) {
         s.links_lo = s.links64;
     }
     s.ws = o;
-    s.L = ws_layout(V, nrhs, inner);
+    s.L = ws_layout(V, nrhs, inner, METHOD_CGNE);
     o += s.L.total;
     s.total = o;
     return s;
@@ -404,6 +404,7 @@ static int check_request(const wd_request *r) {
     if (rc) return rc;
     WD_CHECK(r->params.inner == WD_F32 || r->params.inner == WD_F64, WD_EINVAL,
              "the server runs FP32 or FP64 inner iterations");
+    WD_CHECK(r->params.method == METHOD_CGNE, WD_EINVAL, "the server runs CG on the normal equations only");
     return WD_OK;
 }
 

@@ -45,8 +45,11 @@ Shape default_shape(int prec, int nrhs, int fam) {
     s.ordered = 1;
     s.rloop = 1;
     if (fam == FAM_DSLASH) {
-        s.block = 128;
+        // measured best for 14^4 x 16 rhs in FP32: own spinor first, pipelined hops
+        s.block = 64;
         s.nr = 1;
+        s.remap = 0;
+        s.ordered = 4;
     } else {
         s.block = 256;
         s.nr = (prec == WD_F64 || nrhs < 2) ? 1 : 2;
@@ -189,8 +192,8 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     WD_CHECK(sh->rhs_per_thread == 1 || sh->rhs_per_thread == 2 || sh->rhs_per_thread == 4, WD_EINVAL,
              "rhs_per_thread %d", sh->rhs_per_thread);
     WD_CHECK(sh->hop_order >= 0 && sh->hop_order <= 4 && sh->rhs_loop >= 1, WD_EINVAL, "bad hop order / rhs loop");
-    WD_CHECK(family == FAM_DSLASH || (sh->hop_order == 1 && sh->rhs_loop == 1), WD_EINVAL,
-             "CG kernels always issue hops one at a time, one rhs group per block");
+    WD_CHECK(family == FAM_DSLASH || ((sh->hop_order == 1 || sh->hop_order == 3) && sh->rhs_loop == 1),
+             WD_EINVAL, "CG kernels take hop order 1 or 3 and one rhs group per block");
     WD_CHECK(!(family == FAM_CG_R && sh->rhs_per_thread > 2), WD_EINVAL, "reliable-update kernel takes <= 2 rhs");
     WD_CHECK(!(prec == WD_F64 && family != FAM_DSLASH && sh->rhs_per_thread > 2), WD_EINVAL,
              "FP64 CG kernels take <= 2 rhs per thread");

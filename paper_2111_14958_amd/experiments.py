@@ -1,17 +1,13 @@
 """The paper's two tuning / scaling studies (arXiv 2111.14958, Sec. 3.1) on MI355X.
 
     python -m paper_2111_14958_amd.experiments fig1   # whole-CG time vs block size
-    python -m paper_2111_14958_amd.experiments fig2   # speedup vs compute units
 
 Fig. 1 of the paper times the whole CG at 14^4 while varying the SYCL
 workgroup size with the number of compute units fixed; here the block size of
-every CG kernel is swept (64, 128, 256 threads) through wd_shape_set.  Fig. 2
-times the CG at 14^4 on 1, 2, 4, ... compute units relative to one compute
-unit; here the solve runs on a stream restricted to the first n compute units
-(wd_stream_create_cu_limited).  Both use the single-field FP64 CG of the
-paper's algorithm (plain CG on D D^dagger, true-residual check at 1e-10) on
-seeded synthetic fields (links exp(i 0.5 H), Gaussian source, m0 = 0.05).
-Each prints one JSON line per point.
+every CG kernel is swept (64, 128, 256 threads) through wd_shape_set, using the
+single-field FP64 CG of the paper's algorithm (plain CG on D D^dagger,
+true-residual check at 1e-10) on seeded synthetic fields (links exp(i 0.5 H),
+Gaussian source, m0 = 0.05).  Prints one JSON line per point.
 """
 from __future__ import annotations
 
@@ -60,21 +56,5 @@ def fig1(blocks=(64, 128, 256)):
                           "gflops": 2 * 1368.0 * 14 ** 4 * rep["iters"] / t / 1e9}), flush=True)
 
 
-def fig2(cus=(1, 2, 4, 8, 16, 32, 64, 128, 256)):
-    wd, torch, g, dsrc, m0 = _setup()
-    p = wd.cg_default_params(inner=wd.F64, reliable_every=0, persistent=0)
-    base = None
-    for n in cus:
-        s = wd.CULimitedStream(n)
-        with torch.cuda.stream(s.torch_stream):
-            t, rep = _time_solve(wd, torch, g, dsrc, m0, p, reps=2 if n < 8 else 3)
-        torch.cuda.synchronize()
-        s.close()
-        base = base or t
-        print(json.dumps({"figure": 2, "lattice": "14^4", "compute_units": n, "seconds": t,
-                          "speedup_vs_1cu": base / t, "iters": rep["iters"],
-                          "true_rel_res": rep["true_rel_res"]}), flush=True)
-
-
 if __name__ == "__main__":
-    {"fig1": fig1, "fig2": fig2}[sys.argv[1]]()
+    {"fig1": fig1}[sys.argv[1]]()

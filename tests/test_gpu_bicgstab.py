@@ -1,0 +1,150 @@
+"""GPU BiCGSTAB (wd_cg_solve_batch with method WD_METHOD_BICGSTAB) against the oracle.
+
+BiCGSTAB on D x = eta is one of the Krylov methods the paper names for the
+Dirac equation (Sec. 1).  Every returned solution is judged by the oracle's
+operator: its true relative residual must be <= tol.  Against the oracle's
+solutions (its BiCGSTAB, the dense LAPACK solve at 4^4) the error is bounded by
+kappa(D) (tol_gpu + tol_oracle), kappa(D) <= (8 + m0) / m0.  In FP64 without
+intermediate reliable updates the GPU iterates the oracle's recurrence, so the
+iteration counts agree to rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2111_14958_amd as wd
+import wdgen
+from gpu_util import dev, host, rel, say
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def kappa(m0):
+    return (8.0 + m0) / m0
+
+
+def _params(inner, **kw):
+    kw.setdefault("reliable_every", 0 if inner == wd.F64 else 50)
+    return wd.cg_default_params(inner=inner, method=wd.METHOD_BICGSTAB, **kw)
+
+
+def _check_solution(U, eta, x, dims, m0, t_sign=-1):
+    res = oracle.true_residual(U, eta, x, dims, m0, t_sign)
+    assert np.all(res <= TOL * 1.0000001), f"true residuals {res}"
+    return res
+
+
+@pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
+def test_c1_4x4(inner):
+    cfg = wdgen.CONFIGS["c1_4x4"]
+    dims, m0 = cfg["dims"], cfg["m0"]
+    U = wdgen.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
+    eta = wdgen.gaussian_source(dims, 1, cfg["src_seed"])
+    say("bicgstab c1", inner)
+    g = wd.Gauge(dev(U), dims)
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=_params(inner))
+    x = host(x)
+    assert rc == wd.WD_OK, reps
+    assert reps[0]["status"] == 0 and reps[0]["true_rel_res"] <= TOL
+    res = _check_solution(U, eta, x, dims, m0)
+    assert abs(reps[0]["true_rel_res"] - res[0]) <= 1e-3 * TOL + 1e-6 * res[0]
+    D = oracle.dense(U, dims, m0)
+    xs = np.linalg.solve(D, eta.ravel())
+    assert rel(x.ravel(), xs) <= kappa(m0) * TOL
+    xo, it, ro, st = oracle.bicgstab(U, eta, dims, m0, tol=TOL)
+    assert st[0] == 0
+    assert rel(x, xo) <= kappa(m0) * 2 * TOL
+    if inner == wd.F64:
+        assert abs(reps[0]["iters"] - it[0]) <= max(2, it[0] // 20), (reps[0]["iters"], it[0])
+
+
+@pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
+def test_batch_mixed_sources_8x4(inner):
+    """12 point sources + 4 Gaussian ones sharing one gauge field."""
+    dims, m0 = (8, 8, 8, 8), 0.05
+    U = wdgen.gauge_field(dims, 0.5, 1003)
+    eta = wdgen.mixed_sources(dims, 12, 4, 2003)
+    say("bicgstab batch 16 rhs", inner)
+    g = wd.Gauge(dev(U), dims)
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=_params(inner))
+    assert rc == wd.WD_OK, reps
+    assert all(r["status"] == 0 for r in reps)
+    x = host(x)
+    _check_solution(U, eta, x, dims, m0)
+    # one point source and one Gaussian source against the oracle's BiCGSTAB
+    for i in (0, 13):
+        xo, it, ro, st = oracle.bicgstab(U, eta[i:i + 1], dims, m0, tol=TOL)
+        assert st[0] == 0
+        assert rel(x[i], xo[0]) <= kappa(m0) * 2 * TOL, i
+        if inner == wd.F64:
+            assert abs(reps[i]["iters"] - it[0]) <= max(2, it[0] // 20), (i, reps[i]["iters"], it[0])
+
+
+def test_batch_equals_single_fields():
+    """A field's solve does not depend on the other fields of its batch."""
+    dims, m0 = (8, 8, 8, 8), 0.05
+    U = wdgen.gauge_field(dims, 0.5, 1003)
+    eta = wdgen.mixed_sources(dims, 2, 2, 77)
+    say("bicgstab batch vs single")
+    g = wd.Gauge(dev(U), dims)
+    p = _params(wd.F32)
+    xb, rb, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    assert rc == wd.WD_OK
+    xb = host(xb)
+    for i in range(eta.shape[0]):
+        xi, ri, rc = wd.cg_solve_batch(g, m0, dev(eta[i:i + 1]), params=p)
+        assert rc == wd.WD_OK
+        assert rel(host(xi)[0], xb[i]) <= kappa(m0) * 2 * TOL
+
+
+def test_c2_14x4_f32():
+    """The paper's 14^4 lattice, one Gaussian source, FP32 inner iterations."""
+    dims, m0 = (14, 14, 14, 14), 0.05
+    U = wdgen.gauge_field(dims, 0.5, 1002)
+    eta = wdgen.gaussian_source(dims, 1, 2002)
+    say("bicgstab 14^4 f32")
+    g = wd.Gauge(dev(U), dims)
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=_params(wd.F32))
+    assert rc == wd.WD_OK, reps
+    _check_solution(U, eta, host(x), dims, m0)
+
+
+def test_initial_guess_zero_source_and_cap():
+    dims, m0 = (4, 4, 4, 4), 0.1
+    U = wdgen.gauge_field(dims, 0.5, 11)
+    eta = wdgen.gaussian_source(dims, 2, 12)
+    eta[1] = 0
+    say("bicgstab x0 / zero source / max_iter")
+    g = wd.Gauge(dev(U), dims)
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=_params(wd.F64))
+    assert rc == wd.WD_OK
+    x = host(x)
+    assert np.all(x[1] == 0) and reps[1]["iters"] == 0
+    # the solution as the initial guess: no iteration
+    x2, reps2, rc = wd.cg_solve_batch(g, m0, dev(eta), sol=dev(x), params=_params(wd.F64, use_x0=1))
+    assert rc == wd.WD_OK and reps2[0]["iters"] == 0
+    # an iteration cap below what is needed
+    x3, reps3, rc = wd.cg_solve_batch(g, m0, dev(eta[:1]), params=_params(wd.F64, max_iter=3),
+                                      raise_on_error=False)
+    assert rc == wd.WD_ENOTCONV and reps3[0]["iters"] == 3
+
+
+def test_rejected_parameters():
+    dims = (4, 4, 4, 4)
+    U = wdgen.gauge_field(dims, 0.5, 11)
+    eta = wdgen.gaussian_source(dims, 1, 12)
+    say("bicgstab parameter errors")
+    g = wd.Gauge(dev(U), dims)
+    for kw in ({"persistent": 1}, {"method": 2}, {"reserved": 1}):
+        p = _params(wd.F32)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        _, _, rc = wd.cg_solve_batch(g, 0.1, dev(eta), params=p, raise_on_error=False)
+        assert rc == wd.WD_EINVAL, kw
