@@ -211,7 +211,10 @@ typedef struct {
     int32_t hop_order;    /* 1: hops one at a time, 2: a direction's two hops together,
                              0: compiler order                                    */
     int32_t rhs_loop;     /* rhs groups one block handles one after the other    */
-    int32_t reserved;
+    int32_t site_order;   /* strip | group_major << 16.  strip = W > 0: sites are
+                             processed in strips of W z-planes, t-major inside a
+                             strip (0: lexicographic); group_major = 1: tiles are
+                             ordered rhs-group-major instead of site-block-major  */
     double  us;           /* median time of one application, microseconds        */
     double  gbps;         /* algorithmic bytes / time                             */
 } wd_tune_result;
@@ -235,7 +238,8 @@ int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
 /* Set the launch shape of one kernel family for (g's lattice, prec, nrhs,
  * dagger) by hand -- e.g. to sweep the block size of the whole CG as the paper
  * does for its workgroup size (Sec. 3.1, Fig. 1).  block in {64,128,256},
- * rhs_per_thread in {1,2,4}, hop_order 0..4, rhs_loop >= 1. */
+ * rhs_per_thread in {1,2,4}, hop_order 0..4, rhs_loop >= 1, site_order as in
+ * wd_tune_result. */
 int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, int32_t family,
                  const wd_tune_result *shape);
 

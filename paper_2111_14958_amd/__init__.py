@@ -72,7 +72,7 @@ class CGReport(ctypes.Structure):
 class TuneResult(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("rhs_per_thread", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32), ("hop_order", ctypes.c_int32),
-                ("rhs_loop", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rhs_loop", ctypes.c_int32), ("site_order", ctypes.c_int32),
                 ("us", ctypes.c_double), ("gbps", ctypes.c_double)]
 
 
@@ -407,9 +407,11 @@ FAMILY_DSLASH, FAMILY_CG_A, FAMILY_CG_B, FAMILY_CG_R = 0, 1, 2, 3
 
 
 def shape_set(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int, block: int,
-              rhs_per_thread: int = 1, xcd_remap: int = 1, hop_order: int = 1, rhs_loop: int = 1):
+              rhs_per_thread: int = 1, xcd_remap: int = 1, hop_order: int = 1, rhs_loop: int = 1,
+              strip: int = 0, group_major: int = 0):
     r = TuneResult(block=block, rhs_per_thread=rhs_per_thread, xcd_remap=xcd_remap,
-                   hop_order=hop_order, rhs_loop=rhs_loop)
+                   hop_order=hop_order, rhs_loop=rhs_loop,
+                   site_order=strip | (group_major << 16))
     _check(lib().wd_shape_set(g.handle, prec, nrhs, 1 if dagger else 0, family, ctypes.byref(r)),
            "wd_shape_set")
 

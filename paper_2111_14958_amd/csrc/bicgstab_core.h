@@ -69,9 +69,8 @@ template <int P, int NR, bool S4>
 __device__ __forceinline__ void bi_stencil_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     const int K = S4 ? KS4 : KS2;
-    const int ng = pr.ng[K];
-    const int sb = t / ng, grp = t - sb * ng;
-    const int s = sb * blockDim.x + threadIdx.x;
+    int sb, grp, s;
+    stencil_tile(pr, K, t, sb, grp, s);
     const int rhs0 = grp * NR;
     const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
     double part[3 * NR];

@@ -282,11 +282,15 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.nr = st[k]->nr;
             ks.remap = st[k]->remap;
             ks.ordered = (k == KA || k == KB) && st[k]->ordered == 3 ? 3 : 1;
+            const int strip = (st[k]->strip > 0 && st[k]->strip < g->dims[2]) ? st[k]->strip : 0;
+            ks.order = strip | (st[k]->gmajor ? 1 << 16 : 0);
         } else {
             ks.block = 256;
             ks.nr = 1;
             ks.remap = 0;
+            ks.order = 0;
         }
+        pr.sorder[k] = ks.order;
         pr.nsb[k] = (V + ks.block - 1) / ks.block;
         pr.ng[k] = (nrhs + ks.nr - 1) / ks.nr;
         pr.t0[k] = 0;
@@ -356,7 +360,7 @@ void init_scalars(std::vector<Scal> &sc, int nrhs) {
 struct GraphKey {
     const void *ws;
     int dims[4], nrhs, inner, K, persistent, method;
-    int shp[NKIND][4];
+    int shp[NKIND][5];
     bool operator<(const GraphKey &o) const { return memcmp(this, &o, sizeof(*this)) < 0; }
 };
 
@@ -556,6 +560,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
         key.shp[k][1] = ls.k[k].nr;
         key.shp[k][2] = ls.k[k].remap;
         key.shp[k][3] = ls.k[k].grid;
+        key.shp[k][4] = ls.k[k].order;
     }
     hipGraphExec_t exec = nullptr;
     int rec_rc = WD_OK;

@@ -67,6 +67,7 @@ struct alignas(16) Prob {
     int ng[NKIND];    // rhs groups per kernel kind
     int t0[NKIND];    // first tile of this problem in a grouped launch
     int nt[NKIND];    // tiles of this problem
+    int sorder[NKIND];  // stencil kinds: strip | group-major << 16 (see order_site)
     const void *U_lo; // links in the inner precision
     const void *U64;  // FP64 links
     void *x_lo, *r, *p, *q;   // inner-precision vectors (x_lo: FP32 for FP16N)
@@ -148,6 +149,21 @@ __device__ __forceinline__ int find_prob(const Prob *probs, int nprob, int K, in
     return j;
 }
 
+// Tile t of stencil kind K: its site block, its rhs group and this thread's
+// site (g.V when the thread has no site).
+__device__ __forceinline__ void stencil_tile(const Prob &pr, int K, int t, int &sb, int &grp, int &s) {
+    const int od = pr.sorder[K];
+    if (od >> 16) {
+        grp = t / pr.nsb[K];
+        sb = t - grp * pr.nsb[K];
+    } else {
+        sb = t / pr.ng[K];
+        grp = t - sb * pr.ng[K];
+    }
+    const int L = sb * (int)blockDim.x + (int)threadIdx.x;
+    s = L < pr.g.V ? order_site(pr.g, od & 0xffff, L) : pr.g.V;
+}
+
 // bit j set: rhs rhs0 + j is in state `want`
 template <int NR>
 __device__ __forceinline__ unsigned rhs_mask(const Prob &pr, int rhs0, int want) {
@@ -163,9 +179,8 @@ __device__ __forceinline__ unsigned rhs_mask(const Prob &pr, int rhs0, int want)
 template <int P, int NR, int ORD = 1>
 __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
-    const int ng = pr.ng[KA];
-    const int sb = t / ng, grp = t - sb * ng;
-    const int s = sb * blockDim.x + threadIdx.x;
+    int sb, grp, s;
+    stencil_tile(pr, KA, t, sb, grp, s);
     const int rhs0 = grp * NR;
     const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
     double part[NR];
@@ -226,9 +241,8 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     constexpr int XP = XPrec<P>::value;
     typedef typename real_of<XP>::type RX;
-    const int ng = pr.ng[KB];
-    const int sb = t / ng, grp = t - sb * ng;
-    const int s = sb * blockDim.x + threadIdx.x;
+    int sb, grp, s;
+    stencil_tile(pr, KB, t, sb, grp, s);
     const int rhs0 = grp * NR;
     const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
     double part[NR];
@@ -343,9 +357,8 @@ __device__ __forceinline__ void ru1_tile(const Prob &pr, int t) {
 template <int P, int NR>
 __device__ __forceinline__ void ru2_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
-    const int ng = pr.ng[KR2];
-    const int sb = t / ng, grp = t - sb * ng;
-    const int s = sb * blockDim.x + threadIdx.x;
+    int sb, grp, s;
+    stencil_tile(pr, KR2, t, sb, grp, s);
     const int rhs0 = grp * NR;
     const unsigned act = rhs_mask<NR>(pr, rhs0, ST_FROZEN);
     double part[NR];

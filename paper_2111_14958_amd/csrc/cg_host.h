@@ -11,6 +11,7 @@ namespace wd {
 struct KindShape {
     int block = 256, nr = 1, remap = 0, grid = 0;
     int ordered = 1;   // hop order of phases A and B: 1 or 3 (pipelined)
+    int order = 0;     // stencil kinds: processing order, strip | group-major << 16
 };
 struct LaunchSet {
     KindShape k[NKIND];

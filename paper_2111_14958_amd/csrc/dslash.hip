@@ -2,9 +2,11 @@
 // gamma5-hermiticity, Sec. 2) as a matrix-free stencil on packed fields.
 //
 // One thread computes one lattice site for NR right-hand sides, so each link
-// is loaded once per NR fields.  A block covers `block` consecutive sites of one
-// group of NR right-hand sides; tiles are ordered site-block-major, group-minor,
-// and optionally remapped so each XCD sweeps one contiguous slab of sites.
+// is loaded once per NR fields.  A block covers `block` consecutive sites (of
+// the processing order, order_site) of one group of NR right-hand sides.
+// Tiles are ordered site-block-major (group-minor) or group-major, and
+// optionally remapped so each XCD works through one contiguous range of them.
+// `order` = strip width | group-major << 16.
 #include <algorithm>
 
 #include "wd_device.h"
@@ -14,16 +16,26 @@ namespace wd {
 
 template <int P, bool DAG, int NR, int ORD>
 __global__ __launch_bounds__(256) void k_dslash(Geom g, double diag, const void *__restrict__ U,
-                                                FieldPtr in, FieldPtr out, int ngroups, int remap, int rloop) {
+                                                FieldPtr in, FieldPtr out, int ngroups, int remap, int rloop,
+                                                int order) {
     typedef typename real_of<P>::type R;
     // tile = (site block, group of rloop consecutive rhs groups); the block
     // handles its rhs groups one after the other, so fewer distinct fields are
     // in flight per XCD at a time
     const int nouter = (ngroups + rloop - 1) / rloop;
     const int b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int sb = b / nouter, go = b - sb * nouter;
-    const int s = sb * blockDim.x + threadIdx.x;
-    if (s >= g.V) return;
+    int sb, go;
+    if (order >> 16) {
+        const int nsb = (int)gridDim.x / nouter;
+        go = b / nsb;
+        sb = b - go * nsb;
+    } else {
+        sb = b / nouter;
+        go = b - sb * nouter;
+    }
+    const int L = sb * blockDim.x + threadIdx.x;
+    if (L >= g.V) return;
+    const int s = order_site(g, order & 0xffff, L);
     for (int gi = 0; gi < rloop; ++gi) {
         const int grp = go * rloop + gi;
         if (grp >= ngroups) break;
@@ -62,30 +74,30 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, double diag, const void 
 
 template <int P, bool DAG, int ORD>
 static void launch_nr_o(int nr, dim3 grid, dim3 block, hipStream_t st, const Geom &g, double diag,
-                        const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int rl) {
+                        const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int rl, int od) {
     if constexpr (ORD == 4) {
         // the own spinors of several rhs do not fit in registers: only NR = 1
         if (nr == 1)
-            hipLaunchKernelGGL((k_dslash<P, DAG, 1, 4>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl);
+            hipLaunchKernelGGL((k_dslash<P, DAG, 1, 4>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl, od);
         else
-            launch_nr_o<P, DAG, 3>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
+            launch_nr_o<P, DAG, 3>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
     } else {
         switch (nr) {
-        case 1: hipLaunchKernelGGL((k_dslash<P, DAG, 1, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl); break;
-        case 2: hipLaunchKernelGGL((k_dslash<P, DAG, 2, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl); break;
-        default: hipLaunchKernelGGL((k_dslash<P, DAG, 4, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl); break;
+        case 1: hipLaunchKernelGGL((k_dslash<P, DAG, 1, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl, od); break;
+        case 2: hipLaunchKernelGGL((k_dslash<P, DAG, 2, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl, od); break;
+        default: hipLaunchKernelGGL((k_dslash<P, DAG, 4, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl, od); break;
         }
     }
 }
 
 template <int P, bool DAG>
 static void launch_nr(int nr, int ordered, int rl, dim3 grid, dim3 block, hipStream_t st, const Geom &g, double diag,
-                      const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap) {
-    if (ordered == 1) launch_nr_o<P, DAG, 1>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
-    else if (ordered == 2) launch_nr_o<P, DAG, 2>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
-    else if (ordered == 3) launch_nr_o<P, DAG, 3>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
-    else if (ordered == 4) launch_nr_o<P, DAG, 4>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
-    else launch_nr_o<P, DAG, 0>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl);
+                      const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int od) {
+    if (ordered == 1) launch_nr_o<P, DAG, 1>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
+    else if (ordered == 2) launch_nr_o<P, DAG, 2>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
+    else if (ordered == 3) launch_nr_o<P, DAG, 3>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
+    else if (ordered == 4) launch_nr_o<P, DAG, 4>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
+    else launch_nr_o<P, DAG, 0>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
 }
 
 Geom make_geom(const wd_gauge *gg) {
@@ -108,17 +120,19 @@ int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void 
     const int ngroups = (nrhs + nr - 1) / nr;
     const int rl = sh.rloop >= 1 ? std::min(sh.rloop, ngroups) : 1;
     const int nsb = (g.V + blk - 1) / blk;
+    const int strip = (sh.strip > 0 && sh.strip < g.L[2]) ? sh.strip : 0;
+    const int od = strip | (sh.gmajor ? 1 << 16 : 0);
     const dim3 grid(nsb * ((ngroups + rl - 1) / rl)), block(blk);
     FieldPtr fi{(void *)in, g.V, nrhs}, fo{out, g.V, nrhs};
     const void *U = gg->U[prec];
     const double diag = 4.0 + m0;
     switch (prec * 2 + (dag ? 1 : 0)) {
-    case 0: launch_nr<P64, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
-    case 1: launch_nr<P64, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
-    case 2: launch_nr<P32, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
-    case 3: launch_nr<P32, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
-    case 4: launch_nr<P16, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
-    case 5: launch_nr<P16, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap); break;
+    case 0: launch_nr<P64, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od); break;
+    case 1: launch_nr<P64, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od); break;
+    case 2: launch_nr<P32, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od); break;
+    case 3: launch_nr<P32, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od); break;
+    case 4: launch_nr<P16, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od); break;
+    case 5: launch_nr<P16, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od); break;
     default: return fail(WD_EINVAL, "unknown precision %d", prec);
     }
     WD_HIP(hipGetLastError());

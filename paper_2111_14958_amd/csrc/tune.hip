@@ -69,8 +69,9 @@ static void load_cache_locked() {
         ShapeKey k;
         Shape s;
         double us = 0;
-        if (sscanf(line, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %lf", &k.L[0], &k.L[1], &k.L[2], &k.L[3],
-                   &k.prec, &k.nrhs, &k.dag, &s.block, &s.nr, &s.remap, &s.ordered, &s.rloop, &us) == 13)
+        if (sscanf(line, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %d %d %lf", &k.L[0], &k.L[1], &k.L[2],
+                   &k.L[3], &k.prec, &k.nrhs, &k.dag, &s.block, &s.nr, &s.remap, &s.ordered, &s.rloop, &s.strip,
+                   &s.gmajor, &us) == 15)
             g_table[k] = {s, us};
     }
     fclose(f);
@@ -95,8 +96,8 @@ static void append_cache(const ShapeKey &k, const Shape &s, double us) {
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %.3f\n", k.L[0], k.L[1], k.L[2], k.L[3], k.prec,
-            k.nrhs, k.dag, s.block, s.nr, s.remap, s.ordered, s.rloop, us);
+    fprintf(f, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.3f\n", k.L[0], k.L[1], k.L[2], k.L[3], k.prec,
+            k.nrhs, k.dag, s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor, us);
     fclose(f);
 }
 
@@ -178,6 +179,7 @@ int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     cfg->xcd_remap = s.remap;
     cfg->hop_order = s.ordered;
     cfg->rhs_loop = s.rloop;
+    cfg->site_order = s.strip | (s.gmajor << 16);
     return WD_OK;
 }
 
@@ -197,6 +199,8 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     WD_CHECK(!(family == FAM_CG_R && sh->rhs_per_thread > 2), WD_EINVAL, "reliable-update kernel takes <= 2 rhs");
     WD_CHECK(!(prec == WD_F64 && family != FAM_DSLASH && sh->rhs_per_thread > 2), WD_EINVAL,
              "FP64 CG kernels take <= 2 rhs per thread");
+    const int strip = sh->site_order & 0xffff, gmajor = sh->site_order >> 16;
+    WD_CHECK(sh->site_order >= 0 && (gmajor == 0 || gmajor == 1), WD_EINVAL, "site_order 0x%x", sh->site_order);
     ShapeKey k{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, prec, nrhs, dagger ? 1 : 0, family};
     Shape s;
     s.block = sh->block;
@@ -204,6 +208,8 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     s.remap = sh->xcd_remap ? 1 : 0;
     s.ordered = sh->hop_order;
     s.rloop = sh->rhs_loop;
+    s.strip = strip;
+    s.gmajor = gmajor;
     shape_store(k, s);
     return WD_OK;
 }
@@ -245,18 +251,27 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     const int nrs[3] = {1, 2, 4};
     const bool verbose = getenv("WD_TUNE_VERBOSE") != nullptr;
     const int rloops[3] = {1, 2, 4};
+    // processing orders: lexicographic, z-strips of 2, 4 and about half the z extent
+    const int Lz = g->dims[2];
+    const int strips[4] = {0, Lz > 2 ? 2 : 0, Lz > 4 ? 4 : 0, Lz > 4 ? (Lz + 1) / 2 : 0};
     for (int bi = 0; bi < 3 && !rc; ++bi)
         for (int ni = 0; ni < 3 && !rc; ++ni)
-            for (int cand = 0; cand < 30 && !rc; ++cand) {
+            for (int cand = 0; cand < 30 * 8 && !rc; ++cand) {
                 Shape s;
+                const int c = cand % 30, o = cand / 30;
                 s.block = blocks[bi];
                 s.nr = nrs[ni];
-                s.remap = cand & 1;
-                s.ordered = (cand >> 1) % 5;      // 0 free, 1 per hop, 2 per direction, 3 pipelined,
+                s.remap = c & 1;
+                s.ordered = (c >> 1) % 5;         // 0 free, 1 per hop, 2 per direction, 3 pipelined,
                                                   // 4 pipelined with the own spinor first
-                s.rloop = rloops[cand / 10];
+                s.rloop = rloops[c / 10];
+                s.strip = strips[o & 3];
+                s.gmajor = o >> 2;
+                if (o > 0 && strips[o & 3] == 0 && (o & 3) != 0) continue;   // order unavailable
+                if (s.gmajor && s.rloop > 1) continue;
                 if (s.ordered == 4 && s.nr != 1) continue;
                 const int ngroups = (nrhs + s.nr - 1) / s.nr;
+                if (s.gmajor && ngroups == 1) continue;
                 if (s.rloop > 1 && s.rloop > ngroups) continue;
                 if (s.nr > 1 && s.nr > nrhs) continue;
                 if (prec == WD_F64 && s.nr > 2) continue;
@@ -269,15 +284,16 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
                     break;
                 }
                 if (memcmp(h_out.data(), h_ref.data(), nb) != 0) {   // rejected
-                    if (verbose) fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d: output differs, rejected\n",
-                                         s.block, s.nr, s.remap, s.ordered, s.rloop);
+                    if (verbose) fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d strip %d gmajor %d: "
+                                         "output differs, rejected\n", s.block, s.nr, s.remap, s.ordered, s.rloop,
+                                         s.strip, s.gmajor);
                     continue;
                 }
                 double us = 0;
                 rc = time_shape(g, prec, dag, in, out, nrhs, s, st, 10, &us);
                 if (verbose && !rc)
-                    fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d: %.2f us, %.0f GB/s\n",
-                            s.block, s.nr, s.remap, s.ordered, s.rloop, us,
+                    fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d strip %d gmajor %d: "
+                            "%.2f us, %.0f GB/s\n", s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor, us,
                             algorithmic_bytes(prec, V, nrhs) / (us * 1e-6) / 1e9);
                 if (!rc && us < best_us) { best_us = us; bestshape = s; }
             }
@@ -295,6 +311,7 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
         best->xcd_remap = bestshape.remap;
         best->hop_order = bestshape.ordered;
         best->rhs_loop = bestshape.rloop;
+        best->site_order = bestshape.strip | (bestshape.gmajor << 16);
         best->us = best_us;
         best->gbps = algorithmic_bytes(prec, V, nrhs) / (best_us * 1e-6) / 1e9;
     }

@@ -376,4 +376,21 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
     return xcd * per + (xcd < rem ? xcd : rem) + idx;
 }
 
+// Site at position L of a kernel's processing order.  strip == 0: lexicographic
+// order (x fastest).  strip = W > 0: the (z, t) planes are walked in strips of
+// W consecutive z-planes, t-major within a strip, so a site's t neighbours are
+// W planes away in the order (instead of Lz planes) and the data a block
+// shares with the blocks processed around it stays in the XCD's L2.  Every
+// xy-plane stays contiguous, so a wavefront's accesses remain coalesced.
+__host__ __device__ __forceinline__ int order_site(const Geom &g, int strip, int L) {
+    if (strip <= 0) return L;
+    const int P = g.S[2];                 // sites per xy-plane
+    const int q = L / P, off = L - q * P; // plane number in the order, offset
+    const int per = strip * g.L[3];       // planes of a full strip
+    const int zb = q / per, qq = q - zb * per;
+    const int w = g.L[2] - zb * strip < strip ? g.L[2] - zb * strip : strip;   // last strip may be narrower
+    const int t = qq / w, zi = qq - t * w;
+    return off + P * (zb * strip + zi + g.L[2] * t);
+}
+
 }  // namespace wd

@@ -46,6 +46,8 @@ struct Shape {
     int remap = 1;           // XCD-contiguous tile order
     int ordered = 1;         // hops issued one at a time (see hopping())
     int rloop = 1;           // rhs groups a block handles one after the other
+    int strip = 0;           // processing order: z-strips of this width (0: lexicographic)
+    int gmajor = 0;          // tiles ordered rhs-group-major (1) or site-block-major (0)
 };
 
 // Key of the launch-shape table: lattice, precision, rhs count, dagger, and
