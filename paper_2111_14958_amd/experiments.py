@@ -1,6 +1,7 @@
-"""The paper's two tuning / scaling studies (arXiv 2111.14958, Sec. 3.1) on MI355X.
+"""Experiments beyond the benchmark line, on MI355X.
 
-    python -m paper_2111_14958_amd.experiments fig1   # whole-CG time vs block size
+    python -m paper_2111_14958_amd.experiments fig1    # whole-CG time vs block size
+    python -m paper_2111_14958_amd.experiments serve   # open-loop serving latency
 
 Fig. 1 of the paper times the whole CG at 14^4 while varying the SYCL
 workgroup size with the number of compute units fixed; here the block size of
@@ -56,5 +57,84 @@ def fig1(blocks=(64, 128, 256)):
                           "gflops": 2 * 1368.0 * 14 ** 4 * rep["iters"] / t / 1e9}), flush=True)
 
 
+def serve(n_requests=120, rates=(0.5, 1.0, 1.5), pool=2, arena_gib=24, max_slots=16, seed=10_000):
+    """Continuous-batching solve server under Poisson arrivals.
+
+    Request i (seeded by seed + i): lattice drawn uniformly from 4^4, 8^4, 12^4, 14^4, 16^3 x 32,
+    1..12 Gaussian right-hand sides, m0 uniform in [0.02, 0.2], FP32 inner CG
+    with FP64 reliable updates, tol 1e-10.  Gauge fields (links exp(i 0.5 H))
+    come from a pre-generated pool of `pool` fields per volume; sources are
+    drawn on the device.  Everything is generated before the clock starts.
+    First a closed-loop run (all requests at t = 0) measures the capacity in
+    requests/s; then open-loop runs submit at `rates` x capacity with
+    exponential inter-arrival times.  Latency = submit -> result, measured by
+    the server.  Prints one JSON line per run.
+    """
+    import numpy as np
+    import torch
+
+    import paper_2111_14958_amd as wd
+    import wdgen
+    rng = np.random.default_rng(seed)
+    volumes = wdgen.SERVING_VOLUMES
+    gauges = {}
+    for vi, dims in enumerate(volumes):
+        gauges[vi] = [torch.from_numpy(wdgen.gauge_field(dims, 0.5, seed + 100 * vi + k)).cuda()
+                      for k in range(pool)]
+    print(json.dumps({"serve": "pool ready"}), flush=True)
+    reqs = []
+    gen = torch.Generator(device="cuda")
+    for i in range(n_requests):
+        vi = int(rng.integers(0, len(volumes)))
+        dims = volumes[vi]
+        nrhs = int(rng.integers(1, 13))
+        m0 = float(rng.uniform(0.02, 0.2))
+        V = dims[0] * dims[1] * dims[2] * dims[3]
+        gen.manual_seed(seed + 50_000 + i)
+        src = torch.randn((nrhs, dims[3], dims[2], dims[1], dims[0], 4, 3), dtype=torch.complex128,
+                          device="cuda", generator=gen)
+        reqs.append(dict(dims=dims, nrhs=nrhs, m0=m0, V=V, U=gauges[vi][i % pool], src=src))
+    arena = torch.empty(int(arena_gib) << 30, dtype=torch.uint8, device="cuda")
+    params = wd.cg_default_params(inner=wd.F32, reliable_every=50)
+
+    def run(arrivals):
+        srv = wd.Server(arena, max_slots=max_slots)
+        sols = [torch.zeros_like(r["src"]) for r in reqs]
+        torch.cuda.synchronize()
+        tickets, reps = [None] * len(reqs), [None] * len(reqs)
+        t0 = time.perf_counter()
+        nxt = 0
+        while any(r is None for r in reps):
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and arrivals[nxt] <= now:
+                r = reqs[nxt]
+                req = wd.Server.request(r["dims"], r["nrhs"], r["m0"], r["U"], r["src"], sols[nxt], params)
+                tickets[nxt] = srv.submit(req)
+                nxt += 1
+            for i in range(nxt):
+                if reps[i] is None:
+                    reps[i] = srv.poll(tickets[i])
+            time.sleep(0.0005)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        lat = np.array([rep[0]["seconds"] for rep in reps])
+        ok = all(x["status"] == 0 and x["true_rel_res"] <= 1e-10 for rep in reps for x in rep)
+        nrhs_tot = sum(r["nrhs"] for r in reqs)
+        return dict(requests=len(reqs), wall_s=wall, requests_per_s=len(reqs) / wall,
+                    rhs_solves_per_s=nrhs_tot / wall, p50_latency_s=float(np.percentile(lat, 50)),
+                    p99_latency_s=float(np.percentile(lat, 99)), all_converged=ok,
+                    arena_high_water_gib=st["arena_high_water"] / 2**30, steps=st["steps"])
+
+    closed = run(np.zeros(len(reqs)))
+    print(json.dumps({"serve": "closed-loop", **closed}), flush=True)
+    cap = closed["requests_per_s"]
+    for f in rates:
+        arr = np.cumsum(rng.exponential(1.0 / (f * cap), size=len(reqs)))
+        res = run(arr - arr[0])
+        print(json.dumps({"serve": "poisson", "rate_x_capacity": f, "offered_per_s": f * cap, **res}),
+              flush=True)
+
+
 if __name__ == "__main__":
-    {"fig1": fig1}[sys.argv[1]]()
+    {"fig1": fig1, "serve": serve}[sys.argv[1]]()
