@@ -2,6 +2,7 @@
 
     python -m paper_2111_14958_amd.experiments fig1    # whole-CG time vs block size
     python -m paper_2111_14958_amd.experiments serve   # open-loop serving latency
+    python -m paper_2111_14958_amd.experiments solve   # one profiled 14^4 x 16 solve
 
 Fig. 1 of the paper times the whole CG at 14^4 while varying the SYCL
 workgroup size with the number of compute units fixed; here the block size of
@@ -136,5 +137,38 @@ def serve(n_requests=120, rates=(0.5, 1.0, 1.5), pool=2, arena_gib=24, max_slots
               flush=True)
 
 
+def solve():
+    """One mixed-precision solve of the 14^4 x 16 benchmark workload with the
+    library's profiling mode on (every chunk kernel launched on its own,
+    bracketed by events), then one 256 MiB device copy of known size: the
+    program that hardware-counter runs profile (the copy calibrates the byte
+    counters).  Prints the per-kernel statistics as JSON."""
+    import torch
+
+    import paper_2111_14958_amd as wd
+    import wdgen
+    cfg = wdgen.CONFIGS["c3_14x4_16rhs"]
+    dims = cfg["dims"]
+    U = wdgen.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
+    src = wdgen.mixed_sources(dims, cfg["n_point"], cfg["n_gauss"], cfg["src_seed"])
+    g = wd.Gauge(torch.from_numpy(U).cuda(), dims)
+    dsrc = torch.from_numpy(src).cuda()
+    p = wd.cg_default_params(tol=cfg["tol"], inner=wd.F32, reliable_every=50)
+    sol = torch.zeros_like(dsrc)
+    ws = torch.empty(wd.cg_workspace_bytes(g, dsrc.shape[0], p), dtype=torch.uint8, device="cuda")
+    wd.profile_reset()
+    wd.profile_enable(True)
+    _, reps, rc = wd.cg_solve_batch(g, cfg["m0"], dsrc, sol=sol, params=p, ws=ws)
+    torch.cuda.synchronize()
+    wd.profile_enable(False)
+    prof = wd.profile_read()
+    a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"solve": "c3 mixed", "rc": rc, "iters": max(r["iters"] for r in reps),
+                      "kernels": prof, "copy_bytes_each_way": a.numel()}), flush=True)
+
+
 if __name__ == "__main__":
-    {"fig1": fig1, "serve": serve}[sys.argv[1]]()
+    {"fig1": fig1, "serve": serve, "solve": solve}[sys.argv[1]]()
