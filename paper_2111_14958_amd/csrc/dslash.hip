@@ -72,6 +72,73 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, double diag, const void 
     }
 }
 
+// Plane-blocked variant: a block is one xy-plane (np = Lx Ly <= 256 sites) of
+// one group of NR right-hand sides.  The block first copies its plane's
+// spinors to LDS; the x and y neighbours then come from LDS, so only the own
+// spinor and the z and t neighbours are read from memory.  The own spinor is
+// read back from LDS for the diagonal term.
+template <int P, bool DAG, int NR, int ORD>
+__global__ __launch_bounds__(256) void k_dslash_xy(Geom g, double diag, const void *__restrict__ U,
+                                                   FieldPtr in, FieldPtr out, int ngroups, int remap, int order) {
+    typedef typename real_of<P>::type R;
+    typedef typename LdsSpinor<P>::word W;
+    extern __shared__ uint4 lds_raw[];
+    W *xy = (W *)lds_raw;
+    const int np = (int)blockDim.x;
+    const int b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int npl = (int)gridDim.x / ngroups;
+    int pl, grp;
+    if (order >> 16) {
+        grp = b / npl;
+        pl = b - grp * npl;
+    } else {
+        pl = b / ngroups;
+        grp = b - pl * ngroups;
+    }
+    const int s = order_site(g, order & 0xffff, pl * np + (int)threadIdx.x);
+    const int rhs0 = grp * NR;
+    const int nact = min(NR, in.nrhs - rhs0);
+    const unsigned act = (1u << nact) - 1u;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (act >> j & 1) {
+            cx<R> self[12];
+            Spinor<P>::load(in, rhs0 + j, s, self);
+            LdsSpinor<P>::put(xy, np, j, threadIdx.x, self);
+        }
+    }
+    __syncthreads();
+    cx<R> acc[NR][12];
+    hopping<P, DAG, NR, ORD, true>(g, s, U, in, rhs0, act, acc, nullptr, xy, s - (int)threadIdx.x, np);
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (act >> j & 1) {
+            cx<R> self[12], o[12];
+            LdsSpinor<P>::get(xy, np, j, threadIdx.x, self);
+            wilson_finish<R>((R)diag, self, acc[j], o);
+            Spinor<P>::store(out, rhs0 + j, s, o);
+        }
+    }
+}
+
+// LDS bytes of the plane-blocked variant
+static size_t xy_lds_bytes(int prec, int nr, int np) {
+    return (size_t)nr * (prec == WD_F64 ? 192 : 96) * np;
+}
+
+template <int P, bool DAG>
+static void launch_xy(int nr, int ord, dim3 grid, int np, size_t lds, hipStream_t st, const Geom &g, double diag,
+                      const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int od) {
+    const dim3 block(np);
+    if (nr == 1) {
+        if (ord == 3) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 3>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+        else hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 1>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+    } else {
+        if (ord == 3) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 2, 3>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+        else hipLaunchKernelGGL((k_dslash_xy<P, DAG, 2, 1>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+    }
+}
+
 template <int P, bool DAG, int ORD>
 static void launch_nr_o(int nr, dim3 grid, dim3 block, hipStream_t st, const Geom &g, double diag,
                         const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int rl, int od) {
@@ -122,6 +189,28 @@ int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void 
     const int nsb = (g.V + blk - 1) / blk;
     const int strip = (sh.strip > 0 && sh.strip < g.L[2]) ? sh.strip : 0;
     const int od = strip | (sh.gmajor ? 1 << 16 : 0);
+    if (sh.xylds) {
+        const int np = g.L[0] * g.L[1];
+        const int nrx = prec == WD_F64 ? 1 : std::min(nr, 2);
+        const int ngx = (nrhs + nrx - 1) / nrx;
+        const size_t lds = xy_lds_bytes(prec, nrx, np);
+        WD_CHECK(np <= 256 && lds <= 65536, WD_EINVAL, "plane-blocked operator needs Lx*Ly <= 256");
+        FieldPtr fi{(void *)in, g.V, nrhs}, fo{out, g.V, nrhs};
+        const void *U = gg->U[prec];
+        const dim3 grid((g.V / np) * ngx);
+        const int ord = sh.ordered == 3 ? 3 : 1;
+        switch (prec * 2 + (dag ? 1 : 0)) {
+        case 0: launch_xy<P64, false>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
+        case 1: launch_xy<P64, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
+        case 2: launch_xy<P32, false>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
+        case 3: launch_xy<P32, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
+        case 4: launch_xy<P16, false>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
+        case 5: launch_xy<P16, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
+        default: return fail(WD_EINVAL, "unknown precision %d", prec);
+        }
+        WD_HIP(hipGetLastError());
+        return WD_OK;
+    }
     const dim3 grid(nsb * ((ngroups + rl - 1) / rl)), block(blk);
     FieldPtr fi{(void *)in, g.V, nrhs}, fo{out, g.V, nrhs};
     const void *U = gg->U[prec];

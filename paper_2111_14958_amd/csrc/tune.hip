@@ -69,9 +69,9 @@ static void load_cache_locked() {
         ShapeKey k;
         Shape s;
         double us = 0;
-        if (sscanf(line, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %d %d %lf", &k.L[0], &k.L[1], &k.L[2],
+        if (sscanf(line, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %lf", &k.L[0], &k.L[1], &k.L[2],
                    &k.L[3], &k.prec, &k.nrhs, &k.dag, &s.block, &s.nr, &s.remap, &s.ordered, &s.rloop, &s.strip,
-                   &s.gmajor, &us) == 15)
+                   &s.gmajor, &s.xylds, &us) == 16)
             g_table[k] = {s, us};
     }
     fclose(f);
@@ -96,8 +96,8 @@ static void append_cache(const ShapeKey &k, const Shape &s, double us) {
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.3f\n", k.L[0], k.L[1], k.L[2], k.L[3], k.prec,
-            k.nrhs, k.dag, s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor, us);
+    fprintf(f, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.3f\n", k.L[0], k.L[1], k.L[2], k.L[3],
+            k.prec, k.nrhs, k.dag, s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor, s.xylds, us);
     fclose(f);
 }
 
@@ -179,7 +179,7 @@ int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     cfg->xcd_remap = s.remap;
     cfg->hop_order = s.ordered;
     cfg->rhs_loop = s.rloop;
-    cfg->site_order = s.strip | (s.gmajor << 16);
+    cfg->site_order = s.strip | (s.gmajor << 16) | (s.xylds << 17);
     return WD_OK;
 }
 
@@ -199,8 +199,10 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     WD_CHECK(!(family == FAM_CG_R && sh->rhs_per_thread > 2), WD_EINVAL, "reliable-update kernel takes <= 2 rhs");
     WD_CHECK(!(prec == WD_F64 && family != FAM_DSLASH && sh->rhs_per_thread > 2), WD_EINVAL,
              "FP64 CG kernels take <= 2 rhs per thread");
-    const int strip = sh->site_order & 0xffff, gmajor = sh->site_order >> 16;
-    WD_CHECK(sh->site_order >= 0 && (gmajor == 0 || gmajor == 1), WD_EINVAL, "site_order 0x%x", sh->site_order);
+    const int strip = sh->site_order & 0xffff, gmajor = (sh->site_order >> 16) & 1, xylds = sh->site_order >> 17;
+    WD_CHECK(sh->site_order >= 0 && (xylds == 0 || xylds == 1), WD_EINVAL, "site_order 0x%x", sh->site_order);
+    WD_CHECK(!xylds || (family == FAM_DSLASH && g->dims[0] * g->dims[1] <= 256), WD_EINVAL,
+             "plane-blocked LDS variant: operator kernel only, Lx*Ly <= 256");
     ShapeKey k{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, prec, nrhs, dagger ? 1 : 0, family};
     Shape s;
     s.block = sh->block;
@@ -210,6 +212,7 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     s.rloop = sh->rhs_loop;
     s.strip = strip;
     s.gmajor = gmajor;
+    s.xylds = xylds;
     shape_store(k, s);
     return WD_OK;
 }
@@ -254,6 +257,31 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     // processing orders: lexicographic, z-strips of 2, 4 and about half the z extent
     const int Lz = g->dims[2];
     const int strips[4] = {0, Lz > 2 ? 2 : 0, Lz > 4 ? 4 : 0, Lz > 4 ? (Lz + 1) / 2 : 0};
+    // run one candidate: reject it unless its output equals the reference bit
+    // for bit, else time it and keep the fastest
+    auto try_shape = [&](const Shape &s) {
+        hipMemsetAsync(out, 0, nb, st);
+        rc = launch_dslash(g, 0.1, prec, dag, in, out, nrhs, s, st);
+        if (rc) return;
+        if (hipMemcpyAsync(h_out.data(), out, nb, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = fail(WD_EHIP, "copy of candidate output failed");
+            return;
+        }
+        if (memcmp(h_out.data(), h_ref.data(), nb) != 0) {   // rejected
+            if (verbose) fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d strip %d gmajor %d "
+                                 "xylds %d: output differs, rejected\n", s.block, s.nr, s.remap, s.ordered, s.rloop,
+                                 s.strip, s.gmajor, s.xylds);
+            return;
+        }
+        double us = 0;
+        rc = time_shape(g, prec, dag, in, out, nrhs, s, st, 10, &us);
+        if (verbose && !rc)
+            fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d strip %d gmajor %d xylds %d: "
+                    "%.2f us, %.0f GB/s\n", s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor, s.xylds,
+                    us, algorithmic_bytes(prec, V, nrhs) / (us * 1e-6) / 1e9);
+        if (!rc && us < best_us) { best_us = us; bestshape = s; }
+    };
     for (int bi = 0; bi < 3 && !rc; ++bi)
         for (int ni = 0; ni < 3 && !rc; ++ni)
             for (int cand = 0; cand < 30 * 8 && !rc; ++cand) {
@@ -275,28 +303,27 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
                 if (s.rloop > 1 && s.rloop > ngroups) continue;
                 if (s.nr > 1 && s.nr > nrhs) continue;
                 if (prec == WD_F64 && s.nr > 2) continue;
-                hipMemsetAsync(out, 0, nb, st);
-                rc = launch_dslash(g, 0.1, prec, dag, in, out, nrhs, s, st);
-                if (rc) break;
-                if (hipMemcpyAsync(h_out.data(), out, nb, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                    hipStreamSynchronize(st) != hipSuccess) {
-                    rc = fail(WD_EHIP, "copy of candidate output failed");
-                    break;
-                }
-                if (memcmp(h_out.data(), h_ref.data(), nb) != 0) {   // rejected
-                    if (verbose) fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d strip %d gmajor %d: "
-                                         "output differs, rejected\n", s.block, s.nr, s.remap, s.ordered, s.rloop,
-                                         s.strip, s.gmajor);
-                    continue;
-                }
-                double us = 0;
-                rc = time_shape(g, prec, dag, in, out, nrhs, s, st, 10, &us);
-                if (verbose && !rc)
-                    fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d strip %d gmajor %d: "
-                            "%.2f us, %.0f GB/s\n", s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor, us,
-                            algorithmic_bytes(prec, V, nrhs) / (us * 1e-6) / 1e9);
-                if (!rc && us < best_us) { best_us = us; bestshape = s; }
+                try_shape(s);
             }
+    // plane-blocked variant: one xy-plane per block, x/y neighbours from LDS
+    const int np = g->dims[0] * g->dims[1];
+    if (np <= 256)
+        for (int cand = 0; cand < 2 * 2 * 2 * 8 && !rc; ++cand) {
+            Shape s;
+            const int o = cand >> 3;
+            s.block = np;
+            s.nr = (cand & 1) ? 2 : 1;
+            s.remap = (cand >> 1) & 1;
+            s.ordered = (cand >> 2) & 1 ? 3 : 1;
+            s.rloop = 1;
+            s.strip = strips[o & 3];
+            s.gmajor = o >> 2;
+            s.xylds = 1;
+            if (o > 0 && strips[o & 3] == 0 && (o & 3) != 0) continue;
+            if (s.nr > 1 && (prec == WD_F64 || nrhs < 2)) continue;
+            if (s.gmajor && (nrhs + s.nr - 1) / s.nr == 1) continue;
+            try_shape(s);
+        }
     hipFree(in);
     hipFree(ref);
     hipFree(out);
@@ -311,7 +338,7 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
         best->xcd_remap = bestshape.remap;
         best->hop_order = bestshape.ordered;
         best->rhs_loop = bestshape.rloop;
-        best->site_order = bestshape.strip | (bestshape.gmajor << 16);
+        best->site_order = bestshape.strip | (bestshape.gmajor << 16) | (bestshape.xylds << 17);
         best->us = best_us;
         best->gbps = algorithmic_bytes(prec, V, nrhs) / (best_us * 1e-6) / 1e9;
     }

@@ -258,16 +258,57 @@ __device__ __forceinline__ void link_adj_mul(const cx<R> u[9], const cx<R> h[6],
 
 template <int MU> struct IntC { static constexpr int value = MU; };
 
+// A block's copy of one xy-plane of spinors in LDS, [NR][components][np]
+// with np = sites of the plane (the block size): FP64 as 12 double2 per site,
+// FP32 and FP16N (decoded) as 6 float4 per site.  Consecutive sites are
+// consecutive 16-byte words, so a wavefront's accesses are conflict free.
+template <int P> struct LdsSpinor {
+    static constexpr int BYTES = 96;
+    __device__ static __forceinline__ void put(f4v *b, int np, int j, int i, const cx<float> v[12]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) b[(j * 6 + k) * np + i] = f4v{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im};
+    }
+    __device__ static __forceinline__ void get(const f4v *b, int np, int j, int i, cx<float> v[12]) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const f4v w = b[(j * 6 + k) * np + i];
+            v[2 * k] = {w.x, w.y};
+            v[2 * k + 1] = {w.z, w.w};
+        }
+    }
+    typedef f4v word;
+};
+template <> struct LdsSpinor<P64> {
+    static constexpr int BYTES = 192;
+    __device__ static __forceinline__ void put(d2v *b, int np, int j, int i, const cx<double> v[12]) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) b[(j * 12 + k) * np + i] = d2v{v[k].re, v[k].im};
+    }
+    __device__ static __forceinline__ void get(const d2v *b, int np, int j, int i, cx<double> v[12]) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const d2v w = b[(j * 12 + k) * np + i];
+            v[k] = {w.x, w.y};
+        }
+    }
+    typedef d2v word;
+};
+
 // Hopping sum of Eq. (1) at site s for NR right-hand sides of field `in`
 // starting at rhs0 (only those whose bit is set in `act` are touched):
 //   acc = sum_mu [ (1 + SF gamma_mu) U_mu(s) psi(s+mu) + (1 + SB gamma_mu) U_mu(s-mu)^dag psi(s-mu) ]
 // with SF = -1, SB = +1 for D and SF = +1, SB = -1 for D^dagger, and the
 // boundary sign on hops in t that wrap around.  Each link is loaded once and
 // applied to all NR right-hand sides.
-template <int P, bool DAG, int NR, int ORDERED = 1>
+//
+// XYLDS: the neighbours in x and y are read from the block's LDS copy of its
+// xy-plane (`xy`, plane starting at site `plane0`, np sites) instead of memory.
+template <int P, bool DAG, int NR, int ORDERED = 1, bool XYLDS = false>
 __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, const FieldPtr &in,
                                         int rhs0, unsigned act, cx<typename real_of<P>::type> acc[NR][12],
-                                        const cx<typename real_of<P>::type> (*first)[12] = nullptr) {
+                                        const cx<typename real_of<P>::type> (*first)[12] = nullptr,
+                                        const typename LdsSpinor<P>::word *xy = nullptr, int plane0 = 0,
+                                        int np = 0) {
     typedef typename real_of<P>::type R;
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
@@ -337,7 +378,8 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
                 cx<R> p[12], h[6], w[6];
-                Spinor<P>::load(in, rhs0 + j, nb, p);
+                if constexpr (XYLDS && MU < 2) LdsSpinor<P>::get(xy, np, j, nb - plane0, p);
+                else Spinor<P>::load(in, rhs0 + j, nb, p);
                 project<MU, S>(p, h);
                 if (neg) {
 #pragma unroll
