@@ -10,7 +10,8 @@
 //   S4  t = D s,        <t, s>, <t, t>  -> omega = <t, s> / <t, t>
 //   S5  x += alpha p + omega s, r = s - omega t,
 //       <r_hat, r>, |r|^2  -> rho, beta = (rho / rho_old)(alpha / omega), tests
-// <a, b> = sum conj(a) b.  A reliable update restarts with r_hat = r = eta - D x.
+// <a, b> = sum conj(a) b.  A reliable update restarts with r_hat = r = eta - D x,
+// and so does a (near) breakdown |<r_hat, r>| <= 1e-6 |r_hat| |r|.
 #pragma once
 
 #include "cg_core.h"
@@ -243,7 +244,11 @@ __device__ __forceinline__ void bi5_finish(const Prob &pr) {
             else if (r2 <= c.stop2 || c.iters >= pr.max_iter ||
                      (pr.ru_every > 0 && c.since_ru >= pr.ru_every))
                 c.state = ST_FROZEN;
-            else if (rho_new.re == 0.0 && rho_new.im == 0.0) c.state = ST_FROZEN;   // restart from the true residual
+            // (near) breakdown, <r_hat, r> ~ 0: restart from the true residual.
+            // A point source meets it after one iteration: with r_hat = r0 = e_k,
+            // s has no component along e_k and, since (1 - gamma)(1 + gamma) = 0,
+            // neither has t = D s.
+            else if (rho_new.re * rho_new.re + rho_new.im * rho_new.im <= 1e-12 * b.rh2 * r2) c.state = ST_FROZEN;
             else c.pending_p = 1;
         }
     }

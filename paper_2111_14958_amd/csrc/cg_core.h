@@ -56,6 +56,8 @@ struct alignas(16) Scal {
 // complex scalars of BiCGSTAB, one record per right-hand side
 struct alignas(16) BScal {
     double rho[2], rho_old[2], alpha[2], omega[2], beta[2];
+    double rh2;       // |r_hat|^2, set when r_hat is chosen
+    double pad;
 };
 
 struct alignas(16) Prob {
@@ -430,6 +432,7 @@ __device__ __forceinline__ void ru2_finish(const Prob &pr) {
                     c.restart = 1;
                     pr.bs[i].rho[0] = r2;
                     pr.bs[i].rho[1] = 0.0;
+                    pr.bs[i].rh2 = r2;
                 }
             }
         }

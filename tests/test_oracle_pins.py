@@ -174,3 +174,18 @@ def test_bicgstab_agrees_with_cg():
     xc, itc, rc, sc = oracle.cg(U, eta, dims, m0)
     assert sb == [0, 0] and max(rb) <= 1e-10
     assert np.linalg.norm(xb - xc) / np.linalg.norm(xc) <= pins.kappa_bound(m0) * 2e-10
+
+
+def test_bicgstab_breaks_down_on_a_point_source():
+    """With r_hat = r0 = e_k, alpha = 1 / D_kk makes s orthogonal to e_k, and
+    t = D s has no e_k component either ((1 - gamma)(1 + gamma) = 0 kills the
+    back-and-forth hop), so <r_hat, r1> = 0: plain BiCGSTAB must stop after one
+    iteration on any gauge field, with status 2 (breakdown)."""
+    dims, m0 = (4, 4, 4, 4), 0.1
+    U = wdgen.gauge_field(dims, 0.5, 77)
+    eta = wdgen.point_sources(dims, ks=[0, 7])
+    x, it, res, st = oracle.bicgstab(U, eta, dims, m0)
+    assert st == [2, 2] and it == [1, 1]
+    # a Gaussian source on the same links converges
+    eta = wdgen.gaussian_source(dims, 1, 78)
+    assert oracle.bicgstab(U, eta, dims, m0)[3] == [0]
