@@ -10,8 +10,8 @@
 //   S4  t = D s,        <t, s>, <t, t>  -> omega = <t, s> / <t, t>
 //   S5  x += alpha p + omega s, r = s - omega t,
 //       <r_hat, r>, |r|^2  -> rho, beta = (rho / rho_old)(alpha / omega), tests
-// <a, b> = sum conj(a) b.  A reliable update restarts with r_hat = r = eta - D x,
-// and so does a (near) breakdown |<r_hat, r>| <= 1e-6 |r_hat| |r|.
+// <a, b> = sum conj(a) b.  A reliable update restarts with r_hat = r = eta - D x;
+// a (near) breakdown |<r_hat, r>| <= 1e-6 |r_hat| |r| restarts with r_hat = r.
 #pragma once
 
 #include "cg_core.h"
@@ -244,12 +244,20 @@ __device__ __forceinline__ void bi5_finish(const Prob &pr) {
             else if (r2 <= c.stop2 || c.iters >= pr.max_iter ||
                      (pr.ru_every > 0 && c.since_ru >= pr.ru_every))
                 c.state = ST_FROZEN;
-            // (near) breakdown, <r_hat, r> ~ 0: restart from the true residual.
-            // A point source meets it after one iteration: with r_hat = r0 = e_k,
-            // s has no component along e_k and, since (1 - gamma)(1 + gamma) = 0,
-            // neither has t = D s.
-            else if (rho_new.re * rho_new.re + rho_new.im * rho_new.im <= 1e-12 * b.rh2 * r2) c.state = ST_FROZEN;
-            else c.pending_p = 1;
+            else {
+                // (near) breakdown, <r_hat, r> ~ 0: restart in place with
+                // r_hat = p = r (the iterated residual), rho = |r|^2.  A point
+                // source meets it after one iteration: with r_hat = r0 = e_k, s
+                // has no component along e_k and, since (1 - gamma)(1 + gamma) = 0,
+                // neither has t = D s.
+                if (rho_new.re * rho_new.re + rho_new.im * rho_new.im <= 1e-12 * b.rh2 * r2) {
+                    c.restart = 1;
+                    b.rho[0] = r2;
+                    b.rho[1] = 0.0;
+                    b.rh2 = r2;
+                }
+                c.pending_p = 1;
+            }
         }
     }
 }
