@@ -9,6 +9,7 @@
 // and replays the chunk graph until no right-hand side is active, reading back
 // one counter per replay.  BiCGSTAB (bicgstab_core.h) uses the same driver with
 // the chunk K x [S1, S2, S3, S4, S5], then R1, R2, summary.
+#include <stdlib.h>
 #include <string.h>
 
 #include <atomic>
@@ -24,8 +25,10 @@
 namespace wd {
 
 // ------------------------------------------------------------------ kernels
+// `remap` bit 0: XCD-contiguous tile order; bit 1: the phase's reduction is
+// finished by a separate k_finish launch instead of the last block.
 #define WD_KERNEL_PROLOGUE(K)                                                  \
-    const int b_ = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x; \
+    const int b_ = (remap & 1) ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x; \
     const Prob &pr = probs[find_prob(probs, nprob, K, b_)];                    \
     const int t_ = b_ - pr.t0[K];
 
@@ -33,7 +36,7 @@ template <int P, int NR, int ORD>
 __global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KA)
     phaseA_tile<P, NR, ORD>(pr, t_);
-    if (ticket_last(pr.ticket, pr.nt[KA])) {
+    if (!(remap & 2) && ticket_last(pr.ticket, pr.nt[KA])) {
         phaseA_finish(pr);
         if (threadIdx.x == 0) *pr.ticket = 0;
     }
@@ -43,7 +46,7 @@ template <int P, int NR, int ORD>
 __global__ __launch_bounds__(256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KB)
     phaseB_tile<P, NR, ORD>(pr, t_);
-    if (ticket_last(pr.ticket, pr.nt[KB])) {
+    if (!(remap & 2) && ticket_last(pr.ticket, pr.nt[KB])) {
         phaseB_finish(pr);
         if (threadIdx.x == 0) *pr.ticket = 0;
     }
@@ -65,7 +68,7 @@ template <int P, int NR>
 __global__ __launch_bounds__(256) void k_ru2(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KR2)
     ru2_tile<P, NR>(pr, t_);
-    if (ticket_last(pr.ticket, pr.nt[KR2])) {
+    if (!(remap & 2) && ticket_last(pr.ticket, pr.nt[KR2])) {
         ru2_finish(pr);
         if (threadIdx.x == 0) *pr.ticket = 0;
     }
@@ -74,9 +77,28 @@ __global__ __launch_bounds__(256) void k_ru2(const Prob *__restrict__ probs, int
 __global__ __launch_bounds__(256) void k_norm(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KN)
     norm_tile(pr, t_);
-    if (ticket_last(pr.ticket, pr.nt[KN])) {
+    if (!(remap & 2) && ticket_last(pr.ticket, pr.nt[KN])) {
         norm_finish(pr);
         if (threadIdx.x == 0) *pr.ticket = 0;
+    }
+}
+
+// The reduction of a phase as a launch of its own (one block): the kernel
+// boundary makes every block's partial sums visible, so the tile kernels need
+// no device-wide fence and no ticket.
+__global__ __launch_bounds__(256) void k_finish(const Prob *__restrict__ probs, int nprob, int kind) {
+    for (int j = 0; j < nprob; ++j) {
+        const Prob &pr = probs[j];
+        switch (kind) {
+        case KA: phaseA_finish(pr); break;
+        case KB: phaseB_finish(pr); break;
+        case KR2: ru2_finish(pr); break;
+        case KN: norm_finish(pr); break;
+        case KS2: bi2_finish(pr); break;
+        case KS4: bi4_finish(pr); break;
+        case KS5: bi5_finish(pr); break;
+        default: break;
+        }
     }
 }
 
@@ -106,7 +128,7 @@ __global__ __launch_bounds__(256) void k_bi_stencil(const Prob *__restrict__ pro
     constexpr int K = S4 ? KS4 : KS2;
     WD_KERNEL_PROLOGUE(K)
     bi_stencil_tile<P, NR, S4>(pr, t_);
-    if (ticket_last(pr.ticket, pr.nt[K])) {
+    if (!(remap & 2) && ticket_last(pr.ticket, pr.nt[K])) {
         if (S4) bi4_finish(pr);
         else bi2_finish(pr);
         if (threadIdx.x == 0) *pr.ticket = 0;
@@ -123,7 +145,7 @@ template <int P>
 __global__ __launch_bounds__(256) void k_bi5(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KS5)
     bi5_tile<P>(pr, t_);
-    if (ticket_last(pr.ticket, pr.nt[KS5])) {
+    if (!(remap & 2) && ticket_last(pr.ticket, pr.nt[KS5])) {
         bi5_finish(pr);
         if (threadIdx.x == 0) *pr.ticket = 0;
     }
@@ -178,13 +200,24 @@ static void launch_bicg(int kind, const KindShape &k, hipStream_t st, const Prob
     case KS2: launch_BS<P, false>(k.nr, k.grid, k.block, st, d, n, k.remap); break;
     case KS3: hipLaunchKernelGGL(k_bi3<P>, dim3(k.grid), dim3(k.block), 0, st, d, n, 0); break;
     case KS4: launch_BS<P, true>(k.nr, k.grid, k.block, st, d, n, k.remap); break;
-    case KS5: hipLaunchKernelGGL(k_bi5<P>, dim3(k.grid), dim3(k.block), 0, st, d, n, 0); break;
+    case KS5: hipLaunchKernelGGL(k_bi5<P>, dim3(k.grid), dim3(k.block), 0, st, d, n, k.remap & 2); break;
     }
 }
 
+static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream_t st, const Prob *d, int nprob);
+
 void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob) {
-    const KindShape &k = ls.k[kind];
+    KindShape k = ls.k[kind];
     if (k.grid <= 0) return;
+    const bool reduces = kind == KA || kind == KB || kind == KR2 || kind == KN || kind == KS2 || kind == KS4 ||
+                         kind == KS5;
+    const bool split = reduces && ls.split;
+    if (split) k.remap |= 2;
+    launch_kind_tiles(kind, inner, k, st, d, nprob);
+    if (split) hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, d, nprob, kind);
+}
+
+static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream_t st, const Prob *d, int nprob) {
     switch (kind) {
     case KA:
         if (inner == P64) launch_A<P64>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
@@ -212,7 +245,7 @@ void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const
         else launch_R2<P16>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
         break;
     case KN:
-        hipLaunchKernelGGL(k_norm, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
+        hipLaunchKernelGGL(k_norm, dim3(k.grid), dim3(k.block), 0, st, d, nprob, k.remap & 2);
         break;
     case KS1: case KS2: case KS3: case KS4: case KS5:
         if (inner == P64) launch_bicg<P64>(kind, k, st, d, nprob);
@@ -359,7 +392,7 @@ void init_scalars(std::vector<Scal> &sc, int nrhs) {
 // ------------------------------------------------------------ graph cache
 struct GraphKey {
     const void *ws;
-    int dims[4], nrhs, inner, K, persistent, method;
+    int dims[4], nrhs, inner, K, persistent, method, split;
     int shp[NKIND][5];
     bool operator<(const GraphKey &o) const { return memcmp(this, &o, sizeof(*this)) < 0; }
 };
@@ -516,6 +549,10 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     fill_prob(hp, g, m0, nrhs, p, w, L);
     LaunchSet ls;
     plan_shapes(g, nrhs, p.inner, ls, hp);
+    {
+        const char *e = getenv("WD_SPLIT_FINISH");
+        ls.split = (e && *e == '1') ? 1 : 0;
+    }
     const Prob *dprob = (const Prob *)(w + L.prob);
     int *dsum = (int *)(w + L.summary);
 
@@ -555,6 +592,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     key.K = K;
     key.persistent = persistent;
     key.method = p.method;
+    key.split = ls.split;
     for (int k = 0; k < NKIND; ++k) {
         key.shp[k][0] = ls.k[k].block;
         key.shp[k][1] = ls.k[k].nr;

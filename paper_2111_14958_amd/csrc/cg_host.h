@@ -15,6 +15,7 @@ struct KindShape {
 };
 struct LaunchSet {
     KindShape k[NKIND];
+    int split = 0;     // 1: reductions finished by a separate one-block launch
 };
 
 // Byte offsets of the pieces of a solve workspace.

@@ -189,12 +189,11 @@ int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void 
     const int nsb = (g.V + blk - 1) / blk;
     const int strip = (sh.strip > 0 && sh.strip < g.L[2]) ? sh.strip : 0;
     const int od = strip | (sh.gmajor ? 1 << 16 : 0);
-    if (sh.xylds) {
-        const int np = g.L[0] * g.L[1];
+    const int np = g.L[0] * g.L[1];
+    if (sh.xylds && np <= 256) {   // else the site-blocked kernel below
         const int nrx = prec == WD_F64 ? 1 : std::min(nr, 2);
         const int ngx = (nrhs + nrx - 1) / nrx;
         const size_t lds = xy_lds_bytes(prec, nrx, np);
-        WD_CHECK(np <= 256 && lds <= 65536, WD_EINVAL, "plane-blocked operator needs Lx*Ly <= 256");
         FieldPtr fi{(void *)in, g.V, nrhs}, fo{out, g.V, nrhs};
         const void *U = gg->U[prec];
         const dim3 grid((g.V / np) * ngx);

@@ -35,24 +35,23 @@ static std::mutex g_mu;
 static std::map<ShapeKey, std::pair<Shape, double>> g_table;
 static bool g_loaded = false;
 
-// Untuned shapes.  Operator kernel: one rhs per thread (fewest registers,
-// highest occupancy; the measured best on gfx950 for 14^4 x 16 rhs).  CG phase
-// kernels: two rhs per thread in FP32 / FP16N (the link loads are shared, which
-// matters more with the extra streams of the fused updates), one in FP64.
+// Untuned shapes (the measured best on gfx950 for 14^4 x 16 rhs): XCD-
+// contiguous tiles, z-strips of 4 planes, pipelined hops, 256-thread blocks.
+// Operator kernel: the plane-blocked LDS variant (falls back to site blocks
+// when an xy-plane exceeds 256 sites), two rhs per thread in FP32 / FP16N, one
+// in FP64.  CG phase kernels: two rhs per thread in every precision.
 Shape default_shape(int prec, int nrhs, int fam) {
     Shape s;
+    s.block = 256;
     s.remap = 1;
-    s.ordered = 1;
+    s.ordered = 3;
     s.rloop = 1;
+    s.strip = 4;
     if (fam == FAM_DSLASH) {
-        // measured best for 14^4 x 16 rhs in FP32: own spinor first, pipelined hops
-        s.block = 64;
-        s.nr = 1;
-        s.remap = 0;
-        s.ordered = 4;
-    } else {
-        s.block = 256;
         s.nr = (prec == WD_F64 || nrhs < 2) ? 1 : 2;
+        s.xylds = 1;
+    } else {
+        s.nr = nrhs < 2 ? 1 : 2;
     }
     return s;
 }
@@ -190,7 +189,8 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     WD_CHECK(prec >= 0 && prec <= 2, WD_EINVAL, "unknown precision %d", prec);
     WD_CHECK(nrhs >= 1 && nrhs <= MAX_RHS, WD_EINVAL, "nrhs %d out of range", nrhs);
     WD_CHECK(family >= FAM_DSLASH && family <= FAM_CG_R, WD_EINVAL, "unknown kernel family %d", family);
-    WD_CHECK(sh->block == 64 || sh->block == 128 || sh->block == 256, WD_EINVAL, "block %d", sh->block);
+    WD_CHECK(sh->block == 64 || sh->block == 128 || sh->block == 256 || (sh->site_order >> 17), WD_EINVAL,
+             "block %d", sh->block);   // the plane-blocked variant takes the plane size
     WD_CHECK(sh->rhs_per_thread == 1 || sh->rhs_per_thread == 2 || sh->rhs_per_thread == 4, WD_EINVAL,
              "rhs_per_thread %d", sh->rhs_per_thread);
     WD_CHECK(sh->hop_order >= 0 && sh->hop_order <= 4 && sh->rhs_loop >= 1, WD_EINVAL, "bad hop order / rhs loop");
