@@ -18,8 +18,10 @@ the stand-alone operator bandwidth, a device copy ceiling and the CPU oracle.
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -28,6 +30,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "dslash GB/s (% HBM peak); CG solves/s at res 1e-10, mixed vs FP64"
 HBM_PEAK_GBPS = 8000.0
+# hardware-counter summary of the dominant kernel (FETCH_SIZE / WRITE_SIZE runs)
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_phaseB_f32_14x4_16rhs_pmc.md")
+# sources that define the phase-B kernel; the counter figures hold only for them
+KERNEL_SOURCES = ("wd_device.h", "cg_core.h", "cg.hip")
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2111_14958_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_traffic():
+    """HBM-side bytes per phase-B launch from the committed counter summary, or
+    None when it is missing or was taken on other kernel sources."""
+    try:
+        text = open(PMC_SUMMARY).read()
+    except OSError:
+        return None, "no counter summary"
+    sha = re.search(r"kernel_sources_sha256: ([0-9a-f]+)", text)
+    val = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text)
+    if not sha or not val:
+        return None, "counter summary unreadable"
+    if sha.group(1) != kernel_sources_sha256():
+        return None, "kernel changed since the counters were taken"
+    return float(val.group(1)), "FETCH_SIZE x2 + WRITE_SIZE (copy-calibrated), per launch"
 
 
 def log(*a):
@@ -40,6 +70,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 16^3x32 FP16N context run")
     ap.add_argument("--cpu-iters", type=int, default=150,
                     help="oracle CG iterations timed for the CPU baseline sample")
     args = ap.parse_args()
@@ -76,8 +107,10 @@ def main():
 
     p_mixed = wd.cg_default_params(tol=tol, inner=wd.F32, reliable_every=50)
     p_fp64 = wd.cg_default_params(tol=tol, inner=wd.F64, reliable_every=0)
-    ws = torch.empty(max(wd.cg_workspace_bytes(g, nrhs, p_mixed),
-                         wd.cg_workspace_bytes(g, nrhs, p_fp64)), dtype=torch.uint8, device=dev)
+    p_bicg = wd.cg_default_params(tol=tol, inner=wd.F32, reliable_every=50, method=wd.METHOD_BICGSTAB)
+    p_bicg64 = wd.cg_default_params(tol=tol, inner=wd.F64, reliable_every=0, method=wd.METHOD_BICGSTAB)
+    ws = torch.empty(max(wd.cg_workspace_bytes(g, nrhs, p) for p in (p_mixed, p_fp64, p_bicg, p_bicg64)),
+                     dtype=torch.uint8, device=dev)
 
     def solve(params):
         x, reps, rc = wd.cg_solve_batch(g, m0, dsrc, sol=sol, params=params, ws=ws)
@@ -128,6 +161,19 @@ def main():
     f16_value = nrhs / (time.perf_counter() - t0)
     err16 = ((sol - x64).reshape(nrhs, -1).norm(dim=1) / x64.reshape(nrhs, -1).norm(dim=1)).max().item()
 
+    # --------------------------------- BiCGSTAB on D (Sec. 1 alternative), context
+    bicg = {}
+    for name, pb in (("f32", p_bicg), ("f64", p_bicg64)):
+        solve(pb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        repsb, rcb = solve(pb)
+        torch.cuda.synchronize()
+        bicg[name] = {"solves_per_s": nrhs / (time.perf_counter() - t0), "converged": rcb == wd.WD_OK,
+                      "iters": [r["iters"] for r in repsb],
+                      "err_vs_fp64_cg_solution": ((sol - x64).reshape(nrhs, -1).norm(dim=1) /
+                                                  x64.reshape(nrhs, -1).norm(dim=1)).max().item()}
+
     # ------------------------------------ roofline of the dominant CG kernel
     wd.profile_reset()
     wd.profile_enable(True)
@@ -138,8 +184,14 @@ def main():
     dom_name = max(prof, key=lambda k: prof[k]["total_ms"])
     dom = prof[dom_name]
     dom_gbps = dom["bytes_total"] / (dom["total_ms"] * 1e-3) / 1e9
-    kernel_symbol = {"cg_phaseA": "k_phaseA<P32,NR>", "cg_phaseB": "k_phaseB<P32,NR>",
-                     "cg_phaseC": "k_phaseC<P32>"}[dom_name]
+    fam = {"cg_phaseA": wd.FAMILY_CG_A, "cg_phaseB": wd.FAMILY_CG_B}.get(dom_name)
+    if fam is not None:
+        sh = wd.shape_get(g, wd.F32, nrhs, fam == wd.FAMILY_CG_A, fam)
+        kernel_symbol = "wd::k_%s<1, %d, %d>" % (dom_name[3:], sh["rhs_per_thread"],
+                                                3 if sh["hop_order"] == 3 else 1)
+    else:
+        kernel_symbol = "wd::k_phaseC<1>"
+    traffic, traffic_note = pmc_traffic() if dom_name == "cg_phaseB" else (None, "not measured")
     per_launch = {k: {"launches": v["launches"],
                       "avg_us": 1e3 * v["total_ms"] / max(v["launches"], 1),
                       "GBps": v["bytes_total"] / max(v["total_ms"], 1e-12) / 1e6}
@@ -209,6 +261,38 @@ def main():
     copy_gbps = 2 * a.numel() * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del a, b
 
+    # ------------------- 16^3 x 32, m0 0.02, 12 point sources: FP16N vs FP64 (context)
+    c4 = None
+    if not args.no_c4:
+        c4cfg = wdgen.CONFIGS["c4_16x3x32_12rhs"]
+        log("c4 16^3x32 inputs")
+        U4 = torch.from_numpy(wdgen.gauge_field(c4cfg["dims"], c4cfg["eps"], c4cfg["gauge_seed"])).to(dev)
+        g4 = wd.Gauge(U4, c4cfg["dims"], -1)
+        src4 = torch.from_numpy(wdgen.point_sources(c4cfg["dims"])).to(dev)
+        sol4 = torch.zeros_like(src4)
+        c4 = {"workload": "16^3x32, m0 0.02, eps 0.5, 12 point sources, tol 1e-10"}
+        xs4 = {}
+        for name, pc in (("f16n", wd.cg_default_params(tol=tol, inner=wd.F16N, reliable_every=50)),
+                         ("f32", wd.cg_default_params(tol=tol, inner=wd.F32, reliable_every=50)),
+                         ("f64", wd.cg_default_params(tol=tol, inner=wd.F64, reliable_every=0))):
+            ws4 = torch.empty(wd.cg_workspace_bytes(g4, 12, pc), dtype=torch.uint8, device=dev)
+            wd.cg_solve_batch(g4, c4cfg["m0"], src4, sol=sol4, params=pc, ws=ws4)   # graph capture
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, reps4, rc4 = wd.cg_solve_batch(g4, c4cfg["m0"], src4, sol=sol4, params=pc, ws=ws4)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            xs4[name] = sol4.clone()
+            c4[name] = {"solves_per_s": 12 / dt, "converged": rc4 == wd.WD_OK,
+                        "max_true_rel_res": max(r["true_rel_res"] for r in reps4),
+                        "iters_max": max(r["iters"] for r in reps4)}
+            del ws4
+        for name in ("f16n", "f32"):
+            d4 = (xs4[name] - xs4["f64"]).reshape(12, -1).norm(dim=1) / xs4["f64"].reshape(12, -1).norm(dim=1)
+            c4[name]["err_vs_fp64_solution"] = d4.max().item()
+        c4["f16n_vs_f64_speedup"] = c4["f16n"]["solves_per_s"] / c4["f64"]["solves_per_s"]
+        del U4, g4, src4, sol4, xs4
+
     # ----------------------------------------------------- CPU oracle baseline
     cpu = None
     if not args.no_cpu:
@@ -247,7 +331,7 @@ def main():
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": kernel_symbol, "achieved": dom_gbps,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": dom_gbps / HBM_PEAK_GBPS,
-                     "traffic": None},
+                     "traffic": traffic},
         "cpu_baseline": cpu,
         "details": {
             "device": f"{arch} ({ncu} CUs)",
@@ -263,9 +347,13 @@ def main():
             "f16n_all_converged": rc16 == wd.WD_OK,
             "f16n_err_vs_fp64_solution": err16,
             "cg_kernels": per_launch,
+            "dominant_kernel_alg_bytes_per_launch": dom["bytes_total"] / max(dom["launches"], 1),
+            "traffic_note": traffic_note,
+            "bicgstab_16rhs": bicg,
             "dslash_16rhs": dslash,
             "coo_spmv_1rhs": coo,
             "copy_GBps": copy_gbps,
+            "c4_16x3x32_12rhs": c4,
         },
     }
     print(json.dumps(out), flush=True)

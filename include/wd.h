@@ -242,15 +242,21 @@ int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
  * wd_tune_result. */
 int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, int32_t family,
                  const wd_tune_result *shape);
+/* The launch shape a kernel family uses for the key (set, tuned or default);
+ * us and gbps are 0. */
+int wd_shape_get(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, int32_t family,
+                 wd_tune_result *shape);
 
 
 /* --------------------------------------------------------------- profiling */
 /* Per-kernel statistics of CG solves.  While profiling is on, wd_cg_solve*
  * launch the kernels of each chunk one by one (instead of replaying the chunk
- * graph) and bracket every phase-A/B/C launch with HIP events on the solve's
- * stream; bytes_total sums the algorithmic bytes of those launches (links once,
- * every spinor of every active right-hand side once per read or write).
- * Meant for measurement runs: it adds a host synchronisation per iteration. */
+ * graph) and bracket every phase-A/B/C tile kernel with HIP events on the
+ * solve's stream (the one-block reduction launch after A and B is outside the
+ * brackets); bytes_total sums the algorithmic bytes of those launches (links
+ * once, every spinor of every active right-hand side once per read or write).
+ * Meant for measurement runs; CG (WD_METHOD_CGNE) without the persistent
+ * kernel only. */
 typedef struct {
     char    name[32];       /* "cg_phaseA" (q = D^dagger p), "cg_phaseB" (D q + updates),
                                "cg_phaseC" (p = r + beta p)                              */

@@ -35,7 +35,7 @@ EXPORTS = [
     "wd_dslash", "wd_dslash_dag",
     "wd_coo_create", "wd_coo_destroy", "wd_coo_info", "wd_coo_export", "wd_coo_spmv",
     "wd_cg_default_params", "wd_cg_workspace_bytes", "wd_cg_solve", "wd_cg_solve_batch",
-    "wd_tune_dslash", "wd_tune_lookup", "wd_shape_set",
+    "wd_tune_dslash", "wd_tune_lookup", "wd_shape_set", "wd_shape_get",
     "wd_profile_enable", "wd_profile_reset", "wd_profile_read",
     "wd_serve_footprint", "wd_serve_create", "wd_serve_submit", "wd_serve_poll",
     "wd_serve_stats_get", "wd_serve_destroy",
@@ -143,6 +143,7 @@ def lib():
             "wd_tune_dslash": ([P, I32, I32, I32, ctypes.POINTER(TuneResult), P], ctypes.c_int),
             "wd_tune_lookup": ([P, I32, I32, I32, ctypes.POINTER(TuneResult)], ctypes.c_int),
             "wd_shape_set": ([P, I32, I32, I32, I32, ctypes.POINTER(TuneResult)], ctypes.c_int),
+            "wd_shape_get": ([P, I32, I32, I32, I32, ctypes.POINTER(TuneResult)], ctypes.c_int),
             "wd_profile_enable": ([I32], ctypes.c_int),
             "wd_profile_reset": ([], ctypes.c_int),
             "wd_profile_read": ([ctypes.POINTER(KernelStat), I32, ctypes.POINTER(I32)], ctypes.c_int),
@@ -414,6 +415,17 @@ def shape_set(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int, block: 
                    site_order=strip | (group_major << 16) | (xy_lds << 17))
     _check(lib().wd_shape_set(g.handle, prec, nrhs, 1 if dagger else 0, family, ctypes.byref(r)),
            "wd_shape_set")
+
+
+def shape_get(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int) -> dict:
+    r = TuneResult()
+    _check(lib().wd_shape_get(g.handle, prec, nrhs, 1 if dagger else 0, family, ctypes.byref(r)),
+           "wd_shape_get")
+    out = {f[0]: getattr(r, f[0]) for f in r._fields_ if f[0] not in ("us", "gbps")}
+    out["strip"] = r.site_order & 0xFFFF
+    out["group_major"] = (r.site_order >> 16) & 1
+    out["xy_lds"] = r.site_order >> 17
+    return out
 
 
 def profile_enable(on: bool = True):

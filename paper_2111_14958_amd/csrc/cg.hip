@@ -9,7 +9,6 @@
 // and replays the chunk graph until no right-hand side is active, reading back
 // one counter per replay.  BiCGSTAB (bicgstab_core.h) uses the same driver with
 // the chunk K x [S1, S2, S3, S4, S5], then R1, R2, summary.
-#include <stdlib.h>
 #include <string.h>
 
 #include <atomic>
@@ -25,10 +24,11 @@
 namespace wd {
 
 // ------------------------------------------------------------------ kernels
-// `remap` bit 0: XCD-contiguous tile order; bit 1: the phase's reduction is
-// finished by a separate k_finish launch instead of the last block.
+// `remap`: XCD-contiguous tile order.  Kernels that reduce leave their
+// per-block partial sums in the workspace; k_finish, launched after them,
+// completes the reduction.
 #define WD_KERNEL_PROLOGUE(K)                                                  \
-    const int b_ = (remap & 1) ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x; \
+    const int b_ = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x; \
     const Prob &pr = probs[find_prob(probs, nprob, K, b_)];                    \
     const int t_ = b_ - pr.t0[K];
 
@@ -36,20 +36,12 @@ template <int P, int NR, int ORD>
 __global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KA)
     phaseA_tile<P, NR, ORD>(pr, t_);
-    if (!(remap & 2) && ticket_last(pr.ticket, pr.nt[KA])) {
-        phaseA_finish(pr);
-        if (threadIdx.x == 0) *pr.ticket = 0;
-    }
 }
 
 template <int P, int NR, int ORD>
 __global__ __launch_bounds__(256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KB)
     phaseB_tile<P, NR, ORD>(pr, t_);
-    if (!(remap & 2) && ticket_last(pr.ticket, pr.nt[KB])) {
-        phaseB_finish(pr);
-        if (threadIdx.x == 0) *pr.ticket = 0;
-    }
 }
 
 template <int P>
@@ -68,24 +60,18 @@ template <int P, int NR>
 __global__ __launch_bounds__(256) void k_ru2(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KR2)
     ru2_tile<P, NR>(pr, t_);
-    if (!(remap & 2) && ticket_last(pr.ticket, pr.nt[KR2])) {
-        ru2_finish(pr);
-        if (threadIdx.x == 0) *pr.ticket = 0;
-    }
 }
 
 __global__ __launch_bounds__(256) void k_norm(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KN)
     norm_tile(pr, t_);
-    if (!(remap & 2) && ticket_last(pr.ticket, pr.nt[KN])) {
-        norm_finish(pr);
-        if (threadIdx.x == 0) *pr.ticket = 0;
-    }
 }
 
 // The reduction of a phase as a launch of its own (one block): the kernel
-// boundary makes every block's partial sums visible, so the tile kernels need
-// no device-wide fence and no ticket.
+// boundary makes every block's partial sums visible.  (Finishing it in the
+// last block of the phase instead, found with an atomic ticket, needs a
+// device-scope release fence in every block, which on a multi-XCD GPU writes
+// back the XCD's L2 each time: the whole CG ran 1.4x slower that way.)
 __global__ __launch_bounds__(256) void k_finish(const Prob *__restrict__ probs, int nprob, int kind) {
     for (int j = 0; j < nprob; ++j) {
         const Prob &pr = probs[j];
@@ -128,11 +114,6 @@ __global__ __launch_bounds__(256) void k_bi_stencil(const Prob *__restrict__ pro
     constexpr int K = S4 ? KS4 : KS2;
     WD_KERNEL_PROLOGUE(K)
     bi_stencil_tile<P, NR, S4>(pr, t_);
-    if (!(remap & 2) && ticket_last(pr.ticket, pr.nt[K])) {
-        if (S4) bi4_finish(pr);
-        else bi2_finish(pr);
-        if (threadIdx.x == 0) *pr.ticket = 0;
-    }
 }
 
 template <int P>
@@ -145,10 +126,6 @@ template <int P>
 __global__ __launch_bounds__(256) void k_bi5(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KS5)
     bi5_tile<P>(pr, t_);
-    if (!(remap & 2) && ticket_last(pr.ticket, pr.nt[KS5])) {
-        bi5_finish(pr);
-        if (threadIdx.x == 0) *pr.ticket = 0;
-    }
 }
 
 // x_lo <- 0 (a fill kernel rather than a memset, so it can sit in a graph)
@@ -200,21 +177,23 @@ static void launch_bicg(int kind, const KindShape &k, hipStream_t st, const Prob
     case KS2: launch_BS<P, false>(k.nr, k.grid, k.block, st, d, n, k.remap); break;
     case KS3: hipLaunchKernelGGL(k_bi3<P>, dim3(k.grid), dim3(k.block), 0, st, d, n, 0); break;
     case KS4: launch_BS<P, true>(k.nr, k.grid, k.block, st, d, n, k.remap); break;
-    case KS5: hipLaunchKernelGGL(k_bi5<P>, dim3(k.grid), dim3(k.block), 0, st, d, n, k.remap & 2); break;
+    case KS5: hipLaunchKernelGGL(k_bi5<P>, dim3(k.grid), dim3(k.block), 0, st, d, n, 0); break;
     }
 }
 
 static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream_t st, const Prob *d, int nprob);
 
+static void launch_finish(int kind, hipStream_t st, const Prob *d, int nprob) {
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, d, nprob, kind);
+}
+
 void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob) {
-    KindShape k = ls.k[kind];
+    const KindShape &k = ls.k[kind];
     if (k.grid <= 0) return;
     const bool reduces = kind == KA || kind == KB || kind == KR2 || kind == KN || kind == KS2 || kind == KS4 ||
                          kind == KS5;
-    const bool split = reduces && ls.split;
-    if (split) k.remap |= 2;
     launch_kind_tiles(kind, inner, k, st, d, nprob);
-    if (split) hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, d, nprob, kind);
+    if (reduces) launch_finish(kind, st, d, nprob);
 }
 
 static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream_t st, const Prob *d, int nprob) {
@@ -245,7 +224,7 @@ static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream
         else launch_R2<P16>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
         break;
     case KN:
-        hipLaunchKernelGGL(k_norm, dim3(k.grid), dim3(k.block), 0, st, d, nprob, k.remap & 2);
+        hipLaunchKernelGGL(k_norm, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
         break;
     case KS1: case KS2: case KS3: case KS4: case KS5:
         if (inner == P64) launch_bicg<P64>(kind, k, st, d, nprob);
@@ -273,7 +252,7 @@ WsLayout ws_layout(int64_t V, int nrhs, int inner, int method) {
     size_t o = 0;
     L.prob = o; o += al256(sizeof(Prob));
     L.scal = o; o += al256(sizeof(Scal) * nrhs);
-    L.ticket = o; o += 256;
+    L.bar = o; o += 256;
     L.summary = o; o += 256;
     L.part = o; o += al256((size_t)((V + 63) / 64) * nrhs * PSTRIDE * sizeof(double));
     L.eta64 = o; o += al256(spinor_bytes(WD_F64, V, nrhs));
@@ -369,7 +348,6 @@ void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_par
     pr.x64 = ws + L.x64;
     pr.eta64 = ws + L.eta64;
     pr.part = (double *)(ws + L.part);
-    pr.ticket = (unsigned *)(ws + L.ticket);
     pr.sc = (Scal *)(ws + L.scal);
     pr.v = ws + L.q;
     pr.rh = L.rh ? ws + L.rh : nullptr;
@@ -392,7 +370,7 @@ void init_scalars(std::vector<Scal> &sc, int nrhs) {
 // ------------------------------------------------------------ graph cache
 struct GraphKey {
     const void *ws;
-    int dims[4], nrhs, inner, K, persistent, method, split;
+    int dims[4], nrhs, inner, K, persistent, method;
     int shp[NKIND][5];
     bool operator<(const GraphKey &o) const { return memcmp(this, &o, sizeof(*this)) < 0; }
 };
@@ -475,7 +453,7 @@ static ProfEntry g_prof[3];   // phases A, B, C
 static const char *g_prof_names[3] = {"cg_phaseA", "cg_phaseB", "cg_phaseC"};
 
 // One chunk launched kernel by kernel, back to back, with events around
-// every phase-A/B/C launch.  The number of fields that iterated in each
+// every phase-A/B/C tile kernel.  The number of fields that iterated in each
 // launch is recovered after the chunk from the per-field iteration counters:
 // an active field iterates without gaps from the start of the chunk until it
 // freezes, so field i took part in iteration j of the chunk iff j < d_i, where
@@ -483,7 +461,7 @@ static const char *g_prof_names[3] = {"cg_phaseA", "cg_phaseB", "cg_phaseC"};
 // the iteration in which it froze).
 static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *dprob, int K,
                           int nrhs, int64_t V, void *dscal) {
-    std::vector<hipEvent_t> ev(3 * K + 1);
+    std::vector<hipEvent_t> ev(6 * K);   // start and end of every A, B, C tile kernel
     for (auto &e : ev) WD_HIP(hipEventCreate(&e));
     std::vector<Scal> before(nrhs), after(nrhs);
     const double G = (double)link_bytes(inner, V);
@@ -494,14 +472,14 @@ static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const 
         hipStreamSynchronize(st) != hipSuccess)
         rc = fail(WD_EHIP, "profiling copy failed");
     if (!rc) {
-        hipEventRecord(ev[0], st);
         for (int it = 0; it < K; ++it) {
-            launch_kind(KA, inner, ls, st, dprob, 1);
-            hipEventRecord(ev[3 * it + 1], st);
-            launch_kind(KB, inner, ls, st, dprob, 1);
-            hipEventRecord(ev[3 * it + 2], st);
-            launch_kind(KC, inner, ls, st, dprob, 1);
-            hipEventRecord(ev[3 * it + 3], st);
+            const int kinds[3] = {KA, KB, KC};
+            for (int q = 0; q < 3; ++q) {
+                hipEventRecord(ev[6 * it + 2 * q], st);
+                launch_kind_tiles(kinds[q], inner, ls.k[kinds[q]], st, dprob, 1);
+                hipEventRecord(ev[6 * it + 2 * q + 1], st);
+                if (kinds[q] != KC) launch_finish(kinds[q], st, dprob, 1);
+            }
         }
         if (hipMemcpyAsync(after.data(), dscal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
@@ -525,7 +503,7 @@ static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const 
             for (int k = 0; k < 3; ++k) {
                 if (cnt[k] == 0) continue;
                 float ms = 0;
-                hipEventElapsedTime(&ms, ev[3 * it + k], ev[3 * it + k + 1]);
+                hipEventElapsedTime(&ms, ev[6 * it + 2 * k], ev[6 * it + 2 * k + 1]);
                 g_prof[k].launches += 1;
                 g_prof[k].ms += ms;
                 g_prof[k].bytes += bytes[k];
@@ -549,10 +527,6 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     fill_prob(hp, g, m0, nrhs, p, w, L);
     LaunchSet ls;
     plan_shapes(g, nrhs, p.inner, ls, hp);
-    {
-        const char *e = getenv("WD_SPLIT_FINISH");
-        ls.split = (e && *e == '1') ? 1 : 0;
-    }
     const Prob *dprob = (const Prob *)(w + L.prob);
     int *dsum = (int *)(w + L.summary);
 
@@ -566,7 +540,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     init_scalars(sc, nrhs);
     WD_HIP(hipMemcpyAsync((void *)dprob, &hp, sizeof(hp), hipMemcpyHostToDevice, st));
     WD_HIP(hipMemcpyAsync(w + L.scal, sc.data(), sizeof(Scal) * nrhs, hipMemcpyHostToDevice, st));
-    WD_HIP(hipMemsetAsync(w + L.ticket, 0, 256, st));
+    WD_HIP(hipMemsetAsync(w + L.bar, 0, 256, st));
     // fields
     int rc = launch_pack_spinor(WD_F64, src, w + L.eta64, (int)V, nrhs, st);
     if (rc) return rc;
@@ -579,7 +553,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     launch_kind(KN, p.inner, ls, st, dprob, 1);
     launch_kind(KR2, p.inner, ls, st, dprob, 1);
     if (!bicg) launch_kind(KC, p.inner, ls, st, dprob, 1);
-    const int *dabort = persistent ? (const int *)(w + L.ticket + 128) : nullptr;
+    const int *dabort = persistent ? (const int *)(w + L.bar + 128) : nullptr;
     launch_summary(st, dprob, 1, dsum, dabort);
     WD_HIP(hipGetLastError());
 
@@ -592,7 +566,6 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     key.K = K;
     key.persistent = persistent;
     key.method = p.method;
-    key.split = ls.split;
     for (int k = 0; k < NKIND; ++k) {
         key.shp[k][0] = ls.k[k].block;
         key.shp[k][1] = ls.k[k].nr;
@@ -611,7 +584,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
             launch_summary(cs, dprob, 1, dsum, dabort);
             return;
         }
-        if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, K, w + L.ticket + 64);
+        if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, K, w + L.bar + 64);
         else
             for (int it = 0; it < K; ++it) {
                 launch_kind(KA, p.inner, ls, cs, dprob, 1);

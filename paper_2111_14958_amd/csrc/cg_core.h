@@ -8,8 +8,8 @@
 //     A  q = D^dagger p                     + partial sums of |q|^2   -> alpha
 //     B  t = D q, r -= alpha t, x += alpha q + partial sums of |r|^2   -> beta
 //     C  p = r + beta p
-// Every scalar lives in device memory, one record per right-hand side; the
-// last block of a phase (an atomic ticket) sums the per-block partials in a
+// Every scalar lives in device memory, one record per right-hand side; a
+// one-block launch after each reducing phase sums the per-block partials in a
 // fixed order and updates the scalars, so nothing returns to the host inside
 // an iteration and reductions are bitwise reproducible.
 //
@@ -75,7 +75,6 @@ struct alignas(16) Prob {
     void *x_lo, *r, *p, *q;   // inner-precision vectors (x_lo: FP32 for FP16N)
     void *x64, *eta64;        // FP64 packed vectors
     double *part;             // [nsb][nrhs][PSTRIDE] partial sums of the current phase
-    unsigned *ticket;         // block counter of the current phase (self-resetting)
     Scal *sc;                 // [nrhs]
     void *rh, *v, *sv, *tv;   // BiCGSTAB: shadow residual r_hat, v = D p, s, t = D s
     BScal *bs;                // BiCGSTAB scalars [nrhs]
@@ -112,21 +111,6 @@ __device__ __forceinline__ void block_sum(double v[NR]) {
         }
     }
     __syncthreads();
-}
-
-// After thread 0 has written this block's partials: count the block in the
-// problem's ticket; returns true (in every thread) for the last block of the
-// phase, which then sees every other block's partials.
-__device__ __forceinline__ bool ticket_last(unsigned *ticket, unsigned total) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned t = atomicAdd(ticket, 1u);
-        last = (t == total - 1);
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
 }
 
 // Fixed-order sum over site blocks of partial k of column i; valid on thread 0.

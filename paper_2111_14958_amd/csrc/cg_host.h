@@ -15,12 +15,11 @@ struct KindShape {
 };
 struct LaunchSet {
     KindShape k[NKIND];
-    int split = 0;     // 1: reductions finished by a separate one-block launch
 };
 
 // Byte offsets of the pieces of a solve workspace.
 struct WsLayout {
-    size_t prob, scal, ticket, summary, part, eta64, x64, xlo, r, p, q;
+    size_t prob, scal, bar, summary, part, eta64, x64, xlo, r, p, q;
     size_t bscal, rh, sv, tv;   // BiCGSTAB only (0 otherwise)
     size_t total;
 };

@@ -195,7 +195,7 @@ static int init_slot(wd_server *s, Slot &sl) {
     init_scalars(sl.sc, rq.nrhs);
     WD_HIP(hipMemcpyAsync(w + L.prob, &sl.prob, sizeof(Prob), hipMemcpyHostToDevice, st));
     WD_HIP(hipMemcpyAsync(w + L.scal, sl.sc.data(), sizeof(Scal) * rq.nrhs, hipMemcpyHostToDevice, st));
-    WD_HIP(hipMemsetAsync(w + L.ticket, 0, 256, st));
+    WD_HIP(hipMemsetAsync(w + L.bar, 0, 256, st));
     rc = launch_pack_spinor(WD_F64, rq.src_dev, w + L.eta64, (int)V, rq.nrhs, st);
     if (rc) return rc;
     if (rq.params.use_x0) rc = launch_pack_spinor(WD_F64, rq.sol_dev, w + L.x64, (int)V, rq.nrhs, st);

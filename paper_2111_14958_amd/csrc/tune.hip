@@ -182,6 +182,23 @@ int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     return WD_OK;
 }
 
+int wd_shape_get(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, int32_t family,
+                 wd_tune_result *cfg) {
+    clear_error();
+    WD_CHECK(g && cfg, WD_EINVAL, "null argument");
+    WD_CHECK(family >= FAM_DSLASH && family <= FAM_CG_R, WD_EINVAL, "unknown kernel family %d", family);
+    ShapeKey k{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, prec, nrhs, dagger ? 1 : 0, family};
+    const Shape s = shape_lookup(k);
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->block = s.block;
+    cfg->rhs_per_thread = s.nr;
+    cfg->xcd_remap = s.remap;
+    cfg->hop_order = s.ordered;
+    cfg->rhs_loop = s.rloop;
+    cfg->site_order = s.strip | (s.gmajor << 16) | (s.xylds << 17);
+    return WD_OK;
+}
+
 int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, int32_t family,
                  const wd_tune_result *sh) {
     clear_error();
