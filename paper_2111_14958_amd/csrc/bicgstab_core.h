@@ -126,33 +126,28 @@ __device__ __forceinline__ void bi_stencil_tile(const Prob &pr, int t) {
 }
 
 __device__ __forceinline__ void bi2_finish(const Prob &pr) {
-    for (int i = 0; i < pr.nrhs; ++i) {
+    __shared__ double sums[MAX_SUMS];
+    sum_all(pr, pr.nsb[KS2], 2, sums);
+    for (int i = threadIdx.x; i < pr.nrhs; i += blockDim.x) {
         Scal &c = pr.sc[i];
-        const int stt = c.state;
-        if (stt == ST_ACTIVE) {
-            const double re = sum_partials(pr, pr.nsb[KS2], i, 0);
-            const double im = sum_partials(pr, pr.nsb[KS2], i, 1);
-            if (threadIdx.x == 0) {
-                const dc rv = {re, im};
-                if (!dfinite(rv) || (rv.re == 0.0 && rv.im == 0.0)) c.state = ST_BREAKDOWN;
-                else st(pr.bs[i].alpha, ddiv(ld(pr.bs[i].rho), rv));
-            }
+        if (c.state == ST_ACTIVE) {
+            const dc rv = {sums[2 * i], sums[2 * i + 1]};
+            if (!dfinite(rv) || (rv.re == 0.0 && rv.im == 0.0)) c.state = ST_BREAKDOWN;
+            else st(pr.bs[i].alpha, ddiv(ld(pr.bs[i].rho), rv));
         }
-        if (threadIdx.x == 0) {
-            c.pending_p = 0;
-            c.restart = 0;
-        }
+        c.pending_p = 0;
+        c.restart = 0;
     }
 }
 
 __device__ __forceinline__ void bi4_finish(const Prob &pr) {
-    for (int i = 0; i < pr.nrhs; ++i) {
+    __shared__ double sums[MAX_SUMS];
+    sum_all(pr, pr.nsb[KS4], 3, sums);
+    for (int i = threadIdx.x; i < pr.nrhs; i += blockDim.x) {
         Scal &c = pr.sc[i];
         if (c.state != ST_ACTIVE) continue;
-        const double re = sum_partials(pr, pr.nsb[KS4], i, 0);
-        const double im = sum_partials(pr, pr.nsb[KS4], i, 1);
-        const double tt = sum_partials(pr, pr.nsb[KS4], i, 2);
-        if (threadIdx.x == 0) {
+        const double re = sums[3 * i], im = sums[3 * i + 1], tt = sums[3 * i + 2];
+        {
             const dc w = {re / tt, im / tt};
             if (!finite_pos(tt) || !dfinite(w) || (w.re == 0.0 && w.im == 0.0)) c.state = ST_BREAKDOWN;
             else st(pr.bs[i].omega, w);
@@ -225,13 +220,13 @@ __device__ __forceinline__ void bi5_tile(const Prob &pr, int t) {
 }
 
 __device__ __forceinline__ void bi5_finish(const Prob &pr) {
-    for (int i = 0; i < pr.nrhs; ++i) {
+    __shared__ double sums[MAX_SUMS];
+    sum_all(pr, pr.nsb[KS5], 3, sums);
+    for (int i = threadIdx.x; i < pr.nrhs; i += blockDim.x) {
         Scal &c = pr.sc[i];
         if (c.state != ST_ACTIVE) continue;
-        const double re = sum_partials(pr, pr.nsb[KS5], i, 0);
-        const double im = sum_partials(pr, pr.nsb[KS5], i, 1);
-        const double r2 = sum_partials(pr, pr.nsb[KS5], i, 2);
-        if (threadIdx.x == 0) {
+        const double re = sums[3 * i], im = sums[3 * i + 1], r2 = sums[3 * i + 2];
+        {
             BScal &b = pr.bs[i];
             const dc rho_new = {re, im};
             st(b.rho_old, ld(b.rho));

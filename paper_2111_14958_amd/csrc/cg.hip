@@ -18,6 +18,8 @@
 #include <tuple>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "bicgstab_core.h"
 #include "cg_host.h"
 
@@ -135,18 +137,28 @@ __global__ void k_zero(uint4 *p, size_t n16) {
 }
 
 // ------------------------------------------------------------- launchers
+// Profiling: while set, phase A/B/C tile kernels are launched with these
+// start/stop events, which the runtime records at the kernel's own begin and
+// end (no marker packets around the launch).
+static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+#define WD_TIMED_LAUNCH(K, grid, blk, st, ...)                                                   \
+    do {                                                                                       \
+        if (t_ev_start) hipExtLaunchKernelGGL(K, grid, blk, 0, st, t_ev_start, t_ev_stop, 0, __VA_ARGS__); \
+        else hipLaunchKernelGGL(K, grid, blk, 0, st, __VA_ARGS__);                              \
+    } while (0)
+
 // hop order 3 (pipelined) or 1 (one hop at a time) for the phase kernels
 template <int P, int ORD>
 static void launch_A_o(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (nr == 1) hipLaunchKernelGGL((k_phaseA<P, 1, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else if (nr == 2) hipLaunchKernelGGL((k_phaseA<P, 2, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else hipLaunchKernelGGL((k_phaseA<P, 4, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    if (nr == 1) WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
+    else if (nr == 2) WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
+    else WD_TIMED_LAUNCH((k_phaseA<P, 4, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
 }
 template <int P, int ORD>
 static void launch_B_o(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (nr == 1) hipLaunchKernelGGL((k_phaseB<P, 1, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else if (nr == 2) hipLaunchKernelGGL((k_phaseB<P, 2, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else hipLaunchKernelGGL((k_phaseB<P, 4, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    if (nr == 1) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
+    else if (nr == 2) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
+    else WD_TIMED_LAUNCH((k_phaseB<P, 4, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
 }
 template <int P>
 static void launch_A(int nr, int ord, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
@@ -209,9 +221,9 @@ static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream
         else launch_B<P16>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
         break;
     case KC:
-        if (inner == P64) hipLaunchKernelGGL(k_phaseC<P64>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
-        else if (inner == P32) hipLaunchKernelGGL(k_phaseC<P32>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
-        else hipLaunchKernelGGL(k_phaseC<P16>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
+        if (inner == P64) WD_TIMED_LAUNCH(k_phaseC<P64>, dim3(k.grid), dim3(k.block), st, d, nprob, 0);
+        else if (inner == P32) WD_TIMED_LAUNCH(k_phaseC<P32>, dim3(k.grid), dim3(k.block), st, d, nprob, 0);
+        else WD_TIMED_LAUNCH(k_phaseC<P16>, dim3(k.grid), dim3(k.block), st, d, nprob, 0);
         break;
     case KR1:
         if (inner == P64) hipLaunchKernelGGL(k_ru1<P64>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
@@ -452,8 +464,8 @@ struct ProfEntry {
 static ProfEntry g_prof[3];   // phases A, B, C
 static const char *g_prof_names[3] = {"cg_phaseA", "cg_phaseB", "cg_phaseC"};
 
-// One chunk launched kernel by kernel, back to back, with events around
-// every phase-A/B/C tile kernel.  The number of fields that iterated in each
+// One chunk launched kernel by kernel, back to back, every phase-A/B/C tile
+// kernel launched with start/stop events.  The number of fields that iterated in each
 // launch is recovered after the chunk from the per-field iteration counters:
 // an active field iterates without gaps from the start of the chunk until it
 // freezes, so field i took part in iteration j of the chunk iff j < d_i, where
@@ -475,9 +487,10 @@ static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const 
         for (int it = 0; it < K; ++it) {
             const int kinds[3] = {KA, KB, KC};
             for (int q = 0; q < 3; ++q) {
-                hipEventRecord(ev[6 * it + 2 * q], st);
+                t_ev_start = ev[6 * it + 2 * q];
+                t_ev_stop = ev[6 * it + 2 * q + 1];
                 launch_kind_tiles(kinds[q], inner, ls.k[kinds[q]], st, dprob, 1);
-                hipEventRecord(ev[6 * it + 2 * q + 1], st);
+                t_ev_start = t_ev_stop = nullptr;
                 if (kinds[q] != KC) launch_finish(kinds[q], st, dprob, 1);
             }
         }

@@ -113,13 +113,21 @@ __device__ __forceinline__ void block_sum(double v[NR]) {
     __syncthreads();
 }
 
-// Fixed-order sum over site blocks of partial k of column i; valid on thread 0.
-__device__ __forceinline__ double sum_partials(const Prob &pr, int nsb, int i, int k = 0) {
-    double s[1] = {0.0};
-    for (int b = threadIdx.x; b < nsb; b += blockDim.x)
-        s[0] += pr.part[((size_t)b * pr.nrhs + i) * PSTRIDE + k];
-    block_sum<1>(s);
-    return s[0];
+// Fixed-order sums over the site blocks of partials 0..nk-1 of every column:
+// one wavefront per (column, partial), lane l adding blocks l, l+64, ... in
+// order, then a butterfly.  sums[i * nk + k] is valid in every thread on
+// return.  The block size must be a multiple of 64.
+constexpr int MAX_SUMS = 64 * 3;
+__device__ __forceinline__ void sum_all(const Prob &pr, int nsb, int nk, double *sums) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int job = w; job < pr.nrhs * nk; job += nw) {
+        const int i = job / nk, k = job - i * nk;
+        double x = 0.0;
+        for (int b = lane; b < nsb; b += 64) x += pr.part[((size_t)b * pr.nrhs + i) * PSTRIDE + k];
+        x = wave_sum(x);
+        if (lane == 0) sums[job] = x;
+    }
+    __syncthreads();
 }
 
 __device__ __forceinline__ double &part_at(const Prob &pr, int sb, int i, int k) {
@@ -201,22 +209,21 @@ __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
     }
 }
 
+// The finish functions run in one block; thread i updates the scalars of
+// right-hand side i.
 __device__ __forceinline__ void phaseA_finish(const Prob &pr) {
-    for (int i = 0; i < pr.nrhs; ++i) {
+    __shared__ double sums[MAX_SUMS];
+    sum_all(pr, pr.nsb[KA], 1, sums);
+    for (int i = threadIdx.x; i < pr.nrhs; i += blockDim.x) {
         Scal &c = pr.sc[i];
-        const int st = c.state;   // uniform
-        if (st == ST_ACTIVE) {
-            const double sigma = sum_partials(pr, pr.nsb[KA], i);
-            if (threadIdx.x == 0) {
-                c.sigma = sigma;
-                if (!finite_pos(sigma)) c.state = ST_BREAKDOWN;
-                else c.alpha = c.rho / sigma;
-            }
+        if (c.state == ST_ACTIVE) {
+            const double sigma = sums[i];
+            c.sigma = sigma;
+            if (!finite_pos(sigma)) c.state = ST_BREAKDOWN;
+            else c.alpha = c.rho / sigma;
         }
-        if (threadIdx.x == 0) {
-            c.pending_p = 0;
-            c.restart = 0;
-        }
+        c.pending_p = 0;
+        c.restart = 0;
     }
 }
 
@@ -274,11 +281,13 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
 }
 
 __device__ __forceinline__ void phaseB_finish(const Prob &pr) {
-    for (int i = 0; i < pr.nrhs; ++i) {
+    __shared__ double sums[MAX_SUMS];
+    sum_all(pr, pr.nsb[KB], 1, sums);
+    for (int i = threadIdx.x; i < pr.nrhs; i += blockDim.x) {
         Scal &c = pr.sc[i];
-        if (c.state != ST_ACTIVE) continue;   // uniform
-        const double rho = sum_partials(pr, pr.nsb[KB], i);
-        if (threadIdx.x == 0) {
+        if (c.state != ST_ACTIVE) continue;
+        const double rho = sums[i];
+        {
             c.rho_old = c.rho;
             c.rho = rho;
             c.beta = rho / c.rho_old;
@@ -386,16 +395,18 @@ __device__ __forceinline__ void ru2_tile(const Prob &pr, int t) {
 }
 
 __device__ __forceinline__ void ru2_finish(const Prob &pr) {
-    for (int i = 0; i < pr.nrhs; ++i) {
+    __shared__ double sums[MAX_SUMS];
+    sum_all(pr, pr.nsb[KR2], 1, sums);
+    for (int i = threadIdx.x; i < pr.nrhs; i += blockDim.x) {
         Scal &c = pr.sc[i];
         if (c.state != ST_FROZEN) {
             // CG: the chunk's last phase C has consumed the flag.  BiCGSTAB: a
             // field still iterating keeps it for the next p update.
-            if (threadIdx.x == 0 && pr.method == METHOD_CGNE) c.pending_p = 0;
+            if (pr.method == METHOD_CGNE) c.pending_p = 0;
             continue;
         }
-        const double r2 = sum_partials(pr, pr.nsb[KR2], i);
-        if (threadIdx.x == 0) {
+        const double r2 = sums[i];
+        {
             c.true2 = r2;
             c.n_ru += 1;
             c.since_ru = 0;
@@ -440,9 +451,11 @@ __device__ __forceinline__ void norm_tile(const Prob &pr, int t) {
 }
 
 __device__ __forceinline__ void norm_finish(const Prob &pr) {
-    for (int i = 0; i < pr.nrhs; ++i) {
-        const double e2 = sum_partials(pr, pr.nsb[KN], i);
-        if (threadIdx.x == 0) {
+    __shared__ double sums[MAX_SUMS];
+    sum_all(pr, pr.nsb[KN], 1, sums);
+    for (int i = threadIdx.x; i < pr.nrhs; i += blockDim.x) {
+        const double e2 = sums[i];
+        {
             Scal &c = pr.sc[i];
             c.eta2 = e2;
             c.stop2 = pr.tol2 * e2;
