@@ -122,8 +122,19 @@ __device__ __forceinline__ void sum_all(const Prob &pr, int nsb, int nk, double 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int job = w; job < pr.nrhs * nk; job += nw) {
         const int i = job / nk, k = job - i * nk;
+        const double *col = pr.part + (size_t)i * PSTRIDE + k;
+        const size_t bs = (size_t)pr.nrhs * PSTRIDE;   // stride between site blocks
         double x = 0.0;
-        for (int b = lane; b < nsb; b += 64) x += pr.part[((size_t)b * pr.nrhs + i) * PSTRIDE + k];
+        int b = lane;
+        for (; b + 192 < nsb; b += 256) {   // four loads in flight, summed in order
+            const double a0 = col[b * bs], a1 = col[(b + 64) * bs], a2 = col[(b + 128) * bs],
+                         a3 = col[(b + 192) * bs];
+            x += a0;
+            x += a1;
+            x += a2;
+            x += a3;
+        }
+        for (; b < nsb; b += 64) x += col[b * bs];
         x = wave_sum(x);
         if (lane == 0) sums[job] = x;
     }
