@@ -250,9 +250,11 @@ int wd_shape_get(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
 
 /* --------------------------------------------------------------- profiling */
 /* Per-kernel statistics of CG solves.  While profiling is on, wd_cg_solve*
- * replay a chunk graph that holds a HIP event-record node before and after
- * every phase-A/B/C tile kernel (the one-block reduction launch after A and B
- * is outside them) and read the events after each replay; bytes_total sums the algorithmic bytes of those launches (links
+ * launch the kernels of each chunk one by one (instead of replaying the chunk
+ * graph) and launch every phase-A/B/C tile kernel with HIP start/stop events
+ * on the solve's stream, recorded at the kernel's own begin and end (the
+ * one-block reduction launch after A and B is not included).  Launched one by
+ * one, the kernels run somewhat slower than inside the graph.  bytes_total sums the algorithmic bytes of those launches (links
  * once, every spinor of every active right-hand side once per read or write).
  * Meant for measurement runs; CG (WD_METHOD_CGNE) without the persistent
  * kernel only. */

@@ -18,6 +18,8 @@
 #include <tuple>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "bicgstab_core.h"
 #include "cg_host.h"
 
@@ -135,18 +137,28 @@ __global__ void k_zero(uint4 *p, size_t n16) {
 }
 
 // ------------------------------------------------------------- launchers
+// Profiling: while set, phase A/B/C tile kernels are launched with these
+// start/stop events, which the runtime records at the kernel's own begin and
+// end (no marker packets around the launch).
+static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+#define WD_TIMED_LAUNCH(K, grid, blk, st, ...)                                                   \
+    do {                                                                                       \
+        if (t_ev_start) hipExtLaunchKernelGGL(K, grid, blk, 0, st, t_ev_start, t_ev_stop, 0, __VA_ARGS__); \
+        else hipLaunchKernelGGL(K, grid, blk, 0, st, __VA_ARGS__);                              \
+    } while (0)
+
 // hop order 3 (pipelined) or 1 (one hop at a time) for the phase kernels
 template <int P, int ORD>
 static void launch_A_o(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (nr == 1) hipLaunchKernelGGL((k_phaseA<P, 1, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else if (nr == 2) hipLaunchKernelGGL((k_phaseA<P, 2, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else hipLaunchKernelGGL((k_phaseA<P, 4, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    if (nr == 1) WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
+    else if (nr == 2) WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
+    else WD_TIMED_LAUNCH((k_phaseA<P, 4, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
 }
 template <int P, int ORD>
 static void launch_B_o(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (nr == 1) hipLaunchKernelGGL((k_phaseB<P, 1, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else if (nr == 2) hipLaunchKernelGGL((k_phaseB<P, 2, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else hipLaunchKernelGGL((k_phaseB<P, 4, ORD>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    if (nr == 1) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
+    else if (nr == 2) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
+    else WD_TIMED_LAUNCH((k_phaseB<P, 4, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
 }
 template <int P>
 static void launch_A(int nr, int ord, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
@@ -209,9 +221,9 @@ static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream
         else launch_B<P16>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
         break;
     case KC:
-        if (inner == P64) hipLaunchKernelGGL(k_phaseC<P64>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
-        else if (inner == P32) hipLaunchKernelGGL(k_phaseC<P32>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
-        else hipLaunchKernelGGL(k_phaseC<P16>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
+        if (inner == P64) WD_TIMED_LAUNCH(k_phaseC<P64>, dim3(k.grid), dim3(k.block), st, d, nprob, 0);
+        else if (inner == P32) WD_TIMED_LAUNCH(k_phaseC<P32>, dim3(k.grid), dim3(k.block), st, d, nprob, 0);
+        else WD_TIMED_LAUNCH(k_phaseC<P16>, dim3(k.grid), dim3(k.block), st, d, nprob, 0);
         break;
     case KR1:
         if (inner == P64) hipLaunchKernelGGL(k_ru1<P64>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
@@ -452,78 +464,67 @@ struct ProfEntry {
 static ProfEntry g_prof[3];   // phases A, B, C
 static const char *g_prof_names[3] = {"cg_phaseA", "cg_phaseB", "cg_phaseC"};
 
-// Profiling: the chunk graph with an event-record node before and after every
-// phase-A/B/C tile kernel (the one-block reduction launches stay outside), so
-// the kernels run as in the timed graph.  The number of fields that iterated
-// in each launch is recovered after the replay from the per-field counters: an
-// active field iterates without gaps from the start of the chunk until it
-// freezes, so field i took part in iteration j iff j < d_i, its iteration count
-// advance over the chunk, and it skipped phase C of its last iteration iff it
-// froze (the chunk's reliable update then advanced its update count).
-struct ProfGraph {
-    std::vector<hipEvent_t> ev;   // start and end of every A, B, C tile kernel
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    ~ProfGraph() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        for (auto &e : ev) (void)hipEventDestroy(e);
-    }
-};
-
-static int prof_capture(ProfGraph &pg, int inner, const LaunchSet &ls, const Prob *dprob, int K, int *dsum) {
-    pg.ev.assign(6 * K, nullptr);
-    for (auto &e : pg.ev) WD_HIP(hipEventCreate(&e));
-    hipStream_t cs = capture_stream();
-    WD_CHECK(cs, WD_EHIP, "could not create the capture stream");
-    WD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    const int kinds[3] = {KA, KB, KC};
-    for (int it = 0; it < K; ++it)
-        for (int q = 0; q < 3; ++q) {
-            hipEventRecord(pg.ev[6 * it + 2 * q], cs);
-            launch_kind_tiles(kinds[q], inner, ls.k[kinds[q]], cs, dprob, 1);
-            hipEventRecord(pg.ev[6 * it + 2 * q + 1], cs);
-            if (kinds[q] != KC) launch_finish(kinds[q], cs, dprob, 1);
-        }
-    launch_kind(KR1, inner, ls, cs, dprob, 1);
-    launch_kind(KR2, inner, ls, cs, dprob, 1);
-    launch_kind(KC, inner, ls, cs, dprob, 1);
-    launch_summary(cs, dprob, 1, dsum, nullptr);
-    hipError_t err = hipStreamEndCapture(cs, &pg.graph);
-    if (err != hipSuccess) return fail(WD_EHIP, "profiling graph capture failed: %s", hipGetErrorString(err));
-    err = hipGraphInstantiate(&pg.exec, pg.graph, nullptr, nullptr, 0);
-    if (err != hipSuccess) return fail(WD_EHIP, "profiling graph instantiation failed: %s", hipGetErrorString(err));
-    return WD_OK;
-}
-
-static void prof_account(const ProfGraph &pg, const std::vector<Scal> &before, const std::vector<Scal> &after,
-                         int inner, int K, int nrhs, int64_t V) {
+// One chunk launched kernel by kernel, back to back, every phase-A/B/C tile
+// kernel launched with start/stop events.  The number of fields that iterated in each
+// launch is recovered after the chunk from the per-field iteration counters:
+// an active field iterates without gaps from the start of the chunk until it
+// freezes, so field i took part in iteration j of the chunk iff j < d_i, where
+// d_i is its iteration count advance over the chunk (and skipped phase C of
+// the iteration in which it froze).
+static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *dprob, int K,
+                          int nrhs, int64_t V, void *dscal) {
+    std::vector<hipEvent_t> ev(6 * K);   // start and end of every A, B, C tile kernel
+    for (auto &e : ev) WD_HIP(hipEventCreate(&e));
+    std::vector<Scal> before(nrhs), after(nrhs);
     const double G = (double)link_bytes(inner, V);
     const double S = (double)spinor_bytes(inner, V, 1);
     const double SX = (double)spinor_bytes(inner == WD_F16N ? WD_F32 : inner, V, 1);
-    std::vector<int> d(nrhs), froze(nrhs);
-    for (int i = 0; i < nrhs; ++i) {
-        d[i] = after[i].iters - before[i].iters;
-        froze[i] = (d[i] > 0 && after[i].n_ru > before[i].n_ru) ? 1 : 0;
+    int rc = WD_OK;
+    if (hipMemcpyAsync(before.data(), dscal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        rc = fail(WD_EHIP, "profiling copy failed");
+    if (!rc) {
+        for (int it = 0; it < K; ++it) {
+            const int kinds[3] = {KA, KB, KC};
+            for (int q = 0; q < 3; ++q) {
+                t_ev_start = ev[6 * it + 2 * q];
+                t_ev_stop = ev[6 * it + 2 * q + 1];
+                launch_kind_tiles(kinds[q], inner, ls.k[kinds[q]], st, dprob, 1);
+                t_ev_start = t_ev_stop = nullptr;
+                if (kinds[q] != KC) launch_finish(kinds[q], st, dprob, 1);
+            }
+        }
+        if (hipMemcpyAsync(after.data(), dscal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            rc = fail(WD_EHIP, "profiling copy failed");
     }
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    for (int it = 0; it < K; ++it) {
-        int nact = 0, nc = 0;
+    if (!rc) {
+        std::vector<int> d(nrhs), froze(nrhs);
         for (int i = 0; i < nrhs; ++i) {
-            nact += it < d[i];
-            nc += it < d[i] - froze[i];
+            d[i] = after[i].iters - before[i].iters;
+            froze[i] = (d[i] > 0 && after[i].state != ST_ACTIVE) ? 1 : 0;
         }
-        const double bytes[3] = {G + nact * 2.0 * S, G + nact * (3.0 * S + 2.0 * SX), nc * 3.0 * S};
-        const int cnt[3] = {nact, nact, nc};
-        for (int k = 0; k < 3; ++k) {
-            if (cnt[k] == 0) continue;
-            float ms = 0;
-            hipEventElapsedTime(&ms, pg.ev[6 * it + 2 * k], pg.ev[6 * it + 2 * k + 1]);
-            g_prof[k].launches += 1;
-            g_prof[k].ms += ms;
-            g_prof[k].bytes += bytes[k];
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        for (int it = 0; it < K; ++it) {
+            int nact = 0, nc = 0;
+            for (int i = 0; i < nrhs; ++i) {
+                nact += it < d[i];
+                nc += it < d[i] - froze[i];
+            }
+            const double bytes[3] = {G + nact * 2.0 * S, G + nact * (3.0 * S + 2.0 * SX), nc * 3.0 * S};
+            const int cnt[3] = {nact, nact, nc};
+            for (int k = 0; k < 3; ++k) {
+                if (cnt[k] == 0) continue;
+                float ms = 0;
+                hipEventElapsedTime(&ms, ev[6 * it + 2 * k], ev[6 * it + 2 * k + 1]);
+                g_prof[k].launches += 1;
+                g_prof[k].ms += ms;
+                g_prof[k].bytes += bytes[k];
+            }
         }
     }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    return rc;
 }
 
 // The solve driver shared by wd_cg_solve and wd_cg_solve_batch.
@@ -618,27 +619,18 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     // every chunk either converges a field or spends K iterations of it
     const int max_chunks = p.max_iter / K + 2 * (p.max_iter / (K * 4) + 4);
     const bool prof = g_prof_on.load() != 0 && !persistent && !bicg;
-    ProfGraph pg;
-    std::vector<Scal> before, after;
-    if (prof) {
-        std::lock_guard<std::mutex> lk(g_graph_mu);   // the capture stream is shared
-        rc = prof_capture(pg, p.inner, ls, dprob, K, dsum);
-        if (rc) {
-            (void)hipHostFree(hsum);
-            return rc;
-        }
-        before.resize(nrhs);
-        after.resize(nrhs);
-    }
     for (int c = 0; c < max_chunks && hsum[0] > 0; ++c) {
         hipError_t e = hipSuccess;
         if (prof) {
-            e = hipMemcpyAsync(before.data(), w + L.scal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipGraphLaunch(pg.exec, st);
-            if (e == hipSuccess) e = hipMemcpyAsync(after.data(), w + L.scal, sizeof(Scal) * nrhs,
-                                                    hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e == hipSuccess) prof_account(pg, before, after, p.inner, K, nrhs, V);
+            rc = profiled_chunk(p.inner, ls, st, dprob, K, nrhs, V, w + L.scal);
+            if (rc) {
+                (void)hipHostFree(hsum);
+                return rc;
+            }
+            launch_kind(KR1, p.inner, ls, st, dprob, 1);
+            launch_kind(KR2, p.inner, ls, st, dprob, 1);
+            launch_kind(KC, p.inner, ls, st, dprob, 1);
+            launch_summary(st, dprob, 1, dsum, dabort);
         } else {
             e = hipGraphLaunch(exec, st);
         }
