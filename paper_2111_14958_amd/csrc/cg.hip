@@ -34,16 +34,16 @@ namespace wd {
     const Prob &pr = probs[find_prob(probs, nprob, K, b_)];                    \
     const int t_ = b_ - pr.t0[K];
 
-template <int P, int NR, int ORD>
+template <int P, int NR, int ORD, bool XY>
 __global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KA)
-    phaseA_tile<P, NR, ORD>(pr, t_);
+    phaseA_tile<P, NR, ORD, XY>(pr, t_);
 }
 
-template <int P, int NR, int ORD>
+template <int P, int NR, int ORD, bool XY>
 __global__ __launch_bounds__(256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KB)
-    phaseB_tile<P, NR, ORD>(pr, t_);
+    phaseB_tile<P, NR, ORD, XY>(pr, t_);
 }
 
 template <int P>
@@ -147,28 +147,41 @@ static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
         else hipLaunchKernelGGL(K, grid, blk, 0, st, __VA_ARGS__);                              \
     } while (0)
 
-// hop order 3 (pipelined) or 1 (one hop at a time) for the phase kernels
-template <int P, int ORD>
-static void launch_A_o(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (nr == 1) WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
-    else if (nr == 2) WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
-    else WD_TIMED_LAUNCH((k_phaseA<P, 4, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
-}
-template <int P, int ORD>
-static void launch_B_o(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (nr == 1) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
-    else if (nr == 2) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
-    else WD_TIMED_LAUNCH((k_phaseB<P, 4, ORD>), dim3(grid), dim3(blk), st, d, n, remap);
+// hop order 3 (pipelined) or 1 (one hop at a time) for the phase kernels;
+// the plane-blocked (XY) variants exist for up to 2 rhs per thread (1 in FP64)
+template <int P, int ORD, bool B>
+static void launch_AB_o(int nr, bool xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    const dim3 gr(grid), bl(blk);
+    if (xy) {
+        if (nr == 2 && P != P64) {
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, true>), gr, bl, st, d, n, remap);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, true>), gr, bl, st, d, n, remap);
+        } else {
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, true>), gr, bl, st, d, n, remap);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, true>), gr, bl, st, d, n, remap);
+        }
+        return;
+    }
+    if (nr == 1) {
+        if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, false>), gr, bl, st, d, n, remap);
+        else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, false>), gr, bl, st, d, n, remap);
+    } else if (nr == 2) {
+        if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, false>), gr, bl, st, d, n, remap);
+        else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, false>), gr, bl, st, d, n, remap);
+    } else {
+        if (B) WD_TIMED_LAUNCH((k_phaseB<P, 4, ORD, false>), gr, bl, st, d, n, remap);
+        else WD_TIMED_LAUNCH((k_phaseA<P, 4, ORD, false>), gr, bl, st, d, n, remap);
+    }
 }
 template <int P>
-static void launch_A(int nr, int ord, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (ord == 3) launch_A_o<P, 3>(nr, grid, blk, st, d, n, remap);
-    else launch_A_o<P, 1>(nr, grid, blk, st, d, n, remap);
+static void launch_A(const KindShape &k, hipStream_t st, const Prob *d, int n) {
+    if (k.ordered == 3) launch_AB_o<P, 3, false>(k.nr, k.xy, k.grid, k.block, st, d, n, k.remap);
+    else launch_AB_o<P, 1, false>(k.nr, k.xy, k.grid, k.block, st, d, n, k.remap);
 }
 template <int P>
-static void launch_B(int nr, int ord, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (ord == 3) launch_B_o<P, 3>(nr, grid, blk, st, d, n, remap);
-    else launch_B_o<P, 1>(nr, grid, blk, st, d, n, remap);
+static void launch_B(const KindShape &k, hipStream_t st, const Prob *d, int n) {
+    if (k.ordered == 3) launch_AB_o<P, 3, true>(k.nr, k.xy, k.grid, k.block, st, d, n, k.remap);
+    else launch_AB_o<P, 1, true>(k.nr, k.xy, k.grid, k.block, st, d, n, k.remap);
 }
 template <int P>
 static void launch_R2(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
@@ -211,14 +224,14 @@ void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const
 static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream_t st, const Prob *d, int nprob) {
     switch (kind) {
     case KA:
-        if (inner == P64) launch_A<P64>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
-        else if (inner == P32) launch_A<P32>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
-        else launch_A<P16>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
+        if (inner == P64) launch_A<P64>(k, st, d, nprob);
+        else if (inner == P32) launch_A<P32>(k, st, d, nprob);
+        else launch_A<P16>(k, st, d, nprob);
         break;
     case KB:
-        if (inner == P64) launch_B<P64>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
-        else if (inner == P32) launch_B<P32>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
-        else launch_B<P16>(k.nr, k.ordered, k.grid, k.block, st, d, nprob, k.remap);
+        if (inner == P64) launch_B<P64>(k, st, d, nprob);
+        else if (inner == P32) launch_B<P32>(k, st, d, nprob);
+        else launch_B<P16>(k, st, d, nprob);
         break;
     case KC:
         if (inner == P64) WD_TIMED_LAUNCH(k_phaseC<P64>, dim3(k.grid), dim3(k.block), st, d, nprob, 0);
@@ -288,6 +301,7 @@ WsLayout ws_layout(int64_t V, int nrhs, int inner, int method) {
 // Launch shapes of every kernel kind for one problem (tiles start at 0).
 void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr) {
     const int V = (int)g->V;
+    const int np = g->dims[0] * g->dims[1];
     ShapeKey ka{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, inner, nrhs, 1, FAM_CG_A};
     ShapeKey kb = ka;
     kb.dag = 0;
@@ -308,14 +322,23 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.ordered = (k == KA || k == KB) && st[k]->ordered == 3 ? 3 : 1;
             const int strip = (st[k]->strip > 0 && st[k]->strip < g->dims[2]) ? st[k]->strip : 0;
             ks.order = strip | (st[k]->gmajor ? 1 << 16 : 0);
+            // plane-blocked phases A and B: one xy-plane (<= 256 sites) per block
+            ks.xy = (k == KA || k == KB) && st[k]->xylds && np <= 256;
+            if (ks.xy) {
+                ks.block = 256;
+                if (ks.nr > 2) ks.nr = 2;
+                if (inner == WD_F64) ks.nr = 1;
+                ks.order |= 1 << 17;
+            }
         } else {
             ks.block = 256;
             ks.nr = 1;
             ks.remap = 0;
             ks.order = 0;
+            ks.xy = 0;
         }
         pr.sorder[k] = ks.order;
-        pr.nsb[k] = (V + ks.block - 1) / ks.block;
+        pr.nsb[k] = ks.xy ? V / np : (V + ks.block - 1) / ks.block;
         pr.ng[k] = (nrhs + ks.nr - 1) / ks.nr;
         pr.t0[k] = 0;
         pr.nt[k] = pr.nsb[k] * pr.ng[k];
@@ -334,6 +357,9 @@ void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner) {
         ks.block = blk;
         ks.nr = (k == KC) ? 1 : nr;
         ks.remap = 0;
+        ks.xy = 0;
+        ks.order &= ~(1 << 17);
+        pr.sorder[k] = ks.order;
         pr.nsb[k] = (int)((V + blk - 1) / blk);
         pr.ng[k] = (k == KC) ? nrhs : (nrhs + nr - 1) / nr;
         pr.nt[k] = pr.nsb[k] * pr.ng[k];
@@ -584,7 +610,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
         key.shp[k][1] = ls.k[k].nr;
         key.shp[k][2] = ls.k[k].remap;
         key.shp[k][3] = ls.k[k].grid;
-        key.shp[k][4] = ls.k[k].order;
+        key.shp[k][4] = ls.k[k].order | (ls.k[k].xy << 18);
     }
     hipGraphExec_t exec = nullptr;
     int rec_rc = WD_OK;

@@ -155,18 +155,42 @@ __device__ __forceinline__ int find_prob(const Prob *probs, int nprob, int K, in
 }
 
 // Tile t of stencil kind K: its site block, its rhs group and this thread's
-// site (g.V when the thread has no site).
+// site (g.V when the thread has no site).  XY: a site block is one xy-plane
+// (Lx Ly <= blockDim.x sites), as the plane-blocked variant needs.
+template <bool XY = false>
 __device__ __forceinline__ void stencil_tile(const Prob &pr, int K, int t, int &sb, int &grp, int &s) {
     const int od = pr.sorder[K];
-    if (od >> 16) {
+    if ((od >> 16) & 1) {
         grp = t / pr.nsb[K];
         sb = t - grp * pr.nsb[K];
     } else {
         sb = t / pr.ng[K];
         grp = t - sb * pr.ng[K];
     }
-    const int L = sb * (int)blockDim.x + (int)threadIdx.x;
-    s = L < pr.g.V ? order_site(pr.g, od & 0xffff, L) : pr.g.V;
+    const int rows = XY ? pr.g.S[2] : (int)blockDim.x;
+    const int L = sb * rows + (int)threadIdx.x;
+    s = ((int)threadIdx.x < rows && L < pr.g.V) ? order_site(pr.g, od & 0xffff, L) : pr.g.V;
+}
+
+// Plane-blocked phase kernels: LDS copy of the input field's xy-plane
+template <int P> struct LdsWords { static constexpr int value = 6; };    // float4 per site
+template <> struct LdsWords<P64> { static constexpr int value = 12; };   // double2 per site
+
+// Stage the NR input spinors of this thread's site in the block's LDS plane
+// (every thread of the block must call it: it ends with a barrier).
+template <int P, int NR>
+__device__ __forceinline__ void stage_plane(const FieldPtr &f, int rhs0, unsigned act, int s, int V,
+                                            typename LdsSpinor<P>::word *xy, int np) {
+    typedef typename real_of<P>::type R;
+    if (s < V)
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            if (act >> j & 1) {
+                cx<R> v[12];
+                Spinor<P>::load(f, rhs0 + j, s, v);
+                LdsSpinor<P>::put(xy, np, j, threadIdx.x, v);
+            }
+    __syncthreads();
 }
 
 // bit j set: rhs rhs0 + j is in state `want`
@@ -181,27 +205,33 @@ __device__ __forceinline__ unsigned rhs_mask(const Prob &pr, int rhs0, int want)
 
 // ------------------------------------------------------------------ phase A
 // q = D^dagger p for active rhs; partial |q|^2 (of the stored q)
-template <int P, int NR, int ORD = 1>
+// XY: plane-blocked (one xy-plane per block, x/y neighbours from LDS).
+template <int P, int NR, int ORD = 1, bool XY = false>
 __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
+    typedef typename LdsSpinor<P>::word W;
+    __shared__ W xy[XY ? NR * LdsWords<P>::value * 256 : 1];
     int sb, grp, s;
-    stencil_tile(pr, KA, t, sb, grp, s);
+    stencil_tile<XY>(pr, KA, t, sb, grp, s);
     const int rhs0 = grp * NR;
     const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
     double part[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) part[j] = 0.0;
     const Geom g = pr.g;
+    const int np = g.S[2];
+    FieldPtr fp{pr.p, g.V, pr.nrhs}, fq{pr.q, g.V, pr.nrhs};
+    if (XY && act) stage_plane<P, NR>(fp, rhs0, act, s, g.V, xy, np);
     if (act && s < g.V) {
-        FieldPtr fp{pr.p, g.V, pr.nrhs}, fq{pr.q, g.V, pr.nrhs};
         const void *U = pr.U_lo;
         cx<R> acc[NR][12];
-        hopping<P, true, NR, ORD>(g, s, U, fp, rhs0, act, acc);
+        hopping<P, true, NR, ORD, XY>(g, s, U, fp, rhs0, act, acc, nullptr, xy, s - (int)threadIdx.x, np);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
                 cx<R> self[12], o[12];
-                Spinor<P>::load(fp, rhs0 + j, s, self);
+                if constexpr (XY) LdsSpinor<P>::get(xy, np, j, threadIdx.x, self);
+                else Spinor<P>::load(fp, rhs0 + j, s, self);
                 wilson_finish<R>((R)pr.diag, self, acc[j], o);
                 Spinor<P>::store(fq, rhs0 + j, s, o);
                 double n = 0;
@@ -240,30 +270,35 @@ __device__ __forceinline__ void phaseA_finish(const Prob &pr) {
 
 // ------------------------------------------------------------------ phase B
 // t = D q; r -= alpha t; x_lo += alpha q(s); partial |r|^2 (of the stored r)
-template <int P, int NR, int ORD = 1>
+template <int P, int NR, int ORD = 1, bool XY = false>
 __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     constexpr int XP = XPrec<P>::value;
     typedef typename real_of<XP>::type RX;
+    typedef typename LdsSpinor<P>::word W;
+    __shared__ W xy[XY ? NR * LdsWords<P>::value * 256 : 1];
     int sb, grp, s;
-    stencil_tile(pr, KB, t, sb, grp, s);
+    stencil_tile<XY>(pr, KB, t, sb, grp, s);
     const int rhs0 = grp * NR;
     const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
     double part[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) part[j] = 0.0;
     const Geom g = pr.g;
+    const int np = g.S[2];
+    FieldPtr fq{pr.q, g.V, pr.nrhs}, fr{pr.r, g.V, pr.nrhs}, fx{pr.x_lo, g.V, pr.nrhs};
+    if (XY && act) stage_plane<P, NR>(fq, rhs0, act, s, g.V, xy, np);
     if (act && s < g.V) {
-        FieldPtr fq{pr.q, g.V, pr.nrhs}, fr{pr.r, g.V, pr.nrhs}, fx{pr.x_lo, g.V, pr.nrhs};
         const void *U = pr.U_lo;
         cx<R> acc[NR][12];
-        hopping<P, false, NR, ORD>(g, s, U, fq, rhs0, act, acc);
+        hopping<P, false, NR, ORD, XY>(g, s, U, fq, rhs0, act, acc, nullptr, xy, s - (int)threadIdx.x, np);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
                 const R a = (R)pr.sc[rhs0 + j].alpha;
                 cx<R> q[12], o[12], r[12];
-                Spinor<P>::load(fq, rhs0 + j, s, q);
+                if constexpr (XY) LdsSpinor<P>::get(xy, np, j, threadIdx.x, q);
+                else Spinor<P>::load(fq, rhs0 + j, s, q);
                 wilson_finish<R>((R)pr.diag, q, acc[j], o);
                 Spinor<P>::load(fr, rhs0 + j, s, r);
 #pragma unroll

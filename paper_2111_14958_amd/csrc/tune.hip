@@ -218,8 +218,8 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
              "FP64 CG kernels take <= 2 rhs per thread");
     const int strip = sh->site_order & 0xffff, gmajor = (sh->site_order >> 16) & 1, xylds = sh->site_order >> 17;
     WD_CHECK(sh->site_order >= 0 && (xylds == 0 || xylds == 1), WD_EINVAL, "site_order 0x%x", sh->site_order);
-    WD_CHECK(!xylds || (family == FAM_DSLASH && g->dims[0] * g->dims[1] <= 256), WD_EINVAL,
-             "plane-blocked LDS variant: operator kernel only, Lx*Ly <= 256");
+    WD_CHECK(!xylds || (family != FAM_CG_R && g->dims[0] * g->dims[1] <= 256), WD_EINVAL,
+             "plane-blocked LDS variant: operator and CG phase A/B kernels, Lx*Ly <= 256");
     ShapeKey k{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, prec, nrhs, dagger ? 1 : 0, family};
     Shape s;
     s.block = sh->block;
