@@ -187,8 +187,10 @@ def main():
     fam = {"cg_phaseA": wd.FAMILY_CG_A, "cg_phaseB": wd.FAMILY_CG_B}.get(dom_name)
     if fam is not None:
         sh = wd.shape_get(g, wd.F32, nrhs, fam == wd.FAMILY_CG_A, fam)
-        kernel_symbol = "wd::k_%s<1, %d, %d>" % (dom_name[3:], sh["rhs_per_thread"],
-                                                3 if sh["hop_order"] == 3 else 1)
+        xy = sh["xy_lds"] and dims[0] * dims[1] <= 256
+        nr = min(sh["rhs_per_thread"], 2) if xy else sh["rhs_per_thread"]
+        kernel_symbol = "wd::k_%s<1, %d, %d, %s>" % (dom_name[3:], nr, 3 if sh["hop_order"] == 3 else 1,
+                                                    "true" if xy else "false")
     else:
         kernel_symbol = "wd::k_phaseC<1>"
     traffic, traffic_note = pmc_traffic() if dom_name == "cg_phaseB" else (None, "not measured")

@@ -37,9 +37,11 @@ static bool g_loaded = false;
 
 // Untuned shapes (the measured best on gfx950 for 14^4 x 16 rhs): XCD-
 // contiguous tiles, z-strips of 4 planes, pipelined hops, 256-thread blocks.
-// Operator kernel: the plane-blocked LDS variant (falls back to site blocks
-// when an xy-plane exceeds 256 sites), two rhs per thread in FP32 / FP16N, one
-// in FP64.  CG phase kernels: two rhs per thread in every precision.
+// The plane-blocked LDS variants are used where an xy-plane has at most 256
+// sites (else the site-blocked kernels).  Operator kernel: two rhs per thread
+// in FP32 / FP16N, one in FP64.  CG phase kernels: one rhs per thread,
+// plane-blocked in FP32 and FP64 (in FP16N the site-blocked kernel is faster).
+// The reliable-update kernel: two rhs per thread.
 Shape default_shape(int prec, int nrhs, int fam) {
     Shape s;
     s.block = 256;
@@ -50,8 +52,11 @@ Shape default_shape(int prec, int nrhs, int fam) {
     if (fam == FAM_DSLASH) {
         s.nr = (prec == WD_F64 || nrhs < 2) ? 1 : 2;
         s.xylds = 1;
-    } else {
+    } else if (fam == FAM_CG_R) {
         s.nr = nrhs < 2 ? 1 : 2;
+    } else {
+        s.nr = 1;
+        s.xylds = prec != WD_F16N;
     }
     return s;
 }

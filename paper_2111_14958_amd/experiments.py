@@ -58,7 +58,7 @@ def fig1(blocks=(64, 128, 256)):
                           "gflops": 2 * 1368.0 * 14 ** 4 * rep["iters"] / t / 1e9}), flush=True)
 
 
-def serve(n_requests=120, rates=(0.5, 1.0, 1.5), pool=2, arena_gib=24, max_slots=16, seed=10_000):
+def serve(n_requests=600, rates=(0.25, 0.5, 1.0, 1.5, 2.0), pool=2, arena_gib=24, max_slots=16, seed=10_000):
     """Continuous-batching solve server under Poisson arrivals.
 
     Request i (seeded by seed + i): lattice drawn uniformly from 4^4, 8^4, 12^4, 14^4, 16^3 x 32,
