@@ -322,8 +322,9 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.ordered = (k == KA || k == KB) && st[k]->ordered == 3 ? 3 : 1;
             const int strip = (st[k]->strip > 0 && st[k]->strip < g->dims[2]) ? st[k]->strip : 0;
             ks.order = strip | (st[k]->gmajor ? 1 << 16 : 0);
-            // plane-blocked phases A and B: one xy-plane (<= 256 sites) per block
-            ks.xy = (k == KA || k == KB) && st[k]->xylds && np <= 256;
+            // plane-blocked phases A and B: one xy-plane of 64..256 sites per
+            // block (the partial-sum buffer holds one entry per 64 sites)
+            ks.xy = (k == KA || k == KB) && st[k]->xylds && np >= 64 && np <= 256;
             if (ks.xy) {
                 ks.block = 256;
                 if (ks.nr > 2) ks.nr = 2;
@@ -573,6 +574,9 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     const bool bicg = p.method == METHOD_BICGSTAB;
     const int persistent = (p.persistent == 1 && !bicg) ? 1 : 0;
     if (persistent) plan_persistent(ls, hp, V, nrhs, p.inner);
+    for (int k = 0; k < NKIND; ++k)   // every kind's partial sums fit the buffer
+        WD_CHECK(hp.nsb[k] <= (V + 63) / 64, WD_EINVAL, "kernel kind %d has %d site blocks, the partial-sum "
+                 "buffer holds %lld", k, hp.nsb[k], (long long)((V + 63) / 64));
 
     // upload the problem record and the initial scalars
     std::vector<Scal> sc;

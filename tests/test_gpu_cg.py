@@ -219,11 +219,14 @@ def test_persistent_kernel_matches_oracle(inner):
 
 
 @pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
-@pytest.mark.parametrize("dims", [(8, 8, 4, 6), (14, 14, 6, 4)], ids=["8x8x4x6", "14x14x6x4"])
+@pytest.mark.parametrize("dims", [(8, 8, 4, 6), (14, 14, 6, 4), (4, 8, 4, 6)],
+                         ids=["8x8x4x6", "14x14x6x4", "4x8x4x6"])
 def test_plane_blocked_phase_kernels(inner, dims):
     """Phases A and B with one xy-plane per block (x/y neighbours from LDS) and
     the site-blocked kernels reach the oracle-checked solution; the per-site
-    arithmetic is the same, so the solutions agree to the solver tolerance."""
+    arithmetic is the same, so the solutions agree to the solver tolerance.
+    A plane of fewer than 64 sites (4x8) falls back to site blocks (the
+    partial-sum buffer holds one entry per 64 sites)."""
     m0 = 0.1
     U = wdgen.gauge_field(dims, 0.5, 401)
     eta = wdgen.mixed_sources(dims, 3, 2, 402)
