@@ -57,15 +57,13 @@ __global__ void k_coo_build(Geom g, double diag, const double2 *__restrict__ U64
         const bool fwrap = c[mu] == g.L[mu] - 1, bwrap = c[mu] == 0;
         const int fw = fwrap ? s - (g.L[mu] - 1) * g.S[mu] : s + g.S[mu];
         const int bw = bwrap ? s + (g.L[mu] - 1) * g.S[mu] : s - g.S[mu];
-        const double sf = (mu == 3 && fwrap && g.tsign < 0) ? -1.0 : 1.0;
-        const double sb = (mu == 3 && bwrap && g.tsign < 0) ? -1.0 : 1.0;
         // projector row alpha: identity at beta = alpha, -+ sg gamma at beta = gcol
         const int gb = g_gcol[mu][al];
         const double gre = g_gval[mu][al][0], gim = g_gval[mu][al][1];
         for (int dir = 0; dir < 2; ++dir) {
             // forward: -1/2 (1 - sg gamma) U_mu(x) s_f ; backward: -1/2 (1 + sg gamma) U_mu(x-mu)^dag s_b
             const double ps = dir == 0 ? -sg : sg;
-            const double sfac = -0.5 * (dir == 0 ? sf : sb);
+            const double sfac = -0.5;   // the boundary sign is in the packed t-links
             const int nb = dir == 0 ? fw : bw;
             const int ls = dir == 0 ? s : bw;
             for (int pass = 0; pass < 2; ++pass) {

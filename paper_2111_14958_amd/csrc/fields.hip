@@ -65,13 +65,17 @@ size_t link_bytes(int prec, int64_t V) {
 // ------------------------------------------------------------------ kernels
 // canonical U[site][mu][a][b] (complex128) -> packed [mu][9][V] in precision P
 template <int P>
-__global__ void k_pack_links(const double2 *__restrict__ in, void *__restrict__ out, int V) {
+// t-links of the last time slice (sites >= last0) are stored times -1 when
+// flip is set: the antiperiodic boundary sign of both hops across it.
+__global__ void k_pack_links(const double2 *__restrict__ in, void *__restrict__ out, int V, int last0, int flip) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
     for (int mu = 0; mu < 4; ++mu) {
         const double2 *src = in + ((size_t)s * 4 + mu) * 9;
+        const bool neg = flip && mu == 3 && s >= last0;
         for (int k = 0; k < 9; ++k) {
-            const double2 v = src[k];
+            double2 v = src[k];
+            if (neg) v = make_double2(-v.x, -v.y);
             const size_t o = ((size_t)mu * 9 + k) * V + s;
             if constexpr (P == P64) {
                 ((double2 *)out)[o] = v;
@@ -119,12 +123,15 @@ __global__ void k_unpack_spinor(const void *__restrict__ in, double2 *__restrict
     for (int k = 0; k < 12; ++k) dst[k] = make_double2((double)v[k].re, (double)v[k].im);
 }
 
-int launch_pack_links(int prec, const void *in, void *out, int V, hipStream_t st) {
+int launch_pack_links(int prec, const void *in, void *out, const int dims[4], int tsign, hipStream_t st) {
+    const int V = dims[0] * dims[1] * dims[2] * dims[3];
+    const int last0 = V - dims[0] * dims[1] * dims[2];
+    const int flip = tsign < 0 ? 1 : 0;
     const int blocks = (V + 255) / 256;
     switch (prec) {
-    case WD_F64: hipLaunchKernelGGL(k_pack_links<P64>, dim3(blocks), dim3(256), 0, st, (const double2 *)in, out, V); break;
-    case WD_F32: hipLaunchKernelGGL(k_pack_links<P32>, dim3(blocks), dim3(256), 0, st, (const double2 *)in, out, V); break;
-    case WD_F16N: hipLaunchKernelGGL(k_pack_links<P16>, dim3(blocks), dim3(256), 0, st, (const double2 *)in, out, V); break;
+    case WD_F64: hipLaunchKernelGGL(k_pack_links<P64>, dim3(blocks), dim3(256), 0, st, (const double2 *)in, out, V, last0, flip); break;
+    case WD_F32: hipLaunchKernelGGL(k_pack_links<P32>, dim3(blocks), dim3(256), 0, st, (const double2 *)in, out, V, last0, flip); break;
+    case WD_F16N: hipLaunchKernelGGL(k_pack_links<P16>, dim3(blocks), dim3(256), 0, st, (const double2 *)in, out, V, last0, flip); break;
     default: return fail(WD_EINVAL, "unknown precision %d", prec);
     }
     WD_HIP(hipGetLastError());
@@ -229,7 +236,7 @@ int wd_gauge_create(const int32_t dims[4], int32_t t_sign, const void *U_dev, ui
             delete g;
             return fail(WD_ENOMEM, "hipMalloc of %zu link bytes: %s", link_bytes(p, V), hipGetErrorString(e));
         }
-        launch_pack_links(p, U_dev, g->U[p], (int)V, st);
+        launch_pack_links(p, U_dev, g->U[p], g->dims, g->tsign, st);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);

@@ -177,8 +177,9 @@ static int init_slot(wd_server *s, Slot &sl) {
     const int64_t V = sl.V;
     char *base = arena_ptr(s, sl.off);
     hipStream_t st = s->st;
-    int rc = launch_pack_links(WD_F64, rq.gauge_dev, base + sl.sl.links64, (int)V, st);
-    if (!rc && inner != WD_F64) rc = launch_pack_links(inner, rq.gauge_dev, base + sl.sl.links_lo, (int)V, st);
+    int rc = launch_pack_links(WD_F64, rq.gauge_dev, base + sl.sl.links64, rq.dims, rq.t_sign, st);
+    if (!rc && inner != WD_F64)
+        rc = launch_pack_links(inner, rq.gauge_dev, base + sl.sl.links_lo, rq.dims, rq.t_sign, st);
     if (rc) return rc;
     wd_gauge g;   // a view of the arena copies, for the record
     memset(&g, 0, sizeof(g));

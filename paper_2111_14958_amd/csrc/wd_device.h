@@ -39,6 +39,26 @@ template <typename T> using gptr = __attribute__((address_space(1))) T *;
 template <typename T> __device__ __forceinline__ gptr<T> as_global(void *p) { return (gptr<T>)p; }
 template <typename T> __device__ __forceinline__ gptr<const T> as_global(const void *p) { return (gptr<const T>)p; }
 
+// Element of a plane.  base + plane must be the same in every lane of the
+// wavefront (a field pointer plus plane number times plane bytes); it is moved
+// to scalar registers, so each access is one load or store with a scalar base
+// and a 32-bit vector byte offset and needs no 64-bit address arithmetic.
+typedef __attribute__((address_space(1))) char gchar;
+__device__ __forceinline__ gchar *wave_uniform(gchar *p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (gchar *)(((uint64_t)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ gptr<const T> at(const void *base, size_t plane, uint32_t off) {
+    return (gptr<const T>)(wave_uniform((gchar *)base + plane) + off);
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> at(void *base, size_t plane, uint32_t off) {
+    return (gptr<T>)(wave_uniform((gchar *)base + plane) + off);
+}
+
 template <int P> struct real_of { typedef float type; };
 template <> struct real_of<P64> { typedef double type; };
 
@@ -65,7 +85,6 @@ struct Geom {
     int L[4];     // Lx, Ly, Lz, Lt
     int S[4];     // strides 1, Lx, Lx*Ly, Lx*Ly*Lz
     int V;        // sites
-    int tsign;    // -1 antiperiodic in t, +1 periodic
 };
 
 __device__ __forceinline__ void site_coords(const Geom &g, int s, int c[4]) {
@@ -90,14 +109,17 @@ template <> struct Spinor<P64> {
     typedef double R;
     static constexpr int BYTES_PER_SITE = 192;
     __device__ static __forceinline__ void load(const FieldPtr &f, int r, int s, cx<R> o[12]) {
-        gptr<const d2v> d = as_global<d2v>((const void *)f.p) + (size_t)r * 12 * f.V + s;
+        const size_t pb = (size_t)f.V * 16;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) { d2v v = d[k * f.V]; o[k] = {v.x, v.y}; }
+        for (int k = 0; k < 12; ++k) {
+            const d2v v = *at<d2v>((const void *)f.p, (size_t)(r * 12 + k) * pb, (uint32_t)s * 16u);
+            o[k] = {v.x, v.y};
+        }
     }
     __device__ static __forceinline__ void store(const FieldPtr &f, int r, int s, const cx<R> o[12]) {
-        gptr<d2v> d = as_global<d2v>(f.p) + (size_t)r * 12 * f.V + s;
+        const size_t pb = (size_t)f.V * 16;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) d[k * f.V] = d2v{o[k].re, o[k].im};
+        for (int k = 0; k < 12; ++k) *at<d2v>(f.p, (size_t)(r * 12 + k) * pb, (uint32_t)s * 16u) = d2v{o[k].re, o[k].im};
     }
 };
 
@@ -105,34 +127,36 @@ template <> struct Spinor<P32> {
     typedef float R;
     static constexpr int BYTES_PER_SITE = 96;
     __device__ static __forceinline__ void load(const FieldPtr &f, int r, int s, cx<R> o[12]) {
-        gptr<const f4v> d = as_global<f4v>((const void *)f.p) + (size_t)r * 6 * f.V + s;
+        const size_t pb = (size_t)f.V * 16;
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            f4v v = d[j * f.V];
+            const f4v v = *at<f4v>((const void *)f.p, (size_t)(r * 6 + j) * pb, (uint32_t)s * 16u);
             o[2 * j] = {v.x, v.y};
             o[2 * j + 1] = {v.z, v.w};
         }
     }
     __device__ static __forceinline__ void store(const FieldPtr &f, int r, int s, const cx<R> o[12]) {
-        gptr<f4v> d = as_global<f4v>(f.p) + (size_t)r * 6 * f.V + s;
+        const size_t pb = (size_t)f.V * 16;
 #pragma unroll
         for (int j = 0; j < 6; ++j)
-            d[j * f.V] = f4v{o[2 * j].re, o[2 * j].im, o[2 * j + 1].re, o[2 * j + 1].im};
+            *at<f4v>(f.p, (size_t)(r * 6 + j) * pb, (uint32_t)s * 16u) =
+                f4v{o[2 * j].re, o[2 * j].im, o[2 * j + 1].re, o[2 * j + 1].im};
     }
 };
 
 template <> struct Spinor<P16> {
     typedef float R;
     static constexpr int BYTES_PER_SITE = 52;
-    __device__ static __forceinline__ gptr<float> norms(const FieldPtr &f) {
-        return (gptr<float>)(as_global<half8v>(f.p) + (size_t)f.nrhs * 3 * f.V);
+    // byte offset of the norm plane of rhs r
+    __device__ static __forceinline__ size_t norm_plane(const FieldPtr &f, int r) {
+        return (size_t)f.nrhs * 3 * f.V * 16 + (size_t)r * f.V * 4;
     }
     __device__ static __forceinline__ void load(const FieldPtr &f, int r, int s, cx<R> o[12]) {
-        gptr<const half8v> d = as_global<half8v>((const void *)f.p) + (size_t)r * 3 * f.V + s;
-        const float n = norms(f)[(size_t)r * f.V + s];
+        const size_t pb = (size_t)f.V * 16;
+        const float n = *at<float>((const void *)f.p, norm_plane(f, r), (uint32_t)s * 4u);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            half8v v = d[j * f.V];
+            const half8v v = *at<half8v>((const void *)f.p, (size_t)(r * 3 + j) * pb, (uint32_t)s * 16u);
 #pragma unroll
             for (int k = 0; k < 4; ++k) o[4 * j + k] = {n * (float)v[2 * k], n * (float)v[2 * k + 1]};
         }
@@ -143,7 +167,7 @@ template <> struct Spinor<P16> {
         float n = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) n = fmaxf(n, fmaxf(fabsf(o[k].re), fabsf(o[k].im)));
-        gptr<half8v> d = as_global<half8v>(f.p) + (size_t)r * 3 * f.V + s;
+        const size_t pb = (size_t)f.V * 16;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             half8v v;
@@ -155,9 +179,9 @@ template <> struct Spinor<P16> {
                 v[2 * k + 1] = (h16)b;
                 o[4 * j + k] = {n * (float)v[2 * k], n * (float)v[2 * k + 1]};
             }
-            d[j * f.V] = v;
+            *at<half8v>(f.p, (size_t)(r * 3 + j) * pb, (uint32_t)s * 16u) = v;
         }
-        norms(f)[(size_t)r * f.V + s] = n;
+        *at<float>(f.p, norm_plane(f, r), (uint32_t)s * 4u) = n;
     }
 };
 
@@ -168,27 +192,33 @@ template <> struct Link<P64> {
     typedef double R;
     static constexpr int BYTES_PER_LINK = 144;
     __device__ static __forceinline__ void load(const void *U, int V, int mu, int s, cx<R> u[9]) {
-        gptr<const d2v> d = as_global<d2v>(U) + (size_t)mu * 9 * V + s;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) { d2v v = d[k * V]; u[k] = {v.x, v.y}; }
+        for (int k = 0; k < 9; ++k) {
+            const d2v v = *at<d2v>(U, (size_t)(mu * 9 + k) * V * 16, (uint32_t)s * 16u);
+            u[k] = {v.x, v.y};
+        }
     }
 };
 template <> struct Link<P32> {
     typedef float R;
     static constexpr int BYTES_PER_LINK = 72;
     __device__ static __forceinline__ void load(const void *U, int V, int mu, int s, cx<R> u[9]) {
-        gptr<const f2v> d = as_global<f2v>(U) + (size_t)mu * 9 * V + s;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) { f2v v = d[k * V]; u[k] = {v.x, v.y}; }
+        for (int k = 0; k < 9; ++k) {
+            const f2v v = *at<f2v>(U, (size_t)(mu * 9 + k) * V * 8, (uint32_t)s * 8u);
+            u[k] = {v.x, v.y};
+        }
     }
 };
 template <> struct Link<P16> {
     typedef float R;
     static constexpr int BYTES_PER_LINK = 36;
     __device__ static __forceinline__ void load(const void *U, int V, int mu, int s, cx<R> u[9]) {
-        gptr<const half2v> d = as_global<half2v>(U) + (size_t)mu * 9 * V + s;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) { half2v v = d[k * V]; u[k] = {(float)v.x, (float)v.y}; }
+        for (int k = 0; k < 9; ++k) {
+            const half2v v = *at<half2v>(U, (size_t)(mu * 9 + k) * V * 4, (uint32_t)s * 4u);
+            u[k] = {(float)v.x, (float)v.y};
+        }
     }
 };
 
@@ -234,15 +264,30 @@ __device__ __forceinline__ void accumulate(const cx<R> w[6], cx<R> acc[12]) {
     }
 }
 
-// w = U h   (per spin component)
+// w = U h   (per spin component).  Each output component is one multiply and
+// five fused multiply-adds.
 template <typename R>
 __device__ __forceinline__ void link_mul(const cx<R> u[9], const cx<R> h[6], cx<R> w[6]) {
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            w[3 * sp + a] = cmul(u[3 * a], h[3 * sp]) + cmul(u[3 * a + 1], h[3 * sp + 1]) +
-                            cmul(u[3 * a + 2], h[3 * sp + 2]);
+        for (int a = 0; a < 3; ++a) {
+            const cx<R> u0 = u[3 * a], u1 = u[3 * a + 1], u2 = u[3 * a + 2];
+            const cx<R> h0 = h[3 * sp], h1 = h[3 * sp + 1], h2 = h[3 * sp + 2];
+            R re = u0.re * h0.re;
+            re = fma(-u0.im, h0.im, re);
+            re = fma(u1.re, h1.re, re);
+            re = fma(-u1.im, h1.im, re);
+            re = fma(u2.re, h2.re, re);
+            re = fma(-u2.im, h2.im, re);
+            R im = u0.re * h0.im;
+            im = fma(u0.im, h0.re, im);
+            im = fma(u1.re, h1.im, im);
+            im = fma(u1.im, h1.re, im);
+            im = fma(u2.re, h2.im, im);
+            im = fma(u2.im, h2.re, im);
+            w[3 * sp + a] = {re, im};
+        }
 }
 
 // w = U^dagger h
@@ -251,9 +296,23 @@ __device__ __forceinline__ void link_adj_mul(const cx<R> u[9], const cx<R> h[6],
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            w[3 * sp + a] = cjmul(u[a], h[3 * sp]) + cjmul(u[3 + a], h[3 * sp + 1]) +
-                            cjmul(u[6 + a], h[3 * sp + 2]);
+        for (int a = 0; a < 3; ++a) {
+            const cx<R> u0 = u[a], u1 = u[3 + a], u2 = u[6 + a];
+            const cx<R> h0 = h[3 * sp], h1 = h[3 * sp + 1], h2 = h[3 * sp + 2];
+            R re = u0.re * h0.re;
+            re = fma(u0.im, h0.im, re);
+            re = fma(u1.re, h1.re, re);
+            re = fma(u1.im, h1.im, re);
+            re = fma(u2.re, h2.re, re);
+            re = fma(u2.im, h2.im, re);
+            R im = u0.re * h0.im;
+            im = fma(-u0.im, h0.re, im);
+            im = fma(u1.re, h1.im, im);
+            im = fma(-u1.im, h1.re, im);
+            im = fma(u2.re, h2.im, im);
+            im = fma(-u2.im, h2.re, im);
+            w[3 * sp + a] = {re, im};
+        }
 }
 
 template <int MU> struct IntC { static constexpr int value = MU; };
@@ -297,9 +356,10 @@ template <> struct LdsSpinor<P64> {
 // Hopping sum of Eq. (1) at site s for NR right-hand sides of field `in`
 // starting at rhs0 (only those whose bit is set in `act` are touched):
 //   acc = sum_mu [ (1 + SF gamma_mu) U_mu(s) psi(s+mu) + (1 + SB gamma_mu) U_mu(s-mu)^dag psi(s-mu) ]
-// with SF = -1, SB = +1 for D and SF = +1, SB = -1 for D^dagger, and the
-// boundary sign on hops in t that wrap around.  Each link is loaded once and
-// applied to all NR right-hand sides.
+// with SF = -1, SB = +1 for D and SF = +1, SB = -1 for D^dagger.  The boundary
+// sign of the hops in t that wrap around is carried by the packed t-links of
+// the last time slice (both such hops use those links).  Each link is loaded
+// once and applied to all NR right-hand sides.
 //
 // XYLDS: the neighbours in x and y are read from the block's LDS copy of its
 // xy-plane (`xy`, plane starting at site `plane0`, np sites) instead of memory.
@@ -370,8 +430,6 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
         if constexpr ((ORDERED == 3 || ORDERED == 4) && H + 1 < 8) after_acc(nbi[H + 1], lsi[H + 1]);
         if constexpr (ORDERED == 4 && H == 0) after_first(nbi[0]);
         const int nb = nbi[H];
-        const bool wrap = FWD ? (c[MU] == g.L[MU] - 1) : (c[MU] == 0);
-        const bool neg = (MU == 3) && wrap && g.tsign < 0;
         cx<R> u[9];
         Link<P>::load(U, g.V, MU, lsi[H], u);
 #pragma unroll
@@ -381,10 +439,6 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
                 if constexpr (XYLDS && MU < 2) LdsSpinor<P>::get(xy, np, j, nb - plane0, p);
                 else Spinor<P>::load(in, rhs0 + j, nb, p);
                 project<MU, S>(p, h);
-                if (neg) {
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) h[k] = -h[k];
-                }
                 if constexpr (FWD) link_mul(u, h, w);
                 else link_adj_mul(u, h, w);
                 accumulate<MU, S>(w, acc[j]);
@@ -406,7 +460,7 @@ template <typename R>
 __device__ __forceinline__ void wilson_finish(R diag, const cx<R> self[12], const cx<R> acc[12], cx<R> o[12]) {
 #pragma unroll
     for (int k = 0; k < 12; ++k)
-        o[k] = {diag * self[k].re - R(0.5) * acc[k].re, diag * self[k].im - R(0.5) * acc[k].im};
+        o[k] = {fma(R(-0.5), acc[k].re, diag * self[k].re), fma(R(-0.5), acc[k].im, diag * self[k].im)};
 }
 
 // Blocks are handed to the 8 XCDs round robin (block b runs on XCD b % 8).

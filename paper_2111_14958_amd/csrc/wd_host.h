@@ -79,7 +79,9 @@ struct wd_gauge {
 namespace wd {
 Geom make_geom(const wd_gauge *g);
 // Launchers implemented in the .hip units (all asynchronous on `stream`).
-int launch_pack_links(int prec, const void *U_c128, void *out, int V, hipStream_t st);
+// canonical complex128 links -> packed precision prec; the t-links of the last
+// time slice carry the boundary sign (tsign) from here on
+int launch_pack_links(int prec, const void *U_c128, void *out, const int dims[4], int tsign, hipStream_t st);
 int launch_pack_spinor(int prec, const void *in_c128, void *out, int V, int nrhs, hipStream_t st);
 int launch_unpack_spinor(int prec, const void *in, void *out_c128, int V, int nrhs, hipStream_t st);
 int launch_dslash(const wd_gauge *g, double m0, int prec, bool dag, const void *in, void *out,

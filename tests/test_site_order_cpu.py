@@ -29,7 +29,6 @@ int main() {
         for (int k = 0; k < 4; ++k) g.L[k] = d[k];
         g.S[0] = 1; g.S[1] = d[0]; g.S[2] = d[0] * d[1]; g.S[3] = d[0] * d[1] * d[2];
         g.V = d[0] * d[1] * d[2] * d[3];
-        g.tsign = -1;
         const int P = g.S[2];
         for (int W = 0; W <= d[2] + 1; ++W) {
             std::vector<int> seen(g.V, 0);
