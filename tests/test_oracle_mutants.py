@@ -94,3 +94,46 @@ def test_mutant_is_caught(tmp_path, name, old, new, nth):
     lib = _build(text, tmp_path, str(abs(hash(name))))
     failed = _pins(lib)
     assert failed, f"mutation '{name}' passed every pin"
+
+
+# Mistakes planted in the even-odd Schur complement (NumPy side of the oracle);
+# the dense block-elimination pin must reject each one.
+SCHUR_MUTANTS = [
+    ("Schur sign", "return np.where(even, a * ve - z, 0)", "return np.where(even, a * ve + z, 0)"),
+    ("A^-1 dropped", "dirac(U, ve, dims, m0, t_sign, dagger, lib=lib)) / a", "dirac(U, ve, dims, m0, t_sign, dagger, lib=lib))"),
+    ("diagonal dropped", "return np.where(even, a * ve - z, 0)", "return np.where(even, -z, 0)"),
+    ("parity of the intermediate", "w = np.where(even, 0, dirac(", "w = np.where(even, dirac("),
+    ("dagger ignored in the second hop", "z = dirac(U, w, dims, m0, t_sign, dagger, lib=lib)",
+     "z = dirac(U, w, dims, m0, t_sign, False, lib=lib)"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", SCHUR_MUTANTS, ids=[m[0] for m in SCHUR_MUTANTS])
+def test_schur_mutants_are_caught(name, old, new):
+    import inspect
+
+    import numpy as np
+    import wdgen
+    src = inspect.getsource(oracle.schur)
+    assert old in src, name
+    if name == "parity of the intermediate":
+        new_src = src.replace("w = np.where(even, 0, dirac(U, ve, dims, m0, t_sign, dagger, lib=lib)) / a",
+                              "w = np.where(even, dirac(U, ve, dims, m0, t_sign, dagger, lib=lib), 0) / a")
+    else:
+        new_src = src.replace(old, new)
+    assert new_src != src
+    ns = dict(vars(oracle))
+    exec(new_src, ns)
+    mutant = ns["schur"]
+    dims, m0 = (2, 2, 4, 4), 0.13
+    dagger = name.startswith("dagger")
+    U = wdgen.gauge_field(dims, 0.6, 91)
+    D = oracle.dense(U, dims, m0, dagger=dagger)
+    par = oracle.parity(dims).ravel()
+    rows = np.arange(par.size * 12)
+    ie, io = rows[par[rows // 12] == 0], rows[par[rows // 12] == 1]
+    S = D[np.ix_(ie, ie)] - D[np.ix_(ie, io)] @ np.linalg.solve(D[np.ix_(io, io)], D[np.ix_(io, ie)])
+    v = wdgen.gaussian_source(dims, 1, 92)[0]
+    got = mutant(U, v, dims, m0, dagger=dagger).ravel()
+    want = S @ v.ravel()[ie]
+    assert np.linalg.norm(got[ie] - want) > 1e-6 * np.linalg.norm(want), f"mutant {name} survived"

@@ -189,3 +189,68 @@ def test_bicgstab_breaks_down_on_a_point_source():
     # a Gaussian source on the same links converges
     eta = wdgen.gaussian_source(dims, 1, 78)
     assert oracle.bicgstab(U, eta, dims, m0)[3] == [0]
+
+
+# ------------------------------------------------------------ even-odd
+def _parity_index(dims):
+    """Indices of the even and odd rows of the dense operator (site-major, 12
+    components per site, sites in the canonical order)."""
+    par = oracle.parity(dims).ravel()
+    rows = np.arange(par.size * 12)
+    site_par = par[rows // 12]
+    return rows[site_par == 0], rows[site_par == 1]
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (2, 2, 4, 4), (4, 4, 4, 4)])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_schur_matches_dense_block_elimination(dims, dagger):
+    """oracle.schur against the Schur complement D_ee - D_eo D_oo^-1 D_oe built
+    from the dense operator's blocks with a generic solve (no use of the
+    diagonal form of D_oo)."""
+    m0 = 0.13
+    U = wdgen.gauge_field(dims, 0.6, 91)
+    D = oracle.dense(U, dims, m0, dagger=dagger)
+    ie, io = _parity_index(dims)
+    S = D[np.ix_(ie, ie)] - D[np.ix_(ie, io)] @ np.linalg.solve(D[np.ix_(io, io)], D[np.ix_(io, ie)])
+    v = wdgen.gaussian_source(dims, 1, 92)[0]
+    got = oracle.schur(U, v, dims, m0, dagger=dagger).ravel()
+    want = S @ v.ravel()[ie]
+    assert np.linalg.norm(got[ie] - want) <= 1e-13 * np.linalg.norm(want)
+    assert np.all(got[io] == 0)
+
+
+def test_schur_dagger_is_the_adjoint():
+    dims, m0 = (4, 4, 2, 6), 0.07
+    U = wdgen.gauge_field(dims, 0.5, 93)
+    u, v = wdgen.gaussian_source(dims, 2, 94)
+    even = (oracle.parity(dims) == 0)[..., None, None]
+    u, v = np.where(even, u, 0), np.where(even, v, 0)
+    lhs = np.vdot(u, oracle.schur(U, v, dims, m0))
+    rhs = np.vdot(oracle.schur(U, u, dims, m0, dagger=True), v)
+    assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(u) * np.linalg.norm(v) * 10
+
+
+def test_cg_eo_matches_dense_solve():
+    dims, m0 = (4, 4, 4, 4), 0.1
+    U = wdgen.gauge_field(dims, 0.3, 1001)
+    eta = wdgen.mixed_sources(dims, 1, 1, 95)
+    x, it, res, st = oracle.cg_eo(U, eta, dims, m0)
+    assert st == [0, 0] and max(res) <= 1e-10
+    D = oracle.dense(U, dims, m0)
+    for i in range(2):
+        xs = np.linalg.solve(D, eta[i].ravel())
+        assert np.linalg.norm(x[i].ravel() - xs) <= pins.kappa_bound(m0) * 1e-10 * np.linalg.norm(xs)
+    # the preconditioned system converges in fewer iterations than plain CGNE
+    assert max(it) < min(oracle.cg(U, eta, dims, m0)[1])
+
+
+def test_cg_eo_zero_source_and_free_field():
+    dims, m0 = (8, 8, 8, 8), 0.05
+    U = wdgen.unit_gauge(dims)
+    eta = wdgen.gaussian_source(dims, 2, 96)
+    eta[1] = 0
+    x, it, res, st = oracle.cg_eo(U, eta, dims, m0)
+    assert st == [0, 0] and it[1] == 0 and np.all(x[1] == 0)
+    gam = [oracle.gamma(mu) for mu in range(4)]
+    xs = pins.free_solve_fft(eta[0], dims, m0, -1, gam)
+    assert np.linalg.norm(x[0] - xs) <= pins.kappa_bound(m0) * 2e-10 * np.linalg.norm(xs)
