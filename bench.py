@@ -109,7 +109,10 @@ def main():
     p_fp64 = wd.cg_default_params(tol=tol, inner=wd.F64, reliable_every=0)
     p_bicg = wd.cg_default_params(tol=tol, inner=wd.F32, reliable_every=50, method=wd.METHOD_BICGSTAB)
     p_bicg64 = wd.cg_default_params(tol=tol, inner=wd.F64, reliable_every=0, method=wd.METHOD_BICGSTAB)
-    ws = torch.empty(max(wd.cg_workspace_bytes(g, nrhs, p) for p in (p_mixed, p_fp64, p_bicg, p_bicg64)),
+    p_eo = wd.cg_default_params(tol=tol, inner=wd.F32, reliable_every=50, precondition=wd.PRECOND_EO)
+    p_eo64 = wd.cg_default_params(tol=tol, inner=wd.F64, reliable_every=0, precondition=wd.PRECOND_EO)
+    ws = torch.empty(max(wd.cg_workspace_bytes(g, nrhs, p)
+                         for p in (p_mixed, p_fp64, p_bicg, p_bicg64, p_eo, p_eo64)),
                      dtype=torch.uint8, device=dev)
 
     def solve(params):
@@ -161,15 +164,16 @@ def main():
     f16_value = nrhs / (time.perf_counter() - t0)
     err16 = ((sol - x64).reshape(nrhs, -1).norm(dim=1) / x64.reshape(nrhs, -1).norm(dim=1)).max().item()
 
-    # --------------------------------- BiCGSTAB on D (Sec. 1 alternative), context
-    bicg = {}
-    for name, pb in (("f32", p_bicg), ("f64", p_bicg64)):
+    # ------------- BiCGSTAB on D (Sec. 1 alternative) and even-odd CG, context
+    bicg, eocg = {}, {}
+    for name, pb, dst in (("f32", p_bicg, bicg), ("f64", p_bicg64, bicg), ("f32", p_eo, eocg),
+                          ("f64", p_eo64, eocg)):
         solve(pb)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         repsb, rcb = solve(pb)
         torch.cuda.synchronize()
-        bicg[name] = {"solves_per_s": nrhs / (time.perf_counter() - t0), "converged": rcb == wd.WD_OK,
+        dst[name] = {"solves_per_s": nrhs / (time.perf_counter() - t0), "converged": rcb == wd.WD_OK,
                       "iters": [r["iters"] for r in repsb],
                       "err_vs_fp64_cg_solution": ((sol - x64).reshape(nrhs, -1).norm(dim=1) /
                                                   x64.reshape(nrhs, -1).norm(dim=1)).max().item()}
@@ -352,6 +356,7 @@ def main():
             "dominant_kernel_alg_bytes_per_launch": dom["bytes_total"] / max(dom["launches"], 1),
             "traffic_note": traffic_note,
             "bicgstab_16rhs": bicg,
+            "even_odd_cg_16rhs": eocg,
             "dslash_16rhs": dslash,
             "coo_spmv_1rhs": coo,
             "copy_GBps": copy_gbps,

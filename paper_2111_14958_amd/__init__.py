@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libwd.so")
 
 F64, F32, F16N = 0, 1, 2
 METHOD_CGNE, METHOD_BICGSTAB = 0, 1
+PRECOND_NONE, PRECOND_EO = 0, 1
 PACKED = 1
 GAUGE_F64, GAUGE_F32, GAUGE_F16 = 1, 2, 4
 
@@ -56,7 +57,7 @@ class CGParams(ctypes.Structure):
                 ("reliable_every", ctypes.c_int32), ("inner", ctypes.c_int32),
                 ("use_x0", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("method", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("precondition", ctypes.c_int32)]
 
 
 class CGReport(ctypes.Structure):

@@ -22,6 +22,7 @@
 
 #include "bicgstab_core.h"
 #include "cg_host.h"
+#include "eo_core.h"
 
 namespace wd {
 
@@ -67,6 +68,74 @@ __global__ __launch_bounds__(256) void k_ru2(const Prob *__restrict__ probs, int
 __global__ __launch_bounds__(256) void k_norm(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KN)
     norm_tile(pr, t_);
+}
+
+// Even-odd preconditioning (eo_core.h)
+template <int P, int NR, bool DAG>
+__global__ __launch_bounds__(256) void k_eo_hop1(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(DAG ? KEA1 : KEB1)
+    eo_hop1_tile<P, NR, DAG>(pr, t_);
+}
+template <int P, int NR>
+__global__ __launch_bounds__(256) void k_eo_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KA)
+    eo_phaseA_tile<P, NR>(pr, t_);
+}
+template <int P, int NR>
+__global__ __launch_bounds__(256) void k_eo_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KB)
+    eo_phaseB_tile<P, NR>(pr, t_);
+}
+template <int NR>
+__global__ __launch_bounds__(256) void k_eo_ru2a(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KER2A)
+    eo_ru2a_tile<NR>(pr, t_);
+}
+template <int P, int NR>
+__global__ __launch_bounds__(256) void k_eo_ru2b(const Prob *__restrict__ probs, int nprob, int remap) {
+    WD_KERNEL_PROLOGUE(KR2)
+    eo_ru2b_tile<P, NR>(pr, t_);
+}
+__global__ __launch_bounds__(256) void k_eo_source(const Prob *__restrict__ probs) {
+    eo_source_tile(probs[0], (int)blockIdx.x);
+}
+
+// canonical complex128 [rhs][V][12] -> FP64 half-lattice fields of the even and
+// odd sites (packed layout, V/2 sites each)
+__global__ __launch_bounds__(256) void k_eo_split(const Prob *__restrict__ probs, const double2 *__restrict__ in, void *even, void *odd) {
+    const Prob &pr = probs[0];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (k >= pr.vf) return;
+    FieldPtr fe{even, pr.vf, pr.nrhs}, fo{odd, pr.vf, pr.nrhs};
+    for (int par = 0; par < 2; ++par) {
+        const int s = eo_site(pr.g, k, par);
+        const double2 *src = in + ((size_t)r * pr.g.V + s) * 12;
+        cx<double> v[12];
+#pragma unroll
+        for (int m = 0; m < 12; ++m) v[m] = {src[m].x, src[m].y};
+        Spinor<P64>::store(par ? fo : fe, r, k, v);
+    }
+}
+
+// x_o = (eta_o + H_oe x_e / 2) / A and the canonical complex128 solution
+__global__ __launch_bounds__(256) void k_eo_merge(const Prob *__restrict__ probs, double2 *__restrict__ out) {
+    const Prob &pr = probs[0];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+    if (k >= pr.vf) return;
+    const Geom g = pr.g;
+    FieldPtr fx{pr.x64, pr.vf, pr.nrhs}, fo{pr.eta_o, pr.vf, pr.nrhs};
+    cx<double> v[12], acc[1][12];
+    Spinor<P64>::load(fx, r, k, v);
+    double2 *dst = out + ((size_t)r * g.V + eo_site(g, k, 0)) * 12;
+#pragma unroll
+    for (int m = 0; m < 12; ++m) dst[m] = make_double2(v[m].re, v[m].im);
+    const int so = eo_site(g, k, 1);
+    hopping<P64, false, 1, 1, false, true>(g, so, pr.U64, fx, r, 1u, acc);
+    Spinor<P64>::load(fo, r, k, v);
+    dst = out + ((size_t)r * g.V + so) * 12;
+#pragma unroll
+    for (int m = 0; m < 12; ++m)
+        dst[m] = make_double2(fma(0.5, acc[0][m].re, v[m].re) / pr.diag, fma(0.5, acc[0][m].im, v[m].im) / pr.diag);
 }
 
 // The reduction of a phase as a launch of its own (one block): the kernel
@@ -212,12 +281,52 @@ static void launch_finish(int kind, hipStream_t st, const Prob *d, int nprob) {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, d, nprob, kind);
 }
 
+// even-odd kernels of the stencil kinds (1 or 2 rhs per thread)
+template <int P>
+static void launch_eo(int kind, const KindShape &k, hipStream_t st, const Prob *d, int n) {
+    const dim3 gr(k.grid), bl(k.block);
+    const bool two = k.nr >= 2;
+    switch (kind) {
+    case KEA1:
+        if (two) hipLaunchKernelGGL((k_eo_hop1<P, 2, true>), gr, bl, 0, st, d, n, k.remap);
+        else hipLaunchKernelGGL((k_eo_hop1<P, 1, true>), gr, bl, 0, st, d, n, k.remap);
+        break;
+    case KEB1:
+        if (two) hipLaunchKernelGGL((k_eo_hop1<P, 2, false>), gr, bl, 0, st, d, n, k.remap);
+        else hipLaunchKernelGGL((k_eo_hop1<P, 1, false>), gr, bl, 0, st, d, n, k.remap);
+        break;
+    case KA:
+        if (two) hipLaunchKernelGGL((k_eo_phaseA<P, 2>), gr, bl, 0, st, d, n, k.remap);
+        else hipLaunchKernelGGL((k_eo_phaseA<P, 1>), gr, bl, 0, st, d, n, k.remap);
+        break;
+    case KB:
+        if (two) hipLaunchKernelGGL((k_eo_phaseB<P, 2>), gr, bl, 0, st, d, n, k.remap);
+        else hipLaunchKernelGGL((k_eo_phaseB<P, 1>), gr, bl, 0, st, d, n, k.remap);
+        break;
+    case KER2A:
+        if (two) hipLaunchKernelGGL((k_eo_ru2a<2>), gr, bl, 0, st, d, n, k.remap);
+        else hipLaunchKernelGGL((k_eo_ru2a<1>), gr, bl, 0, st, d, n, k.remap);
+        break;
+    case KR2:
+        if (two) hipLaunchKernelGGL((k_eo_ru2b<P, 2>), gr, bl, 0, st, d, n, k.remap);
+        else hipLaunchKernelGGL((k_eo_ru2b<P, 1>), gr, bl, 0, st, d, n, k.remap);
+        break;
+    }
+}
+
 void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob) {
     const KindShape &k = ls.k[kind];
     if (k.grid <= 0) return;
     const bool reduces = kind == KA || kind == KB || kind == KR2 || kind == KN || kind == KS2 || kind == KS4 ||
                          kind == KS5;
-    launch_kind_tiles(kind, inner, k, st, d, nprob);
+    const bool eo_kind = kind == KA || kind == KB || kind == KR2 || kind == KEA1 || kind == KEB1 || kind == KER2A;
+    if (ls.eo && eo_kind) {
+        if (inner == P64) launch_eo<P64>(kind, k, st, d, nprob);
+        else if (inner == P32) launch_eo<P32>(kind, k, st, d, nprob);
+        else launch_eo<P16>(kind, k, st, d, nprob);
+    } else {
+        launch_kind_tiles(kind, inner, k, st, d, nprob);
+    }
     if (reduces) launch_finish(kind, st, d, nprob);
 }
 
@@ -272,22 +381,29 @@ void launch_zero(void *p, size_t bytes, hipStream_t st) {
 // ------------------------------------------------------------- host plan
 static size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
-WsLayout ws_layout(int64_t V, int nrhs, int inner, int method) {
+WsLayout ws_layout(int64_t V, int nrhs, int inner, int method, int eo) {
     WsLayout L;
     size_t o = 0;
+    const int64_t Vf = eo ? V / 2 : V;   // sites of a vector
     L.prob = o; o += al256(sizeof(Prob));
     L.scal = o; o += al256(sizeof(Scal) * nrhs);
     L.bar = o; o += 256;
     L.summary = o; o += 256;
     L.part = o; o += al256((size_t)((V + 63) / 64) * nrhs * PSTRIDE * sizeof(double));
-    L.eta64 = o; o += al256(spinor_bytes(WD_F64, V, nrhs));
-    L.x64 = o; o += al256(spinor_bytes(WD_F64, V, nrhs));
+    L.eta64 = o; o += al256(spinor_bytes(WD_F64, Vf, nrhs));
+    L.x64 = o; o += al256(spinor_bytes(WD_F64, Vf, nrhs));
     const int xp = inner == WD_F16N ? WD_F32 : inner;
-    L.xlo = o; o += al256(spinor_bytes(xp, V, nrhs));
-    L.r = o; o += al256(spinor_bytes(inner, V, nrhs));
-    L.p = o; o += al256(spinor_bytes(inner, V, nrhs));
-    L.q = o; o += al256(spinor_bytes(inner, V, nrhs));   // BiCGSTAB: v
+    L.xlo = o; o += al256(spinor_bytes(xp, Vf, nrhs));
+    L.r = o; o += al256(spinor_bytes(inner, Vf, nrhs));
+    L.p = o; o += al256(spinor_bytes(inner, Vf, nrhs));
+    L.q = o; o += al256(spinor_bytes(inner, Vf, nrhs));   // BiCGSTAB: v
     L.bscal = L.rh = L.sv = L.tv = 0;
+    L.eta_o = L.tmp = L.w64 = 0;
+    if (eo) {
+        L.eta_o = o; o += al256(spinor_bytes(WD_F64, Vf, nrhs));
+        L.tmp = o; o += al256(spinor_bytes(inner, Vf, nrhs));
+        L.w64 = o; o += al256(spinor_bytes(WD_F64, Vf, nrhs));
+    }
     if (method == METHOD_BICGSTAB) {
         L.bscal = o; o += al256(sizeof(BScal) * nrhs);
         L.rh = o; o += al256(spinor_bytes(inner, V, nrhs));
@@ -312,7 +428,11 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
     Shape sa = shape_lookup(ka), sb = shape_lookup(kb), sr = shape_lookup(kr);
     if (sr.nr > 2) sr.nr = 2;
     // stencil kinds: A (D^dagger), B, S2 and S4 (D), R2 (FP64 D); the rest stream
-    const Shape *st[NKIND] = {&sa, &sb, nullptr, nullptr, &sr, nullptr, nullptr, &sb, nullptr, &sb, nullptr};
+    // even-odd: the first half hops take the shape of their phase
+    const Shape *st[NKIND] = {&sa, &sb, nullptr, nullptr, &sr, nullptr, nullptr, &sb, nullptr, &sb, nullptr,
+                              &sa, &sb, &sr};
+    const int Vf = pr.vf;
+    ls.eo = pr.eo;
     for (int k = 0; k < NKIND; ++k) {
         KindShape &ks = ls.k[k];
         if (st[k]) {
@@ -324,7 +444,11 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.order = strip | (st[k]->gmajor ? 1 << 16 : 0);
             // plane-blocked phases A and B: one xy-plane of 64..256 sites per
             // block (the partial-sum buffer holds one entry per 64 sites)
-            ks.xy = (k == KA || k == KB) && st[k]->xylds && np >= 64 && np <= 256;
+            ks.xy = (k == KA || k == KB) && st[k]->xylds && np >= 64 && np <= 256 && !pr.eo;
+            if (pr.eo) {   // the half-lattice kernels: site blocks, lexicographic order
+                ks.order = 0;
+                if (ks.nr > 2) ks.nr = 2;
+            }
             if (ks.xy) {
                 ks.block = 256;
                 if (ks.nr > 2) ks.nr = 2;
@@ -339,7 +463,7 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.xy = 0;
         }
         pr.sorder[k] = ks.order;
-        pr.nsb[k] = ks.xy ? V / np : (V + ks.block - 1) / ks.block;
+        pr.nsb[k] = ks.xy ? V / np : (Vf + ks.block - 1) / ks.block;
         pr.ng[k] = (nrhs + ks.nr - 1) / ks.nr;
         pr.t0[k] = 0;
         pr.nt[k] = pr.nsb[k] * pr.ng[k];
@@ -373,6 +497,9 @@ void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_par
                char *ws, const WsLayout &L) {
     pr.g = make_geom(g);
     pr.diag = 4.0 + m0;
+    pr.eo = p.precondition == WD_PRECOND_EO ? 1 : 0;
+    pr.vf = pr.eo ? (int)(g->V / 2) : (int)g->V;
+    pr.eo_c = 0.25 / pr.diag;
     pr.tol2 = p.tol * p.tol;
     pr.nrhs = nrhs;
     pr.max_iter = p.max_iter;
@@ -393,6 +520,9 @@ void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_par
     pr.sv = L.sv ? ws + L.sv : nullptr;
     pr.tv = L.tv ? ws + L.tv : nullptr;
     pr.bs = L.bscal ? (BScal *)(ws + L.bscal) : nullptr;
+    pr.eta_o = L.eta_o ? ws + L.eta_o : nullptr;
+    pr.tmp = L.tmp ? ws + L.tmp : nullptr;
+    pr.w64 = L.w64 ? ws + L.w64 : nullptr;
 }
 
 void init_scalars(std::vector<Scal> &sc, int nrhs) {
@@ -559,7 +689,8 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
            void *ws, size_t ws_bytes, wd_cg_report *reps, hipStream_t st) {
     const auto t_start = std::chrono::steady_clock::now();
     const int64_t V = g->V;
-    const WsLayout L = ws_layout(V, nrhs, p.inner, p.method);
+    const int eo = p.precondition == WD_PRECOND_EO ? 1 : 0;
+    const WsLayout L = ws_layout(V, nrhs, p.inner, p.method, eo);
     WD_CHECK(ws_bytes >= L.total, WD_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
     char *w = (char *)ws;
     Prob hp;
@@ -585,15 +716,32 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     WD_HIP(hipMemcpyAsync(w + L.scal, sc.data(), sizeof(Scal) * nrhs, hipMemcpyHostToDevice, st));
     WD_HIP(hipMemsetAsync(w + L.bar, 0, 256, st));
     // fields
-    int rc = launch_pack_spinor(WD_F64, src, w + L.eta64, (int)V, nrhs, st);
-    if (rc) return rc;
-    if (p.use_x0) rc = launch_pack_spinor(WD_F64, sol, w + L.x64, (int)V, nrhs, st);
-    else launch_zero(w + L.x64, spinor_bytes(WD_F64, V, nrhs), st);
-    if (rc) return rc;
-    launch_zero(w + L.xlo, spinor_bytes(p.inner == WD_F16N ? WD_F32 : p.inner, V, nrhs), st);
+    const int64_t Vf = hp.vf;
+    int rc = WD_OK;
+    if (eo) {   // even and odd halves of the source (and of x0: its odd half is not used)
+        const dim3 gsplit((unsigned)((Vf + 255) / 256), (unsigned)nrhs);
+        hipLaunchKernelGGL(k_eo_split, gsplit, dim3(256), 0, st, dprob, (const double2 *)src, (void *)(w + L.eta64),
+                           (void *)(w + L.eta_o));
+        if (p.use_x0)
+            hipLaunchKernelGGL(k_eo_split, gsplit, dim3(256), 0, st, dprob, (const double2 *)sol,
+                               (void *)(w + L.x64), (void *)(w + L.w64));
+        else launch_zero(w + L.x64, spinor_bytes(WD_F64, Vf, nrhs), st);
+    } else {
+        rc = launch_pack_spinor(WD_F64, src, w + L.eta64, (int)V, nrhs, st);
+        if (rc) return rc;
+        if (p.use_x0) rc = launch_pack_spinor(WD_F64, sol, w + L.x64, (int)V, nrhs, st);
+        else launch_zero(w + L.x64, spinor_bytes(WD_F64, V, nrhs), st);
+        if (rc) return rc;
+    }
+    launch_zero(w + L.xlo, spinor_bytes(p.inner == WD_F16N ? WD_F32 : p.inner, Vf, nrhs), st);
     if (bicg) launch_zero(w + L.bscal, al256(sizeof(BScal) * nrhs), st);
-    // |eta|, first true residual, p = r (BiCGSTAB: its first stage S1 does that)
+    // |eta|, (even-odd: the Schur system's source), first true residual, p = r
+    // (BiCGSTAB: its first stage S1 does that)
     launch_kind(KN, p.inner, ls, st, dprob, 1);
+    if (eo) {
+        hipLaunchKernelGGL(k_eo_source, dim3((unsigned)(((Vf + 255) / 256) * nrhs)), dim3(256), 0, st, dprob);
+        launch_kind(KER2A, p.inner, ls, st, dprob, 1);
+    }
     launch_kind(KR2, p.inner, ls, st, dprob, 1);
     if (!bicg) launch_kind(KC, p.inner, ls, st, dprob, 1);
     const int *dabort = persistent ? (const int *)(w + L.bar + 128) : nullptr;
@@ -608,7 +756,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     key.inner = p.inner;
     key.K = K;
     key.persistent = persistent;
-    key.method = p.method;
+    key.method = p.method | (eo << 4);
     for (int k = 0; k < NKIND; ++k) {
         key.shp[k][0] = ls.k[k].block;
         key.shp[k][1] = ls.k[k].nr;
@@ -630,11 +778,14 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
         if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, K, w + L.bar + 64);
         else
             for (int it = 0; it < K; ++it) {
+                if (eo) launch_kind(KEA1, p.inner, ls, cs, dprob, 1);
                 launch_kind(KA, p.inner, ls, cs, dprob, 1);
+                if (eo) launch_kind(KEB1, p.inner, ls, cs, dprob, 1);
                 launch_kind(KB, p.inner, ls, cs, dprob, 1);
                 launch_kind(KC, p.inner, ls, cs, dprob, 1);
             }
         launch_kind(KR1, p.inner, ls, cs, dprob, 1);
+        if (eo) launch_kind(KER2A, p.inner, ls, cs, dprob, 1);
         launch_kind(KR2, p.inner, ls, cs, dprob, 1);
         launch_kind(KC, p.inner, ls, cs, dprob, 1);
         launch_summary(cs, dprob, 1, dsum, dabort);
@@ -648,7 +799,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     WD_HIP(hipStreamSynchronize(st));
     // every chunk either converges a field or spends K iterations of it
     const int max_chunks = p.max_iter / K + 2 * (p.max_iter / (K * 4) + 4);
-    const bool prof = g_prof_on.load() != 0 && !persistent && !bicg;
+    const bool prof = g_prof_on.load() != 0 && !persistent && !bicg && !eo;
     for (int c = 0; c < max_chunks && hsum[0] > 0; ++c) {
         hipError_t e = hipSuccess;
         if (prof) {
@@ -676,9 +827,15 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
         }
     }
     (void)hipHostFree(hsum);
-    // solution out, scalars back
-    rc = launch_unpack_spinor(WD_F64, w + L.x64, sol, (int)V, nrhs, st);
-    if (rc) return rc;
+    // solution out (even-odd: x_o from x_e), scalars back
+    if (eo) {
+        hipLaunchKernelGGL(k_eo_merge, dim3((unsigned)((Vf + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, dprob,
+                           (double2 *)sol);
+        WD_HIP(hipGetLastError());
+    } else {
+        rc = launch_unpack_spinor(WD_F64, w + L.x64, sol, (int)V, nrhs, st);
+        if (rc) return rc;
+    }
     WD_HIP(hipMemcpyAsync(sc.data(), w + L.scal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st));
     WD_HIP(hipStreamSynchronize(st));
     int first_bad = WD_OK;
@@ -715,7 +872,10 @@ int check_params(const wd_cg_params *p) {
     WD_CHECK(p->method == METHOD_CGNE || p->method == METHOD_BICGSTAB, WD_EINVAL, "unknown method %d", p->method);
     WD_CHECK(p->method == METHOD_CGNE || p->persistent != 1, WD_EINVAL,
              "the persistent kernel runs CG only");
-    WD_CHECK(p->reserved == 0, WD_EINVAL, "reserved field of the parameters is not 0");
+    WD_CHECK(p->precondition == WD_PRECOND_NONE || p->precondition == WD_PRECOND_EO, WD_EINVAL,
+             "unknown preconditioning %d", p->precondition);
+    WD_CHECK(p->precondition == WD_PRECOND_NONE || (p->method == METHOD_CGNE && p->persistent != 1), WD_EINVAL,
+             "even-odd preconditioning runs CG without the persistent kernel");
     return WD_OK;
 }
 
@@ -741,7 +901,8 @@ void wd_cg_default_params(wd_cg_params *p) {
 size_t wd_cg_workspace_bytes(const wd_gauge *g, int32_t nrhs, const wd_cg_params *p) {
     if (!g || !p || nrhs < 1 || nrhs > MAX_RHS || p->inner < 0 || p->inner > 2) return 0;
     if (p->method != METHOD_CGNE && p->method != METHOD_BICGSTAB) return 0;
-    return ws_layout(g->V, nrhs, p->inner, p->method).total;
+    if (p->precondition != WD_PRECOND_NONE && p->precondition != WD_PRECOND_EO) return 0;
+    return ws_layout(g->V, nrhs, p->inner, p->method, p->precondition == WD_PRECOND_EO).total;
 }
 
 int wd_cg_solve_batch(const wd_gauge *g, double m0, const void *src, void *sol, int32_t nrhs,
@@ -754,6 +915,8 @@ int wd_cg_solve_batch(const wd_gauge *g, double m0, const void *src, void *sol, 
     if (rc) return rc;
     WD_CHECK(g->U[p->inner], WD_EINVAL, "gauge handle holds no links in precision %d", p->inner);
     WD_CHECK(src != sol, WD_EINVAL, "src and sol must not overlap");
+    WD_CHECK(p->precondition != WD_PRECOND_EO || g->dims[0] % 2 == 0, WD_EINVAL,
+             "even-odd preconditioning needs an even Lx (got %d)", g->dims[0]);
     rc = require_gfx950();
     if (rc) return rc;
     return cg_run(g, m0, src, sol, nrhs, *p, ws, ws_bytes, reps, (hipStream_t)stream);

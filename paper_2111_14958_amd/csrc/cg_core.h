@@ -29,8 +29,11 @@ enum : int { ST_ACTIVE = 0, ST_FROZEN = 1, ST_DONE = 2, ST_BREAKDOWN = 3, ST_NOT
 // reliable update R2 (r = eta - D x64), source norm N, and the five BiCGSTAB
 // stages S1 (p update), S2 (v = D p), S3 (s = r - alpha v), S4 (t = D s),
 // S5 (x and r updates)
+// With even-odd preconditioning (eo_core.h) A, B and R2 apply the Schur
+// complement in two half-lattice hops: EA1, EB1 and ER2A are the first ones.
 enum : int { KA = 0, KB = 1, KC = 2, KR1 = 3, KR2 = 4, KN = 5,
-             KS1 = 6, KS2 = 7, KS3 = 8, KS4 = 9, KS5 = 10, NKIND = 11 };
+             KS1 = 6, KS2 = 7, KS3 = 8, KS4 = 9, KS5 = 10,
+             KEA1 = 11, KEB1 = 12, KER2A = 13, NKIND = 14 };
 enum : int { METHOD_CGNE = 0, METHOD_BICGSTAB = 1 };
 // doubles per (site block, rhs) partial-sum entry (complex dot products need
 // up to three numbers)
@@ -65,6 +68,9 @@ struct alignas(16) Prob {
     double diag;      // 4 + m0
     double tol2;
     int nrhs, max_iter, ru_every, method;
+    int eo;           // 1: even-odd preconditioned (vectors live on the even sites)
+    int vf;           // sites of a vector: V, or V/2 with even-odd
+    double eo_c;      // 1 / (4 diag): Dhat = diag - eo_c H_eo H_oe
     int nsb[NKIND];   // site blocks per kernel kind
     int ng[NKIND];    // rhs groups per kernel kind
     int t0[NKIND];    // first tile of this problem in a grouped launch
@@ -78,6 +84,9 @@ struct alignas(16) Prob {
     Scal *sc;                 // [nrhs]
     void *rh, *v, *sv, *tv;   // BiCGSTAB: shadow residual r_hat, v = D p, s, t = D s
     BScal *bs;                // BiCGSTAB scalars [nrhs]
+    void *eta_o;              // even-odd: odd half of the source (FP64)
+    void *tmp;                // even-odd: odd-site intermediate of A and B (inner precision)
+    void *w64;                // even-odd: odd-site intermediate of R2 (FP64)
 };
 
 // precision x_lo is stored in
@@ -356,8 +365,8 @@ __device__ __forceinline__ void phaseC_tile(const Prob &pr, int t) {
     const int sb = t / pr.nrhs, i = t - sb * pr.nrhs;
     const int s = sb * blockDim.x + threadIdx.x;
     const Scal &c = pr.sc[i];
-    if (c.state != ST_ACTIVE || !c.pending_p || s >= pr.g.V) return;
-    FieldPtr fr{pr.r, pr.g.V, pr.nrhs}, fp{pr.p, pr.g.V, pr.nrhs};
+    if (c.state != ST_ACTIVE || !c.pending_p || s >= pr.vf) return;
+    FieldPtr fr{pr.r, pr.vf, pr.nrhs}, fp{pr.p, pr.vf, pr.nrhs};
     cx<R> r[12], p[12];
     Spinor<P>::load(fr, i, s, r);
     if (!c.restart) {
@@ -377,8 +386,8 @@ __device__ __forceinline__ void ru1_tile(const Prob &pr, int t) {
     typedef typename real_of<XP>::type RX;
     const int sb = t / pr.nrhs, i = t - sb * pr.nrhs;
     const int s = sb * blockDim.x + threadIdx.x;
-    if (pr.sc[i].state != ST_FROZEN || s >= pr.g.V) return;
-    FieldPtr fx{pr.x_lo, pr.g.V, pr.nrhs}, f64{pr.x64, pr.g.V, pr.nrhs};
+    if (pr.sc[i].state != ST_FROZEN || s >= pr.vf) return;
+    FieldPtr fx{pr.x_lo, pr.vf, pr.nrhs}, f64{pr.x64, pr.vf, pr.nrhs};
     cx<RX> xl[12];
     cx<double> x[12];
     Spinor<XP>::load(fx, i, s, xl);
@@ -485,12 +494,18 @@ __device__ __forceinline__ void norm_tile(const Prob &pr, int t) {
     const int sb = t / pr.nrhs, i = t - sb * pr.nrhs;
     const int s = sb * blockDim.x + threadIdx.x;
     double part[1] = {0.0};
-    if (s < pr.g.V) {
-        FieldPtr fe{pr.eta64, pr.g.V, pr.nrhs};
+    if (s < pr.vf) {
+        FieldPtr fe{pr.eta64, pr.vf, pr.nrhs};
         cx<double> e[12];
         Spinor<P64>::load(fe, i, s, e);
 #pragma unroll
         for (int k = 0; k < 12; ++k) part[0] += norm2(e[k]);
+        if (pr.eo) {   // |eta|^2 of the whole field: the odd half too
+            FieldPtr fo{pr.eta_o, pr.vf, pr.nrhs};
+            Spinor<P64>::load(fo, i, s, e);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) part[0] += norm2(e[k]);
+        }
     }
     block_sum<1>(part);
     if (threadIdx.x == 0) part_at(pr, sb, i, 0) = part[0];

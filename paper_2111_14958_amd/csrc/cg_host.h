@@ -16,16 +16,18 @@ struct KindShape {
 };
 struct LaunchSet {
     KindShape k[NKIND];
+    int eo = 0;   // even-odd preconditioned solve: A, B, R2 are Schur kernels
 };
 
 // Byte offsets of the pieces of a solve workspace.
 struct WsLayout {
     size_t prob, scal, bar, summary, part, eta64, x64, xlo, r, p, q;
     size_t bscal, rh, sv, tv;   // BiCGSTAB only (0 otherwise)
+    size_t eta_o, tmp, w64;     // even-odd only (0 otherwise)
     size_t total;
 };
 
-WsLayout ws_layout(int64_t V, int nrhs, int inner, int method);
+WsLayout ws_layout(int64_t V, int nrhs, int inner, int method, int eo = 0);
 void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr);
 void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner);
 void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_params &p, char *ws,

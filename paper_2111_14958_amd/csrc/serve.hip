@@ -405,7 +405,8 @@ static int check_request(const wd_request *r) {
     if (rc) return rc;
     WD_CHECK(r->params.inner == WD_F32 || r->params.inner == WD_F64, WD_EINVAL,
              "the server runs FP32 or FP64 inner iterations");
-    WD_CHECK(r->params.method == METHOD_CGNE, WD_EINVAL, "the server runs CG on the normal equations only");
+    WD_CHECK(r->params.method == METHOD_CGNE && r->params.precondition == WD_PRECOND_NONE, WD_EINVAL,
+             "the server runs unpreconditioned CG on the normal equations only");
     return WD_OK;
 }
 

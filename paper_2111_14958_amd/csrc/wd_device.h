@@ -363,7 +363,9 @@ template <> struct LdsSpinor<P64> {
 //
 // XYLDS: the neighbours in x and y are read from the block's LDS copy of its
 // xy-plane (`xy`, plane starting at site `plane0`, np sites) instead of memory.
-template <int P, bool DAG, int NR, int ORDERED = 1, bool XYLDS = false>
+// HALF: `in` holds only the sites of the other parity, site n at index n / 2
+// (even-odd preconditioning; needs an even Lx).
+template <int P, bool DAG, int NR, int ORDERED = 1, bool XYLDS = false, bool HALF = false>
 __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, const FieldPtr &in,
                                         int rhs0, unsigned act, cx<typename real_of<P>::type> acc[NR][12],
                                         const cx<typename real_of<P>::type> (*first)[12] = nullptr,
@@ -437,7 +439,7 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
             if (act >> j & 1) {
                 cx<R> p[12], h[6], w[6];
                 if constexpr (XYLDS && MU < 2) LdsSpinor<P>::get(xy, np, j, nb - plane0, p);
-                else Spinor<P>::load(in, rhs0 + j, nb, p);
+                else Spinor<P>::load(in, rhs0 + j, HALF ? nb >> 1 : nb, p);
                 project<MU, S>(p, h);
                 if constexpr (FWD) link_mul(u, h, w);
                 else link_adj_mul(u, h, w);

@@ -150,7 +150,7 @@ def test_rejected_parameters():
     eta = wdgen.gaussian_source(dims, 1, 12)
     say("bicgstab parameter errors")
     g = wd.Gauge(dev(U), dims)
-    for kw in ({"persistent": 1}, {"method": 2}, {"reserved": 1}):
+    for kw in ({"persistent": 1}, {"method": 2}, {"precondition": 1}, {"precondition": 7}):
         p = _params(wd.F32)
         for k, v in kw.items():
             setattr(p, k, v)
