@@ -410,10 +410,10 @@ FAMILY_DSLASH, FAMILY_CG_A, FAMILY_CG_B, FAMILY_CG_R = 0, 1, 2, 3
 
 def shape_set(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int, block: int,
               rhs_per_thread: int = 1, xcd_remap: int = 1, hop_order: int = 1, rhs_loop: int = 1,
-              strip: int = 0, group_major: int = 0, xy_lds: int = 0):
+              strip: int = 0, group_major: int = 0, xy_lds: int = 0, max_blocks_per_cu: int = 0):
     r = TuneResult(block=block, rhs_per_thread=rhs_per_thread, xcd_remap=xcd_remap,
                    hop_order=hop_order, rhs_loop=rhs_loop,
-                   site_order=strip | (group_major << 16) | (xy_lds << 17))
+                   site_order=strip | (group_major << 16) | (xy_lds << 17) | (max_blocks_per_cu << 18))
     _check(lib().wd_shape_set(g.handle, prec, nrhs, 1 if dagger else 0, family, ctypes.byref(r)),
            "wd_shape_set")
 
@@ -425,7 +425,8 @@ def shape_get(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int) -> dict
     out = {f[0]: getattr(r, f[0]) for f in r._fields_ if f[0] not in ("us", "gbps")}
     out["strip"] = r.site_order & 0xFFFF
     out["group_major"] = (r.site_order >> 16) & 1
-    out["xy_lds"] = r.site_order >> 17
+    out["xy_lds"] = (r.site_order >> 17) & 1
+    out["max_blocks_per_cu"] = r.site_order >> 18
     return out
 
 

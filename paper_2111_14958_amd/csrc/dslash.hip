@@ -192,7 +192,10 @@ int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void 
     if (sh.xylds && np <= 256) {   // else the site-blocked kernel below
         const int nrx = prec == WD_F64 ? 1 : std::min(nr, 2);
         const int ngx = (nrhs + nrx - 1) / nrx;
-        const size_t lds = xy_lds_bytes(prec, nrx, np);
+        size_t lds = xy_lds_bytes(prec, nrx, np);
+        // fewer resident blocks keep an XCD's in-flight data within its L2: the
+        // LDS request is padded so at most occ blocks fit the 160 KB of a CU
+        if (sh.occ > 0 && (size_t)(163840 / sh.occ) > lds) lds = std::min<size_t>(163840 / sh.occ, 65536);
         FieldPtr fi{(void *)in, g.V, nrhs}, fo{out, g.V, nrhs};
         const void *U = gg->U[prec];
         const dim3 grid((g.V / np) * ngx);

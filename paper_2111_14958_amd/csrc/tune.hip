@@ -73,9 +73,9 @@ static void load_cache_locked() {
         ShapeKey k;
         Shape s;
         double us = 0;
-        if (sscanf(line, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %lf", &k.L[0], &k.L[1], &k.L[2],
+        if (sscanf(line, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %lf", &k.L[0], &k.L[1], &k.L[2],
                    &k.L[3], &k.prec, &k.nrhs, &k.dag, &s.block, &s.nr, &s.remap, &s.ordered, &s.rloop, &s.strip,
-                   &s.gmajor, &s.xylds, &us) == 16)
+                   &s.gmajor, &s.xylds, &s.occ, &us) == 17)
             g_table[k] = {s, us};
     }
     fclose(f);
@@ -100,8 +100,8 @@ static void append_cache(const ShapeKey &k, const Shape &s, double us) {
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.3f\n", k.L[0], k.L[1], k.L[2], k.L[3],
-            k.prec, k.nrhs, k.dag, s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor, s.xylds, us);
+    fprintf(f, "gfx950 %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.3f\n", k.L[0], k.L[1], k.L[2], k.L[3],
+            k.prec, k.nrhs, k.dag, s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor, s.xylds, s.occ, us);
     fclose(f);
 }
 
@@ -183,7 +183,7 @@ int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     cfg->xcd_remap = s.remap;
     cfg->hop_order = s.ordered;
     cfg->rhs_loop = s.rloop;
-    cfg->site_order = s.strip | (s.gmajor << 16) | (s.xylds << 17);
+    cfg->site_order = s.strip | (s.gmajor << 16) | (s.xylds << 17) | (s.occ << 18);
     return WD_OK;
 }
 
@@ -200,7 +200,7 @@ int wd_shape_get(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     cfg->xcd_remap = s.remap;
     cfg->hop_order = s.ordered;
     cfg->rhs_loop = s.rloop;
-    cfg->site_order = s.strip | (s.gmajor << 16) | (s.xylds << 17);
+    cfg->site_order = s.strip | (s.gmajor << 16) | (s.xylds << 17) | (s.occ << 18);
     return WD_OK;
 }
 
@@ -221,8 +221,9 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     WD_CHECK(!(family == FAM_CG_R && sh->rhs_per_thread > 2), WD_EINVAL, "reliable-update kernel takes <= 2 rhs");
     WD_CHECK(!(prec == WD_F64 && family != FAM_DSLASH && sh->rhs_per_thread > 2), WD_EINVAL,
              "FP64 CG kernels take <= 2 rhs per thread");
-    const int strip = sh->site_order & 0xffff, gmajor = (sh->site_order >> 16) & 1, xylds = sh->site_order >> 17;
-    WD_CHECK(sh->site_order >= 0 && (xylds == 0 || xylds == 1), WD_EINVAL, "site_order 0x%x", sh->site_order);
+    const int strip = sh->site_order & 0xffff, gmajor = (sh->site_order >> 16) & 1,
+              xylds = (sh->site_order >> 17) & 1, occ = sh->site_order >> 18;
+    WD_CHECK(sh->site_order >= 0 && occ <= 8, WD_EINVAL, "site_order 0x%x", sh->site_order);
     WD_CHECK(!xylds || (family != FAM_CG_R && g->dims[0] * g->dims[1] <= 256), WD_EINVAL,
              "plane-blocked LDS variant: operator and CG phase A/B kernels, Lx*Ly <= 256");
     ShapeKey k{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, prec, nrhs, dagger ? 1 : 0, family};
@@ -235,6 +236,7 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     s.strip = strip;
     s.gmajor = gmajor;
     s.xylds = xylds;
+    s.occ = occ;
     shape_store(k, s);
     return WD_OK;
 }
@@ -292,16 +294,16 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
         }
         if (memcmp(h_out.data(), h_ref.data(), nb) != 0) {   // rejected
             if (verbose) fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d strip %d gmajor %d "
-                                 "xylds %d: output differs, rejected\n", s.block, s.nr, s.remap, s.ordered, s.rloop,
-                                 s.strip, s.gmajor, s.xylds);
+                                 "xylds %d occ %d: output differs, rejected\n", s.block, s.nr, s.remap, s.ordered, s.rloop,
+                                 s.strip, s.gmajor, s.xylds, s.occ);
             return;
         }
         double us = 0;
         rc = time_shape(g, prec, dag, in, out, nrhs, s, st, 10, &us);
         if (verbose && !rc)
-            fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d strip %d gmajor %d xylds %d: "
+            fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d strip %d gmajor %d xylds %d occ %d: "
                     "%.2f us, %.0f GB/s\n", s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor, s.xylds,
-                    us, algorithmic_bytes(prec, V, nrhs) / (us * 1e-6) / 1e9);
+                    s.occ, us, algorithmic_bytes(prec, V, nrhs) / (us * 1e-6) / 1e9);
         if (!rc && us < best_us) { best_us = us; bestshape = s; }
     };
     for (int bi = 0; bi < 3 && !rc; ++bi)
@@ -330,9 +332,11 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     // plane-blocked variant: one xy-plane per block, x/y neighbours from LDS
     const int np = g->dims[0] * g->dims[1];
     if (np <= 256)
-        for (int cand = 0; cand < 2 * 2 * 2 * 8 && !rc; ++cand) {
+        for (int cand = 0; cand < 2 * 2 * 2 * 8 * 4 && !rc; ++cand) {
             Shape s;
-            const int o = cand >> 3;
+            const int occs[4] = {0, 3, 4, 6};
+            s.occ = occs[cand / 64];
+            const int o = (cand >> 3) & 7;
             s.block = np;
             s.nr = (cand & 1) ? 2 : 1;
             s.remap = (cand >> 1) & 1;
@@ -360,7 +364,7 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
         best->xcd_remap = bestshape.remap;
         best->hop_order = bestshape.ordered;
         best->rhs_loop = bestshape.rloop;
-        best->site_order = bestshape.strip | (bestshape.gmajor << 16) | (bestshape.xylds << 17);
+        best->site_order = bestshape.strip | (bestshape.gmajor << 16) | (bestshape.xylds << 17) | (bestshape.occ << 18);
         best->us = best_us;
         best->gbps = algorithmic_bytes(prec, V, nrhs) / (best_us * 1e-6) / 1e9;
     }

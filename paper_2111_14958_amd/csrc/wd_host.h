@@ -48,7 +48,8 @@ struct Shape {
     int rloop = 1;           // rhs groups a block handles one after the other
     int strip = 0;           // processing order: z-strips of this width (0: lexicographic)
     int gmajor = 0;          // tiles ordered rhs-group-major (1) or site-block-major (0)
-    int xylds = 0;           // operator kernel only: one xy-plane per block, x/y neighbours from LDS
+    int xylds = 0;           // plane-blocked: one xy-plane per block, x/y neighbours from LDS
+    int occ = 0;             // plane-blocked operator: at most occ blocks per CU (0: no limit)
 };
 
 // Key of the launch-shape table: lattice, precision, rhs count, dagger, and
