@@ -306,7 +306,8 @@ typedef struct {
     const void *gauge_dev;  /* canonical complex128 links; read during admission     */
     const void *src_dev;    /* canonical complex128 [nrhs][V][12]; read at admission */
     void       *sol_dev;    /* canonical complex128 [nrhs][V][12]; written at retire */
-    wd_cg_params params;    /* inner must be WD_F32 or WD_F64                         */
+    wd_cg_params params;    /* inner WD_F32 or WD_F64; WD_METHOD_CGNE; precondition
+                               WD_PRECOND_NONE or WD_PRECOND_EO (even Lx)              */
 } wd_request;
 
 typedef struct {

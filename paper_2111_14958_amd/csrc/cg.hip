@@ -138,6 +138,18 @@ __global__ __launch_bounds__(256) void k_eo_merge(const Prob *__restrict__ probs
         dst[m] = make_double2(fma(0.5, acc[0][m].re, v[m].re) / pr.diag, fma(0.5, acc[0][m].im, v[m].im) / pr.diag);
 }
 
+void launch_eo_split(const Prob *d, int64_t vf, int nrhs, const void *src, void *even, void *odd, hipStream_t st) {
+    hipLaunchKernelGGL(k_eo_split, dim3((unsigned)((vf + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, d,
+                       (const double2 *)src, even, odd);
+}
+void launch_eo_source(const Prob *d, int64_t vf, int nrhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_eo_source, dim3((unsigned)(((vf + 255) / 256) * nrhs)), dim3(256), 0, st, d);
+}
+void launch_eo_merge(const Prob *d, int64_t vf, int nrhs, void *sol, hipStream_t st) {
+    hipLaunchKernelGGL(k_eo_merge, dim3((unsigned)((vf + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, d,
+                       (double2 *)sol);
+}
+
 // The reduction of a phase as a launch of its own (one block): the kernel
 // boundary makes every block's partial sums visible.  (Finishing it in the
 // last block of the phase instead, found with an atomic ticket, needs a
@@ -719,12 +731,8 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     const int64_t Vf = hp.vf;
     int rc = WD_OK;
     if (eo) {   // even and odd halves of the source (and of x0: its odd half is not used)
-        const dim3 gsplit((unsigned)((Vf + 255) / 256), (unsigned)nrhs);
-        hipLaunchKernelGGL(k_eo_split, gsplit, dim3(256), 0, st, dprob, (const double2 *)src, (void *)(w + L.eta64),
-                           (void *)(w + L.eta_o));
-        if (p.use_x0)
-            hipLaunchKernelGGL(k_eo_split, gsplit, dim3(256), 0, st, dprob, (const double2 *)sol,
-                               (void *)(w + L.x64), (void *)(w + L.w64));
+        launch_eo_split(dprob, Vf, nrhs, src, w + L.eta64, w + L.eta_o, st);
+        if (p.use_x0) launch_eo_split(dprob, Vf, nrhs, sol, w + L.x64, w + L.w64, st);
         else launch_zero(w + L.x64, spinor_bytes(WD_F64, Vf, nrhs), st);
     } else {
         rc = launch_pack_spinor(WD_F64, src, w + L.eta64, (int)V, nrhs, st);
@@ -739,7 +747,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     // (BiCGSTAB: its first stage S1 does that)
     launch_kind(KN, p.inner, ls, st, dprob, 1);
     if (eo) {
-        hipLaunchKernelGGL(k_eo_source, dim3((unsigned)(((Vf + 255) / 256) * nrhs)), dim3(256), 0, st, dprob);
+        launch_eo_source(dprob, Vf, nrhs, st);
         launch_kind(KER2A, p.inner, ls, st, dprob, 1);
     }
     launch_kind(KR2, p.inner, ls, st, dprob, 1);
@@ -829,8 +837,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     (void)hipHostFree(hsum);
     // solution out (even-odd: x_o from x_e), scalars back
     if (eo) {
-        hipLaunchKernelGGL(k_eo_merge, dim3((unsigned)((Vf + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, dprob,
-                           (double2 *)sol);
+        launch_eo_merge(dprob, Vf, nrhs, sol, st);
         WD_HIP(hipGetLastError());
     } else {
         rc = launch_unpack_spinor(WD_F64, w + L.x64, sol, (int)V, nrhs, st);

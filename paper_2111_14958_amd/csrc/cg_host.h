@@ -37,6 +37,13 @@ void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const
 void launch_summary(hipStream_t st, const Prob *d, int nprob, int *out, const int *abort_flag);
 void launch_zero(void *p, size_t bytes, hipStream_t st);
 int check_params(const wd_cg_params *p);
+// Even-odd preconditioning (one problem record at d, vf = V/2 sites per half):
+// split a canonical complex128 field into its FP64 even and odd halves; form
+// the Schur system's source b_e over eta_e; rebuild the odd half of x and write
+// the canonical complex128 solution.
+void launch_eo_split(const Prob *d, int64_t vf, int nrhs, const void *src, void *even, void *odd, hipStream_t st);
+void launch_eo_source(const Prob *d, int64_t vf, int nrhs, hipStream_t st);
+void launch_eo_merge(const Prob *d, int64_t vf, int nrhs, void *sol, hipStream_t st);
 int cg_status_of(int state);
 // Record one persistent chunk kernel (K iterations of phases A, B, C with grid
 // barriers) on `st`; `bar` is 256 bytes of device scratch for the barrier.

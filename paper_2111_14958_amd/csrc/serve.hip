@@ -78,7 +78,7 @@ struct SlotLayout {
     WsLayout L;
 };
 
-static SlotLayout slot_layout(int64_t V, int nrhs, int inner) {
+static SlotLayout slot_layout(int64_t V, int nrhs, int inner, int eo) {
     SlotLayout s;
     size_t o = 0;
     s.links64 = o;
@@ -90,7 +90,7 @@ static SlotLayout slot_layout(int64_t V, int nrhs, int inner) {
         s.links_lo = s.links64;
     }
     s.ws = o;
-    s.L = ws_layout(V, nrhs, inner, METHOD_CGNE);
+    s.L = ws_layout(V, nrhs, inner, METHOD_CGNE, eo);
     o += s.L.total;
     s.total = o;
     return s;
@@ -120,30 +120,36 @@ static void server_shapes(int inner, int &blk, int &nr_ab) {
     nr_ab = inner == WD_F64 ? 1 : 2;
 }
 
-static void prob_tiles(Prob &pr, int inner, int64_t V, int nrhs) {
+// tiles of every kernel kind for one request (vectors of vf sites)
+static void prob_tiles(Prob &pr, int inner, int64_t vf, int nrhs) {
     int blk, nr;
     server_shapes(inner, blk, nr);
     for (int k = 0; k < NKIND; ++k) {
-        const int knr = (k == KA || k == KB) ? nr : 1;
-        pr.nsb[k] = (int)((V + blk - 1) / blk);
+        const int knr = (k == KA || k == KB || k == KEA1 || k == KEB1) ? nr : 1;
+        pr.nsb[k] = (int)((vf + blk - 1) / blk);
         pr.ng[k] = (k == KC || k == KR1 || k == KN) ? nrhs : (nrhs + knr - 1) / knr;
         pr.nt[k] = pr.nsb[k] * pr.ng[k];
         pr.t0[k] = 0;
     }
 }
 
-static LaunchSet single_launch(const Prob &pr, int inner) {
+// launch shapes of the server's kernels, with the grid of every kind
+static LaunchSet server_launch(int inner, int eo, const int grid[NKIND]) {
     int blk, nr;
     server_shapes(inner, blk, nr);
     LaunchSet ls;
+    ls.eo = eo;
     for (int k = 0; k < NKIND; ++k) {
+        const bool stencil = k == KA || k == KB || k == KR2 || k == KEA1 || k == KEB1 || k == KER2A;
         ls.k[k].block = blk;
-        ls.k[k].nr = (k == KA || k == KB) ? nr : 1;
-        ls.k[k].remap = (k == KA || k == KB || k == KR2) ? 1 : 0;
-        ls.k[k].grid = pr.nt[k];
+        ls.k[k].nr = (k == KA || k == KB || k == KEA1 || k == KEB1) ? nr : 1;
+        ls.k[k].remap = stencil ? 1 : 0;
+        ls.k[k].grid = grid[k];
     }
     return ls;
 }
+
+static LaunchSet single_launch(const Prob &pr, int inner) { return server_launch(inner, pr.eo, pr.nt); }
 
 }  // namespace wd
 
@@ -161,8 +167,9 @@ struct wd_server {
     std::thread th;
     hipStream_t st = nullptr;
     wd_serve_stats stats{};
-    size_t table_off[3] = {0, 0, 0};   // per inner precision: max_slots Prob records
-    std::vector<wd::Prob> table[3];     // host staging of the tables (alive until the step syncs)
+    // per (inner precision, even-odd) group: max_slots Prob records
+    size_t table_off[6] = {0, 0, 0, 0, 0, 0};
+    std::vector<wd::Prob> table[6];     // host staging of the tables (alive until the step syncs)
     int chunk = 25;
 };
 
@@ -192,20 +199,32 @@ static int init_slot(wd_server *s, Slot &sl) {
     const WsLayout &L = sl.sl.L;
     memset(&sl.prob, 0, sizeof(sl.prob));
     fill_prob(sl.prob, &g, rq.m0, rq.nrhs, rq.params, w, L);
-    prob_tiles(sl.prob, inner, V, rq.nrhs);
+    const int eo = sl.prob.eo;
+    const int64_t vf = sl.prob.vf;
+    prob_tiles(sl.prob, inner, vf, rq.nrhs);
     init_scalars(sl.sc, rq.nrhs);
     WD_HIP(hipMemcpyAsync(w + L.prob, &sl.prob, sizeof(Prob), hipMemcpyHostToDevice, st));
     WD_HIP(hipMemcpyAsync(w + L.scal, sl.sc.data(), sizeof(Scal) * rq.nrhs, hipMemcpyHostToDevice, st));
     WD_HIP(hipMemsetAsync(w + L.bar, 0, 256, st));
-    rc = launch_pack_spinor(WD_F64, rq.src_dev, w + L.eta64, (int)V, rq.nrhs, st);
-    if (rc) return rc;
-    if (rq.params.use_x0) rc = launch_pack_spinor(WD_F64, rq.sol_dev, w + L.x64, (int)V, rq.nrhs, st);
-    else launch_zero(w + L.x64, spinor_bytes(WD_F64, V, rq.nrhs), st);
-    if (rc) return rc;
-    launch_zero(w + L.xlo, spinor_bytes(inner == WD_F16N ? WD_F32 : inner, V, rq.nrhs), st);
-    const LaunchSet ls = single_launch(sl.prob, inner);
     const Prob *dp = (const Prob *)(w + L.prob);
+    if (eo) {
+        launch_eo_split(dp, vf, rq.nrhs, rq.src_dev, w + L.eta64, w + L.eta_o, st);
+        if (rq.params.use_x0) launch_eo_split(dp, vf, rq.nrhs, rq.sol_dev, w + L.x64, w + L.w64, st);
+        else launch_zero(w + L.x64, spinor_bytes(WD_F64, vf, rq.nrhs), st);
+    } else {
+        rc = launch_pack_spinor(WD_F64, rq.src_dev, w + L.eta64, (int)V, rq.nrhs, st);
+        if (rc) return rc;
+        if (rq.params.use_x0) rc = launch_pack_spinor(WD_F64, rq.sol_dev, w + L.x64, (int)V, rq.nrhs, st);
+        else launch_zero(w + L.x64, spinor_bytes(WD_F64, V, rq.nrhs), st);
+        if (rc) return rc;
+    }
+    launch_zero(w + L.xlo, spinor_bytes(inner == WD_F16N ? WD_F32 : inner, vf, rq.nrhs), st);
+    const LaunchSet ls = single_launch(sl.prob, inner);
     launch_kind(KN, inner, ls, st, dp, 1);
+    if (eo) {
+        launch_eo_source(dp, vf, rq.nrhs, st);
+        launch_kind(KER2A, inner, ls, st, dp, 1);
+    }
     launch_kind(KR2, inner, ls, st, dp, 1);
     launch_kind(KC, inner, ls, st, dp, 1);
     WD_HIP(hipGetLastError());
@@ -213,12 +232,13 @@ static int init_slot(wd_server *s, Slot &sl) {
 }
 
 // One step: `chunk` iterations plus a reliable update for every resident
-// request of one inner precision, as grouped launches.
-static int step_group(wd_server *s, int inner, const std::vector<Slot *> &grp) {
+// request of one group (inner precision, even-odd or not), as grouped launches.
+static int step_group(wd_server *s, int gkey, const std::vector<Slot *> &grp) {
     if (grp.empty()) return WD_OK;
-    std::vector<Prob> &table = s->table[inner];
+    const int inner = gkey >> 1, eo = gkey & 1;
+    std::vector<Prob> &table = s->table[gkey];
     table.clear();
-    int tot[NKIND] = {0, 0, 0, 0, 0, 0};
+    int tot[NKIND] = {};
     for (Slot *sl : grp) {
         Prob p = sl->prob;
         for (int k = 0; k < NKIND; ++k) {
@@ -227,24 +247,19 @@ static int step_group(wd_server *s, int inner, const std::vector<Slot *> &grp) {
         }
         table.push_back(p);
     }
-    int blk, nr;
-    server_shapes(inner, blk, nr);
-    LaunchSet ls;
-    for (int k = 0; k < NKIND; ++k) {
-        ls.k[k].block = blk;
-        ls.k[k].nr = (k == KA || k == KB) ? nr : 1;
-        ls.k[k].remap = (k == KA || k == KB || k == KR2) ? 1 : 0;
-        ls.k[k].grid = tot[k];
-    }
-    Prob *dt = (Prob *)arena_ptr(s, s->table_off[inner]);
+    const LaunchSet ls = server_launch(inner, eo, tot);
+    Prob *dt = (Prob *)arena_ptr(s, s->table_off[gkey]);
     const int n = (int)table.size();
     WD_HIP(hipMemcpyAsync(dt, table.data(), sizeof(Prob) * n, hipMemcpyHostToDevice, s->st));
     for (int it = 0; it < s->chunk; ++it) {
+        if (eo) launch_kind(KEA1, inner, ls, s->st, dt, n);
         launch_kind(KA, inner, ls, s->st, dt, n);
+        if (eo) launch_kind(KEB1, inner, ls, s->st, dt, n);
         launch_kind(KB, inner, ls, s->st, dt, n);
         launch_kind(KC, inner, ls, s->st, dt, n);
     }
     launch_kind(KR1, inner, ls, s->st, dt, n);
+    if (eo) launch_kind(KER2A, inner, ls, s->st, dt, n);
     launch_kind(KR2, inner, ls, s->st, dt, n);
     launch_kind(KC, inner, ls, s->st, dt, n);
     WD_HIP(hipGetLastError());
@@ -315,7 +330,8 @@ static void scheduler(wd_server *s) {
                 const int nslots = (int)(s->active.size() + admitted.size());
                 const SlotLayout lay = slot_layout((int64_t)it->req.dims[0] * it->req.dims[1] *
                                                        it->req.dims[2] * it->req.dims[3],
-                                                   it->req.nrhs, it->req.params.inner);
+                                                   it->req.nrhs, it->req.params.inner,
+                                                   it->req.params.precondition == WD_PRECOND_EO);
                 size_t off = 0;
                 if (nslots < s->cfg.max_slots && s->arena.alloc(lay.total, &off)) {
                     Slot sl;
@@ -344,9 +360,9 @@ static void scheduler(wd_server *s) {
         }
         if (rc) { fail_all(s, rc); continue; }
         // one step over every resident request
-        std::vector<Slot *> grp[3];
-        for (Slot &sl : s->active) grp[sl.req.params.inner].push_back(&sl);
-        for (int p = 0; p < 3 && !rc; ++p) rc = step_group(s, p, grp[p]);
+        std::vector<Slot *> grp[6];
+        for (Slot &sl : s->active) grp[sl.req.params.inner * 2 + sl.prob.eo].push_back(&sl);
+        for (int p = 0; p < 6 && !rc; ++p) rc = step_group(s, p, grp[p]);
         if (!rc && hipStreamSynchronize(s->st) != hipSuccess) rc = WD_EHIP;
         for (Slot &sl : s->active) {
             if (rc) break;
@@ -361,7 +377,12 @@ static void scheduler(wd_server *s) {
         for (Slot &sl : s->active) (slot_finished(sl) ? fin : keep).push_back(sl);
         for (Slot &sl : fin) {
             char *w = arena_ptr(s, sl.off) + sl.sl.ws;
-            rc = launch_unpack_spinor(WD_F64, w + sl.sl.L.x64, sl.req.sol_dev, (int)sl.V, sl.req.nrhs, s->st);
+            if (sl.prob.eo) {
+                launch_eo_merge((const Prob *)(w + sl.sl.L.prob), sl.prob.vf, sl.req.nrhs, sl.req.sol_dev, s->st);
+                if (hipGetLastError() != hipSuccess) rc = WD_EHIP;
+            } else {
+                rc = launch_unpack_spinor(WD_F64, w + sl.sl.L.x64, sl.req.sol_dev, (int)sl.V, sl.req.nrhs, s->st);
+            }
             for (int i = 0; i < sl.req.nrhs && !rc; ++i)
                 if (sl.sc[i].zero_src &&
                     hipMemsetAsync((char *)sl.req.sol_dev + (size_t)i * sl.V * 192, 0, (size_t)sl.V * 192,
@@ -405,8 +426,9 @@ static int check_request(const wd_request *r) {
     if (rc) return rc;
     WD_CHECK(r->params.inner == WD_F32 || r->params.inner == WD_F64, WD_EINVAL,
              "the server runs FP32 or FP64 inner iterations");
-    WD_CHECK(r->params.method == METHOD_CGNE && r->params.precondition == WD_PRECOND_NONE, WD_EINVAL,
-             "the server runs unpreconditioned CG on the normal equations only");
+    WD_CHECK(r->params.method == METHOD_CGNE, WD_EINVAL, "the server runs CG on the normal equations only");
+    WD_CHECK(r->params.precondition == WD_PRECOND_NONE || r->dims[0] % 2 == 0, WD_EINVAL,
+             "even-odd preconditioning needs an even Lx");
     return WD_OK;
 }
 
@@ -419,7 +441,7 @@ extern "C" {
 size_t wd_serve_footprint(const wd_request *req) {
     if (check_request(req) != WD_OK) return 0;
     const int64_t V = (int64_t)req->dims[0] * req->dims[1] * req->dims[2] * req->dims[3];
-    return al256s(slot_layout(V, req->nrhs, req->params.inner).total);
+    return al256s(slot_layout(V, req->nrhs, req->params.inner, req->params.precondition == WD_PRECOND_EO).total);
 }
 
 int wd_serve_create(const wd_serve_config *cfg, wd_server **out) {
@@ -440,7 +462,7 @@ int wd_serve_create(const wd_serve_config *cfg, wd_server **out) {
     s->chunk = cfg->chunk > 0 ? cfg->chunk : 25;
     s->arena.init(cfg->arena_bytes);
     const size_t tb = al256s(sizeof(Prob) * cfg->max_slots);
-    for (int p = 0; p < 3; ++p) {
+    for (int p = 0; p < 6; ++p) {
         if (!s->arena.alloc(tb, &s->table_off[p])) {
             delete s;
             return fail(WD_ETOOBIG, "arena too small for the request tables");

@@ -2,6 +2,7 @@
 
     python -m paper_2111_14958_amd.experiments fig1    # whole-CG time vs block size
     python -m paper_2111_14958_amd.experiments serve   # open-loop serving latency
+    python -m paper_2111_14958_amd.experiments serve eo   # the same, even-odd preconditioned
     python -m paper_2111_14958_amd.experiments solve   # one profiled 14^4 x 16 solve
 
 Fig. 1 of the paper times the whole CG at 14^4 while varying the SYCL
@@ -58,7 +59,8 @@ def fig1(blocks=(64, 128, 256)):
                           "gflops": 2 * 1368.0 * 14 ** 4 * rep["iters"] / t / 1e9}), flush=True)
 
 
-def serve(n_requests=600, rates=(0.25, 0.5, 1.0, 1.5, 2.0), pool=2, arena_gib=24, max_slots=16, seed=10_000):
+def serve(n_requests=600, rates=(0.25, 0.5, 1.0, 1.5, 2.0), pool=2, arena_gib=24, max_slots=16, seed=10_000,
+          eo=False):
     """Continuous-batching solve server under Poisson arrivals.
 
     Request i (seeded by seed + i): lattice drawn uniformly from 4^4, 8^4, 12^4, 14^4, 16^3 x 32,
@@ -69,7 +71,8 @@ def serve(n_requests=600, rates=(0.25, 0.5, 1.0, 1.5, 2.0), pool=2, arena_gib=24
     First a closed-loop run (all requests at t = 0) measures the capacity in
     requests/s; then open-loop runs submit at `rates` x capacity with
     exponential inter-arrival times.  Latency = submit -> result, measured by
-    the server.  Prints one JSON line per run.
+    the server.  eo: every request even-odd preconditioned.  Prints one JSON
+    line per run.
     """
     import numpy as np
     import torch
@@ -96,7 +99,8 @@ def serve(n_requests=600, rates=(0.25, 0.5, 1.0, 1.5, 2.0), pool=2, arena_gib=24
                           device="cuda", generator=gen)
         reqs.append(dict(dims=dims, nrhs=nrhs, m0=m0, V=V, U=gauges[vi][i % pool], src=src))
     arena = torch.empty(int(arena_gib) << 30, dtype=torch.uint8, device="cuda")
-    params = wd.cg_default_params(inner=wd.F32, reliable_every=50)
+    params = wd.cg_default_params(inner=wd.F32, reliable_every=50,
+                                  precondition=wd.PRECOND_EO if eo else wd.PRECOND_NONE)
 
     def run(arrivals):
         srv = wd.Server(arena, max_slots=max_slots)
@@ -128,13 +132,13 @@ def serve(n_requests=600, rates=(0.25, 0.5, 1.0, 1.5, 2.0), pool=2, arena_gib=24
                     arena_high_water_gib=st["arena_high_water"] / 2**30, steps=st["steps"])
 
     closed = run(np.zeros(len(reqs)))
-    print(json.dumps({"serve": "closed-loop", **closed}), flush=True)
+    print(json.dumps({"serve": "closed-loop", "even_odd": eo, **closed}), flush=True)
     cap = closed["requests_per_s"]
     for f in rates:
         arr = np.cumsum(rng.exponential(1.0 / (f * cap), size=len(reqs)))
         res = run(arr - arr[0])
-        print(json.dumps({"serve": "poisson", "rate_x_capacity": f, "offered_per_s": f * cap, **res}),
-              flush=True)
+        print(json.dumps({"serve": "poisson", "even_odd": eo, "rate_x_capacity": f, "offered_per_s": f * cap,
+                          **res}), flush=True)
 
 
 def solve():
@@ -171,4 +175,7 @@ def solve():
 
 
 if __name__ == "__main__":
-    {"fig1": fig1, "serve": serve, "solve": solve}[sys.argv[1]]()
+    if sys.argv[1] == "serve" and sys.argv[2:] == ["eo"]:
+        serve(eo=True)
+    else:
+        {"fig1": fig1, "serve": serve, "solve": solve}[sys.argv[1]]()

@@ -29,7 +29,8 @@ def _requests():
         U = wdgen.gauge_field(dims, 0.5, 10_000 + i)
         src = wdgen.gaussian_source(dims, nrhs, 60_000 + i)
         inner = wd.F64 if i % 3 == 2 else wd.F32
-        out.append(dict(dims=dims, nrhs=nrhs, m0=m0, U=U, src=src, inner=inner))
+        eo = i % 2   # every other request even-odd preconditioned
+        out.append(dict(dims=dims, nrhs=nrhs, m0=m0, U=U, src=src, inner=inner, eo=eo))
     return out
 
 
@@ -41,7 +42,8 @@ def _run(reqs, arena_bytes, max_slots=8, chunk=10):
     for r in reqs:
         dU, dsrc = dev(r["U"]), dev(r["src"])
         sol = torch.zeros_like(dsrc)
-        p = wd.cg_default_params(inner=r["inner"], reliable_every=0 if r["inner"] == wd.F64 else 50)
+        p = wd.cg_default_params(inner=r["inner"], reliable_every=0 if r["inner"] == wd.F64 else 50,
+                                 precondition=wd.PRECOND_EO if r["eo"] else wd.PRECOND_NONE)
         req = wd.Server.request(r["dims"], r["nrhs"], r["m0"], dU, dsrc, sol, p)
         tickets.append(srv.submit(req, keep=(dU, dsrc, sol)))
         keep.append(sol)
@@ -79,7 +81,7 @@ def test_serve_admission_respects_arena():
     reqs = _requests()[:5]
     fps = []
     for r in reqs:
-        p = wd.cg_default_params(inner=r["inner"])
+        p = wd.cg_default_params(inner=r["inner"], precondition=wd.PRECOND_EO if r["eo"] else wd.PRECOND_NONE)
         req = wd.Request()
         req.dims[:] = list(r["dims"])
         req.t_sign, req.nrhs, req.m0 = -1, r["nrhs"], r["m0"]
@@ -88,7 +90,7 @@ def test_serve_admission_respects_arena():
         req.params = p
         fps.append(wd.Server.footprint(req))
     assert all(f > 0 for f in fps)
-    table = 3 * ((256 * 8 + 255) // 256 * 256)   # request tables, see wd_serve_create
+    table = 6 * 8 * 1024   # request tables (6 groups x max_slots records), see wd_serve_create
     arena = table + max(fps) + min(fps) + 4096      # room for about two requests at once
     say("serve small arena", arena)
     xs, reps, st = _run(reqs, arena, max_slots=8)
