@@ -59,6 +59,18 @@ __device__ __forceinline__ gptr<T> at(void *base, size_t plane, uint32_t off) {
     return (gptr<T>)(wave_uniform((gchar *)base + plane) + off);
 }
 
+// Loads and stores of data a kernel touches once.  NT sets the nontemporal
+// hint, which makes the L2 evict these lines first, so that stencil inputs
+// which neighbouring blocks read again stay resident.
+template <bool NT, typename T> __device__ __forceinline__ T ld(gptr<const T> p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T> __device__ __forceinline__ void st(gptr<T> p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 template <int P> struct real_of { typedef float type; };
 template <> struct real_of<P64> { typedef double type; };
 
@@ -108,39 +120,44 @@ template <int P> struct Spinor;
 template <> struct Spinor<P64> {
     typedef double R;
     static constexpr int BYTES_PER_SITE = 192;
+    template <bool NT = false>
     __device__ static __forceinline__ void load(const FieldPtr &f, int r, int s, cx<R> o[12]) {
         const size_t pb = (size_t)f.V * 16;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            const d2v v = *at<d2v>((const void *)f.p, (size_t)(r * 12 + k) * pb, (uint32_t)s * 16u);
+            const d2v v = ld<NT>(at<d2v>((const void *)f.p, (size_t)(r * 12 + k) * pb, (uint32_t)s * 16u));
             o[k] = {v.x, v.y};
         }
     }
+    template <bool NT = false>
     __device__ static __forceinline__ void store(const FieldPtr &f, int r, int s, const cx<R> o[12]) {
         const size_t pb = (size_t)f.V * 16;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) *at<d2v>(f.p, (size_t)(r * 12 + k) * pb, (uint32_t)s * 16u) = d2v{o[k].re, o[k].im};
+        for (int k = 0; k < 12; ++k)
+            st<NT>(at<d2v>(f.p, (size_t)(r * 12 + k) * pb, (uint32_t)s * 16u), d2v{o[k].re, o[k].im});
     }
 };
 
 template <> struct Spinor<P32> {
     typedef float R;
     static constexpr int BYTES_PER_SITE = 96;
+    template <bool NT = false>
     __device__ static __forceinline__ void load(const FieldPtr &f, int r, int s, cx<R> o[12]) {
         const size_t pb = (size_t)f.V * 16;
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            const f4v v = *at<f4v>((const void *)f.p, (size_t)(r * 6 + j) * pb, (uint32_t)s * 16u);
+            const f4v v = ld<NT>(at<f4v>((const void *)f.p, (size_t)(r * 6 + j) * pb, (uint32_t)s * 16u));
             o[2 * j] = {v.x, v.y};
             o[2 * j + 1] = {v.z, v.w};
         }
     }
+    template <bool NT = false>
     __device__ static __forceinline__ void store(const FieldPtr &f, int r, int s, const cx<R> o[12]) {
         const size_t pb = (size_t)f.V * 16;
 #pragma unroll
         for (int j = 0; j < 6; ++j)
-            *at<f4v>(f.p, (size_t)(r * 6 + j) * pb, (uint32_t)s * 16u) =
-                f4v{o[2 * j].re, o[2 * j].im, o[2 * j + 1].re, o[2 * j + 1].im};
+            st<NT>(at<f4v>(f.p, (size_t)(r * 6 + j) * pb, (uint32_t)s * 16u),
+                   f4v{o[2 * j].re, o[2 * j].im, o[2 * j + 1].re, o[2 * j + 1].im});
     }
 };
 
@@ -151,18 +168,20 @@ template <> struct Spinor<P16> {
     __device__ static __forceinline__ size_t norm_plane(const FieldPtr &f, int r) {
         return (size_t)f.nrhs * 3 * f.V * 16 + (size_t)r * f.V * 4;
     }
+    template <bool NT = false>
     __device__ static __forceinline__ void load(const FieldPtr &f, int r, int s, cx<R> o[12]) {
         const size_t pb = (size_t)f.V * 16;
-        const float n = *at<float>((const void *)f.p, norm_plane(f, r), (uint32_t)s * 4u);
+        const float n = ld<NT>(at<float>((const void *)f.p, norm_plane(f, r), (uint32_t)s * 4u));
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const half8v v = *at<half8v>((const void *)f.p, (size_t)(r * 3 + j) * pb, (uint32_t)s * 16u);
+            const half8v v = ld<NT>(at<half8v>((const void *)f.p, (size_t)(r * 3 + j) * pb, (uint32_t)s * 16u));
 #pragma unroll
             for (int k = 0; k < 4; ++k) o[4 * j + k] = {n * (float)v[2 * k], n * (float)v[2 * k + 1]};
         }
     }
     // Quantise: norm = max |re|,|im| over the site; code = half(v / norm), the
     // FP32 quotient rounded to nearest even.  Returns the stored values in o.
+    template <bool NT = false>
     __device__ static __forceinline__ void store(const FieldPtr &f, int r, int s, cx<R> o[12]) {
         float n = 0.f;
 #pragma unroll
@@ -179,9 +198,9 @@ template <> struct Spinor<P16> {
                 v[2 * k + 1] = (h16)b;
                 o[4 * j + k] = {n * (float)v[2 * k], n * (float)v[2 * k + 1]};
             }
-            *at<half8v>(f.p, (size_t)(r * 3 + j) * pb, (uint32_t)s * 16u) = v;
+            st<NT>(at<half8v>(f.p, (size_t)(r * 3 + j) * pb, (uint32_t)s * 16u), v);
         }
-        *at<float>(f.p, norm_plane(f, r), (uint32_t)s * 4u) = n;
+        st<NT>(at<float>(f.p, norm_plane(f, r), (uint32_t)s * 4u), n);
     }
 };
 
