@@ -159,7 +159,19 @@ typedef struct {
     int32_t chunk;          /* CG iterations per graph replay, 0 = library default     */
     int32_t method;         /* WD_METHOD_CGNE (default) or WD_METHOD_BICGSTAB           */
     int32_t precondition;   /* WD_PRECOND_NONE (default) or WD_PRECOND_EO               */
+    int32_t max_cus;        /* 0: all compute units.  n > 0: the CG iterations run on n
+                               compute units (see below); needs persistent = 1         */
 } wd_cg_params;
+
+/* Compute-unit-limited CG (max_cus = n > 0), for speedup-versus-compute-units
+ * studies (Sec. 3.1, Fig. 2).  The persistent kernel is launched with
+ * min(n, compute units) blocks of 1024 threads whose register demand leaves room
+ * for one block per compute unit, so each block holds a compute unit of its own
+ * and the CG iterations use exactly that many.  The set-up, the reliable
+ * updates and the final FP64 residual still run on the whole device.  Results
+ * are identical (bitwise) for every n.  Returns WD_EHIP if the kernel would fit
+ * twice on a compute unit.  FP32 or FP16N inner iterations only.  Not for the
+ * server. */
 
 /* Krylov method of wd_cg_solve / wd_cg_solve_batch.
  * WD_METHOD_CGNE: CG on the normal equations D D^dagger chi = eta, x = D^dagger chi

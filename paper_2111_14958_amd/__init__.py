@@ -57,7 +57,7 @@ class CGParams(ctypes.Structure):
                 ("reliable_every", ctypes.c_int32), ("inner", ctypes.c_int32),
                 ("use_x0", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("method", ctypes.c_int32),
-                ("precondition", ctypes.c_int32)]
+                ("precondition", ctypes.c_int32), ("max_cus", ctypes.c_int32)]
 
 
 class CGReport(ctypes.Structure):

@@ -483,22 +483,25 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
     }
 }
 
-// The persistent kernel runs phases A, B and C with one block shape.
-void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner) {
-    const int blk = ls.k[KB].block;
-    int nr = ls.k[KB].nr;
+// The persistent kernel runs phases A and B with one block shape: phase B's,
+// or 1024 threads and one rhs per thread when it is limited to max_cus compute
+// units.  Its phase C tiles follow from its block size; phase C launched on
+// its own (set-up, after reliable updates) keeps the shape of plan_shapes.
+void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner, int max_cus) {
+    const int blk = max_cus > 0 ? 1024 : ls.k[KB].block;
+    int nr = max_cus > 0 ? 1 : ls.k[KB].nr;
     if (inner == WD_F64 && nr > 2) nr = 2;
-    const int kinds[3] = {KA, KB, KC};
+    const int kinds[2] = {KA, KB};
     for (int k : kinds) {
         KindShape &ks = ls.k[k];
         ks.block = blk;
-        ks.nr = (k == KC) ? 1 : nr;
+        ks.nr = nr;
         ks.remap = 0;
         ks.xy = 0;
         ks.order &= ~(1 << 17);
         pr.sorder[k] = ks.order;
         pr.nsb[k] = (int)((V + blk - 1) / blk);
-        pr.ng[k] = (k == KC) ? nrhs : (nrhs + nr - 1) / nr;
+        pr.ng[k] = (nrhs + nr - 1) / nr;
         pr.nt[k] = pr.nsb[k] * pr.ng[k];
         ks.grid = pr.nt[k];
     }
@@ -551,7 +554,7 @@ void init_scalars(std::vector<Scal> &sc, int nrhs) {
 // ------------------------------------------------------------ graph cache
 struct GraphKey {
     const void *ws;
-    int dims[4], nrhs, inner, K, persistent, method;
+    int dims[4], nrhs, inner, K, persistent, method, max_cus;
     int shp[NKIND][5];
     bool operator<(const GraphKey &o) const { return memcmp(this, &o, sizeof(*this)) < 0; }
 };
@@ -716,7 +719,10 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     const int K = p.chunk > 0 ? p.chunk : (p.reliable_every > 0 ? p.reliable_every : 50);
     const bool bicg = p.method == METHOD_BICGSTAB;
     const int persistent = (p.persistent == 1 && !bicg) ? 1 : 0;
-    if (persistent) plan_persistent(ls, hp, V, nrhs, p.inner);
+    if (persistent) plan_persistent(ls, hp, V, nrhs, p.inner, p.max_cus);
+    for (int k = 0; k < NKIND; ++k)   // kernels launched one by one are compiled for <= 256 threads
+        WD_CHECK(ls.k[k].block <= 256 || (persistent && (k == KA || k == KB)), WD_EINVAL,
+                 "kernel kind %d planned with %d threads per block", k, ls.k[k].block);
     for (int k = 0; k < NKIND; ++k)   // every kind's partial sums fit the buffer
         WD_CHECK(hp.nsb[k] <= (V + 63) / 64, WD_EINVAL, "kernel kind %d has %d site blocks, the partial-sum "
                  "buffer holds %lld", k, hp.nsb[k], (long long)((V + 63) / 64));
@@ -764,6 +770,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     key.inner = p.inner;
     key.K = K;
     key.persistent = persistent;
+    key.max_cus = p.max_cus;
     key.method = p.method | (eo << 4);
     for (int k = 0; k < NKIND; ++k) {
         key.shp[k][0] = ls.k[k].block;
@@ -783,7 +790,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
             launch_summary(cs, dprob, 1, dsum, dabort);
             return;
         }
-        if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, K, w + L.bar + 64);
+        if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, K, w + L.bar + 64, p.max_cus);
         else
             for (int it = 0; it < K; ++it) {
                 if (eo) launch_kind(KEA1, p.inner, ls, cs, dprob, 1);
@@ -883,6 +890,10 @@ int check_params(const wd_cg_params *p) {
              "unknown preconditioning %d", p->precondition);
     WD_CHECK(p->precondition == WD_PRECOND_NONE || (p->method == METHOD_CGNE && p->persistent != 1), WD_EINVAL,
              "even-odd preconditioning runs CG without the persistent kernel");
+    WD_CHECK(p->max_cus >= 0, WD_EINVAL, "max_cus %d < 0", p->max_cus);
+    WD_CHECK(p->max_cus == 0 || (p->persistent == 1 && p->method == METHOD_CGNE), WD_EINVAL,
+             "max_cus needs the persistent CG kernel (persistent = 1)");
+    WD_CHECK(p->max_cus == 0 || p->inner != WD_F64, WD_EINVAL, "max_cus needs an FP32 or FP16N inner iteration");
     return WD_OK;
 }
 

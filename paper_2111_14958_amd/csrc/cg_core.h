@@ -105,10 +105,11 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
-// Sum v[j] over the block in a fixed order; result valid on thread 0.
+// Sum v[j] over the block (at most 1024 threads) in a fixed order; result
+// valid on thread 0.
 template <int NR>
 __device__ __forceinline__ void block_sum(double v[NR]) {
-    __shared__ double red[4][NR > 0 ? NR : 1];
+    __shared__ double red[16][NR > 0 ? NR : 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NR; ++j) v[j] = wave_sum(v[j]);

@@ -29,7 +29,7 @@ struct WsLayout {
 
 WsLayout ws_layout(int64_t V, int nrhs, int inner, int method, int eo = 0);
 void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr);
-void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner);
+void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner, int max_cus = 0);
 void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_params &p, char *ws,
                const WsLayout &L);
 void init_scalars(std::vector<Scal> &sc, int nrhs);
@@ -47,7 +47,8 @@ void launch_eo_merge(const Prob *d, int64_t vf, int nrhs, void *sol, hipStream_t
 int cg_status_of(int state);
 // Record one persistent chunk kernel (K iterations of phases A, B, C with grid
 // barriers) on `st`; `bar` is 256 bytes of device scratch for the barrier.
+// max_cus > 0: one 1024-thread block on each of max_cus compute units.
 int record_persistent_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob,
-                            int K, void *bar);
+                            int K, void *bar, int max_cus = 0);
 
 }  // namespace wd

@@ -64,15 +64,22 @@ __device__ __forceinline__ int bar_wait(const Barrier &b, unsigned e) {
     return aborted;
 }
 
-// Tiles of one phase for this block: the XCD of block b (b mod 8) owns the
-// contiguous range [x nt / 8, (x+1) nt / 8); its blocks stride through it.
+// Tiles of one phase for this block.  With a grid of whole XCD rounds the XCD
+// of block b (b mod 8) owns the contiguous range [x nt / 8, (x+1) nt / 8) and
+// its blocks stride through it; any other grid strides through all tiles.
 #define FOR_MY_TILES(nt, t)                                                       \
-    const int x_ = blockIdx.x & 7, i_ = blockIdx.x >> 3, per_ = gridDim.x >> 3;  \
-    const int lo_ = (int)(((long long)(nt) * x_) / 8), hi_ = (int)(((long long)(nt) * (x_ + 1)) / 8); \
+    const bool xr_ = (gridDim.x & 7) == 0;                                        \
+    const int x_ = xr_ ? (int)(blockIdx.x & 7) : 0;                               \
+    const int i_ = xr_ ? (int)(blockIdx.x >> 3) : (int)blockIdx.x;                \
+    const int per_ = xr_ ? (int)(gridDim.x >> 3) : (int)gridDim.x;                \
+    const int lo_ = xr_ ? (int)(((long long)(nt) * x_) / 8) : 0;                  \
+    const int hi_ = xr_ ? (int)(((long long)(nt) * (x_ + 1)) / 8) : (nt);         \
     for (int t = lo_ + i_; t < hi_; t += per_)
 
-template <int P, int NR>
-__global__ __launch_bounds__(256) void k_persistent(const Prob *__restrict__ probs, int K, Barrier b) {
+// BLK is the block size the kernel is compiled for: 256, or 1024 for the
+// compute-unit-limited launch (one block fills a compute unit).
+template <int P, int NR, int BLK = 256>
+__global__ __launch_bounds__(BLK) void k_persistent(const Prob *__restrict__ probs, int K, Barrier b) {
     const Prob &pr = probs[0];
     const unsigned nblk = gridDim.x;
     unsigned e = 0;
@@ -97,8 +104,9 @@ __global__ __launch_bounds__(256) void k_persistent(const Prob *__restrict__ pro
             return;
         }
         ++e;
-        {   // phase C
-            FOR_MY_TILES(pr.nt[KC], t) phaseC_tile<P>(pr, t);
+        {   // phase C: tiles of blockDim.x sites and one rhs
+            const int ntc = (int)((pr.vf + blockDim.x - 1) / blockDim.x) * pr.nrhs;
+            FOR_MY_TILES(ntc, t) phaseC_tile<P>(pr, t);
         }
         if (bar_arrive(b, nblk, e)) bar_release(b, e);
         else if (bar_wait(b, e)) return;
@@ -108,6 +116,13 @@ __global__ __launch_bounds__(256) void k_persistent(const Prob *__restrict__ pro
 
 __global__ void k_bar_reset(unsigned *p) {
     if (threadIdx.x < 32) p[threadIdx.x] = 0u;   // count, gen, abort (128 bytes)
+}
+
+static void make_barrier(Barrier &b, void *bar, int khz) {
+    b.count = (unsigned *)bar;
+    b.gen = (unsigned *)((char *)bar + 32);
+    b.abort = (int *)((char *)bar + 64);
+    b.limit = (unsigned long long)khz * 1000ull * 2ull;   // two seconds
 }
 
 template <int P, int NR>
@@ -123,23 +138,50 @@ static int launch_persistent(int blk, hipStream_t st, const Prob *d, int K, void
     nblk &= ~7;   // whole XCD rounds
     if (nblk < 8) nblk = 8;
     Barrier b;
-    b.count = (unsigned *)bar;
-    b.gen = (unsigned *)((char *)bar + 32);
-    b.abort = (int *)((char *)bar + 64);
-    b.limit = (unsigned long long)khz * 1000ull * 2ull;   // two seconds
+    make_barrier(b, bar, khz);
     hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, st, (unsigned *)bar);
     hipLaunchKernelGGL((k_persistent<P, NR>), dim3(nblk), dim3(blk), 0, st, d, K, b);
     WD_HIP(hipGetLastError());
     return WD_OK;
 }
 
+// min(max_cus, compute units) blocks of 1024 threads (FP32 and FP16 storage;
+// the FP64 kernel would spill registers at this block size).  A compute unit has room
+// for one such block only (checked), so every block runs on a compute unit of
+// its own: the launch uses exactly that many compute units.  All blocks are
+// resident at once, which the grid barriers need.
+template <int P>
+static int launch_persistent_cus(hipStream_t st, const Prob *d, int K, void *bar, int max_cus) {
+    int dev = 0, ncu = 0, per_cu = 0, khz = 0;
+    WD_HIP(hipGetDevice(&dev));
+    WD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    WD_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    WD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<P, 1, 1024>, 1024, 0));
+    WD_CHECK(per_cu == 1, WD_EHIP, "the compute-unit-limited kernel fits %d times on a compute unit", per_cu);
+    const int nblk = max_cus < ncu ? max_cus : ncu;
+    Barrier b;
+    make_barrier(b, bar, khz);
+    hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, st, (unsigned *)bar);
+    hipLaunchKernelGGL((k_persistent<P, 1, 1024>), dim3(nblk), dim3(1024), 0, st, d, K, b);
+    WD_HIP(hipGetLastError());
+    return WD_OK;
+}
+
 int record_persistent_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob,
-                            int K, void *bar) {
+                            int K, void *bar, int max_cus) {
     WD_CHECK(nprob == 1, WD_EINVAL, "the persistent kernel serves one problem");
     const KindShape &ka = ls.k[KA], &kb = ls.k[KB], &kc = ls.k[KC];
-    WD_CHECK(ka.block == kb.block && ka.block == kc.block && ka.nr == kb.nr, WD_EINVAL,
-             "persistent kernel needs one block shape for phases A, B and C");
-    const int max_tiles = std::max(ka.grid, std::max(kb.grid, kc.grid));
+    WD_CHECK(ka.block == kb.block && ka.nr == kb.nr, WD_EINVAL,
+             "persistent kernel needs one block shape for phases A and B");
+    if (max_cus > 0) {
+        WD_CHECK(ka.block == 1024 && ka.nr == 1, WD_EINVAL, "compute-unit-limited kernel needs 1024 threads, 1 rhs");
+        switch (inner) {
+        case P32: return launch_persistent_cus<P32>(st, d, K, bar, max_cus);
+        case P16: return launch_persistent_cus<P16>(st, d, K, bar, max_cus);
+        }
+        return fail(WD_EINVAL, "no compute-unit-limited kernel for precision %d", inner);
+    }
+    const int max_tiles = std::max(ka.grid, std::max(kb.grid, kc.grid * kc.block / ka.block));
     const int blk = ka.block;
     switch (inner * 4 + ka.nr) {
     case P64 * 4 + 1: return launch_persistent<P64, 1>(blk, st, d, K, bar, max_tiles);

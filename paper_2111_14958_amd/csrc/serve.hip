@@ -427,6 +427,7 @@ static int check_request(const wd_request *r) {
     WD_CHECK(r->params.inner == WD_F32 || r->params.inner == WD_F64, WD_EINVAL,
              "the server runs FP32 or FP64 inner iterations");
     WD_CHECK(r->params.method == METHOD_CGNE, WD_EINVAL, "the server runs CG on the normal equations only");
+    WD_CHECK(r->params.max_cus == 0, WD_EINVAL, "the server runs on the whole device (max_cus 0)");
     WD_CHECK(r->params.precondition == WD_PRECOND_NONE || r->dims[0] % 2 == 0, WD_EINVAL,
              "even-odd preconditioning needs an even Lx");
     return WD_OK;

@@ -1,6 +1,7 @@
 """Experiments beyond the benchmark line, on MI355X.
 
     python -m paper_2111_14958_amd.experiments fig1    # whole-CG time vs block size
+    python -m paper_2111_14958_amd.experiments fig2    # whole-CG speedup vs compute units
     python -m paper_2111_14958_amd.experiments serve   # open-loop serving latency
     python -m paper_2111_14958_amd.experiments serve eo   # the same, even-odd preconditioned
     python -m paper_2111_14958_amd.experiments solve   # one profiled 14^4 x 16 solve
@@ -11,6 +12,13 @@ every CG kernel is swept (64, 128, 256 threads) through wd_shape_set, using the
 single-field FP64 CG of the paper's algorithm (plain CG on D D^dagger,
 true-residual check at 1e-10) on seeded synthetic fields (links exp(i 0.5 H),
 Gaussian source, m0 = 0.05).  Prints one JSON line per point.
+
+Fig. 2 of the paper plots the speedup of the whole CG at 14^4 against the
+number of compute units, relative to one compute unit.  Here the persistent CG
+kernel is confined to n compute units (wd_cg_params.max_cus: n blocks of 1024
+threads, one per compute unit) and the speedup is T(1) / T(n), for one
+Gaussian source and for the 16-source batch (12 point + 4 Gaussian), FP32
+inner iterations with FP64 reliable updates every 50.
 """
 from __future__ import annotations
 
@@ -19,13 +27,13 @@ import sys
 import time
 
 
-def _setup(dims=(14, 14, 14, 14), m0=0.05):
+def _setup(dims=(14, 14, 14, 14), m0=0.05, nrhs=1):
     import torch
 
     import paper_2111_14958_amd as wd
     import wdgen
     U = wdgen.gauge_field(dims, 0.5, 1002)
-    src = wdgen.gaussian_source(dims, 1, 2002)
+    src = wdgen.gaussian_source(dims, 1, 2002) if nrhs == 1 else wdgen.mixed_sources(dims, 12, nrhs - 12, 2002)
     g = wd.Gauge(torch.from_numpy(U).cuda(), dims)
     dsrc = torch.from_numpy(src).cuda()
     return wd, torch, g, dsrc, m0
@@ -33,7 +41,7 @@ def _setup(dims=(14, 14, 14, 14), m0=0.05):
 
 def _time_solve(wd, torch, g, dsrc, m0, params, reps=3):
     sol = torch.zeros_like(dsrc)
-    ws = torch.empty(wd.cg_workspace_bytes(g, 1, params), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(wd.cg_workspace_bytes(g, dsrc.shape[0], params), dtype=torch.uint8, device="cuda")
     wd.cg_solve_batch(g, m0, dsrc, sol=sol, params=params, ws=ws)   # warm (graph capture)
     torch.cuda.synchronize()
     best, rep = 1e30, None
@@ -57,6 +65,24 @@ def fig1(blocks=(64, 128, 256)):
         print(json.dumps({"figure": 1, "lattice": "14^4", "block": blk, "seconds": t,
                           "iters": rep["iters"], "true_rel_res": rep["true_rel_res"],
                           "gflops": 2 * 1368.0 * 14 ** 4 * rep["iters"] / t / 1e9}), flush=True)
+
+
+def fig2(cus=(1, 2, 4, 8, 16, 32, 64, 128, 256), batches=(1, 16)):
+    for nrhs in batches:
+        wd, torch, g, dsrc, m0 = _setup(nrhs=nrhs)
+        t1 = None
+        for n in cus:
+            p = wd.cg_default_params(inner=wd.F32, reliable_every=50, persistent=1, max_cus=n)
+            t, rep = _time_solve(wd, torch, g, dsrc, m0, p, reps=2 if n < 8 else 3)
+            t1 = t if t1 is None else t1
+            print(json.dumps({"figure": 2, "lattice": "14^4", "rhs": nrhs, "compute_units": n, "seconds": t,
+                              "speedup": t1 / t, "iters": rep["iters"], "true_rel_res": rep["true_rel_res"]}),
+                  flush=True)
+        p = wd.cg_default_params(inner=wd.F32, reliable_every=50)
+        t, rep = _time_solve(wd, torch, g, dsrc, m0, p)
+        print(json.dumps({"figure": 2, "lattice": "14^4", "rhs": nrhs, "compute_units": "all, default kernels",
+                          "seconds": t, "speedup": t1 / t, "iters": rep["iters"]}), flush=True)
+        del g
 
 
 def serve(n_requests=600, rates=(0.25, 0.5, 1.0, 1.5, 2.0), pool=2, arena_gib=24, max_slots=16, seed=10_000,
@@ -178,4 +204,4 @@ if __name__ == "__main__":
     if sys.argv[1] == "serve" and sys.argv[2:] == ["eo"]:
         serve(eo=True)
     else:
-        {"fig1": fig1, "serve": serve, "solve": solve}[sys.argv[1]]()
+        {"fig1": fig1, "fig2": fig2, "serve": serve, "solve": solve}[sys.argv[1]]()

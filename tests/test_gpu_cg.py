@@ -218,6 +218,35 @@ def test_persistent_kernel_matches_oracle(inner):
     assert rel(x, host(x0)) <= kappa(m0) * 2 * TOL
 
 
+@pytest.mark.parametrize("inner", [wd.F32, wd.F16N], ids=["f32", "f16n"])
+def test_compute_unit_limited_persistent_kernel(inner):
+    """The persistent kernel confined to n compute units (one 1024-thread block
+    each) gives the same bits for every n, including grids that are not whole
+    XCD rounds and n above the device's compute units; the oracle accepts the
+    solution and it agrees with the kernel-per-phase path."""
+    dims, m0 = (8, 8, 8, 12), 0.05   # 6144 sites: 6 site blocks of 1024 per rhs
+    U = wdgen.gauge_field(dims, 0.5, 1013)
+    eta = wdgen.mixed_sources(dims, 2, 1, 2013)
+    g = wd.Gauge(dev(U), dims)
+    sols = {}
+    for n in (1, 3, 8, 40, 100000):
+        say("cg compute-unit-limited", inner, n)
+        p = wd.cg_default_params(inner=inner, reliable_every=50, persistent=1, max_cus=n)
+        x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+        assert rc == wd.WD_OK, reps
+        sols[n] = host(x)
+        assert np.array_equal(sols[n], sols[1]), n
+    _check_solution(U, eta, sols[1], dims, m0)
+    x0, _, rc0 = wd.cg_solve_batch(g, m0, dev(eta), params=wd.cg_default_params(inner=inner, reliable_every=50))
+    assert rc0 == wd.WD_OK
+    assert rel(sols[1], host(x0)) <= kappa(m0) * 2 * TOL
+    # max_cus needs the persistent kernel, a lower-precision inner iteration, n >= 0
+    for kw in ({"max_cus": 4}, {"max_cus": 4, "persistent": 1, "inner": wd.F64},
+               {"max_cus": -1, "persistent": 1}, {"max_cus": 4, "persistent": 1, "method": wd.METHOD_BICGSTAB}):
+        _, _, rc = wd.cg_solve_batch(g, m0, dev(eta), params=wd.cg_default_params(**kw), raise_on_error=False)
+        assert rc == wd.WD_EINVAL, kw
+
+
 @pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
 @pytest.mark.parametrize("dims", [(8, 8, 4, 6), (14, 14, 6, 4), (4, 8, 4, 6)],
                          ids=["8x8x4x6", "14x14x6x4", "4x8x4x6"])
