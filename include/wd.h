@@ -235,13 +235,18 @@ typedef struct {
     int32_t hop_order;    /* 1: hops one at a time, 2: a direction's two hops together,
                              0: compiler order                                    */
     int32_t rhs_loop;     /* rhs groups one block handles one after the other    */
-    int32_t site_order;   /* strip | group_major << 16 | xy_lds << 17 | occ << 18.
+    int32_t site_order;   /* strip | group_major << 16 | xy_lds << 17 | occ << 18
+                             | z_march << 24.
                              strip = W > 0: sites are processed in strips of W
                              z-planes, t-major inside a strip (0: lexicographic);
                              group_major = 1: tiles are ordered rhs-group-major
                              instead of site-block-major; xy_lds = 1: one xy-plane
                              per block with the x/y neighbours in LDS; occ > 0: at
-                             most occ plane blocks per compute unit (operator)    */
+                             most occ plane blocks per compute unit (operator);
+                             z_march = 1 (with xy_lds = 1; CG phases A and B in
+                             FP32/FP16N storage): a block walks a column of
+                             xy-planes along z with two planes in LDS, and strip
+                             is then the number of z-chunks (0: automatic)     */
     double  us;           /* median time of one application, microseconds        */
     double  gbps;         /* algorithmic bytes / time                             */
 } wd_tune_result;

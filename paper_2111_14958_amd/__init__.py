@@ -413,7 +413,8 @@ def shape_set(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int, block: 
               strip: int = 0, group_major: int = 0, xy_lds: int = 0, max_blocks_per_cu: int = 0):
     r = TuneResult(block=block, rhs_per_thread=rhs_per_thread, xcd_remap=xcd_remap,
                    hop_order=hop_order, rhs_loop=rhs_loop,
-                   site_order=strip | (group_major << 16) | (xy_lds << 17) | (max_blocks_per_cu << 18))
+                   site_order=strip | (group_major << 16) | ((1 if xy_lds else 0) << 17) |
+                   (max_blocks_per_cu << 18) | ((1 if xy_lds == 2 else 0) << 24))
     _check(lib().wd_shape_set(g.handle, prec, nrhs, 1 if dagger else 0, family, ctypes.byref(r)),
            "wd_shape_set")
 
@@ -425,8 +426,8 @@ def shape_get(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int) -> dict
     out = {f[0]: getattr(r, f[0]) for f in r._fields_ if f[0] not in ("us", "gbps")}
     out["strip"] = r.site_order & 0xFFFF
     out["group_major"] = (r.site_order >> 16) & 1
-    out["xy_lds"] = (r.site_order >> 17) & 1
-    out["max_blocks_per_cu"] = r.site_order >> 18
+    out["xy_lds"] = (1 + ((r.site_order >> 24) & 1)) if (r.site_order >> 17) & 1 else 0
+    out["max_blocks_per_cu"] = (r.site_order >> 18) & 0x3F
     return out
 
 

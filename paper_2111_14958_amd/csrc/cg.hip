@@ -47,6 +47,21 @@ __global__ __launch_bounds__(256) void k_phaseB(const Prob *__restrict__ probs, 
     phaseB_tile<P, NR, ORD, XY>(pr, t_);
 }
 
+// z-marching phases A and B (zm_tile); dynamic LDS of two plane buffers
+template <int P, int ORD>
+__global__ __launch_bounds__(256) void k_phaseA_zm(const Prob *__restrict__ probs, int nprob, int remap) {
+    extern __shared__ uint4 zm_lds[];
+    WD_KERNEL_PROLOGUE(KA)
+    zm_tile<P, ORD, false>(pr, t_, (typename LdsSpinor<P>::word *)zm_lds);
+}
+
+template <int P, int ORD>
+__global__ __launch_bounds__(256) void k_phaseB_zm(const Prob *__restrict__ probs, int nprob, int remap) {
+    extern __shared__ uint4 zm_lds[];
+    WD_KERNEL_PROLOGUE(KB)
+    zm_tile<P, ORD, true>(pr, t_, (typename LdsSpinor<P>::word *)zm_lds);
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_phaseC(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KC)
@@ -222,17 +237,26 @@ __global__ void k_zero(uint4 *p, size_t n16) {
 // start/stop events, which the runtime records at the kernel's own begin and
 // end (no marker packets around the launch).
 static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
-#define WD_TIMED_LAUNCH(K, grid, blk, st, ...)                                                   \
-    do {                                                                                       \
-        if (t_ev_start) hipExtLaunchKernelGGL(K, grid, blk, 0, st, t_ev_start, t_ev_stop, 0, __VA_ARGS__); \
-        else hipLaunchKernelGGL(K, grid, blk, 0, st, __VA_ARGS__);                              \
+#define WD_TIMED_LAUNCH_LDS(K, grid, blk, lds, st, ...)                                            \
+    do {                                                                                         \
+        if (t_ev_start) hipExtLaunchKernelGGL(K, grid, blk, lds, st, t_ev_start, t_ev_stop, 0, __VA_ARGS__); \
+        else hipLaunchKernelGGL(K, grid, blk, lds, st, __VA_ARGS__);                              \
     } while (0)
+#define WD_TIMED_LAUNCH(K, grid, blk, st, ...) WD_TIMED_LAUNCH_LDS(K, grid, blk, 0, st, __VA_ARGS__)
 
 // hop order 3 (pipelined) or 1 (one hop at a time) for the phase kernels;
 // the plane-blocked (XY) variants exist for up to 2 rhs per thread (1 in FP64)
 template <int P, int ORD, bool B>
-static void launch_AB_o(int nr, bool xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+static void launch_AB_o(int nr, int xy, int lds, int grid, int blk, hipStream_t st, const Prob *d, int n,
+                        int remap) {
     const dim3 gr(grid), bl(blk);
+    if (xy == 2) {
+        if constexpr (P != P64) {
+            if (B) WD_TIMED_LAUNCH_LDS((k_phaseB_zm<P, ORD>), gr, bl, lds, st, d, n, remap);
+            else WD_TIMED_LAUNCH_LDS((k_phaseA_zm<P, ORD>), gr, bl, lds, st, d, n, remap);
+        }
+        return;
+    }
     if (xy) {
         if (nr == 2 && P != P64) {
             if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, true>), gr, bl, st, d, n, remap);
@@ -256,13 +280,13 @@ static void launch_AB_o(int nr, bool xy, int grid, int blk, hipStream_t st, cons
 }
 template <int P>
 static void launch_A(const KindShape &k, hipStream_t st, const Prob *d, int n) {
-    if (k.ordered == 3) launch_AB_o<P, 3, false>(k.nr, k.xy, k.grid, k.block, st, d, n, k.remap);
-    else launch_AB_o<P, 1, false>(k.nr, k.xy, k.grid, k.block, st, d, n, k.remap);
+    if (k.ordered == 3) launch_AB_o<P, 3, false>(k.nr, k.xy, k.lds, k.grid, k.block, st, d, n, k.remap);
+    else launch_AB_o<P, 1, false>(k.nr, k.xy, k.lds, k.grid, k.block, st, d, n, k.remap);
 }
 template <int P>
 static void launch_B(const KindShape &k, hipStream_t st, const Prob *d, int n) {
-    if (k.ordered == 3) launch_AB_o<P, 3, true>(k.nr, k.xy, k.grid, k.block, st, d, n, k.remap);
-    else launch_AB_o<P, 1, true>(k.nr, k.xy, k.grid, k.block, st, d, n, k.remap);
+    if (k.ordered == 3) launch_AB_o<P, 3, true>(k.nr, k.xy, k.lds, k.grid, k.block, st, d, n, k.remap);
+    else launch_AB_o<P, 1, true>(k.nr, k.xy, k.lds, k.grid, k.block, st, d, n, k.remap);
 }
 template <int P>
 static void launch_R2(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
@@ -467,6 +491,19 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
                 if (inner == WD_F64) ks.nr = 1;
                 ks.order |= 1 << 17;
             }
+            // z-marching columns of planes (FP32 and FP16 storage, one rhs per
+            // tile); strip = number of z-chunks, by default enough for about
+            // three tiles per compute unit with chunks of at least two planes
+            if (ks.xy && st[k]->xylds == 2 && inner != WD_F64 && g->dims[2] >= 2) {
+                const int Lz = g->dims[2], Lt = g->dims[3];
+                int nzc = st[k]->strip > 0 ? std::min(st[k]->strip, Lz)
+                                           : std::min((768 + Lt * nrhs - 1) / (Lt * nrhs), Lz / 2);
+                if (nzc < 1) nzc = 1;
+                ks.xy = 2;
+                ks.nr = 1;
+                ks.order = nzc;
+                ks.lds = 2 * 6 * np * 16;   // two planes of 6 float4 per site
+            }
         } else {
             ks.block = 256;
             ks.nr = 1;
@@ -475,7 +512,7 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.xy = 0;
         }
         pr.sorder[k] = ks.order;
-        pr.nsb[k] = ks.xy ? V / np : (Vf + ks.block - 1) / ks.block;
+        pr.nsb[k] = ks.xy == 2 ? ks.order * g->dims[3] : ks.xy ? V / np : (Vf + ks.block - 1) / ks.block;
         pr.ng[k] = (nrhs + ks.nr - 1) / ks.nr;
         pr.t0[k] = 0;
         pr.nt[k] = pr.nsb[k] * pr.ng[k];
@@ -497,8 +534,9 @@ void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner, in
         ks.block = blk;
         ks.nr = nr;
         ks.remap = 0;
+        ks.order = ks.xy == 2 ? 0 : ks.order & ~(1 << 17);   // z-marching: the order held the chunk count
         ks.xy = 0;
-        ks.order &= ~(1 << 17);
+        ks.lds = 0;
         pr.sorder[k] = ks.order;
         pr.nsb[k] = (int)((V + blk - 1) / blk);
         pr.ng[k] = (nrhs + nr - 1) / nr;

@@ -364,6 +364,101 @@ __device__ __forceinline__ void phaseB_finish(const Prob &pr) {
     }
 }
 
+// ---------------------------------------------- z-marching phases A and B
+// A tile is a column of xy-planes: one t, one rhs, the planes z0 <= z < z1 of
+// z-chunk c (the chunk count is pr.sorder[K]).  The block walks the column
+// with two LDS plane buffers `lds` (dynamic, 2 x np sites): at each step it
+// stages plane z+1, then forms phase A's or B's epilogue for plane z with the
+// x, y and forward-z neighbours from LDS, the backward-z hop carried in
+// registers from the previous step (hopping() with ZM) and only the t
+// neighbours from memory.  A site of the column is thus read from memory once
+// (plus one plane before the chunk), against five times (own plane and four
+// neighbour planes) for plane blocks.  Tiles are ordered rhs fastest, then t,
+// then the chunk, so the blocks sharing links or t neighbours run together on
+// one XCD.  Partial sums are per column: part[c Lt + t][rhs].
+// Needs Lx Ly <= blockDim.x and one rhs per tile; FP32 and FP16 storage.
+template <int P, int ORD, bool B>
+__device__ __forceinline__ void zm_tile(const Prob &pr, int t, typename LdsSpinor<P>::word *lds) {
+    typedef typename real_of<P>::type R;
+    constexpr int XP = XPrec<P>::value;
+    typedef typename real_of<XP>::type RX;
+    constexpr int K = B ? KB : KA;
+    const Geom g = pr.g;
+    const int np = g.S[2], Lz = g.L[2], Lt = g.L[3];
+    const int nzc = pr.sorder[K] & 0xffff;
+    const int rhs = t % pr.nrhs, col = t / pr.nrhs;
+    const int c = col / Lt, tt = col - c * Lt;
+    const int z0 = (c * Lz) / nzc, z1 = ((c + 1) * Lz) / nzc;
+    const unsigned act = rhs_mask<1>(pr, rhs, ST_ACTIVE);
+    if (!act) return;   // the same for every thread of the block
+    const int i = threadIdx.x;
+    const bool on = i < np;
+    typename LdsSpinor<P>::word *buf[2] = {lds, lds + LdsWords<P>::value * np};
+    FieldPtr fin{B ? pr.q : pr.p, g.V, pr.nrhs};
+    FieldPtr fr{pr.r, g.V, pr.nrhs}, fx{pr.x_lo, g.V, pr.nrhs}, fq{pr.q, g.V, pr.nrhs};
+    const void *U = pr.U_lo;
+    constexpr int SB = B ? +1 : -1;   // backward-hop sign of D (B) or D^dagger (A)
+    cx<R> carry[1][12];
+    if (on) {   // backward z hop of plane z0 from plane z0 - 1; stage plane z0
+        const int sp = i + np * ((z0 == 0 ? Lz - 1 : z0 - 1) + Lz * tt);
+        cx<R> u[9], v[12], h[6], w[6];
+        Link<P>::load(U, g.V, 2, sp, u);
+        Spinor<P>::load(fin, rhs, sp, v);
+        project<2, SB>(v, h);
+        link_adj_mul(u, h, w);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) carry[0][k] = {R(0), R(0)};
+        accumulate<2, SB>(w, carry[0]);
+        Spinor<P>::load(fin, rhs, i + np * (z0 + Lz * tt), v);
+        LdsSpinor<P>::put(buf[0], np, 0, i, v);
+    }
+    double part = 0.0;
+    for (int z = z0; z < z1; ++z) {
+        const int cur = (z - z0) & 1;
+        const int s = i + np * (z + Lz * tt);
+        if (on) {   // stage plane z + 1 (the forward z neighbours)
+            cx<R> v[12];
+            Spinor<P>::load(fin, rhs, i + np * ((z + 1 == Lz ? 0 : z + 1) + Lz * tt), v);
+            LdsSpinor<P>::put(buf[cur ^ 1], np, 0, i, v);
+        }
+        __syncthreads();
+        if (on) {
+            cx<R> acc[1][12], self[12], o[12];
+            hopping<P, !B, 1, ORD, true, false, true>(g, s, U, fin, rhs, act, acc, nullptr, buf[cur], s - i, np,
+                                                      buf[cur ^ 1], carry);
+            LdsSpinor<P>::get(buf[cur], np, 0, i, self);
+            wilson_finish<R>((R)pr.diag, self, acc[0], o);
+            double n = 0;
+            if constexpr (B) {   // r -= alpha D q; x_lo += alpha q
+                const R a = (R)pr.sc[rhs].alpha;
+                cx<R> r[12];
+                Spinor<P>::template load<Stream<P>::ld>(fr, rhs, s, r);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) r[k] = {r[k].re - a * o[k].re, r[k].im - a * o[k].im};
+                Spinor<P>::template store<Stream<P>::st>(fr, rhs, s, r);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) n += (double)norm2(r[k]);
+                cx<RX> x[12];
+                Spinor<XP>::template load<Stream<P>::ld>(fx, rhs, s, x);
+                const RX ax = (RX)pr.sc[rhs].alpha;
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    x[k] = {x[k].re + ax * (RX)self[k].re, x[k].im + ax * (RX)self[k].im};
+                Spinor<XP>::template store<Stream<P>::st>(fx, rhs, s, x);
+            } else {             // q = D^dagger p
+                Spinor<P>::template store<Stream<P>::st>(fq, rhs, s, o);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) n += (double)norm2(o[k]);
+            }
+            part += n;
+        }
+        __syncthreads();   // buf[cur] is overwritten by the next step
+    }
+    double pv[1] = {part};
+    block_sum<1>(pv);
+    if (threadIdx.x == 0) part_at(pr, col, rhs, 0) = pv[0];
+}
+
 // ------------------------------------------------------------------ phase C
 // p = r + beta p (or p = r after a restart), streaming, tile = (site block, rhs)
 template <int P>

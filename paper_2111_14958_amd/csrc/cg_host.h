@@ -12,7 +12,9 @@ struct KindShape {
     int block = 256, nr = 1, remap = 0, grid = 0;
     int ordered = 1;   // hop order of phases A and B: 1 or 3 (pipelined)
     int order = 0;     // stencil kinds: processing order, strip | group-major << 16 | plane-blocked << 17
-    int xy = 0;        // phases A and B: plane-blocked variant (x/y neighbours from LDS)
+    int xy = 0;        // phases A and B: 1 plane-blocked variant (x/y neighbours from LDS),
+                       // 2 z-marching columns of planes (zm_tile)
+    int lds = 0;       // dynamic LDS bytes per block (z-marching)
 };
 struct LaunchSet {
     KindShape k[NKIND];

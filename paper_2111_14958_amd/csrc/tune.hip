@@ -42,6 +42,12 @@ static bool g_loaded = false;
 // in FP32 / FP16N, one in FP64.  CG phase kernels: one rhs per thread,
 // plane-blocked in FP32 and FP64 (in FP16N the site-blocked kernel is faster).
 // The reliable-update kernel: two rhs per thread.
+// wd_tune_result.site_order: strip | group-major << 16 | plane-blocked << 17 |
+// blocks-per-CU cap << 18 | z-marching << 24 (z-marching: xylds 2)
+static int encode_order(const Shape &s) {
+    return s.strip | (s.gmajor << 16) | ((s.xylds ? 1 : 0) << 17) | (s.occ << 18) | ((s.xylds == 2) << 24);
+}
+
 Shape default_shape(int prec, int nrhs, int fam) {
     Shape s;
     s.block = 256;
@@ -183,7 +189,7 @@ int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
     cfg->xcd_remap = s.remap;
     cfg->hop_order = s.ordered;
     cfg->rhs_loop = s.rloop;
-    cfg->site_order = s.strip | (s.gmajor << 16) | (s.xylds << 17) | (s.occ << 18);
+    cfg->site_order = encode_order(s);
     return WD_OK;
 }
 
@@ -200,7 +206,7 @@ int wd_shape_get(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     cfg->xcd_remap = s.remap;
     cfg->hop_order = s.ordered;
     cfg->rhs_loop = s.rloop;
-    cfg->site_order = s.strip | (s.gmajor << 16) | (s.xylds << 17) | (s.occ << 18);
+    cfg->site_order = encode_order(s);
     return WD_OK;
 }
 
@@ -211,7 +217,7 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     WD_CHECK(prec >= 0 && prec <= 2, WD_EINVAL, "unknown precision %d", prec);
     WD_CHECK(nrhs >= 1 && nrhs <= MAX_RHS, WD_EINVAL, "nrhs %d out of range", nrhs);
     WD_CHECK(family >= FAM_DSLASH && family <= FAM_CG_R, WD_EINVAL, "unknown kernel family %d", family);
-    WD_CHECK(sh->block == 64 || sh->block == 128 || sh->block == 256 || (sh->site_order >> 17), WD_EINVAL,
+    WD_CHECK(sh->block == 64 || sh->block == 128 || sh->block == 256 || ((sh->site_order >> 17) & 1), WD_EINVAL,
              "block %d", sh->block);   // the plane-blocked variant takes the plane size
     WD_CHECK(sh->rhs_per_thread == 1 || sh->rhs_per_thread == 2 || sh->rhs_per_thread == 4, WD_EINVAL,
              "rhs_per_thread %d", sh->rhs_per_thread);
@@ -221,11 +227,16 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     WD_CHECK(!(family == FAM_CG_R && sh->rhs_per_thread > 2), WD_EINVAL, "reliable-update kernel takes <= 2 rhs");
     WD_CHECK(!(prec == WD_F64 && family != FAM_DSLASH && sh->rhs_per_thread > 2), WD_EINVAL,
              "FP64 CG kernels take <= 2 rhs per thread");
+    const int zm = (sh->site_order >> 24) & 1;
     const int strip = sh->site_order & 0xffff, gmajor = (sh->site_order >> 16) & 1,
-              xylds = (sh->site_order >> 17) & 1, occ = sh->site_order >> 18;
-    WD_CHECK(sh->site_order >= 0 && occ <= 8, WD_EINVAL, "site_order 0x%x", sh->site_order);
+              xylds = (sh->site_order >> 17) & 1 ? 1 + zm : 0, occ = (sh->site_order >> 18) & 0x3f;
+    WD_CHECK(sh->site_order >= 0 && (sh->site_order >> 25) == 0 && occ <= 8, WD_EINVAL, "site_order 0x%x",
+             sh->site_order);
+    WD_CHECK(!zm || ((sh->site_order >> 17) & 1), WD_EINVAL, "z-marching needs the plane-blocked bit");
     WD_CHECK(!xylds || (family != FAM_CG_R && g->dims[0] * g->dims[1] <= 256), WD_EINVAL,
              "plane-blocked LDS variant: operator and CG phase A/B kernels, Lx*Ly <= 256");
+    WD_CHECK(!zm || family == FAM_CG_A || family == FAM_CG_B, WD_EINVAL,
+             "z-marching: CG phase A/B kernels only (FP64 falls back to plane blocks)");
     ShapeKey k{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, prec, nrhs, dagger ? 1 : 0, family};
     Shape s;
     s.block = sh->block;
@@ -364,7 +375,7 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
         best->xcd_remap = bestshape.remap;
         best->hop_order = bestshape.ordered;
         best->rhs_loop = bestshape.rloop;
-        best->site_order = bestshape.strip | (bestshape.gmajor << 16) | (bestshape.xylds << 17) | (bestshape.occ << 18);
+        best->site_order = encode_order(bestshape);
         best->us = best_us;
         best->gbps = algorithmic_bytes(prec, V, nrhs) / (best_us * 1e-6) / 1e9;
     }

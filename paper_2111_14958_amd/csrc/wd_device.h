@@ -384,12 +384,19 @@ template <> struct LdsSpinor<P64> {
 // xy-plane (`xy`, plane starting at site `plane0`, np sites) instead of memory.
 // HALF: `in` holds only the sites of the other parity, site n at index n / 2
 // (even-odd preconditioning; needs an even Lx).
-template <int P, bool DAG, int NR, int ORDERED = 1, bool XYLDS = false, bool HALF = false>
+// ZM (with XYLDS; for a block that walks a column of xy-planes in z): `zn` is
+// the LDS copy of the next plane, which supplies the forward z neighbour.  The
+// backward z hop is not formed here: acc starts from `carry`, which holds it
+// on entry, and on return `carry` holds the backward z hop of site s + z,
+// (1 + SB gamma_z) U_z(s)^dag psi(s), made from the link the forward z hop loads.
+template <int P, bool DAG, int NR, int ORDERED = 1, bool XYLDS = false, bool HALF = false, bool ZM = false>
 __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, const FieldPtr &in,
                                         int rhs0, unsigned act, cx<typename real_of<P>::type> acc[NR][12],
                                         const cx<typename real_of<P>::type> (*first)[12] = nullptr,
                                         const typename LdsSpinor<P>::word *xy = nullptr, int plane0 = 0,
-                                        int np = 0) {
+                                        int np = 0, const typename LdsSpinor<P>::word *zn = nullptr,
+                                        cx<typename real_of<P>::type> (*carry)[12] = nullptr) {
+    static_assert(!ZM || XYLDS, "z-marching reads the x and y neighbours from LDS");
     typedef typename real_of<P>::type R;
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
@@ -398,7 +405,7 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
 #pragma unroll
     for (int j = 0; j < NR; ++j)
 #pragma unroll
-        for (int k = 0; k < 12; ++k) acc[j][k] = {R(0), R(0)};
+        for (int k = 0; k < 12; ++k) acc[j][k] = ZM ? carry[j][k] : cx<R>{R(0), R(0)};
 
     // ORDERED (1): one hop at a time.  Each hop's load addresses pass through empty asm
     // statements that also consume every accumulator of the previous hop, so
@@ -450,6 +457,7 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
         if constexpr (ORDERED == 2 && FWD) after_acc(nbi[H + 1], lsi[H + 1]);
         if constexpr ((ORDERED == 3 || ORDERED == 4) && H + 1 < 8) after_acc(nbi[H + 1], lsi[H + 1]);
         if constexpr (ORDERED == 4 && H == 0) after_first(nbi[0]);
+        if constexpr (ZM && MU == 2 && !FWD) return;   // carried in from the previous plane
         const int nb = nbi[H];
         cx<R> u[9];
         Link<P>::load(U, g.V, MU, lsi[H], u);
@@ -458,11 +466,20 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
             if (act >> j & 1) {
                 cx<R> p[12], h[6], w[6];
                 if constexpr (XYLDS && MU < 2) LdsSpinor<P>::get(xy, np, j, nb - plane0, p);
+                else if constexpr (ZM && MU == 2) LdsSpinor<P>::get(zn, np, j, s - plane0, p);
                 else Spinor<P>::load(in, rhs0 + j, HALF ? nb >> 1 : nb, p);
                 project<MU, S>(p, h);
                 if constexpr (FWD) link_mul(u, h, w);
                 else link_adj_mul(u, h, w);
                 accumulate<MU, S>(w, acc[j]);
+                if constexpr (ZM && MU == 2) {   // backward z hop of s + z from this link and psi(s)
+                    LdsSpinor<P>::get(xy, np, j, s - plane0, p);
+                    project<2, SB>(p, h);
+                    link_adj_mul(u, h, w);
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) carry[j][k] = {R(0), R(0)};
+                    accumulate<2, SB>(w, carry[j]);
+                }
             }
         }
     };

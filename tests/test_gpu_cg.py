@@ -264,7 +264,7 @@ def test_plane_blocked_phase_kernels(inner, dims):
     g = wd.Gauge(dev(U), dims)
     p = wd.cg_default_params(inner=inner, reliable_every=0 if inner == wd.F64 else 50)
     sols = {}
-    for xy in (0, 1):
+    for xy in (0, 1, 2):
         for fam, dag in ((wd.FAMILY_CG_A, True), (wd.FAMILY_CG_B, False)):
             wd.shape_set(g, inner, nrhs, dag, fam, 256, 2, 1, 3, 1, 4, 0, xy)
             got = wd.shape_get(g, inner, nrhs, dag, fam)
@@ -273,4 +273,40 @@ def test_plane_blocked_phase_kernels(inner, dims):
         assert rc == wd.WD_OK, reps
         sols[xy] = host(x)
     _check_solution(U, eta, sols[1], dims, m0)
+    _check_solution(U, eta, sols[2], dims, m0)
     assert rel(sols[1], sols[0]) <= kappa(m0) * 2 * TOL
+    assert rel(sols[2], sols[0]) <= kappa(m0) * 2 * TOL
+
+
+@pytest.mark.parametrize("inner", [wd.F32, wd.F16N], ids=["f32", "f16n"])
+@pytest.mark.parametrize("dims,chunks", [((8, 8, 6, 6), (1, 2, 3, 6, 0)), ((16, 8, 5, 4), (1, 2, 5, 0)),
+                                         ((8, 16, 2, 6), (1, 2)), ((14, 14, 14, 4), (4, 7))],
+                         ids=["8x8x6x6", "16x8x5x4", "8x16x2x6", "14x14x14x4"])
+def test_z_marching_phase_kernels(inner, dims, chunks):
+    """Phases A and B walking columns of xy-planes along z (two planes in LDS,
+    the backward z hop carried from the previous plane): for every z-chunk
+    count, from whole columns to one plane per chunk (0 = automatic), and for
+    odd Lz and Lz = 2, the solution passes the oracle and agrees with the
+    site-blocked kernels to the solver tolerance."""
+    m0 = 0.1
+    U = wdgen.gauge_field(dims, 0.5, 411)
+    eta = wdgen.mixed_sources(dims, 2, 2, 412)
+    nrhs = eta.shape[0]
+    g = wd.Gauge(dev(U), dims)
+    p = wd.cg_default_params(inner=inner, reliable_every=50)
+    for fam, dag in ((wd.FAMILY_CG_A, True), (wd.FAMILY_CG_B, False)):
+        wd.shape_set(g, inner, nrhs, dag, fam, 256, 1, 1, 3, 1, 0, 0, 0)
+    say("cg site-blocked reference", dims, inner)
+    x0, reps0, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    assert rc == wd.WD_OK, reps0
+    x0 = host(x0)
+    for nzc in chunks:
+        for fam, dag in ((wd.FAMILY_CG_A, True), (wd.FAMILY_CG_B, False)):
+            wd.shape_set(g, inner, nrhs, dag, fam, 256, 1, 1, 3, 1, nzc, 0, 2)
+            assert wd.shape_get(g, inner, nrhs, dag, fam)["xy_lds"] == 2
+        say("cg z-marching", dims, inner, "chunks", nzc)
+        x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+        assert rc == wd.WD_OK, reps
+        x = host(x)
+        _check_solution(U, eta, x, dims, m0)
+        assert rel(x, x0) <= kappa(m0) * 2 * TOL, nzc
