@@ -89,10 +89,20 @@ typedef struct wd_gauge wd_gauge;
 #define WD_GAUGE_F64  (1u << WD_F64)
 #define WD_GAUGE_F32  (1u << WD_F32)
 #define WD_GAUGE_F16  (1u << WD_F16N)
+/* Reconstruct-12: beside each FP32 and FP16 copy, keep one with rows 0 and 1 of
+ * each link only (12 reals instead of 18); the CG kernels of phases A and B
+ * (plane or site blocks, not even-odd, not the persistent or z-marching
+ * kernels) read it and rebuild row 2 as the complex conjugate of the cross
+ * product of rows 0 and 1, which holds for SU(3) matrices (unitary, det 1).
+ * That cuts a third of their link bytes.  The paper's Conclusions ask for
+ * operator representations better suited to the Dirac operator; this is a
+ * standard one.  wd_gauge_create returns WD_EINVAL (and keeps nothing) when a
+ * link's row 2 differs from that product by more than 1e-6 in any component. */
+#define WD_GAUGE_RECON12 (1u << 8)
 
 /* Pack the canonical complex128 links U_dev (dims, see above) into device-resident
- * copies in the precisions of prec_mask (the FP64 copy is always made: the solver
- * uses it for true residuals).  t_sign is -1 (antiperiodic time boundary) or +1.
+ * copies in the precisions of prec_mask, optionally | WD_GAUGE_RECON12 (the FP64
+ * copy is always made: the solver uses it for true residuals).  t_sign is -1 (antiperiodic time boundary) or +1.
  * Lower-precision copies are rounded to nearest even (FP16 via FP32).
  * Synchronises `stream` before returning; U_dev may be freed afterwards. */
 int wd_gauge_create(const int32_t dims[4], int32_t t_sign, const void *U_dev,

@@ -23,6 +23,7 @@ F64, F32, F16N = 0, 1, 2
 METHOD_CGNE, METHOD_BICGSTAB = 0, 1
 PRECOND_NONE, PRECOND_EO = 0, 1
 PACKED = 1
+GAUGE_RECON12 = 1 << 8   # wd_gauge_create: also keep two-row (reconstruct-12) FP32/FP16 copies
 GAUGE_F64, GAUGE_F32, GAUGE_F16 = 1, 2, 4
 
 WD_OK, WD_EINVAL, WD_ENODEV, WD_EHIP, WD_ENOMEM = 0, -1, -2, -3, -4
@@ -208,7 +209,7 @@ class Gauge:
     """Device-resident packed links (wd_gauge).  U: complex128 GPU tensor
     [Lt, Lz, Ly, Lx, 4, 3, 3]; dims = (Lx, Ly, Lz, Lt)."""
 
-    def __init__(self, U, dims, t_sign: int = -1, precs=(F64, F32, F16N)):
+    def __init__(self, U, dims, t_sign: int = -1, precs=(F64, F32, F16N), recon12: bool = False):
         torch = _torch()
         _require_cuda(U, torch.complex128, "U")
         self.dims = tuple(int(d) for d in dims)
@@ -216,7 +217,7 @@ class Gauge:
         self.sites = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
         if U.numel() != self.sites * 36:
             raise ValueError("U does not match dims")
-        mask = 0
+        mask = GAUGE_RECON12 if recon12 else 0
         for p in precs:
             mask |= 1 << p
         d = (ctypes.c_int32 * 4)(*self.dims)

@@ -35,16 +35,17 @@ namespace wd {
     const Prob &pr = probs[find_prob(probs, nprob, K, b_)];                    \
     const int t_ = b_ - pr.t0[K];
 
-template <int P, int NR, int ORD, bool XY>
+// R12: links from the reconstruct-12 copy (FP32/FP16 storage)
+template <int P, int NR, int ORD, bool XY, bool R12 = false>
 __global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KA)
-    phaseA_tile<P, NR, ORD, XY>(pr, t_);
+    phaseA_tile<P, NR, ORD, XY, R12>(pr, t_);
 }
 
-template <int P, int NR, int ORD, bool XY>
+template <int P, int NR, int ORD, bool XY, bool R12 = false>
 __global__ __launch_bounds__(256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KB)
-    phaseB_tile<P, NR, ORD, XY>(pr, t_);
+    phaseB_tile<P, NR, ORD, XY, R12>(pr, t_);
 }
 
 // z-marching phases A and B (zm_tile); dynamic LDS of two plane buffers
@@ -246,10 +247,37 @@ static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
 
 // hop order 3 (pipelined) or 1 (one hop at a time) for the phase kernels;
 // the plane-blocked (XY) variants exist for up to 2 rhs per thread (1 in FP64)
+// reconstruct-12 variants: FP32/FP16 storage, plane or site blocks, 1 or 2 rhs per thread
 template <int P, int ORD, bool B>
-static void launch_AB_o(int nr, int xy, int lds, int grid, int blk, hipStream_t st, const Prob *d, int n,
+static void launch_AB_r12(int nr, int xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    const dim3 gr(grid), bl(blk);
+    if constexpr (P != P64) {
+        if (xy) {
+            if (nr == 2) {
+                if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, true, true>), gr, bl, st, d, n, remap);
+                else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, true, true>), gr, bl, st, d, n, remap);
+            } else {
+                if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, true, true>), gr, bl, st, d, n, remap);
+                else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, true, true>), gr, bl, st, d, n, remap);
+            }
+        } else if (nr == 2) {
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, false, true>), gr, bl, st, d, n, remap);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, false, true>), gr, bl, st, d, n, remap);
+        } else {
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, false, true>), gr, bl, st, d, n, remap);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, false, true>), gr, bl, st, d, n, remap);
+        }
+    }
+}
+
+template <int P, int ORD, bool B>
+static void launch_AB_o(int nr, int xy, int lds, int r12, int grid, int blk, hipStream_t st, const Prob *d, int n,
                         int remap) {
     const dim3 gr(grid), bl(blk);
+    if (r12) {
+        launch_AB_r12<P, ORD, B>(nr, xy, grid, blk, st, d, n, remap);
+        return;
+    }
     if (xy == 2) {
         if constexpr (P != P64) {
             if (B) WD_TIMED_LAUNCH_LDS((k_phaseB_zm<P, ORD>), gr, bl, lds, st, d, n, remap);
@@ -280,13 +308,13 @@ static void launch_AB_o(int nr, int xy, int lds, int grid, int blk, hipStream_t 
 }
 template <int P>
 static void launch_A(const KindShape &k, hipStream_t st, const Prob *d, int n) {
-    if (k.ordered == 3) launch_AB_o<P, 3, false>(k.nr, k.xy, k.lds, k.grid, k.block, st, d, n, k.remap);
-    else launch_AB_o<P, 1, false>(k.nr, k.xy, k.lds, k.grid, k.block, st, d, n, k.remap);
+    if (k.ordered == 3) launch_AB_o<P, 3, false>(k.nr, k.xy, k.lds, k.r12, k.grid, k.block, st, d, n, k.remap);
+    else launch_AB_o<P, 1, false>(k.nr, k.xy, k.lds, k.r12, k.grid, k.block, st, d, n, k.remap);
 }
 template <int P>
 static void launch_B(const KindShape &k, hipStream_t st, const Prob *d, int n) {
-    if (k.ordered == 3) launch_AB_o<P, 3, true>(k.nr, k.xy, k.lds, k.grid, k.block, st, d, n, k.remap);
-    else launch_AB_o<P, 1, true>(k.nr, k.xy, k.lds, k.grid, k.block, st, d, n, k.remap);
+    if (k.ordered == 3) launch_AB_o<P, 3, true>(k.nr, k.xy, k.lds, k.r12, k.grid, k.block, st, d, n, k.remap);
+    else launch_AB_o<P, 1, true>(k.nr, k.xy, k.lds, k.r12, k.grid, k.block, st, d, n, k.remap);
 }
 template <int P>
 static void launch_R2(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
@@ -504,6 +532,11 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
                 ks.order = nzc;
                 ks.lds = 2 * 6 * np * 16;   // two planes of 6 float4 per site
             }
+            // reconstruct-12 links for phases A and B (plane or site blocks, <= 2 rhs per thread)
+            if ((k == KA || k == KB) && pr.U12 && !pr.eo && ks.xy != 2) {
+                ks.r12 = 1;
+                if (ks.nr > 2) ks.nr = 2;
+            }
         } else {
             ks.block = 256;
             ks.nr = 1;
@@ -537,6 +570,7 @@ void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner, in
         ks.order = ks.xy == 2 ? 0 : ks.order & ~(1 << 17);   // z-marching: the order held the chunk count
         ks.xy = 0;
         ks.lds = 0;
+        ks.r12 = 0;   // the persistent kernel reads the complete copy
         pr.sorder[k] = ks.order;
         pr.nsb[k] = (int)((V + blk - 1) / blk);
         pr.ng[k] = (nrhs + nr - 1) / nr;
@@ -559,6 +593,7 @@ void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_par
     pr.ru_every = p.reliable_every;
     pr.method = p.method;
     pr.U_lo = g->U[p.inner];
+    pr.U12 = p.inner != WD_F64 ? g->U12[p.inner] : nullptr;
     pr.U64 = g->U[WD_F64];
     pr.x_lo = ws + L.xlo;
     pr.r = ws + L.r;
@@ -682,11 +717,11 @@ static const char *g_prof_names[3] = {"cg_phaseA", "cg_phaseB", "cg_phaseC"};
 // d_i is its iteration count advance over the chunk (and skipped phase C of
 // the iteration in which it froze).
 static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *dprob, int K,
-                          int nrhs, int64_t V, void *dscal) {
+                          int nrhs, int64_t V, void *dscal, bool r12) {
     std::vector<hipEvent_t> ev(6 * K);   // start and end of every A, B, C tile kernel
     for (auto &e : ev) WD_HIP(hipEventCreate(&e));
     std::vector<Scal> before(nrhs), after(nrhs);
-    const double G = (double)link_bytes(inner, V);
+    const double G = (double)link_bytes(inner, V, r12);
     const double S = (double)spinor_bytes(inner, V, 1);
     const double SX = (double)spinor_bytes(inner == WD_F16N ? WD_F32 : inner, V, 1);
     int rc = WD_OK;
@@ -815,7 +850,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
         key.shp[k][1] = ls.k[k].nr;
         key.shp[k][2] = ls.k[k].remap;
         key.shp[k][3] = ls.k[k].grid;
-        key.shp[k][4] = ls.k[k].order | (ls.k[k].xy << 18);
+        key.shp[k][4] = ls.k[k].order | (ls.k[k].xy << 18) | (ls.k[k].r12 << 20);
     }
     hipGraphExec_t exec = nullptr;
     int rec_rc = WD_OK;
@@ -856,7 +891,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     for (int c = 0; c < max_chunks && hsum[0] > 0; ++c) {
         hipError_t e = hipSuccess;
         if (prof) {
-            rc = profiled_chunk(p.inner, ls, st, dprob, K, nrhs, V, w + L.scal);
+            rc = profiled_chunk(p.inner, ls, st, dprob, K, nrhs, V, w + L.scal, ls.k[KB].r12 != 0);
             if (rc) {
                 (void)hipHostFree(hsum);
                 return rc;

@@ -77,6 +77,7 @@ struct alignas(16) Prob {
     int nt[NKIND];    // tiles of this problem
     int sorder[NKIND];  // stencil kinds: strip | group-major << 16 (see order_site)
     const void *U_lo; // links in the inner precision
+    const void *U12;  // reconstruct-12 copy in the inner precision, or null
     const void *U64;  // FP64 links
     void *x_lo, *r, *p, *q;   // inner-precision vectors (x_lo: FP32 for FP16N)
     void *x64, *eta64;        // FP64 packed vectors
@@ -222,7 +223,8 @@ __device__ __forceinline__ unsigned rhs_mask(const Prob &pr, int rhs0, int want)
 // ------------------------------------------------------------------ phase A
 // q = D^dagger p for active rhs; partial |q|^2 (of the stored q)
 // XY: plane-blocked (one xy-plane per block, x/y neighbours from LDS).
-template <int P, int NR, int ORD = 1, bool XY = false>
+// R12: the links are the gauge's reconstruct-12 copy pr.U12 (two rows per link).
+template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false>
 __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     typedef typename LdsSpinor<P>::word W;
@@ -239,9 +241,10 @@ __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
     FieldPtr fp{pr.p, g.V, pr.nrhs}, fq{pr.q, g.V, pr.nrhs};
     if (XY && act) stage_plane<P, NR>(fp, rhs0, act, s, g.V, xy, np);
     if (act && s < g.V) {
-        const void *U = pr.U_lo;
+        const void *U = R12 ? pr.U12 : pr.U_lo;
         cx<R> acc[NR][12];
-        hopping<P, true, NR, ORD, XY>(g, s, U, fp, rhs0, act, acc, nullptr, xy, s - (int)threadIdx.x, np);
+        hopping<P, true, NR, ORD, XY, false, false, R12>(g, s, U, fp, rhs0, act, acc, nullptr, xy,
+                                                         s - (int)threadIdx.x, np);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
@@ -286,7 +289,7 @@ __device__ __forceinline__ void phaseA_finish(const Prob &pr) {
 
 // ------------------------------------------------------------------ phase B
 // t = D q; r -= alpha t; x_lo += alpha q(s); partial |r|^2 (of the stored r)
-template <int P, int NR, int ORD = 1, bool XY = false>
+template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false>
 __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     constexpr int XP = XPrec<P>::value;
@@ -305,9 +308,10 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
     FieldPtr fq{pr.q, g.V, pr.nrhs}, fr{pr.r, g.V, pr.nrhs}, fx{pr.x_lo, g.V, pr.nrhs};
     if (XY && act) stage_plane<P, NR>(fq, rhs0, act, s, g.V, xy, np);
     if (act && s < g.V) {
-        const void *U = pr.U_lo;
+        const void *U = R12 ? pr.U12 : pr.U_lo;
         cx<R> acc[NR][12];
-        hopping<P, false, NR, ORD, XY>(g, s, U, fq, rhs0, act, acc, nullptr, xy, s - (int)threadIdx.x, np);
+        hopping<P, false, NR, ORD, XY, false, false, R12>(g, s, U, fq, rhs0, act, acc, nullptr, xy,
+                                                          s - (int)threadIdx.x, np);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
@@ -402,7 +406,7 @@ __device__ __forceinline__ void zm_tile(const Prob &pr, int t, typename LdsSpino
     if (on) {   // backward z hop of plane z0 from plane z0 - 1; stage plane z0
         const int sp = i + np * ((z0 == 0 ? Lz - 1 : z0 - 1) + Lz * tt);
         cx<R> u[9], v[12], h[6], w[6];
-        Link<P>::load(U, g.V, 2, sp, u);
+        Link<P>::load(U, g, 2, sp, false, u);
         Spinor<P>::load(fin, rhs, sp, v);
         project<2, SB>(v, h);
         link_adj_mul(u, h, w);

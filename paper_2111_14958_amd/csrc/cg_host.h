@@ -15,6 +15,7 @@ struct KindShape {
     int xy = 0;        // phases A and B: 1 plane-blocked variant (x/y neighbours from LDS),
                        // 2 z-marching columns of planes (zm_tile)
     int lds = 0;       // dynamic LDS bytes per block (z-marching)
+    int r12 = 0;       // phases A and B: links from the reconstruct-12 copy
 };
 struct LaunchSet {
     KindShape k[NKIND];

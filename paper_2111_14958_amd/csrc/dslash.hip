@@ -175,6 +175,7 @@ Geom make_geom(const wd_gauge *gg) {
     g.S[2] = g.L[0] * g.L[1];
     g.S[3] = g.L[0] * g.L[1] * g.L[2];
     g.V = (int)gg->V;
+    g.tsign = gg->tsign;
     return g;
 }
 

@@ -53,30 +53,43 @@ size_t spinor_bytes(int prec, int64_t V, int nrhs) {
     return 0;
 }
 
-size_t link_bytes(int prec, int64_t V) {
+size_t link_bytes(int prec, int64_t V, bool r12) {
     switch (prec) {
     case WD_F64: return (size_t)V * 4 * 144;
-    case WD_F32: return (size_t)V * 4 * 72;
-    case WD_F16N: return (size_t)V * 4 * 36;
+    case WD_F32: return (size_t)V * 4 * (r12 ? 48 : 72);
+    case WD_F16N: return (size_t)V * 4 * (r12 ? 24 : 36);
     }
     return 0;
 }
 
 // ------------------------------------------------------------------ kernels
 // canonical U[site][mu][a][b] (complex128) -> packed [mu][9][V] in precision P
-template <int P>
 // t-links of the last time slice (sites >= last0) are stored times -1 when
 // flip is set: the antiperiodic boundary sign of both hops across it.
-__global__ void k_pack_links(const double2 *__restrict__ in, void *__restrict__ out, int V, int last0, int flip) {
+// R12: rows 0 and 1 only ([mu][6][V]); a link whose row 2 is not
+// sign * conj(row 0 x row 1) to 1e-6 (sign -1 for a flipped link) sets *bad.
+template <int P, bool R12>
+__global__ void k_pack_links(const double2 *__restrict__ in, void *__restrict__ out, int V, int last0, int flip,
+                             int *bad) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= V) return;
+    constexpr int NK = R12 ? 6 : 9;
     for (int mu = 0; mu < 4; ++mu) {
         const double2 *src = in + ((size_t)s * 4 + mu) * 9;
         const bool neg = flip && mu == 3 && s >= last0;
-        for (int k = 0; k < 9; ++k) {
+        if constexpr (R12) {   // check the input matrix (before the sign): det 1 and unitary rows
+            cx<double> u[9];
+            for (int k = 0; k < 9; ++k) u[k] = {src[k].x, src[k].y};
+            const cx<double> r2[3] = {u[6], u[7], u[8]};
+            third_row<double>(u, 1.0);
+            double dev = 0.0;
+            for (int k = 0; k < 3; ++k) dev = fmax(dev, fabs(r2[k].re - u[6 + k].re) + fabs(r2[k].im - u[6 + k].im));
+            if (!(dev <= 1e-6)) *bad = 1;   // a plain store from the lanes that found one
+        }
+        for (int k = 0; k < NK; ++k) {
             double2 v = src[k];
             if (neg) v = make_double2(-v.x, -v.y);
-            const size_t o = ((size_t)mu * 9 + k) * V + s;
+            const size_t o = ((size_t)mu * NK + k) * V + s;
             if constexpr (P == P64) {
                 ((double2 *)out)[o] = v;
             } else if constexpr (P == P32) {
@@ -123,15 +136,20 @@ __global__ void k_unpack_spinor(const void *__restrict__ in, double2 *__restrict
     for (int k = 0; k < 12; ++k) dst[k] = make_double2((double)v[k].re, (double)v[k].im);
 }
 
-int launch_pack_links(int prec, const void *in, void *out, const int dims[4], int tsign, hipStream_t st) {
+int launch_pack_links(int prec, const void *in, void *out, const int dims[4], int tsign, hipStream_t st, bool r12,
+                      int *bad) {
     const int V = dims[0] * dims[1] * dims[2] * dims[3];
     const int last0 = V - dims[0] * dims[1] * dims[2];
     const int flip = tsign < 0 ? 1 : 0;
     const int blocks = (V + 255) / 256;
-    switch (prec) {
-    case WD_F64: hipLaunchKernelGGL(k_pack_links<P64>, dim3(blocks), dim3(256), 0, st, (const double2 *)in, out, V, last0, flip); break;
-    case WD_F32: hipLaunchKernelGGL(k_pack_links<P32>, dim3(blocks), dim3(256), 0, st, (const double2 *)in, out, V, last0, flip); break;
-    case WD_F16N: hipLaunchKernelGGL(k_pack_links<P16>, dim3(blocks), dim3(256), 0, st, (const double2 *)in, out, V, last0, flip); break;
+    WD_CHECK(!r12 || (prec != WD_F64 && bad), WD_EINVAL, "reconstruct-12 packs FP32/FP16 copies with a flag");
+    const double2 *src = (const double2 *)in;
+    switch (prec * 2 + (r12 ? 1 : 0)) {
+    case WD_F64 * 2: hipLaunchKernelGGL((k_pack_links<P64, false>), dim3(blocks), dim3(256), 0, st, src, out, V, last0, flip, bad); break;
+    case WD_F32 * 2: hipLaunchKernelGGL((k_pack_links<P32, false>), dim3(blocks), dim3(256), 0, st, src, out, V, last0, flip, bad); break;
+    case WD_F32 * 2 + 1: hipLaunchKernelGGL((k_pack_links<P32, true>), dim3(blocks), dim3(256), 0, st, src, out, V, last0, flip, bad); break;
+    case WD_F16N * 2: hipLaunchKernelGGL((k_pack_links<P16, false>), dim3(blocks), dim3(256), 0, st, src, out, V, last0, flip, bad); break;
+    case WD_F16N * 2 + 1: hipLaunchKernelGGL((k_pack_links<P16, true>), dim3(blocks), dim3(256), 0, st, src, out, V, last0, flip, bad); break;
     default: return fail(WD_EINVAL, "unknown precision %d", prec);
     }
     WD_HIP(hipGetLastError());
@@ -210,7 +228,7 @@ int wd_gauge_create(const int32_t dims[4], int32_t t_sign, const void *U_dev, ui
     clear_error();
     WD_CHECK(dims && U_dev && out, WD_EINVAL, "null argument");
     WD_CHECK(t_sign == 1 || t_sign == -1, WD_EINVAL, "t_sign must be +1 or -1, got %d", t_sign);
-    WD_CHECK((prec_mask & ~7u) == 0, WD_EINVAL, "bad precision mask 0x%x", prec_mask);
+    WD_CHECK((prec_mask & ~(7u | WD_GAUGE_RECON12)) == 0, WD_EINVAL, "bad precision mask 0x%x", prec_mask);
     int64_t V = 1;
     for (int d = 0; d < 4; ++d) {
         WD_CHECK(dims[d] >= 1 && dims[d] <= 4096, WD_EINVAL, "bad lattice extent dims[%d] = %d", d, dims[d]);
@@ -225,26 +243,56 @@ int wd_gauge_create(const int32_t dims[4], int32_t t_sign, const void *U_dev, ui
     g->tsign = t_sign;
     g->V = V;
     g->mask = prec_mask | WD_GAUGE_F64;
+    const bool r12 = (g->mask & WD_GAUGE_RECON12) != 0;
     hipGetDevice(&g->device);
     hipStream_t st = (hipStream_t)stream;
-    for (int p = 0; p < 3; ++p) {
-        g->U[p] = nullptr;
-        if (!(g->mask & (1u << p))) continue;
-        hipError_t e = hipMalloc(&g->U[p], link_bytes(p, V));
-        if (e != hipSuccess) {
-            for (int q = 0; q < p; ++q) hipFree(g->U[q]);
-            delete g;
-            return fail(WD_ENOMEM, "hipMalloc of %zu link bytes: %s", link_bytes(p, V), hipGetErrorString(e));
+    int *bad = nullptr;   // reconstruct-12: set by the packing kernels for a non-SU(3) link
+    auto release = [&]() {
+        for (int p = 0; p < 3; ++p) {
+            if (g->U[p]) hipFree(g->U[p]);
+            if (g->U12[p]) hipFree(g->U12[p]);
         }
-        launch_pack_links(p, U_dev, g->U[p], g->dims, g->tsign, st);
+        if (bad) hipFree(bad);
+        delete g;
+    };
+    for (int p = 0; p < 3; ++p) g->U[p] = g->U12[p] = nullptr;
+    if (r12) {
+        hipError_t e = hipMalloc(&bad, sizeof(int));
+        if (e != hipSuccess) {
+            bad = nullptr;
+            release();
+            return fail(WD_ENOMEM, "hipMalloc of the link check flag: %s", hipGetErrorString(e));
+        }
+        hipMemsetAsync(bad, 0, sizeof(int), st);
+    }
+    // the complete copies, then (reconstruct-12) the two-row FP32/FP16 copies beside them
+    for (int c = 0; c < 6; ++c) {
+        const int p = c % 3;
+        const bool pr12 = c >= 3;
+        if (!(g->mask & (1u << p)) || (pr12 && (!r12 || p == WD_F64))) continue;
+        void **dst = pr12 ? &g->U12[p] : &g->U[p];
+        hipError_t e = hipMalloc(dst, link_bytes(p, V, pr12));
+        if (e != hipSuccess) {
+            *dst = nullptr;
+            release();
+            return fail(WD_ENOMEM, "hipMalloc of %zu link bytes: %s", link_bytes(p, V, pr12), hipGetErrorString(e));
+        }
+        launch_pack_links(p, U_dev, *dst, g->dims, g->tsign, st, pr12, bad);
     }
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    int nonsu3 = 0;
+    if (e == hipSuccess && bad) e = hipMemcpy(&nonsu3, bad, sizeof(int), hipMemcpyDeviceToHost);
     if (e != hipSuccess) {
-        for (int p = 0; p < 3; ++p) if (g->U[p]) hipFree(g->U[p]);
-        delete g;
+        release();
         return fail(WD_EHIP, "packing links: %s", hipGetErrorString(e));
     }
+    if (nonsu3) {
+        release();
+        return fail(WD_EINVAL, "reconstruct-12 needs SU(3) links: a link's third row differs from the "
+                               "conjugated cross product of its first two by more than 1e-6");
+    }
+    if (bad) hipFree(bad);
     *out = g;
     return WD_OK;
 }
@@ -255,7 +303,10 @@ int wd_gauge_destroy(wd_gauge *g) {
     int cur = 0;
     hipGetDevice(&cur);
     if (cur != g->device) hipSetDevice(g->device);
-    for (int p = 0; p < 3; ++p) if (g->U[p]) hipFree(g->U[p]);
+    for (int p = 0; p < 3; ++p) {
+        if (g->U[p]) hipFree(g->U[p]);
+        if (g->U12[p]) hipFree(g->U12[p]);
+    }
     if (cur != g->device) hipSetDevice(cur);
     delete g;
     return WD_OK;

@@ -14,8 +14,8 @@
 //          P16  half8   [rhs][3][V]      (four complex components per 16 bytes)
 //               + float [rhs][V] norms after the codes of all rhs
 //   links  P64  double2 [mu][9][V]       (U_mu(x)[a][b] at index 3a+b)
-//          P32  float2  [mu][9][V]
-//          P16  half2   [mu][9][V]
+//          P32  float2  [mu][9][V]       (reconstruct-12: [mu][6][V], rows 0 and 1)
+//          P16  half2   [mu][9][V]       (reconstruct-12: [mu][6][V])
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -97,6 +97,7 @@ struct Geom {
     int L[4];     // Lx, Ly, Lz, Lt
     int S[4];     // strides 1, Lx, Lx*Ly, Lx*Ly*Lz
     int V;        // sites
+    int tsign;    // time boundary sign, carried by the t-links of the last slice
 };
 
 __device__ __forceinline__ void site_coords(const Geom &g, int s, int c[4]) {
@@ -205,15 +206,32 @@ template <> struct Spinor<P16> {
 };
 
 // --------------------------------------------------------------- link views
+// Link<P>::load<R12>(U, g, mu, s, last_t, u): the link U_mu at site s.  last_t:
+// s is on the last time slice and mu = t, so the stored link carries the
+// boundary sign.  With reconstruct-12 (R12: a gauge's extra FP32/FP16 copies
+// in the [mu][6][V] layout) only rows 0 and 1 are stored.  The third row of an SU(3) matrix is the complex conjugate of the
+// cross product of the first two.  A link stored times the boundary sign -1
+// has determinant -1, so its third row is that product times -1.
 template <int P> struct Link;
+
+template <typename R>
+__device__ __forceinline__ void third_row(cx<R> u[9], R sg) {
+    const cx<R> c0 = cmul(u[1], u[5]) - cmul(u[2], u[4]);
+    const cx<R> c1 = cmul(u[2], u[3]) - cmul(u[0], u[5]);
+    const cx<R> c2 = cmul(u[0], u[4]) - cmul(u[1], u[3]);
+    u[6] = {sg * c0.re, -sg * c0.im};
+    u[7] = {sg * c1.re, -sg * c1.im};
+    u[8] = {sg * c2.re, -sg * c2.im};
+}
 
 template <> struct Link<P64> {
     typedef double R;
     static constexpr int BYTES_PER_LINK = 144;
-    __device__ static __forceinline__ void load(const void *U, int V, int mu, int s, cx<R> u[9]) {
+    template <bool R12 = false>   // the FP64 copy is always complete
+    __device__ static __forceinline__ void load(const void *U, const Geom &g, int mu, int s, bool, cx<R> u[9]) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            const d2v v = *at<d2v>(U, (size_t)(mu * 9 + k) * V * 16, (uint32_t)s * 16u);
+            const d2v v = *at<d2v>(U, (size_t)(mu * 9 + k) * g.V * 16, (uint32_t)s * 16u);
             u[k] = {v.x, v.y};
         }
     }
@@ -221,22 +239,46 @@ template <> struct Link<P64> {
 template <> struct Link<P32> {
     typedef float R;
     static constexpr int BYTES_PER_LINK = 72;
-    __device__ static __forceinline__ void load(const void *U, int V, int mu, int s, cx<R> u[9]) {
+    template <bool R12 = false>
+    __device__ static __forceinline__ void load(const void *U, const Geom &g, int mu, int s, bool last_t,
+                                                cx<R> u[9]) {
+        constexpr int nk = R12 ? 6 : 9;   // stored entries per link
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const f2v v = *at<f2v>(U, (size_t)(mu * 9 + k) * V * 8, (uint32_t)s * 8u);
+        for (int k = 0; k < 6; ++k) {
+            const f2v v = *at<f2v>(U, (size_t)(mu * nk + k) * g.V * 8, (uint32_t)s * 8u);
             u[k] = {v.x, v.y};
+        }
+        if constexpr (R12) {
+            third_row<R>(u, last_t ? (R)g.tsign : R(1));
+        } else {
+#pragma unroll
+            for (int k = 6; k < 9; ++k) {
+                const f2v v = *at<f2v>(U, (size_t)(mu * 9 + k) * g.V * 8, (uint32_t)s * 8u);
+                u[k] = {v.x, v.y};
+            }
         }
     }
 };
 template <> struct Link<P16> {
     typedef float R;
     static constexpr int BYTES_PER_LINK = 36;
-    __device__ static __forceinline__ void load(const void *U, int V, int mu, int s, cx<R> u[9]) {
+    template <bool R12 = false>
+    __device__ static __forceinline__ void load(const void *U, const Geom &g, int mu, int s, bool last_t,
+                                                cx<R> u[9]) {
+        constexpr int nk = R12 ? 6 : 9;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const half2v v = *at<half2v>(U, (size_t)(mu * 9 + k) * V * 4, (uint32_t)s * 4u);
+        for (int k = 0; k < 6; ++k) {
+            const half2v v = *at<half2v>(U, (size_t)(mu * nk + k) * g.V * 4, (uint32_t)s * 4u);
             u[k] = {(float)v.x, (float)v.y};
+        }
+        if constexpr (R12) {
+            third_row<R>(u, last_t ? (R)g.tsign : R(1));
+        } else {
+#pragma unroll
+            for (int k = 6; k < 9; ++k) {
+                const half2v v = *at<half2v>(U, (size_t)(mu * 9 + k) * g.V * 4, (uint32_t)s * 4u);
+                u[k] = {(float)v.x, (float)v.y};
+            }
         }
     }
 };
@@ -384,12 +426,14 @@ template <> struct LdsSpinor<P64> {
 // xy-plane (`xy`, plane starting at site `plane0`, np sites) instead of memory.
 // HALF: `in` holds only the sites of the other parity, site n at index n / 2
 // (even-odd preconditioning; needs an even Lx).
+// R12: U is a reconstruct-12 copy (two rows per link, FP32/FP16).
 // ZM (with XYLDS; for a block that walks a column of xy-planes in z): `zn` is
 // the LDS copy of the next plane, which supplies the forward z neighbour.  The
 // backward z hop is not formed here: acc starts from `carry`, which holds it
 // on entry, and on return `carry` holds the backward z hop of site s + z,
 // (1 + SB gamma_z) U_z(s)^dag psi(s), made from the link the forward z hop loads.
-template <int P, bool DAG, int NR, int ORDERED = 1, bool XYLDS = false, bool HALF = false, bool ZM = false>
+template <int P, bool DAG, int NR, int ORDERED = 1, bool XYLDS = false, bool HALF = false, bool ZM = false,
+          bool R12 = false>
 __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, const FieldPtr &in,
                                         int rhs0, unsigned act, cx<typename real_of<P>::type> acc[NR][12],
                                         const cx<typename real_of<P>::type> (*first)[12] = nullptr,
@@ -460,7 +504,8 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
         if constexpr (ZM && MU == 2 && !FWD) return;   // carried in from the previous plane
         const int nb = nbi[H];
         cx<R> u[9];
-        Link<P>::load(U, g.V, MU, lsi[H], u);
+        // the t-link of the last slice: the forward hop from t = Lt-1, the backward hop from t = 0
+        Link<P>::template load<R12>(U, g, MU, lsi[H], MU == 3 && c[3] == (FWD ? g.L[3] - 1 : 0), u);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {

@@ -37,7 +37,7 @@ constexpr int MAX_RHS = 64;
 int require_gfx950(int *num_cu = nullptr);
 
 size_t spinor_bytes(int prec, int64_t V, int nrhs);
-size_t link_bytes(int prec, int64_t V);   // all four directions
+size_t link_bytes(int prec, int64_t V, bool r12 = false);   // all four directions; r12: two rows (FP32/FP16)
 
 // Launch shape of one operator kernel.
 struct Shape {
@@ -75,6 +75,7 @@ struct wd_gauge {
     uint32_t mask;
     int device;
     void *U[3];     // packed links per precision (device), nullptr when absent
+    void *U12[3];   // reconstruct-12 copies (FP32, FP16; WD_GAUGE_RECON12), nullptr when absent
 };
 
 namespace wd {
@@ -82,7 +83,10 @@ Geom make_geom(const wd_gauge *g);
 // Launchers implemented in the .hip units (all asynchronous on `stream`).
 // canonical complex128 links -> packed precision prec; the t-links of the last
 // time slice carry the boundary sign (tsign) from here on
-int launch_pack_links(int prec, const void *U_c128, void *out, const int dims[4], int tsign, hipStream_t st);
+// r12 (FP32/FP16): keep rows 0 and 1 only, and set *bad (device int) to 1 where
+// row 2 is not the conjugated cross product of rows 0 and 1 to 1e-6
+int launch_pack_links(int prec, const void *U_c128, void *out, const int dims[4], int tsign, hipStream_t st,
+                      bool r12 = false, int *bad = nullptr);
 int launch_pack_spinor(int prec, const void *in_c128, void *out, int V, int nrhs, hipStream_t st);
 int launch_unpack_spinor(int prec, const void *in, void *out_c128, int V, int nrhs, hipStream_t st);
 int launch_dslash(const wd_gauge *g, double m0, int prec, bool dag, const void *in, void *out,

@@ -120,3 +120,16 @@ def test_no_kernel_spills_to_scratch(lib):
     assert len(lines) > 50
     for line in lines:
         assert "scratch=0 " in line, line
+
+
+def test_header_constants_match_binding():
+    text = open(HEADER).read()
+    defs = {m.group(1): m.group(2) for m in re.finditer(r"#define\s+(WD_[A-Z0-9_]+)\s+(.+?)\s*(?:/\*.*)?$",
+                                                        text, flags=re.M)}
+    want = {"WD_METHOD_CGNE": wd.METHOD_CGNE, "WD_METHOD_BICGSTAB": wd.METHOD_BICGSTAB,
+            "WD_PRECOND_NONE": wd.PRECOND_NONE, "WD_PRECOND_EO": wd.PRECOND_EO,
+            "WD_GAUGE_RECON12": wd.GAUGE_RECON12, "WD_FAMILY_CG_A": wd.FAMILY_CG_A,
+            "WD_FAMILY_CG_B": wd.FAMILY_CG_B}
+    for name, value in want.items():
+        expr = defs[name].replace("u", "")
+        assert eval(expr, {}) == value, (name, defs[name], value)

@@ -5,7 +5,8 @@
   the benchmark times, i.e. the default launch shapes:
   - the operator D and D^dagger on all 16 fields, in each storage precision,
     against the oracle's operator over the whole lattice;
-  - the mixed-precision CG (FP32 inner, FP64 reliable updates every 50): the
+  - the mixed-precision CG (FP32 inner, FP64 reliable updates every 50; with
+    the reconstruct-12 link copies, as the benchmark, and without them): the
     oracle's FP64 operator recomputes every solution's true residual, which must
     be <= tol and agree with the residual the library reports; the solution
     agrees with the FP64 CG solution within kappa(D) (2 tol), the bound on the
@@ -60,11 +61,12 @@ def test_bench_operator_16_fields(bench_fields, prec):
             assert err <= OP_TOL[prec], (prec, dag, i, err)
 
 
-def test_bench_cg_workload(bench_fields):
+@pytest.mark.parametrize("recon12", [True, False], ids=["recon12", "complete-links"])
+def test_bench_cg_workload(bench_fields, recon12):
     cfg, U, src = bench_fields
     dims, m0, tol = cfg["dims"], cfg["m0"], cfg["tol"]
-    g = wd.Gauge(dev(U), dims)
-    say("full-size mixed CG 14^4 x 16")
+    g = wd.Gauge(dev(U), dims, recon12=recon12)
+    say("full-size mixed CG 14^4 x 16", "recon12" if recon12 else "complete links")
     x, reps, rc = wd.cg_solve_batch(g, m0, dev(src), params=wd.cg_default_params(tol=tol, inner=wd.F32,
                                                                                   reliable_every=50))
     assert rc == wd.WD_OK, reps

@@ -1,0 +1,99 @@
+"""Reconstruct-12 links (WD_GAUGE_RECON12): phases A and B of CG read two-row
+FP32/FP16 copies of the links and rebuild the third row from the first two.
+
+The oracle's FP64 operator recomputes the true residual of every solution.
+The solution agrees with the solve on the complete links within kappa(D) (2 tol).
+The profiling mode's byte count shows that the two-row copy was read: a phase-B
+launch moves exactly 4 x 6 complex numbers fewer per site.  Links that are not
+SU(3) are refused.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2111_14958_amd as wd
+import wdgen
+from gpu_util import dev, host, rel, say
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def kappa(m0):
+    return (8.0 + m0) / m0
+
+
+def _phase_b_bytes(g, m0, eta, p):
+    wd.profile_reset()
+    wd.profile_enable(True)
+    try:
+        wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    finally:
+        wd.profile_enable(False)
+    st = wd.profile_read()["cg_phaseB"]
+    return st["bytes_total"], st["launches"]
+
+
+@pytest.mark.parametrize("inner", [wd.F32, wd.F16N], ids=["f32", "f16n"])
+@pytest.mark.parametrize("dims,t_sign", [((8, 8, 4, 6), -1), ((8, 8, 4, 6), 1), ((6, 5, 4, 6), -1),
+                                         ((14, 14, 6, 4), -1)],
+                         ids=["8x8x4x6-anti", "8x8x4x6-peri", "6x5x4x6-site", "14x14x6x4"])
+def test_r12_cg_matches_oracle(inner, dims, t_sign):
+    m0 = 0.1
+    U = wdgen.gauge_field(dims, 0.5, 501)
+    eta = wdgen.mixed_sources(dims, 3, 2, 502)
+    V = wdgen.volume(dims)
+    p = wd.cg_default_params(inner=inner, reliable_every=50)
+    say("r12 cg", dims, t_sign, inner)
+    g12 = wd.Gauge(dev(U), dims, t_sign, recon12=True)
+    x, reps, rc = wd.cg_solve_batch(g12, m0, dev(eta), params=p)
+    assert rc == wd.WD_OK, reps
+    x = host(x)
+    res = oracle.true_residual(U, eta, x, dims, m0, t_sign=t_sign)
+    assert np.all(res <= TOL * 1.0000001), res
+    g = wd.Gauge(dev(U), dims, t_sign)
+    x0, reps0, rc0 = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    assert rc0 == wd.WD_OK
+    assert rel(x, host(x0)) <= kappa(m0) * 2 * TOL
+    # the phase-B kernel read the two-row copy: per launch with work (one field, so every
+    # such launch has one active field), 4 links x 3 complex numbers (FP32: 8 bytes, FP16:
+    # 4 bytes each) fewer per site
+    b12, n12 = _phase_b_bytes(g12, m0, eta[:1], p)
+    b, n = _phase_b_bytes(g, m0, eta[:1], p)
+    per_complex = 8 if inner == wd.F32 else 4
+    assert n12 > 0 and n > 0
+    assert abs(b / n - b12 / n12 - 4 * 3 * per_complex * V) <= 1e-6 * b / n, (b / n, b12 / n12)
+
+
+def test_r12_gauge_serves_every_solver():
+    """Kernels without a two-row variant (even-odd, BiCGSTAB, the persistent
+    kernel) keep reading the complete copy of a reconstruct-12 gauge."""
+    dims, m0 = (8, 8, 4, 6), 0.1
+    U = wdgen.gauge_field(dims, 0.5, 511)
+    eta = wdgen.mixed_sources(dims, 2, 1, 512)
+    g12 = wd.Gauge(dev(U), dims, recon12=True)
+    for kw in ({"precondition": wd.PRECOND_EO}, {"method": wd.METHOD_BICGSTAB}, {"persistent": 1}):
+        say("r12 gauge", kw)
+        x, reps, rc = wd.cg_solve_batch(g12, m0, dev(eta), params=wd.cg_default_params(inner=wd.F32, **kw))
+        assert rc == wd.WD_OK, (kw, reps)
+        assert np.all(oracle.true_residual(U, eta, host(x), dims, m0) <= TOL * 1.0000001), kw
+    say("r12 gauge operator")
+    got = host(wd.dslash(g12, m0, dev(eta), wd.F32))
+    assert rel(got, oracle.dirac(U, eta, dims, m0, -1)) <= 1e-6
+
+
+def test_r12_refuses_links_outside_su3():
+    dims = (4, 4, 4, 4)
+    U = wdgen.gauge_field(dims, 0.5, 521)
+    U[1, 2, 3, 0, 2] *= np.exp(0.3j)   # one link of U(3) with det e^{0.9 i}
+    say("r12 refuses a U(3) link")
+    with pytest.raises(wd.WDError) as e:
+        wd.Gauge(dev(U), dims, recon12=True)
+    assert e.value.code == wd.WD_EINVAL
+    wd.Gauge(dev(U), dims)   # the complete copies take any links

@@ -254,3 +254,21 @@ def test_cg_eo_zero_source_and_free_field():
     gam = [oracle.gamma(mu) for mu in range(4)]
     xs = pins.free_solve_fft(eta[0], dims, m0, -1, gam)
     assert np.linalg.norm(x[0] - xs) <= pins.kappa_bound(m0) * 2e-10 * np.linalg.norm(xs)
+
+
+def test_third_row_of_su3_links_is_conjugated_cross_product():
+    """The identity reconstruct-12 relies on: for U in SU(3), row 2 is the complex
+    conjugate of row 0 x row 1; for -U (a link carrying the boundary sign -1,
+    det -1) it is minus that."""
+    U = wdgen.gauge_field((4, 4, 4, 4), 0.5, 531).reshape(-1, 3, 3)
+    c = np.conj(np.cross(U[:, 0, :], U[:, 1, :]))
+    assert np.max(np.abs(c - U[:, 2, :])) <= 1e-13
+    W = -U
+    cw = np.conj(np.cross(W[:, 0, :], W[:, 1, :]))
+    assert np.max(np.abs(-cw - W[:, 2, :])) <= 1e-13
+    # a U(3) matrix with det e^{i phi} has row 2 = e^{i phi} conj(row 0 x row 1), not the plain product
+    ph = np.exp(0.3j)
+    X = U[:5] * ph
+    cx = np.conj(np.cross(X[:, 0, :], X[:, 1, :]))
+    assert np.max(np.abs(cx - X[:, 2, :])) > 0.1
+    assert np.max(np.abs(np.linalg.det(X)[:, None] * cx - X[:, 2, :])) <= 1e-13
