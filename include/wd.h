@@ -89,12 +89,13 @@ typedef struct wd_gauge wd_gauge;
 #define WD_GAUGE_F64  (1u << WD_F64)
 #define WD_GAUGE_F32  (1u << WD_F32)
 #define WD_GAUGE_F16  (1u << WD_F16N)
-/* Reconstruct-12: beside each FP32 and FP16 copy, keep one with rows 0 and 1 of
- * each link only (12 reals instead of 18); the CG kernels of phases A and B
- * (plane or site blocks, not even-odd, not the persistent or z-marching
- * kernels) read it and rebuild row 2 as the complex conjugate of the cross
- * product of rows 0 and 1, which holds for SU(3) matrices (unitary, det 1).
- * That cuts a third of their link bytes.  The paper's Conclusions ask for
+/* Reconstruct-12: beside the FP32 copy, keep one with rows 0 and 1 of each link
+ * only (12 reals instead of 18); the kernels of phases A and B of CG with FP32
+ * inner iterations (plane or site blocks, not even-odd, not the persistent or
+ * z-marching kernels) read it and rebuild row 2 as the complex conjugate of the
+ * cross product of rows 0 and 1, which holds for SU(3) matrices (unitary, det 1).
+ * That cuts a third of their link bytes.  (With FP16 storage the rebuilt row
+ * cost more than the bytes saved, so those kernels keep the complete copy.)  The paper's Conclusions ask for
  * operator representations better suited to the Dirac operator; this is a
  * standard one.  wd_gauge_create returns WD_EINVAL (and keeps nothing) when a
  * link's row 2 differs from that product by more than 1e-6 in any component. */

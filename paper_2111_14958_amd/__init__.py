@@ -23,7 +23,7 @@ F64, F32, F16N = 0, 1, 2
 METHOD_CGNE, METHOD_BICGSTAB = 0, 1
 PRECOND_NONE, PRECOND_EO = 0, 1
 PACKED = 1
-GAUGE_RECON12 = 1 << 8   # wd_gauge_create: also keep two-row (reconstruct-12) FP32/FP16 copies
+GAUGE_RECON12 = 1 << 8   # wd_gauge_create: also keep a two-row (reconstruct-12) FP32 copy
 GAUGE_F64, GAUGE_F32, GAUGE_F16 = 1, 2, 4
 
 WD_OK, WD_EINVAL, WD_ENODEV, WD_EHIP, WD_ENOMEM = 0, -1, -2, -3, -4

@@ -247,11 +247,11 @@ static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
 
 // hop order 3 (pipelined) or 1 (one hop at a time) for the phase kernels;
 // the plane-blocked (XY) variants exist for up to 2 rhs per thread (1 in FP64)
-// reconstruct-12 variants: FP32/FP16 storage, plane or site blocks, 1 or 2 rhs per thread
+// reconstruct-12 variants: FP32 storage, plane or site blocks, 1 or 2 rhs per thread
 template <int P, int ORD, bool B>
 static void launch_AB_r12(int nr, int xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
     const dim3 gr(grid), bl(blk);
-    if constexpr (P != P64) {
+    if constexpr (P == P32) {
         if (xy) {
             if (nr == 2) {
                 if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, true, true>), gr, bl, st, d, n, remap);
@@ -532,7 +532,7 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
                 ks.order = nzc;
                 ks.lds = 2 * 6 * np * 16;   // two planes of 6 float4 per site
             }
-            // reconstruct-12 links for phases A and B (plane or site blocks, <= 2 rhs per thread)
+            // reconstruct-12 links for phases A and B (FP32; plane or site blocks, <= 2 rhs per thread)
             if ((k == KA || k == KB) && pr.U12 && !pr.eo && ks.xy != 2) {
                 ks.r12 = 1;
                 if (ks.nr > 2) ks.nr = 2;
@@ -593,7 +593,7 @@ void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_par
     pr.ru_every = p.reliable_every;
     pr.method = p.method;
     pr.U_lo = g->U[p.inner];
-    pr.U12 = p.inner != WD_F64 ? g->U12[p.inner] : nullptr;
+    pr.U12 = p.inner == WD_F32 ? g->U12[WD_F32] : nullptr;
     pr.U64 = g->U[WD_F64];
     pr.x_lo = ws + L.xlo;
     pr.r = ws + L.r;

@@ -265,11 +265,11 @@ int wd_gauge_create(const int32_t dims[4], int32_t t_sign, const void *U_dev, ui
         }
         hipMemsetAsync(bad, 0, sizeof(int), st);
     }
-    // the complete copies, then (reconstruct-12) the two-row FP32/FP16 copies beside them
-    for (int c = 0; c < 6; ++c) {
-        const int p = c % 3;
-        const bool pr12 = c >= 3;
-        if (!(g->mask & (1u << p)) || (pr12 && (!r12 || p == WD_F64))) continue;
+    // the complete copies, then (reconstruct-12) the two-row FP32 copy beside them
+    for (int c = 0; c < 4; ++c) {
+        const int p = c < 3 ? c : WD_F32;
+        const bool pr12 = c == 3;
+        if (!(g->mask & (1u << p)) || (pr12 && !r12)) continue;
         void **dst = pr12 ? &g->U12[p] : &g->U[p];
         hipError_t e = hipMalloc(dst, link_bytes(p, V, pr12));
         if (e != hipSuccess) {
