@@ -291,6 +291,47 @@ def main():
     copy_gbps = 2 * a.numel() * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del a, b
 
+    # ------ 8^4, 12^4, 14^4 single field: operator alone and CG, FP64 and FP32 (context)
+    c2 = {}
+    for key in ("c2_8x4", "c2_12x4", "c2_14x4"):
+        c2cfg = wdgen.CONFIGS[key]
+        d2 = c2cfg["dims"]
+        V2 = wdgen.volume(d2)
+        U2 = torch.from_numpy(wdgen.gauge_field(d2, c2cfg["eps"], c2cfg["gauge_seed"])).to(dev)
+        s2 = torch.from_numpy(wdgen.gaussian_source(d2, 1, c2cfg["src_seed"])).to(dev)
+        g2 = wd.Gauge(U2, d2, -1, recon12=True)
+        row = {}
+        for prec, name in ((wd.F64, "f64"), (wd.F32, "f32")):
+            pin = wd.pack_spinor(g2, s2, prec)
+            pout = wd.empty_packed(g2, prec, 1)
+            for _ in range(3):
+                wd.dslash(g2, c2cfg["m0"], pin, prec, packed=True, nrhs=1, out=pout)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(200):
+                wd.dslash(g2, c2cfg["m0"], pin, prec, packed=True, nrhs=1, out=pout)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / 200
+            alg = V2 * ({wd.F64: 576, wd.F32: 288}[prec] + 2 * {wd.F64: 192, wd.F32: 96}[prec])
+            pc = wd.cg_default_params(tol=c2cfg["tol"], inner=prec, reliable_every=0 if prec == wd.F64 else 50)
+            sol2 = torch.zeros_like(s2)
+            ws2 = torch.empty(wd.cg_workspace_bytes(g2, 1, pc), dtype=torch.uint8, device=dev)
+            wd.cg_solve_batch(g2, c2cfg["m0"], s2, sol=sol2, params=pc, ws=ws2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                _, rep2, rc2 = wd.cg_solve_batch(g2, c2cfg["m0"], s2, sol=sol2, params=pc, ws=ws2)
+            torch.cuda.synchronize()
+            row[name] = {"dslash_us": us, "dslash_GBps": alg / (us * 1e-6) / 1e9,
+                         "cg_solves_per_s": 3 / (time.perf_counter() - t0), "cg_iters": rep2[0]["iters"],
+                         "true_rel_res": rep2[0]["true_rel_res"], "converged": rc2 == wd.WD_OK}
+            del pin, pout
+        c2["x".join(str(d) for d in d2)] = row
+        del g2
+    log("single-field context", json.dumps(c2))
+
     # ------------------- 16^3 x 32, m0 0.02, 12 point sources: FP16N vs FP64 (context)
     c4 = None
     if not args.no_c4:
@@ -386,6 +427,7 @@ def main():
             "dslash_16rhs": dslash,
             "coo_spmv_1rhs": coo,
             "copy_GBps": copy_gbps,
+            "c2_single_field": c2,
             "c4_16x3x32_12rhs": c4,
         },
     }
