@@ -133,25 +133,26 @@ __device__ __forceinline__ void block_sum(double v[NR]) {
 // Fixed-order sums over the site blocks of partials 0..nk-1 of every column:
 // one wavefront per (column, partial), lane l adding blocks l, l+64, ... in
 // order, then a butterfly.  sums[i * nk + k] is valid in every thread on
-// return.  The block size must be a multiple of 64.
+// return.  The block size must be a multiple of 64.  A lane's first four
+// blocks are loaded together (absent ones as 0, which leaves the sum
+// unchanged), so up to 256 site blocks cost one memory round trip.
 constexpr int MAX_SUMS = 64 * 3;
 __device__ __forceinline__ void sum_all(const Prob &pr, int nsb, int nk, double *sums) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const size_t bs = (size_t)pr.nrhs * PSTRIDE;   // stride between site blocks
     for (int job = w; job < pr.nrhs * nk; job += nw) {
         const int i = job / nk, k = job - i * nk;
         const double *col = pr.part + (size_t)i * PSTRIDE + k;
-        const size_t bs = (size_t)pr.nrhs * PSTRIDE;   // stride between site blocks
+        const double a0 = lane < nsb ? col[(size_t)lane * bs] : 0.0;
+        const double a1 = lane + 64 < nsb ? col[(size_t)(lane + 64) * bs] : 0.0;
+        const double a2 = lane + 128 < nsb ? col[(size_t)(lane + 128) * bs] : 0.0;
+        const double a3 = lane + 192 < nsb ? col[(size_t)(lane + 192) * bs] : 0.0;
         double x = 0.0;
-        int b = lane;
-        for (; b + 192 < nsb; b += 256) {   // four loads in flight, summed in order
-            const double a0 = col[b * bs], a1 = col[(b + 64) * bs], a2 = col[(b + 128) * bs],
-                         a3 = col[(b + 192) * bs];
-            x += a0;
-            x += a1;
-            x += a2;
-            x += a3;
-        }
-        for (; b < nsb; b += 64) x += col[b * bs];
+        x += a0;
+        x += a1;
+        x += a2;
+        x += a3;
+        for (int b = lane + 256; b < nsb; b += 64) x += col[(size_t)b * bs];
         x = wave_sum(x);
         if (lane == 0) sums[job] = x;
     }
@@ -271,16 +272,21 @@ __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
 
 // The finish functions run in one block; thread i updates the scalars of
 // right-hand side i.
+// Each reads its thread's scalar record before the partial sums, so the two
+// loads overlap (nrhs <= 64 < blockDim.x: one field per thread).
 __device__ __forceinline__ void phaseA_finish(const Prob &pr) {
     __shared__ double sums[MAX_SUMS];
+    const int i = threadIdx.x;
+    Scal c0;
+    if (i < pr.nrhs) c0 = pr.sc[i];
     sum_all(pr, pr.nsb[KA], 1, sums);
-    for (int i = threadIdx.x; i < pr.nrhs; i += blockDim.x) {
+    if (i < pr.nrhs) {
         Scal &c = pr.sc[i];
-        if (c.state == ST_ACTIVE) {
+        if (c0.state == ST_ACTIVE) {
             const double sigma = sums[i];
             c.sigma = sigma;
             if (!finite_pos(sigma)) c.state = ST_BREAKDOWN;
-            else c.alpha = c.rho / sigma;
+            else c.alpha = c0.rho / sigma;
         }
         c.pending_p = 0;
         c.restart = 0;
@@ -348,23 +354,23 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
 
 __device__ __forceinline__ void phaseB_finish(const Prob &pr) {
     __shared__ double sums[MAX_SUMS];
+    const int i = threadIdx.x;
+    Scal c0;
+    if (i < pr.nrhs) c0 = pr.sc[i];
     sum_all(pr, pr.nsb[KB], 1, sums);
-    for (int i = threadIdx.x; i < pr.nrhs; i += blockDim.x) {
+    if (i < pr.nrhs && c0.state == ST_ACTIVE) {
         Scal &c = pr.sc[i];
-        if (c.state != ST_ACTIVE) continue;
         const double rho = sums[i];
-        {
-            c.rho_old = c.rho;
-            c.rho = rho;
-            c.beta = rho / c.rho_old;
-            c.iters += 1;
-            c.since_ru += 1;
-            if (!(rho < 1e300)) c.state = ST_BREAKDOWN;   // NaN or Inf
-            else if (rho <= c.stop2 || c.iters >= pr.max_iter ||
-                     (pr.ru_every > 0 && c.since_ru >= pr.ru_every))
-                c.state = ST_FROZEN;                       // wants a reliable update
-            else c.pending_p = 1;
-        }
+        const int iters = c0.iters + 1, since_ru = c0.since_ru + 1;
+        c.rho_old = c0.rho;
+        c.rho = rho;
+        c.beta = rho / c0.rho;
+        c.iters = iters;
+        c.since_ru = since_ru;
+        if (!(rho < 1e300)) c.state = ST_BREAKDOWN;   // NaN or Inf
+        else if (rho <= c0.stop2 || iters >= pr.max_iter || (pr.ru_every > 0 && since_ru >= pr.ru_every))
+            c.state = ST_FROZEN;                       // wants a reliable update
+        else c.pending_p = 1;
     }
 }
 
