@@ -75,10 +75,10 @@ __global__ __launch_bounds__(256) void k_ru1(const Prob *__restrict__ probs, int
     ru1_tile<P>(pr, t_);
 }
 
-template <int P, int NR>
+template <int P, int NR, bool XY = false>
 __global__ __launch_bounds__(256) void k_ru2(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KR2)
-    ru2_tile<P, NR>(pr, t_);
+    ru2_tile<P, NR, XY>(pr, t_);
 }
 
 __global__ __launch_bounds__(256) void k_norm(const Prob *__restrict__ probs, int nprob, int remap) {
@@ -317,8 +317,9 @@ static void launch_B(const KindShape &k, hipStream_t st, const Prob *d, int n) {
     else launch_AB_o<P, 1, true>(k.nr, k.xy, k.lds, k.r12, k.grid, k.block, st, d, n, k.remap);
 }
 template <int P>
-static void launch_R2(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (nr == 1) hipLaunchKernelGGL((k_ru2<P, 1>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+static void launch_R2(int nr, int xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    if (xy) hipLaunchKernelGGL((k_ru2<P, 1, true>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else if (nr == 1) hipLaunchKernelGGL((k_ru2<P, 1>), dim3(grid), dim3(blk), 0, st, d, n, remap);
     else hipLaunchKernelGGL((k_ru2<P, 2>), dim3(grid), dim3(blk), 0, st, d, n, remap);
 }
 
@@ -417,9 +418,9 @@ static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream
         else hipLaunchKernelGGL(k_ru1<P16>, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
         break;
     case KR2:
-        if (inner == P64) launch_R2<P64>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
-        else if (inner == P32) launch_R2<P32>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
-        else launch_R2<P16>(k.nr, k.grid, k.block, st, d, nprob, k.remap);
+        if (inner == P64) launch_R2<P64>(k.nr, k.xy, k.grid, k.block, st, d, nprob, k.remap);
+        else if (inner == P32) launch_R2<P32>(k.nr, k.xy, k.grid, k.block, st, d, nprob, k.remap);
+        else launch_R2<P16>(k.nr, k.xy, k.grid, k.block, st, d, nprob, k.remap);
         break;
     case KN:
         hipLaunchKernelGGL(k_norm, dim3(k.grid), dim3(k.block), 0, st, d, nprob, 0);
@@ -508,7 +509,7 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.order = strip | (st[k]->gmajor ? 1 << 16 : 0);
             // plane-blocked phases A and B: one xy-plane of 64..256 sites per
             // block (the partial-sum buffer holds one entry per 64 sites)
-            ks.xy = (k == KA || k == KB) && st[k]->xylds && np >= 64 && np <= 256 && !pr.eo;
+            ks.xy = (k == KA || k == KB || k == KR2) && st[k]->xylds && np >= 64 && np <= 256 && !pr.eo;
             if (pr.eo) {   // the half-lattice kernels: site blocks, lexicographic order
                 ks.order = 0;
                 if (ks.nr > 2) ks.nr = 2;
@@ -516,7 +517,7 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             if (ks.xy) {
                 ks.block = 256;
                 if (ks.nr > 2) ks.nr = 2;
-                if (inner == WD_F64) ks.nr = 1;
+                if (inner == WD_F64 || k == KR2) ks.nr = 1;   // FP64 planes: one rhs per thread
                 ks.order |= 1 << 17;
             }
             // z-marching columns of planes (FP32 and FP16 storage, one rhs per

@@ -515,28 +515,34 @@ __device__ __forceinline__ void ru1_tile(const Prob &pr, int t) {
 
 // ------------------------------------------------------- reliable update R2
 // r = eta - D x64 in FP64 with FP64 links; r_lo = r rounded to the inner
-// precision; partial |r|^2 in FP64 (frozen rhs)
-template <int P, int NR>
+// precision; partial |r|^2 in FP64 (frozen rhs).  XY: one xy-plane per block,
+// x64 of the plane staged in LDS (x and y neighbours and the site itself).
+template <int P, int NR, bool XY = false>
 __device__ __forceinline__ void ru2_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
+    typedef typename LdsSpinor<P64>::word W;
+    __shared__ W xy[XY ? NR * LdsWords<P64>::value * 256 : 1];
     int sb, grp, s;
-    stencil_tile(pr, KR2, t, sb, grp, s);
+    stencil_tile<XY>(pr, KR2, t, sb, grp, s);
     const int rhs0 = grp * NR;
     const unsigned act = rhs_mask<NR>(pr, rhs0, ST_FROZEN);
     double part[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) part[j] = 0.0;
     const Geom g = pr.g;
+    const int np = g.S[2];
+    FieldPtr fx{pr.x64, g.V, pr.nrhs}, fe{pr.eta64, g.V, pr.nrhs}, fr{pr.r, g.V, pr.nrhs};
+    if (XY && act) stage_plane<P64, NR>(fx, rhs0, act, s, g.V, xy, np);
     if (act && s < g.V) {
-        FieldPtr fx{pr.x64, g.V, pr.nrhs}, fe{pr.eta64, g.V, pr.nrhs}, fr{pr.r, g.V, pr.nrhs};
         const void *U = pr.U64;
         cx<double> acc[NR][12];
-        hopping<P64, false, NR>(g, s, U, fx, rhs0, act, acc);
+        hopping<P64, false, NR, XY ? 3 : 1, XY>(g, s, U, fx, rhs0, act, acc, nullptr, xy, s - (int)threadIdx.x, np);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
                 cx<double> x[12], e[12], o[12];
-                Spinor<P64>::load(fx, rhs0 + j, s, x);
+                if constexpr (XY) LdsSpinor<P64>::get(xy, np, j, threadIdx.x, x);
+                else Spinor<P64>::load(fx, rhs0 + j, s, x);
                 wilson_finish<double>(pr.diag, x, acc[j], o);
                 Spinor<P64>::load(fe, rhs0 + j, s, e);
                 cx<R> rl[12];

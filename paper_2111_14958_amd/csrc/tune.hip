@@ -59,7 +59,8 @@ Shape default_shape(int prec, int nrhs, int fam) {
         s.nr = (prec == WD_F64 || nrhs < 2) ? 1 : 2;
         s.xylds = 1;
     } else if (fam == FAM_CG_R) {
-        s.nr = nrhs < 2 ? 1 : 2;
+        s.nr = 1;
+        s.xylds = 1;
     } else {
         s.nr = 1;
         s.xylds = prec != WD_F16N;
@@ -235,8 +236,9 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     WD_CHECK(sh->site_order >= 0 && (sh->site_order >> 25) == 0 && occ <= 8, WD_EINVAL, "site_order 0x%x",
              sh->site_order);
     WD_CHECK(!zm || ((sh->site_order >> 17) & 1), WD_EINVAL, "z-marching needs the plane-blocked bit");
-    WD_CHECK(!xylds || (family != FAM_CG_R && g->dims[0] * g->dims[1] <= 256), WD_EINVAL,
-             "plane-blocked LDS variant: operator and CG phase A/B kernels, Lx*Ly <= 256");
+    WD_CHECK(!xylds || g->dims[0] * g->dims[1] <= 256, WD_EINVAL, "plane-blocked LDS variant: Lx*Ly <= 256");
+    WD_CHECK(!(xylds && family == FAM_CG_R && sh->rhs_per_thread != 1), WD_EINVAL,
+             "plane-blocked reliable update: one rhs per thread");
     WD_CHECK(!zm || family == FAM_CG_A || family == FAM_CG_B, WD_EINVAL,
              "z-marching: CG phase A/B kernels only (FP64 falls back to plane blocks)");
     ShapeKey k{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, prec, nrhs, dagger ? 1 : 0, family};
