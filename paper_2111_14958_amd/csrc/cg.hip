@@ -35,17 +35,18 @@ namespace wd {
     const Prob &pr = probs[find_prob(probs, nprob, K, b_)];                    \
     const int t_ = b_ - pr.t0[K];
 
-// R12: links from the reconstruct-12 copy (FP32/FP16 storage)
-template <int P, int NR, int ORD, bool XY, bool R12 = false>
+// R12: links from the reconstruct-12 copy (FP32 storage).  NT: nontemporal
+// streaming accesses (FP64 solves larger than the MALL).
+template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KA)
-    phaseA_tile<P, NR, ORD, XY, R12>(pr, t_);
+    phaseA_tile<P, NR, ORD, XY, R12, NT>(pr, t_);
 }
 
-template <int P, int NR, int ORD, bool XY, bool R12 = false>
+template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KB)
-    phaseB_tile<P, NR, ORD, XY, R12>(pr, t_);
+    phaseB_tile<P, NR, ORD, XY, R12, NT>(pr, t_);
 }
 
 // z-marching phases A and B (zm_tile); dynamic LDS of two plane buffers
@@ -63,10 +64,10 @@ __global__ __launch_bounds__(256) void k_phaseB_zm(const Prob *__restrict__ prob
     zm_tile<P, ORD, true>(pr, t_, (typename LdsSpinor<P>::word *)zm_lds);
 }
 
-template <int P>
+template <int P, bool NT = false>
 __global__ __launch_bounds__(256) void k_phaseC(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KC)
-    phaseC_tile<P>(pr, t_);
+    phaseC_tile<P, NT>(pr, t_);
 }
 
 template <int P>
@@ -270,12 +271,34 @@ static void launch_AB_r12(int nr, int xy, int grid, int blk, hipStream_t st, con
     }
 }
 
+// nontemporal-stream variants: FP64, plane blocks (1 rhs per thread) or site blocks (1 or 2)
 template <int P, int ORD, bool B>
-static void launch_AB_o(int nr, int xy, int lds, int r12, int grid, int blk, hipStream_t st, const Prob *d, int n,
-                        int remap) {
+static void launch_AB_nt(int nr, int xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    const dim3 gr(grid), bl(blk);
+    if constexpr (P == P64) {
+        if (xy) {
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, true, false, true>), gr, bl, st, d, n, remap);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, true, false, true>), gr, bl, st, d, n, remap);
+        } else if (nr == 2) {
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, false, false, true>), gr, bl, st, d, n, remap);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, false, false, true>), gr, bl, st, d, n, remap);
+        } else {
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, false, false, true>), gr, bl, st, d, n, remap);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, false, false, true>), gr, bl, st, d, n, remap);
+        }
+    }
+}
+
+template <int P, int ORD, bool B>
+static void launch_AB_o(int nr, int xy, int lds, int r12, int nt, int grid, int blk, hipStream_t st, const Prob *d,
+                        int n, int remap) {
     const dim3 gr(grid), bl(blk);
     if (r12) {
         launch_AB_r12<P, ORD, B>(nr, xy, grid, blk, st, d, n, remap);
+        return;
+    }
+    if (nt) {
+        launch_AB_nt<P, ORD, B>(nr, xy, grid, blk, st, d, n, remap);
         return;
     }
     if (xy == 2) {
@@ -308,13 +331,13 @@ static void launch_AB_o(int nr, int xy, int lds, int r12, int grid, int blk, hip
 }
 template <int P>
 static void launch_A(const KindShape &k, hipStream_t st, const Prob *d, int n) {
-    if (k.ordered == 3) launch_AB_o<P, 3, false>(k.nr, k.xy, k.lds, k.r12, k.grid, k.block, st, d, n, k.remap);
-    else launch_AB_o<P, 1, false>(k.nr, k.xy, k.lds, k.r12, k.grid, k.block, st, d, n, k.remap);
+    if (k.ordered == 3) launch_AB_o<P, 3, false>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
+    else launch_AB_o<P, 1, false>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
 }
 template <int P>
 static void launch_B(const KindShape &k, hipStream_t st, const Prob *d, int n) {
-    if (k.ordered == 3) launch_AB_o<P, 3, true>(k.nr, k.xy, k.lds, k.r12, k.grid, k.block, st, d, n, k.remap);
-    else launch_AB_o<P, 1, true>(k.nr, k.xy, k.lds, k.r12, k.grid, k.block, st, d, n, k.remap);
+    if (k.ordered == 3) launch_AB_o<P, 3, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
+    else launch_AB_o<P, 1, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
 }
 template <int P>
 static void launch_R2(int nr, int xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
@@ -408,7 +431,8 @@ static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream
         else launch_B<P16>(k, st, d, nprob);
         break;
     case KC:
-        if (inner == P64) WD_TIMED_LAUNCH(k_phaseC<P64>, dim3(k.grid), dim3(k.block), st, d, nprob, 0);
+        if (inner == P64 && k.nt) WD_TIMED_LAUNCH((k_phaseC<P64, true>), dim3(k.grid), dim3(k.block), st, d, nprob, 0);
+        else if (inner == P64) WD_TIMED_LAUNCH(k_phaseC<P64>, dim3(k.grid), dim3(k.block), st, d, nprob, 0);
         else if (inner == P32) WD_TIMED_LAUNCH(k_phaseC<P32>, dim3(k.grid), dim3(k.block), st, d, nprob, 0);
         else WD_TIMED_LAUNCH(k_phaseC<P16>, dim3(k.grid), dim3(k.block), st, d, nprob, 0);
         break;
@@ -498,6 +522,8 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
                               &sa, &sb, &sr};
     const int Vf = pr.vf;
     ls.eo = pr.eo;
+    // the six vectors of the FP64 iteration exceed the 256 MB MALL
+    const bool mall_exceeded = 6.0 * 192.0 * (double)Vf * nrhs > 256.0 * 1024 * 1024;
     for (int k = 0; k < NKIND; ++k) {
         KindShape &ks = ls.k[k];
         if (st[k]) {
@@ -533,6 +559,11 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
                 ks.order = nzc;
                 ks.lds = 2 * 6 * np * 16;   // two planes of 6 float4 per site
             }
+            // nontemporal streams: FP64 phases A and B when the solve's fields outgrow the MALL
+            if ((k == KA || k == KB) && inner == WD_F64 && mall_exceeded && ks.xy != 2) {
+                ks.nt = 1;
+                if (ks.nr > 2) ks.nr = 2;
+            }
             // reconstruct-12 links for phases A and B (FP32; plane or site blocks, <= 2 rhs per thread)
             if ((k == KA || k == KB) && pr.U12 && !pr.eo && ks.xy != 2) {
                 ks.r12 = 1;
@@ -544,6 +575,7 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.remap = 0;
             ks.order = 0;
             ks.xy = 0;
+            ks.nt = k == KC && inner == WD_F64 && mall_exceeded && !pr.eo;
         }
         pr.sorder[k] = ks.order;
         pr.nsb[k] = ks.xy == 2 ? ks.order * g->dims[3] : ks.xy ? V / np : (Vf + ks.block - 1) / ks.block;
@@ -572,6 +604,7 @@ void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner, in
         ks.xy = 0;
         ks.lds = 0;
         ks.r12 = 0;   // the persistent kernel reads the complete copy
+        ks.nt = 0;
         pr.sorder[k] = ks.order;
         pr.nsb[k] = (int)((V + blk - 1) / blk);
         pr.ng[k] = (nrhs + nr - 1) / nr;
@@ -851,7 +884,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
         key.shp[k][1] = ls.k[k].nr;
         key.shp[k][2] = ls.k[k].remap;
         key.shp[k][3] = ls.k[k].grid;
-        key.shp[k][4] = ls.k[k].order | (ls.k[k].xy << 18) | (ls.k[k].r12 << 20);
+        key.shp[k][4] = ls.k[k].order | (ls.k[k].xy << 18) | (ls.k[k].r12 << 20) | (ls.k[k].nt << 21);
     }
     hipGraphExec_t exec = nullptr;
     int rec_rc = WD_OK;

@@ -91,11 +91,12 @@ struct alignas(16) Prob {
 };
 
 // precision x_lo is stored in
-// Streaming accesses of the CG phases (fields each thread reads or writes once)
-// carry the nontemporal hint in FP64 only: there the L2 then keeps more of the
-// neighbouring input planes and phases A, B and C run 5-9 % faster, while in
-// FP32 and FP16 storage the hint made phase B 13-23 % slower (14^4, 16 rhs).
-template <int P> struct Stream { static constexpr bool ld = P == P64, st = P == P64; };
+// NT (phase tiles): the streaming accesses (fields each thread reads or writes
+// once) carry the nontemporal hint.  The host sets it for FP64 solves whose
+// fields exceed the 256 MB MALL: there the L2 then keeps more of the
+// neighbouring input planes and phases A, B and C ran 5-9 % faster (14^4, 16
+// rhs), while a single FP64 field, which the MALL holds, ran 6 % slower with
+// it, and FP32/FP16 storage 13-23 % slower.
 
 template <int P> struct XPrec { static constexpr int value = P; };
 template <> struct XPrec<P16> { static constexpr int value = P32; };
@@ -225,7 +226,7 @@ __device__ __forceinline__ unsigned rhs_mask(const Prob &pr, int rhs0, int want)
 // q = D^dagger p for active rhs; partial |q|^2 (of the stored q)
 // XY: plane-blocked (one xy-plane per block, x/y neighbours from LDS).
 // R12: the links are the gauge's reconstruct-12 copy pr.U12 (two rows per link).
-template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false>
+template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false, bool NT = false>
 __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     typedef typename LdsSpinor<P>::word W;
@@ -253,7 +254,7 @@ __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
                 if constexpr (XY) LdsSpinor<P>::get(xy, np, j, threadIdx.x, self);
                 else Spinor<P>::load(fp, rhs0 + j, s, self);
                 wilson_finish<R>((R)pr.diag, self, acc[j], o);
-                Spinor<P>::template store<Stream<P>::st>(fq, rhs0 + j, s, o);
+                Spinor<P>::template store<NT>(fq, rhs0 + j, s, o);
                 double n = 0;
 #pragma unroll
                 for (int k = 0; k < 12; ++k) n += (double)norm2(o[k]);
@@ -295,7 +296,7 @@ __device__ __forceinline__ void phaseA_finish(const Prob &pr) {
 
 // ------------------------------------------------------------------ phase B
 // t = D q; r -= alpha t; x_lo += alpha q(s); partial |r|^2 (of the stored r)
-template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false>
+template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false, bool NT = false>
 __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     constexpr int XP = XPrec<P>::value;
@@ -326,20 +327,20 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
                 if constexpr (XY) LdsSpinor<P>::get(xy, np, j, threadIdx.x, q);
                 else Spinor<P>::load(fq, rhs0 + j, s, q);
                 wilson_finish<R>((R)pr.diag, q, acc[j], o);
-                Spinor<P>::template load<Stream<P>::ld>(fr, rhs0 + j, s, r);
+                Spinor<P>::template load<NT>(fr, rhs0 + j, s, r);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) r[k] = {r[k].re - a * o[k].re, r[k].im - a * o[k].im};
-                Spinor<P>::template store<Stream<P>::st>(fr, rhs0 + j, s, r);
+                Spinor<P>::template store<NT>(fr, rhs0 + j, s, r);
                 double n = 0;
 #pragma unroll
                 for (int k = 0; k < 12; ++k) n += (double)norm2(r[k]);
                 part[j] = n;
                 cx<RX> x[12];
-                Spinor<XP>::template load<Stream<P>::ld>(fx, rhs0 + j, s, x);
+                Spinor<XP>::template load<NT>(fx, rhs0 + j, s, x);
                 const RX ax = (RX)pr.sc[rhs0 + j].alpha;
 #pragma unroll
                 for (int k = 0; k < 12; ++k) x[k] = {x[k].re + ax * (RX)q[k].re, x[k].im + ax * (RX)q[k].im};
-                Spinor<XP>::template store<Stream<P>::st>(fx, rhs0 + j, s, x);
+                Spinor<XP>::template store<NT>(fx, rhs0 + j, s, x);
             }
         }
     }
@@ -442,21 +443,21 @@ __device__ __forceinline__ void zm_tile(const Prob &pr, int t, typename LdsSpino
             if constexpr (B) {   // r -= alpha D q; x_lo += alpha q
                 const R a = (R)pr.sc[rhs].alpha;
                 cx<R> r[12];
-                Spinor<P>::template load<Stream<P>::ld>(fr, rhs, s, r);
+                Spinor<P>::template load<false>(fr, rhs, s, r);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) r[k] = {r[k].re - a * o[k].re, r[k].im - a * o[k].im};
-                Spinor<P>::template store<Stream<P>::st>(fr, rhs, s, r);
+                Spinor<P>::template store<false>(fr, rhs, s, r);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) n += (double)norm2(r[k]);
                 cx<RX> x[12];
-                Spinor<XP>::template load<Stream<P>::ld>(fx, rhs, s, x);
+                Spinor<XP>::template load<false>(fx, rhs, s, x);
                 const RX ax = (RX)pr.sc[rhs].alpha;
 #pragma unroll
                 for (int k = 0; k < 12; ++k)
                     x[k] = {x[k].re + ax * (RX)self[k].re, x[k].im + ax * (RX)self[k].im};
-                Spinor<XP>::template store<Stream<P>::st>(fx, rhs, s, x);
+                Spinor<XP>::template store<false>(fx, rhs, s, x);
             } else {             // q = D^dagger p
-                Spinor<P>::template store<Stream<P>::st>(fq, rhs, s, o);
+                Spinor<P>::template store<false>(fq, rhs, s, o);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) n += (double)norm2(o[k]);
             }
@@ -471,7 +472,7 @@ __device__ __forceinline__ void zm_tile(const Prob &pr, int t, typename LdsSpino
 
 // ------------------------------------------------------------------ phase C
 // p = r + beta p (or p = r after a restart), streaming, tile = (site block, rhs)
-template <int P>
+template <int P, bool NT = false>
 __device__ __forceinline__ void phaseC_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     const int sb = t / pr.nrhs, i = t - sb * pr.nrhs;
@@ -480,14 +481,14 @@ __device__ __forceinline__ void phaseC_tile(const Prob &pr, int t) {
     if (c.state != ST_ACTIVE || !c.pending_p || s >= pr.vf) return;
     FieldPtr fr{pr.r, pr.vf, pr.nrhs}, fp{pr.p, pr.vf, pr.nrhs};
     cx<R> r[12], p[12];
-    Spinor<P>::template load<Stream<P>::ld>(fr, i, s, r);
+    Spinor<P>::template load<NT>(fr, i, s, r);
     if (!c.restart) {
         const R b = (R)c.beta;
-        Spinor<P>::template load<Stream<P>::ld>(fp, i, s, p);
+        Spinor<P>::template load<NT>(fp, i, s, p);
 #pragma unroll
         for (int k = 0; k < 12; ++k) r[k] = {r[k].re + b * p[k].re, r[k].im + b * p[k].im};
     }
-    Spinor<P>::template store<Stream<P>::st>(fp, i, s, r);
+    Spinor<P>::template store<NT>(fp, i, s, r);
 }
 
 // ------------------------------------------------------- reliable update R1

@@ -16,6 +16,7 @@ struct KindShape {
                        // 2 z-marching columns of planes (zm_tile)
     int lds = 0;       // dynamic LDS bytes per block (z-marching)
     int r12 = 0;       // phases A and B: links from the reconstruct-12 copy
+    int nt = 0;        // phases A, B and C: nontemporal streaming accesses (FP64)
 };
 struct LaunchSet {
     KindShape k[NKIND];
