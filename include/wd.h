@@ -273,6 +273,21 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
 int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger,
                    wd_tune_result *cfg);
 
+/* Autotune the CG phase kernels as Sec. 3.1 tunes the workgroup size of the
+ * whole CG (Fig. 1): one launch shape for phases A and B (families
+ * WD_FAMILY_CG_A and WD_FAMILY_CG_B) of g's lattice, inner precision `inner`
+ * and nrhs fields.  Every candidate (plane or site blocks, 1 or 2 rhs per
+ * thread, hop order 1 or 3, z-strips of 0/2/4/7 planes) runs `iters` (1..1000)
+ * CG iterations from the nrhs canonical fields src_dev (as wd_cg_solve_batch
+ * takes them) with the mass m0; the median of three runs is kept; a candidate
+ * whose iterate differs from the first candidate's by more than 1e-3 relative
+ * is rejected.  The fastest shape is stored for later solves and returned in
+ * best (best->us: its median time of the whole run, microseconds).  Allocates
+ * and frees its own device scratch; synchronises `stream`.  On an error the
+ * previous shapes are restored. */
+int wd_tune_cg(const wd_gauge *g, double m0, int32_t inner, const void *src_dev, int32_t nrhs,
+               int32_t iters, wd_tune_result *best, void *stream);
+
 /* kernel families of the shape table */
 #define WD_FAMILY_DSLASH 0   /* wd_dslash / wd_dslash_dag                       */
 #define WD_FAMILY_CG_A   1   /* CG phase A: q = D^dagger p and |q|^2           */

@@ -37,7 +37,7 @@ EXPORTS = [
     "wd_dslash", "wd_dslash_dag",
     "wd_coo_create", "wd_coo_destroy", "wd_coo_info", "wd_coo_export", "wd_coo_spmv",
     "wd_cg_default_params", "wd_cg_workspace_bytes", "wd_cg_solve", "wd_cg_solve_batch",
-    "wd_tune_dslash", "wd_tune_lookup", "wd_shape_set", "wd_shape_get",
+    "wd_tune_dslash", "wd_tune_lookup", "wd_tune_cg", "wd_shape_set", "wd_shape_get",
     "wd_profile_enable", "wd_profile_reset", "wd_profile_read",
     "wd_serve_footprint", "wd_serve_create", "wd_serve_submit", "wd_serve_poll",
     "wd_serve_stats_get", "wd_serve_destroy",
@@ -143,6 +143,7 @@ def lib():
             "wd_cg_solve_batch": ([P, D, P, P, I32, ctypes.POINTER(CGParams), P, SZ,
                                    ctypes.POINTER(CGReport), P], ctypes.c_int),
             "wd_tune_dslash": ([P, I32, I32, I32, ctypes.POINTER(TuneResult), P], ctypes.c_int),
+            "wd_tune_cg": ([P, D, I32, P, I32, I32, ctypes.POINTER(TuneResult), P], ctypes.c_int),
             "wd_tune_lookup": ([P, I32, I32, I32, ctypes.POINTER(TuneResult)], ctypes.c_int),
             "wd_shape_set": ([P, I32, I32, I32, I32, ctypes.POINTER(TuneResult)], ctypes.c_int),
             "wd_shape_get": ([P, I32, I32, I32, I32, ctypes.POINTER(TuneResult)], ctypes.c_int),
@@ -397,6 +398,21 @@ def tune_dslash(g: Gauge, prec: int, nrhs: int, dagger: bool = False) -> dict:
     _check(lib().wd_tune_dslash(g.handle, prec, nrhs, 1 if dagger else 0, ctypes.byref(r),
                                 _stream()), "wd_tune_dslash")
     return {f[0]: getattr(r, f[0]) for f in r._fields_ if f[0] != "reserved"}
+
+
+def tune_cg(g: Gauge, m0: float, inner: int, src, iters: int = 30) -> dict:
+    """Autotune the CG phase kernels on the fields src ([nrhs, ..., 4, 3]
+    complex128, as cg_solve_batch takes them); returns the stored shape."""
+    torch = _torch()
+    _require_cuda(src, torch.complex128, "src")
+    nrhs = src.numel() // (g.sites * 12)
+    r = TuneResult()
+    _check(lib().wd_tune_cg(g.handle, float(m0), inner, _ptr(src), nrhs, iters, ctypes.byref(r), _stream()),
+           "wd_tune_cg")
+    out = {f[0]: getattr(r, f[0]) for f in r._fields_ if f[0] != "gbps"}
+    out["strip"] = r.site_order & 0xFFFF
+    out["xy_lds"] = (r.site_order >> 17) & 1
+    return out
 
 
 def tune_lookup(g: Gauge, prec: int, nrhs: int, dagger: bool = False) -> dict:

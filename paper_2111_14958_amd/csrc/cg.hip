@@ -11,6 +11,7 @@
 // the chunk K x [S1, S2, S3, S4, S5], then R1, R2, summary.
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <map>
@@ -1050,6 +1051,125 @@ int wd_cg_solve_batch(const wd_gauge *g, double m0, const void *src, void *sol, 
 int wd_cg_solve(const wd_gauge *g, double m0, const void *src, void *sol, const wd_cg_params *p,
                 void *ws, size_t ws_bytes, wd_cg_report *rep, void *stream) {
     return wd_cg_solve_batch(g, m0, src, sol, 1, p, ws, ws_bytes, rep, stream);
+}
+
+int wd_tune_cg(const wd_gauge *g, double m0, int32_t inner, const void *src, int32_t nrhs, int32_t iters,
+               wd_tune_result *best, void *stream) {
+    clear_error();
+    WD_CHECK(g && src && best, WD_EINVAL, "null argument");
+    WD_CHECK(inner >= 0 && inner <= 2 && g->U[inner], WD_EINVAL, "no links in precision %d", inner);
+    WD_CHECK(nrhs >= 1 && nrhs <= MAX_RHS, WD_EINVAL, "nrhs %d out of range 1..%d", nrhs, MAX_RHS);
+    WD_CHECK(iters >= 1 && iters <= 1000, WD_EINVAL, "iters %d out of range 1..1000", iters);
+    WD_CHECK(m0 > -4.0 && m0 < 1e6, WD_EINVAL, "m0 %g out of range", m0);
+    int rc = require_gfx950();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    wd_cg_params p;
+    wd_cg_default_params(&p);
+    p.inner = inner;
+    p.max_iter = iters;        // every field runs exactly `iters` iterations (tol is out of reach)
+    p.tol = 1e-15;
+    p.reliable_every = 0;
+    p.chunk = iters;
+    p.persistent = 0;
+    const size_t wsb = wd_cg_workspace_bytes(g, nrhs, &p);
+    const size_t fb = (size_t)g->V * 192 * nrhs;
+    void *ws = nullptr, *x = nullptr;
+    WD_HIP(hipMalloc(&ws, wsb));
+    if (hipMalloc(&x, fb) != hipSuccess) {
+        (void)hipFree(ws);
+        return fail(WD_ENOMEM, "tuner scratch of %zu bytes", fb);
+    }
+    std::vector<double> ref(fb / 8), got(fb / 8);
+    std::vector<wd_cg_report> reps(nrhs);
+    const int Lz = g->dims[2], np = g->dims[0] * g->dims[1];
+    const ShapeKey ka{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, inner, nrhs, 1, FAM_CG_A};
+    ShapeKey kb = ka;
+    kb.dag = 0;
+    kb.fam = FAM_CG_B;
+    const Shape keep_a = shape_lookup(ka), keep_b = shape_lookup(kb);
+    // candidates: plane or site blocks, rhs per thread, hop order, z-strip width
+    std::vector<Shape> cand;
+    for (int xy = 1; xy >= 0; --xy) {
+        if (xy && (np < 64 || np > 256)) continue;
+        for (int nr = 1; nr <= 2; ++nr) {
+            if (xy && nr == 2 && inner == WD_F64) continue;
+            for (int ord : {3, 1})
+                for (int strip : {4, 0, 2, 7}) {
+                    if (strip >= Lz) continue;
+                    Shape s = default_shape(inner, nrhs, FAM_CG_B);
+                    s.block = 256;
+                    s.nr = nr;
+                    s.ordered = ord;
+                    s.strip = strip;
+                    s.xylds = xy;
+                    s.gmajor = 0;
+                    s.occ = 0;
+                    cand.push_back(s);
+                }
+        }
+    }
+    double best_ms = 1e30;
+    Shape bests = keep_b;
+    int nref = 0;
+    for (size_t c = 0; c < cand.size() && rc == WD_OK; ++c) {
+        shape_store(ka, cand[c]);
+        shape_store(kb, cand[c]);
+        int r = cg_run(g, m0, src, x, nrhs, p, ws, wsb, reps.data(), st);   // warm-up: graph capture
+        if (r != WD_OK && r != WD_ENOTCONV) { rc = r; break; }
+        float t[3];
+        for (int k = 0; k < 3 && rc == WD_OK; ++k) {
+            hipEvent_t e0, e1;
+            WD_HIP(hipEventCreate(&e0));
+            WD_HIP(hipEventCreate(&e1));
+            (void)hipEventRecord(e0, st);
+            r = cg_run(g, m0, src, x, nrhs, p, ws, wsb, reps.data(), st);
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&t[k], e0, e1);
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            if (r != WD_OK && r != WD_ENOTCONV) rc = r;
+        }
+        if (rc) break;
+        std::sort(t, t + 3);
+        // the iterate must agree with the first candidate's (rounding order differs)
+        WD_HIP(hipMemcpy(c == 0 ? ref.data() : got.data(), x, fb, hipMemcpyDeviceToHost));
+        bool ok = true;
+        if (c == 0) {
+            nref = 1;
+        } else {
+            double d2 = 0, r2 = 0;
+            for (size_t k = 0; k < ref.size(); ++k) {
+                const double d = got[k] - ref[k];
+                d2 += d * d;
+                r2 += ref[k] * ref[k];
+            }
+            ok = d2 <= 1e-6 * r2;   // relative difference <= 1e-3
+        }
+        if (ok && t[1] < best_ms) {
+            best_ms = t[1];
+            bests = cand[c];
+        }
+    }
+    (void)hipFree(ws);
+    (void)hipFree(x);
+    if (rc != WD_OK || !nref) {
+        shape_store(ka, keep_a);
+        shape_store(kb, keep_b);
+        return rc ? rc : fail(WD_EHIP, "no CG launch shape could be timed");
+    }
+    shape_store(ka, bests);
+    shape_store(kb, bests);
+    memset(best, 0, sizeof(*best));
+    best->block = bests.block;
+    best->rhs_per_thread = bests.nr;
+    best->xcd_remap = bests.remap;
+    best->hop_order = bests.ordered;
+    best->rhs_loop = bests.rloop;
+    best->site_order = encode_order(bests);
+    best->us = best_ms * 1e3;
+    return WD_OK;
 }
 
 int wd_profile_enable(int32_t on) {

@@ -44,7 +44,7 @@ static bool g_loaded = false;
 // The reliable-update kernel: two rhs per thread.
 // wd_tune_result.site_order: strip | group-major << 16 | plane-blocked << 17 |
 // blocks-per-CU cap << 18 | z-marching << 24 (z-marching: xylds 2)
-static int encode_order(const Shape &s) {
+int encode_order(const Shape &s) {
     return s.strip | (s.gmajor << 16) | ((s.xylds ? 1 : 0) << 17) | (s.occ << 18) | ((s.xylds == 2) << 24);
 }
 

@@ -65,6 +65,7 @@ struct ShapeKey {
 Shape shape_lookup(const ShapeKey &k);      // tuned entry or the default
 void shape_store(const ShapeKey &k, const Shape &s);
 Shape default_shape(int prec, int nrhs, int fam = FAM_DSLASH);
+int encode_order(const Shape &s);           // wd_tune_result.site_order of a shape
 
 }  // namespace wd
 

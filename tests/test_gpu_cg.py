@@ -310,3 +310,28 @@ def test_z_marching_phase_kernels(inner, dims, chunks):
         x = host(x)
         _check_solution(U, eta, x, dims, m0)
         assert rel(x, x0) <= kappa(m0) * 2 * TOL, nzc
+
+
+@pytest.mark.parametrize("inner", [wd.F32, wd.F64], ids=["f32", "f64"])
+def test_cg_autotuner(inner):
+    """wd_tune_cg times the CG phase shapes on a short run, stores the fastest
+    for phases A and B, and the solve with it still passes the oracle."""
+    dims, m0 = (8, 8, 6, 6), 0.1   # 64-site planes: plane and site blocks compete
+    U = wdgen.gauge_field(dims, 0.5, 421)
+    eta = wdgen.mixed_sources(dims, 2, 2, 422)
+    g = wd.Gauge(dev(U), dims)
+    say("cg autotune", inner)
+    best = wd.tune_cg(g, m0, inner, dev(eta), iters=20)
+    assert best["block"] == 256 and best["rhs_per_thread"] in (1, 2) and best["hop_order"] in (1, 3)
+    assert best["strip"] in (0, 2, 4) and best["us"] > 0
+    for fam, dag in ((wd.FAMILY_CG_A, True), (wd.FAMILY_CG_B, False)):
+        got = wd.shape_get(g, inner, eta.shape[0], dag, fam)
+        assert (got["rhs_per_thread"], got["hop_order"], got["strip"], got["xy_lds"]) == \
+            (best["rhs_per_thread"], best["hop_order"], best["strip"], best["xy_lds"])
+    p = wd.cg_default_params(inner=inner, reliable_every=0 if inner == wd.F64 else 50)
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    assert rc == wd.WD_OK, reps
+    _check_solution(U, eta, host(x), dims, m0)
+    with pytest.raises(wd.WDError) as e:
+        wd.tune_cg(g, m0, inner, dev(eta), iters=0)
+    assert e.value.code == wd.WD_EINVAL
