@@ -291,19 +291,6 @@ def main():
     copy_gbps = 2 * a.numel() * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del a, b
 
-    # ---------- the CG autotuner on this workload (context; the timed run keeps
-    # the default shapes, whose kernels the committed counter profile covers)
-    gt = wd.Gauge(dU, dims, -1, recon12=True)
-    tuned = wd.tune_cg(gt, m0, wd.F32, dsrc, iters=30)
-    _, rt, rct = wd.cg_solve_batch(gt, m0, dsrc, sol=sol, params=p_mixed, ws=ws)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, rt, rct = wd.cg_solve_batch(gt, m0, dsrc, sol=sol, params=p_mixed, ws=ws)
-    torch.cuda.synchronize()
-    cg_tuner = {"shape": tuned, "solves_per_s": nrhs / (time.perf_counter() - t0), "converged": rct == wd.WD_OK}
-    del gt
-    log("cg tuner", json.dumps(cg_tuner))
-
     # ------ 8^4, 12^4, 14^4 single field: operator alone and CG, FP64 and FP32 (context)
     c2 = {}
     for key in ("c2_8x4", "c2_12x4", "c2_14x4"):
@@ -441,7 +428,6 @@ def main():
             "coo_spmv_1rhs": coo,
             "copy_GBps": copy_gbps,
             "c2_single_field": c2,
-            "cg_autotuner_14x4_16rhs": cg_tuner,
             "c4_16x3x32_12rhs": c4,
         },
     }
