@@ -70,13 +70,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-c4", action="store_true", help="skip the 16^3x32 FP16N context run")
+    ap.add_argument("--no-big", action="store_true", help="skip the 16^3x32 FP16N context run")
     ap.add_argument("--cpu-iters", type=int, default=150,
                     help="oracle CG iterations timed for the CPU baseline sample")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(independent solves would shard by request, see the design notes)", file=sys.stderr)
         sys.exit(2)
 
@@ -93,7 +93,7 @@ def main():
     dev = torch.device("cuda:0")
     arch, ncu = wd.device_info(0)
 
-    cfg = wdgen.CONFIGS["c3_14x4_16rhs"]
+    cfg = wdgen.CONFIGS["lat14x4_16rhs"]
     dims, m0, tol = cfg["dims"], cfg["m0"], cfg["tol"]
     nrhs = cfg["n_point"] + cfg["n_gauss"]
     V = wdgen.volume(dims)
@@ -292,77 +292,77 @@ def main():
     del a, b
 
     # ------ 8^4, 12^4, 14^4 single field: operator alone and CG, FP64 and FP32 (context)
-    c2 = {}
-    for key in ("c2_8x4", "c2_12x4", "c2_14x4"):
-        c2cfg = wdgen.CONFIGS[key]
-        d2 = c2cfg["dims"]
+    single = {}
+    for key in ("lat8x4_1rhs", "lat12x4_1rhs", "lat14x4_1rhs"):
+        sfcfg = wdgen.CONFIGS[key]
+        d2 = sfcfg["dims"]
         V2 = wdgen.volume(d2)
-        U2 = torch.from_numpy(wdgen.gauge_field(d2, c2cfg["eps"], c2cfg["gauge_seed"])).to(dev)
-        s2 = torch.from_numpy(wdgen.gaussian_source(d2, 1, c2cfg["src_seed"])).to(dev)
+        U2 = torch.from_numpy(wdgen.gauge_field(d2, sfcfg["eps"], sfcfg["gauge_seed"])).to(dev)
+        s2 = torch.from_numpy(wdgen.gaussian_source(d2, 1, sfcfg["src_seed"])).to(dev)
         g2 = wd.Gauge(U2, d2, -1, recon12=True)
         row = {}
         for prec, name in ((wd.F64, "f64"), (wd.F32, "f32")):
             pin = wd.pack_spinor(g2, s2, prec)
             pout = wd.empty_packed(g2, prec, 1)
             for _ in range(3):
-                wd.dslash(g2, c2cfg["m0"], pin, prec, packed=True, nrhs=1, out=pout)
+                wd.dslash(g2, sfcfg["m0"], pin, prec, packed=True, nrhs=1, out=pout)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
             for _ in range(200):
-                wd.dslash(g2, c2cfg["m0"], pin, prec, packed=True, nrhs=1, out=pout)
+                wd.dslash(g2, sfcfg["m0"], pin, prec, packed=True, nrhs=1, out=pout)
             e1.record()
             torch.cuda.synchronize()
             us = e0.elapsed_time(e1) * 1e3 / 200
             alg = V2 * ({wd.F64: 576, wd.F32: 288}[prec] + 2 * {wd.F64: 192, wd.F32: 96}[prec])
-            pc = wd.cg_default_params(tol=c2cfg["tol"], inner=prec, reliable_every=0 if prec == wd.F64 else 50)
+            pc = wd.cg_default_params(tol=sfcfg["tol"], inner=prec, reliable_every=0 if prec == wd.F64 else 50)
             sol2 = torch.zeros_like(s2)
             ws2 = torch.empty(wd.cg_workspace_bytes(g2, 1, pc), dtype=torch.uint8, device=dev)
-            wd.cg_solve_batch(g2, c2cfg["m0"], s2, sol=sol2, params=pc, ws=ws2)
+            wd.cg_solve_batch(g2, sfcfg["m0"], s2, sol=sol2, params=pc, ws=ws2)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(3):
-                _, rep2, rc2 = wd.cg_solve_batch(g2, c2cfg["m0"], s2, sol=sol2, params=pc, ws=ws2)
+                _, rep2, rc2 = wd.cg_solve_batch(g2, sfcfg["m0"], s2, sol=sol2, params=pc, ws=ws2)
             torch.cuda.synchronize()
             row[name] = {"dslash_us": us, "dslash_GBps": alg / (us * 1e-6) / 1e9,
                          "cg_solves_per_s": 3 / (time.perf_counter() - t0), "cg_iters": rep2[0]["iters"],
                          "true_rel_res": rep2[0]["true_rel_res"], "converged": rc2 == wd.WD_OK}
             del pin, pout
-        c2["x".join(str(d) for d in d2)] = row
+        single["x".join(str(d) for d in d2)] = row
         del g2
-    log("single-field context", json.dumps(c2))
+    log("single-field context", json.dumps(single))
 
     # ------------------- 16^3 x 32, m0 0.02, 12 point sources: FP16N vs FP64 (context)
-    c4 = None
-    if not args.no_c4:
-        c4cfg = wdgen.CONFIGS["c4_16x3x32_12rhs"]
-        log("c4 16^3x32 inputs")
-        U4 = torch.from_numpy(wdgen.gauge_field(c4cfg["dims"], c4cfg["eps"], c4cfg["gauge_seed"])).to(dev)
-        g4 = wd.Gauge(U4, c4cfg["dims"], -1, recon12=True)
-        src4 = torch.from_numpy(wdgen.point_sources(c4cfg["dims"])).to(dev)
-        sol4 = torch.zeros_like(src4)
-        c4 = {"workload": "16^3x32, m0 0.02, eps 0.5, 12 point sources, tol 1e-10"}
-        xs4 = {}
+    big = None
+    if not args.no_big:
+        bigcfg = wdgen.CONFIGS["lat16x3x32_12rhs"]
+        log("big 16^3x32 inputs")
+        Ub = torch.from_numpy(wdgen.gauge_field(bigcfg["dims"], bigcfg["eps"], bigcfg["gauge_seed"])).to(dev)
+        gb = wd.Gauge(Ub, bigcfg["dims"], -1, recon12=True)
+        srcb = torch.from_numpy(wdgen.point_sources(bigcfg["dims"])).to(dev)
+        solb = torch.zeros_like(srcb)
+        big = {"workload": "16^3x32, m0 0.02, eps 0.5, 12 point sources, tol 1e-10"}
+        xsb = {}
         for name, pc in (("f16n", wd.cg_default_params(tol=tol, inner=wd.F16N, reliable_every=50)),
                          ("f32", wd.cg_default_params(tol=tol, inner=wd.F32, reliable_every=50)),
                          ("f64", wd.cg_default_params(tol=tol, inner=wd.F64, reliable_every=0))):
-            ws4 = torch.empty(wd.cg_workspace_bytes(g4, 12, pc), dtype=torch.uint8, device=dev)
-            wd.cg_solve_batch(g4, c4cfg["m0"], src4, sol=sol4, params=pc, ws=ws4)   # graph capture
+            wsb = torch.empty(wd.cg_workspace_bytes(gb, 12, pc), dtype=torch.uint8, device=dev)
+            wd.cg_solve_batch(gb, bigcfg["m0"], srcb, sol=solb, params=pc, ws=wsb)   # graph capture
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, reps4, rc4 = wd.cg_solve_batch(g4, c4cfg["m0"], src4, sol=sol4, params=pc, ws=ws4)
+            _, repsb, rcb = wd.cg_solve_batch(gb, bigcfg["m0"], srcb, sol=solb, params=pc, ws=wsb)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            xs4[name] = sol4.clone()
-            c4[name] = {"solves_per_s": 12 / dt, "converged": rc4 == wd.WD_OK,
-                        "max_true_rel_res": max(r["true_rel_res"] for r in reps4),
-                        "iters_max": max(r["iters"] for r in reps4)}
-            del ws4
+            xsb[name] = solb.clone()
+            big[name] = {"solves_per_s": 12 / dt, "converged": rcb == wd.WD_OK,
+                        "max_true_rel_res": max(r["true_rel_res"] for r in repsb),
+                        "iters_max": max(r["iters"] for r in repsb)}
+            del wsb
         for name in ("f16n", "f32"):
-            d4 = (xs4[name] - xs4["f64"]).reshape(12, -1).norm(dim=1) / xs4["f64"].reshape(12, -1).norm(dim=1)
-            c4[name]["err_vs_fp64_solution"] = d4.max().item()
-        c4["f16n_vs_f64_speedup"] = c4["f16n"]["solves_per_s"] / c4["f64"]["solves_per_s"]
-        del U4, g4, src4, sol4, xs4
+            db = (xsb[name] - xsb["f64"]).reshape(12, -1).norm(dim=1) / xsb["f64"].reshape(12, -1).norm(dim=1)
+            big[name]["err_vs_fp64_solution"] = db.max().item()
+        big["f16n_vs_f64_speedup"] = big["f16n"]["solves_per_s"] / big["f64"]["solves_per_s"]
+        del Ub, gb, srcb, solb, xsb
 
     # ----------------------------------------------------- CPU oracle baseline
     cpu = None
@@ -427,8 +427,8 @@ def main():
             "dslash_16rhs": dslash,
             "coo_spmv_1rhs": coo,
             "copy_GBps": copy_gbps,
-            "c2_single_field": c2,
-            "c4_16x3x32_12rhs": c4,
+            "single_field": single,
+            "lat16x3x32_12rhs": big,
         },
     }
     print(json.dumps(out), flush=True)

@@ -2,7 +2,7 @@
 
 Plain FP64 reference implementations (C for the operator and the Krylov
 iteration, NumPy for the storage encodings and the coordinate-format matrix)
-against which the GPU library is judged.  Only the tests, the smoke check and
+against which the GPU library is checked.  Only the tests, the smoke check and
 the CPU-baseline leg of the benchmark may import this package; the GPU library
 never does, and this package never imports the GPU library.
 

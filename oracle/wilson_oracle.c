@@ -3,7 +3,7 @@
  *
  * A plain, slow, obviously correct FP64 implementation of what the solver
  * computes, used by the tests, the smoke check and the CPU baseline of the
- * benchmark to judge the GPU library.  It shares no code, header, table or
+ * benchmark to check the GPU library.  It shares no code, header, table or
  * constant with the GPU library and must never be linked into it.
  *
  * What it computes (arXiv 2111.14958):

@@ -178,7 +178,7 @@ def solve():
 
     import paper_2111_14958_amd as wd
     import wdgen
-    cfg = wdgen.CONFIGS["c3_14x4_16rhs"]
+    cfg = wdgen.CONFIGS["lat14x4_16rhs"]
     dims = cfg["dims"]
     U = wdgen.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
     src = wdgen.mixed_sources(dims, cfg["n_point"], cfg["n_gauss"], cfg["src_seed"])

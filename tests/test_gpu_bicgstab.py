@@ -1,7 +1,7 @@
 """GPU BiCGSTAB (wd_cg_solve_batch with method WD_METHOD_BICGSTAB) against the oracle.
 
 BiCGSTAB on D x = eta is one of the Krylov methods the paper names for the
-Dirac equation (Sec. 1).  Every returned solution is judged by the oracle's
+Dirac equation (Sec. 1).  Every returned solution is checked by the oracle's
 operator: its true relative residual must be <= tol.  Against the oracle's
 solutions (its BiCGSTAB, the dense LAPACK solve at 4^4) the error is bounded by
 kappa(D) (tol_gpu + tol_oracle), kappa(D) <= (8 + m0) / m0.  In FP64 without
@@ -42,8 +42,8 @@ def _check_solution(U, eta, x, dims, m0, t_sign=-1):
 
 
 @pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
-def test_c1_4x4(inner):
-    cfg = wdgen.CONFIGS["c1_4x4"]
+def test_lat4x4_1rhs(inner):
+    cfg = wdgen.CONFIGS["lat4x4_1rhs"]
     dims, m0 = cfg["dims"], cfg["m0"]
     U = wdgen.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
     eta = wdgen.gaussian_source(dims, 1, cfg["src_seed"])
@@ -112,7 +112,7 @@ def test_batch_equals_single_fields():
         assert rel(host(xi)[0], xb[i]) <= kappa(m0) * 2 * TOL
 
 
-def test_c2_14x4_f32():
+def test_lat14x4_1rhs_f32():
     """The paper's 14^4 lattice, one Gaussian source, FP32 inner iterations."""
     dims, m0 = (14, 14, 14, 14), 0.05
     U = wdgen.gauge_field(dims, 0.5, 1002)

@@ -27,7 +27,7 @@ def _device():
 
 
 def test_c4_fp16n_against_fp64():
-    cfg = wdgen.CONFIGS["c4_16x3x32_12rhs"]
+    cfg = wdgen.CONFIGS["lat16x3x32_12rhs"]
     dims, m0 = cfg["dims"], cfg["m0"]
     U = wdgen.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
     eta = wdgen.point_sources(dims)

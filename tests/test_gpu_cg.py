@@ -1,6 +1,6 @@
 """GPU solver parity: wd_cg_solve / wd_cg_solve_batch against the FP64 oracle.
 
-Every returned solution is judged by the oracle's own operator: its true
+Every returned solution is checked by the oracle's own operator: its true
 relative residual |eta - D x| / |eta| must be <= tol = 1e-10.  Against the
 oracle's CG solution the error is bounded by kappa(D) (tol_gpu + tol_oracle)
 with kappa(D) <= (8 + m0) / m0 (|D| <= 8 + m0, sigma_min(D) >= m0); the
@@ -36,8 +36,8 @@ def _check_solution(U, eta, x, dims, m0, t_sign=-1):
 
 
 @pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
-def test_c1_4x4(inner):
-    cfg = wdgen.CONFIGS["c1_4x4"]
+def test_lat4x4_1rhs(inner):
+    cfg = wdgen.CONFIGS["lat4x4_1rhs"]
     dims, m0 = cfg["dims"], cfg["m0"]
     U = wdgen.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
     eta = wdgen.gaussian_source(dims, 1, cfg["src_seed"])

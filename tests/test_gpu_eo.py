@@ -1,7 +1,7 @@
 """GPU even-odd preconditioned CG (precondition = WD_PRECOND_EO) against the oracle.
 
 The GPU solves the Schur complement system on the even sites and rebuilds the
-odd half.  Every returned solution is judged by the oracle's full operator:
+odd half.  Every returned solution is checked by the oracle's full operator:
 true relative residual <= tol.  Against the oracle's even-odd CG and the dense
 or plain-CG solutions the error is bounded by kappa(D) (tol_gpu + tol_oracle),
 kappa(D) <= (8 + m0) / m0.  In FP64 without intermediate reliable updates the
@@ -41,8 +41,8 @@ def _check_solution(U, eta, x, dims, m0):
 
 
 @pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
-def test_c1_4x4(inner):
-    cfg = wdgen.CONFIGS["c1_4x4"]
+def test_lat4x4_1rhs(inner):
+    cfg = wdgen.CONFIGS["lat4x4_1rhs"]
     dims, m0 = cfg["dims"], cfg["m0"]
     U = wdgen.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
     eta = wdgen.gaussian_source(dims, 1, cfg["src_seed"])

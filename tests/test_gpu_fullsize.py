@@ -35,7 +35,7 @@ def _device():
 
 @pytest.fixture(scope="module")
 def bench_fields():
-    cfg = wdgen.CONFIGS["c3_14x4_16rhs"]
+    cfg = wdgen.CONFIGS["lat14x4_16rhs"]
     dims = cfg["dims"]
     U = wdgen.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
     src = wdgen.mixed_sources(dims, cfg["n_point"], cfg["n_gauss"], cfg["src_seed"])

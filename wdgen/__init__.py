@@ -156,21 +156,22 @@ def apply_site_matrix(Om: np.ndarray, psi: np.ndarray, dagger: bool = False) -> 
     return np.einsum("tzyxab,...tzyxsb->...tzyxsa", M, psi)
 
 
-# Benchmark / test configurations (lattice dims (Lx, Ly, Lz, Lt), bare mass m0,
-# link disorder eps, seeds).  Gauge seed = 1000 + config, source seed = 2000 + config.
+# Benchmark / test workloads (lattice dims (Lx, Ly, Lz, Lt), bare mass m0, link
+# disorder eps, seeds): gauge seeds 1001..1004 and source seeds 2001..2004 in the
+# order of the workloads (the single-field lattices 8^4..14^4 share one pair).
 CONFIGS = {
-    "c1_4x4": dict(dims=(4, 4, 4, 4), m0=0.1, eps=0.3, gauge_seed=1001, src_seed=2001,
+    "lat4x4_1rhs": dict(dims=(4, 4, 4, 4), m0=0.1, eps=0.3, gauge_seed=1001, src_seed=2001,
                    nrhs=1, tol=1e-10),
-    "c2_8x4": dict(dims=(8, 8, 8, 8), m0=0.05, eps=0.5, gauge_seed=1002, src_seed=2002,
+    "lat8x4_1rhs": dict(dims=(8, 8, 8, 8), m0=0.05, eps=0.5, gauge_seed=1002, src_seed=2002,
                    nrhs=1, tol=1e-10),
-    "c2_12x4": dict(dims=(12, 12, 12, 12), m0=0.05, eps=0.5, gauge_seed=1002, src_seed=2002,
+    "lat12x4_1rhs": dict(dims=(12, 12, 12, 12), m0=0.05, eps=0.5, gauge_seed=1002, src_seed=2002,
                     nrhs=1, tol=1e-10),
-    "c2_14x4": dict(dims=(14, 14, 14, 14), m0=0.05, eps=0.5, gauge_seed=1002, src_seed=2002,
+    "lat14x4_1rhs": dict(dims=(14, 14, 14, 14), m0=0.05, eps=0.5, gauge_seed=1002, src_seed=2002,
                     nrhs=1, tol=1e-10),
     # 12 spin-colour point sources at the origin, then 4 Gaussian sources
-    "c3_14x4_16rhs": dict(dims=(14, 14, 14, 14), m0=0.05, eps=0.5, gauge_seed=1003,
+    "lat14x4_16rhs": dict(dims=(14, 14, 14, 14), m0=0.05, eps=0.5, gauge_seed=1003,
                           src_seed=2003, n_point=12, n_gauss=4, tol=1e-10),
-    "c4_16x3x32_12rhs": dict(dims=(16, 16, 16, 32), m0=0.02, eps=0.5, gauge_seed=1004,
+    "lat16x3x32_12rhs": dict(dims=(16, 16, 16, 32), m0=0.02, eps=0.5, gauge_seed=1004,
                              src_seed=2004, n_point=12, n_gauss=0, tol=1e-10),
 }
 
