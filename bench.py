@@ -77,7 +77,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
-              "(independent solves would shard by request, see the design notes)", file=sys.stderr)
+              "(independent solves would shard by request)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
