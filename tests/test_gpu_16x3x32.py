@@ -26,12 +26,12 @@ def _device():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
 
 
-def test_c4_fp16n_against_fp64():
+def test_16x3x32_fp16n_against_fp64():
     cfg = wdgen.CONFIGS["lat16x3x32_12rhs"]
     dims, m0 = cfg["dims"], cfg["m0"]
     U = wdgen.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
     eta = wdgen.point_sources(dims)
-    say("c4 16^3x32 f16n + f64")
+    say("16^3x32 f16n + f64")
     g = wd.Gauge(dev(U), dims)
     deta = dev(eta)
     p16 = wd.cg_default_params(inner=wd.F16N, reliable_every=50)
@@ -47,6 +47,6 @@ def test_c4_fp16n_against_fp64():
     assert np.all(res64 <= TOL * 1.0000001), res64
     kappa = (8.0 + m0) / m0
     errs = [rel(x16[i], x64[i]) for i in range(eta.shape[0])]
-    print("c4 iters f16n", [r["iters"] for r in r16], "f64", [r["iters"] for r in r64],
+    print("16^3x32 iters f16n", [r["iters"] for r in r16], "f64", [r["iters"] for r in r64],
           "max err f16n vs f64", max(errs), flush=True)
     assert max(errs) <= kappa * 2 * TOL

@@ -62,7 +62,7 @@ def test_lat4x4_1rhs(inner):
 @pytest.mark.parametrize("dims", [(8, 8, 8, 8), (12, 12, 12, 12), (14, 14, 14, 14)],
                          ids=["8^4", "12^4", "14^4"])
 @pytest.mark.parametrize("inner", [wd.F64, wd.F32], ids=["f64", "f32"])
-def test_c2_single_rhs(dims, inner):
+def test_single_rhs_volumes(dims, inner):
     m0, eps = 0.05, 0.5
     U = wdgen.gauge_field(dims, eps, 1002)
     eta = wdgen.gaussian_source(dims, 1, 2002)
