@@ -2,8 +2,9 @@
 // arXiv 2111.14958, Sec. 2, carried in the solution space) in one launch.
 //
 // The grid is sized so that every block is resident at once (occupancy x CU
-// count).  Blocks sweep the tiles of a phase, XCD by XCD in contiguous ranges,
-// then meet at a grid barrier.  The last block to arrive performs the phase's
+// count, or one 1024-thread block on each of max_cus compute units).  Blocks
+// sweep the tiles of a phase (XCD by XCD in contiguous ranges when the grid is
+// whole XCD rounds), then meet at a grid barrier.  The last block to arrive performs the phase's
 // fixed-order reduction (alpha or beta and the convergence tests) and releases
 // the others, so a CG iteration costs three grid-wide synchronisations and no
 // kernel launches.  Every wait is bounded: a block that waits longer than the
