@@ -90,7 +90,6 @@ struct alignas(16) Prob {
     void *w64;                // even-odd: odd-site intermediate of R2 (FP64)
 };
 
-// precision x_lo is stored in
 // NT (phase tiles): the streaming accesses (fields each thread reads or writes
 // once) carry the nontemporal hint.  The host sets it for FP64 solves whose
 // fields exceed the 256 MB MALL: there the L2 then keeps more of the
@@ -98,6 +97,7 @@ struct alignas(16) Prob {
 // rhs), while a single FP64 field, which the MALL holds, ran 6 % slower with
 // it, and FP32/FP16 storage 13-23 % slower.
 
+// precision x_lo is stored in
 template <int P> struct XPrec { static constexpr int value = P; };
 template <> struct XPrec<P16> { static constexpr int value = P32; };
 
