@@ -14,7 +14,8 @@
 
 namespace wd {
 
-template <int P, bool DAG, int NR, int ORD>
+// R12: U is the gauge's reconstruct-12 FP32 copy (two rows per link)
+template <int P, bool DAG, int NR, int ORD, bool R12 = false>
 __global__ __launch_bounds__(256) void k_dslash(Geom g, double diag, const void *__restrict__ U,
                                                 FieldPtr in, FieldPtr out, int ngroups, int remap, int rloop,
                                                 int order) {
@@ -48,7 +49,7 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, double diag, const void 
 #pragma unroll
             for (int j = 0; j < NR; ++j)
                 if (act >> j & 1) Spinor<P>::load(in, rhs0 + j, s, self[j]);
-            hopping<P, DAG, NR, ORD>(g, s, U, in, rhs0, act, acc, self);
+            hopping<P, DAG, NR, ORD, false, false, false, R12>(g, s, U, in, rhs0, act, acc, self);
 #pragma unroll
             for (int j = 0; j < NR; ++j) {
                 if (act >> j & 1) {
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, double diag, const void 
                 }
             }
         } else {
-            hopping<P, DAG, NR, ORD>(g, s, U, in, rhs0, act, acc);
+            hopping<P, DAG, NR, ORD, false, false, false, R12>(g, s, U, in, rhs0, act, acc);
 #pragma unroll
             for (int j = 0; j < NR; ++j) {
                 if (act >> j & 1) {
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, double diag, const void 
 // spinors to LDS; the x and y neighbours then come from LDS, so only the own
 // spinor and the z and t neighbours are read from memory.  The own spinor is
 // read back from LDS for the diagonal term.
-template <int P, bool DAG, int NR, int ORD>
+template <int P, bool DAG, int NR, int ORD, bool R12 = false>
 __global__ __launch_bounds__(256) void k_dslash_xy(Geom g, double diag, const void *__restrict__ U,
                                                    FieldPtr in, FieldPtr out, int ngroups, int remap, int order) {
     typedef typename real_of<P>::type R;
@@ -109,7 +110,8 @@ __global__ __launch_bounds__(256) void k_dslash_xy(Geom g, double diag, const vo
     }
     __syncthreads();
     cx<R> acc[NR][12];
-    hopping<P, DAG, NR, ORD, true>(g, s, U, in, rhs0, act, acc, nullptr, xy, s - (int)threadIdx.x, np);
+    hopping<P, DAG, NR, ORD, true, false, false, R12>(g, s, U, in, rhs0, act, acc, nullptr, xy, s - (int)threadIdx.x,
+                                                      np);
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (act >> j & 1) {
@@ -126,45 +128,45 @@ static size_t xy_lds_bytes(int prec, int nr, int np) {
     return (size_t)nr * (prec == WD_F64 ? 192 : 96) * np;
 }
 
-template <int P, bool DAG>
+template <int P, bool DAG, bool R12 = false>
 static void launch_xy(int nr, int ord, dim3 grid, int np, size_t lds, hipStream_t st, const Geom &g, double diag,
                       const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int od) {
     const dim3 block(np);
     if (nr == 1) {
-        if (ord == 3) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 3>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
-        else hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 1>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+        if (ord == 3) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 3, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+        else hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 1, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
     } else {
-        if (ord == 3) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 2, 3>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
-        else hipLaunchKernelGGL((k_dslash_xy<P, DAG, 2, 1>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+        if (ord == 3) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 2, 3, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+        else hipLaunchKernelGGL((k_dslash_xy<P, DAG, 2, 1, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
     }
 }
 
-template <int P, bool DAG, int ORD>
+template <int P, bool DAG, int ORD, bool R12 = false>
 static void launch_nr_o(int nr, dim3 grid, dim3 block, hipStream_t st, const Geom &g, double diag,
                         const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int rl, int od) {
     if constexpr (ORD == 4) {
         // the own spinors of several rhs do not fit in registers: only NR = 1
         if (nr == 1)
-            hipLaunchKernelGGL((k_dslash<P, DAG, 1, 4>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl, od);
+            hipLaunchKernelGGL((k_dslash<P, DAG, 1, 4, R12>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl, od);
         else
-            launch_nr_o<P, DAG, 3>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
+            launch_nr_o<P, DAG, 3, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
     } else {
         switch (nr) {
-        case 1: hipLaunchKernelGGL((k_dslash<P, DAG, 1, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl, od); break;
-        case 2: hipLaunchKernelGGL((k_dslash<P, DAG, 2, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl, od); break;
-        default: hipLaunchKernelGGL((k_dslash<P, DAG, 4, ORD>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl, od); break;
+        case 1: hipLaunchKernelGGL((k_dslash<P, DAG, 1, ORD, R12>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl, od); break;
+        case 2: hipLaunchKernelGGL((k_dslash<P, DAG, 2, ORD, R12>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl, od); break;
+        default: hipLaunchKernelGGL((k_dslash<P, DAG, 4, ORD, R12>), grid, block, 0, st, g, diag, U, in, out, ngroups, remap, rl, od); break;
         }
     }
 }
 
-template <int P, bool DAG>
+template <int P, bool DAG, bool R12 = false>
 static void launch_nr(int nr, int ordered, int rl, dim3 grid, dim3 block, hipStream_t st, const Geom &g, double diag,
                       const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int od) {
-    if (ordered == 1) launch_nr_o<P, DAG, 1>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
-    else if (ordered == 2) launch_nr_o<P, DAG, 2>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
-    else if (ordered == 3) launch_nr_o<P, DAG, 3>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
-    else if (ordered == 4) launch_nr_o<P, DAG, 4>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
-    else launch_nr_o<P, DAG, 0>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
+    if (ordered == 1) launch_nr_o<P, DAG, 1, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
+    else if (ordered == 2) launch_nr_o<P, DAG, 2, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
+    else if (ordered == 3) launch_nr_o<P, DAG, 3, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
+    else if (ordered == 4) launch_nr_o<P, DAG, 4, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
+    else launch_nr_o<P, DAG, 0, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
 }
 
 Geom make_geom(const wd_gauge *gg) {
@@ -190,6 +192,8 @@ int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void 
     const int strip = (sh.strip > 0 && sh.strip < g.L[2]) ? sh.strip : 0;
     const int od = strip | (sh.gmajor ? 1 << 16 : 0);
     const int np = g.L[0] * g.L[1];
+    // FP32 with a reconstruct-12 copy: every shape reads the two-row links
+    const bool r12 = prec == WD_F32 && gg->U12[WD_F32] != nullptr;
     if (sh.xylds && np <= 256) {   // else the site-blocked kernel below
         const int nrx = prec == WD_F64 ? 1 : std::min(nr, 2);
         const int ngx = (nrhs + nrx - 1) / nrx;
@@ -198,14 +202,20 @@ int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void 
         // LDS request is padded so at most occ blocks fit the 160 KB of a CU
         if (sh.occ > 0 && (size_t)(163840 / sh.occ) > lds) lds = std::min<size_t>(163840 / sh.occ, 65536);
         FieldPtr fi{(void *)in, g.V, nrhs}, fo{out, g.V, nrhs};
-        const void *U = gg->U[prec];
+        const void *U = r12 ? gg->U12[WD_F32] : gg->U[prec];
         const dim3 grid((g.V / np) * ngx);
         const int ord = sh.ordered == 3 ? 3 : 1;
         switch (prec * 2 + (dag ? 1 : 0)) {
         case 0: launch_xy<P64, false>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
         case 1: launch_xy<P64, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
-        case 2: launch_xy<P32, false>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
-        case 3: launch_xy<P32, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
+        case 2:
+            if (r12) launch_xy<P32, false, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od);
+            else launch_xy<P32, false>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od);
+            break;
+        case 3:
+            if (r12) launch_xy<P32, true, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od);
+            else launch_xy<P32, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od);
+            break;
         case 4: launch_xy<P16, false>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
         case 5: launch_xy<P16, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
         default: return fail(WD_EINVAL, "unknown precision %d", prec);
@@ -215,13 +225,19 @@ int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void 
     }
     const dim3 grid(nsb * ((ngroups + rl - 1) / rl)), block(blk);
     FieldPtr fi{(void *)in, g.V, nrhs}, fo{out, g.V, nrhs};
-    const void *U = gg->U[prec];
+    const void *U = r12 ? gg->U12[WD_F32] : gg->U[prec];
     const double diag = 4.0 + m0;
     switch (prec * 2 + (dag ? 1 : 0)) {
     case 0: launch_nr<P64, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od); break;
     case 1: launch_nr<P64, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od); break;
-    case 2: launch_nr<P32, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od); break;
-    case 3: launch_nr<P32, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od); break;
+    case 2:
+        if (r12) launch_nr<P32, false, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od);
+        else launch_nr<P32, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od);
+        break;
+    case 3:
+        if (r12) launch_nr<P32, true, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od);
+        else launch_nr<P32, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od);
+        break;
     case 4: launch_nr<P16, false>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od); break;
     case 5: launch_nr<P16, true>(nr, sh.ordered, rl, grid, block, st, g, diag, U, fi, fo, ngroups, sh.remap, od); break;
     default: return fail(WD_EINVAL, "unknown precision %d", prec);

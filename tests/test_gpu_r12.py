@@ -1,6 +1,12 @@
-"""Reconstruct-12 links (WD_GAUGE_RECON12): phases A and B of CG with FP32
-inner iterations read a two-row FP32 copy of the links and rebuild the third
-row from the first two.
+"""Reconstruct-12 links (WD_GAUGE_RECON12): the FP32 operator and phases A and
+B of CG with FP32 inner iterations read a two-row FP32 copy of the links and
+rebuild the third row from the first two.
+
+The operator on such a gauge matches the oracle's D and D^dagger in every launch
+shape (plane and site blocks, one or two fields per thread, both hop orders,
+both time boundaries, a 288-site plane); its result differs in the last
+bits from the one on the complete FP32 links, which shows the rebuilt row was
+used.
 
 The oracle's FP64 operator recomputes the true residual of every solution.
 The solution agrees with the solve on the complete links within kappa(D) (2 tol).
@@ -68,6 +74,32 @@ def test_r12_cg_matches_oracle(inner, dims, t_sign):
     b, n = _phase_b_bytes(g, m0, eta[:1], p)
     assert n12 > 0 and n > 0
     assert abs(b / n - b12 / n12 - 4 * 3 * 8 * V) <= 1e-6 * b / n, (b / n, b12 / n12)
+
+
+@pytest.mark.parametrize("dims,t_sign", [((8, 8, 4, 6), -1), ((8, 8, 4, 6), 1), ((6, 5, 4, 6), -1),
+                                         ((18, 16, 2, 4), -1)],
+                         ids=["8x8x4x6-anti", "8x8x4x6-peri", "6x5x4x6", "18x16x2x4-plane288"])
+def test_r12_operator_matches_oracle(dims, t_sign):
+    m0 = 0.1
+    U = wdgen.gauge_field(dims, 0.5, 531)
+    eta = wdgen.mixed_sources(dims, 2, 1, 532)   # 3 fields: a ragged pair with 2 per thread
+    g12 = wd.Gauge(dev(U), dims, t_sign, recon12=True)
+    g = wd.Gauge(dev(U), dims, t_sign)
+    for dag in (False, True):
+        want = oracle.dirac(U, eta, dims, m0, t_sign, dagger=dag)
+        # planes of more than 256 sites take the site-blocked kernel only
+        for xy in ((1, 0) if dims[0] * dims[1] <= 256 else (0,)):
+            for nr in (1, 2):
+                for order in (1, 3):
+                    say("r12 operator", dims, t_sign, "dag", dag, "xy", xy, "nr", nr, "order", order)
+                    for gg in (g12, g):
+                        wd.shape_set(gg, wd.F32, eta.shape[0], dag, wd.FAMILY_DSLASH, 256, nr, 1, order, 1,
+                                     0, 0, xy)
+                    got12 = host(wd.dslash(g12, m0, dev(eta), wd.F32, dagger=dag))
+                    got = host(wd.dslash(g, m0, dev(eta), wd.F32, dagger=dag))
+                    for i in range(eta.shape[0]):
+                        assert rel(got12[i], want[i]) <= 1e-6, (dag, xy, nr, order, i)
+                    assert np.any(got12 != got), (dag, xy, nr, order)
 
 
 def test_r12_gauge_serves_every_solver():
