@@ -37,7 +37,9 @@ namespace wd {
     const int t_ = b_ - pr.t0[K];
 
 // R12: links from the reconstruct-12 copy (FP32 storage).  NT: nontemporal
-// streaming accesses (FP64 solves larger than the MALL).
+// streaming accesses (FP64 solves larger than the MALL).  k_phaseB completes
+// phase A's reduction in its blocks (phaseB_tile with FA), so phase A has no
+// finish launch of its own.
 template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KA)
@@ -47,7 +49,7 @@ __global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, 
 template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KB)
-    phaseB_tile<P, NR, ORD, XY, R12, NT>(pr, t_);
+    phaseB_tile<P, NR, ORD, XY, R12, NT, true>(pr, t_);
 }
 
 // z-marching phases A and B (zm_tile); dynamic LDS of two plane buffers
@@ -173,12 +175,15 @@ void launch_eo_merge(const Prob *d, int64_t vf, int nrhs, void *sol, hipStream_t
 // last block of the phase instead, found with an atomic ticket, needs a
 // device-scope release fence in every block, which on a multi-XCD GPU writes
 // back the XCD's L2 each time: the whole CG ran 1.4x slower that way.)
+// kind | FIN_AB: phase B's finish after k_phaseB, which also completes phase A's.
+constexpr int FIN_AB = 0x100;
 __global__ __launch_bounds__(1024) void k_finish(const Prob *__restrict__ probs, int nprob, int kind) {
     for (int j = 0; j < nprob; ++j) {
         const Prob &pr = probs[j];
         switch (kind) {
         case KA: phaseA_finish(pr); break;
         case KB: phaseB_finish(pr); break;
+        case KB | FIN_AB: phaseAB_finish(pr); break;
         case KR2: ru2_finish(pr); break;
         case KN: norm_finish(pr); break;
         case KS2: bi2_finish(pr); break;
@@ -370,6 +375,15 @@ static void launch_finish(int kind, hipStream_t st, const Prob *d, int nprob) {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, d, nprob, kind);
 }
 
+// The finish after the tiles of `kind`.  Phase B by k_phaseB (not even-odd,
+// not z-marching) completes phase A's reduction in its blocks: then phase A
+// has no finish and phase B's finishes both.
+static void launch_finish_after(int kind, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob) {
+    const bool fa = !ls.eo && ls.k[KB].xy != 2;
+    if (kind == KA && fa) return;
+    launch_finish(kind == KB && fa ? (KB | FIN_AB) : kind, st, d, nprob);
+}
+
 // even-odd kernels of the stencil kinds (1 or 2 rhs per thread)
 template <int P>
 static void launch_eo(int kind, const KindShape &k, hipStream_t st, const Prob *d, int n) {
@@ -416,7 +430,7 @@ void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const
     } else {
         launch_kind_tiles(kind, inner, k, st, d, nprob);
     }
-    if (reduces) launch_finish(kind, st, d, nprob);
+    if (reduces) launch_finish_after(kind, ls, st, d, nprob);
 }
 
 static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream_t st, const Prob *d, int nprob) {
@@ -771,7 +785,7 @@ static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const 
                 t_ev_stop = ev[6 * it + 2 * q + 1];
                 launch_kind_tiles(kinds[q], inner, ls.k[kinds[q]], st, dprob, 1);
                 t_ev_start = t_ev_stop = nullptr;
-                if (kinds[q] != KC) launch_finish(kinds[q], st, dprob, 1);
+                if (kinds[q] != KC) launch_finish_after(kinds[q], ls, st, dprob, 1);
             }
         }
         if (hipMemcpyAsync(after.data(), dscal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||

@@ -138,12 +138,13 @@ __device__ __forceinline__ void block_sum(double v[NR]) {
 // blocks are loaded together (absent ones as 0, which leaves the sum
 // unchanged), so up to 256 site blocks cost one memory round trip.
 constexpr int MAX_SUMS = 64 * 3;
-__device__ __forceinline__ void sum_all(const Prob &pr, int nsb, int nk, double *sums) {
+// Partials k0 .. k0 + nk - 1 of each entry are summed.
+__device__ __forceinline__ void sum_all(const Prob &pr, int nsb, int nk, double *sums, int k0 = 0) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const size_t bs = (size_t)pr.nrhs * PSTRIDE;   // stride between site blocks
     for (int job = w; job < pr.nrhs * nk; job += nw) {
         const int i = job / nk, k = job - i * nk;
-        const double *col = pr.part + (size_t)i * PSTRIDE + k;
+        const double *col = pr.part + (size_t)i * PSTRIDE + k0 + k;
         const double a0 = lane < nsb ? col[(size_t)lane * bs] : 0.0;
         const double a1 = lane + 64 < nsb ? col[(size_t)(lane + 64) * bs] : 0.0;
         const double a2 = lane + 128 < nsb ? col[(size_t)(lane + 128) * bs] : 0.0;
@@ -197,9 +198,13 @@ template <> struct LdsWords<P64> { static constexpr int value = 12; };   // doub
 
 // Stage the NR input spinors of this thread's site in the block's LDS plane
 // (every thread of the block must call it: it ends with a barrier).
-template <int P, int NR>
+struct NoHook {
+    __device__ void operator()() const {}
+};
+// `hook` runs after the staging and before the barrier.
+template <int P, int NR, typename Hook = NoHook>
 __device__ __forceinline__ void stage_plane(const FieldPtr &f, int rhs0, unsigned act, int s, int V,
-                                            typename LdsSpinor<P>::word *xy, int np) {
+                                            typename LdsSpinor<P>::word *xy, int np, Hook hook = {}) {
     typedef typename real_of<P>::type R;
     if (s < V)
 #pragma unroll
@@ -209,6 +214,7 @@ __device__ __forceinline__ void stage_plane(const FieldPtr &f, int rhs0, unsigne
                 Spinor<P>::load(f, rhs0 + j, s, v);
                 LdsSpinor<P>::put(xy, np, j, threadIdx.x, v);
             }
+    hook();
     __syncthreads();
 }
 
@@ -295,25 +301,94 @@ __device__ __forceinline__ void phaseA_finish(const Prob &pr) {
 }
 
 // ------------------------------------------------------------------ phase B
+// Phase A's reduction inside the phase-B blocks (FA): each block sums phase
+// A's partials of its own fields, so alpha = rho / sigma is known without a
+// finish launch between the phases.  Wave w takes fields j = w, w + nw, ...
+// of the tile and adds exactly as sum_all does (same lanes, same order, same
+// butterfly), so every block gets the sigma the finish after phase B records.
+// fa_issue loads a lane's first four partials (before the plane staging, whose
+// latency then covers them); fa_reduce completes the sums into sig[j] (LDS,
+// read after the block's next barrier).
+template <int NR>
+__device__ __forceinline__ void fa_issue(const Prob &pr, int rhs0, unsigned act, double (&a)[NR][4]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int nsb = pr.nsb[KA];
+    const size_t bs = (size_t)pr.nrhs * PSTRIDE;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        a[j][0] = a[j][1] = a[j][2] = a[j][3] = 0.0;
+        if (j % nw == w && (act >> j & 1)) {
+            const double *col = pr.part + (size_t)(rhs0 + j) * PSTRIDE;
+            if (lane < nsb) a[j][0] = col[(size_t)lane * bs];
+            if (lane + 64 < nsb) a[j][1] = col[(size_t)(lane + 64) * bs];
+            if (lane + 128 < nsb) a[j][2] = col[(size_t)(lane + 128) * bs];
+            if (lane + 192 < nsb) a[j][3] = col[(size_t)(lane + 192) * bs];
+        }
+    }
+}
+
+template <int NR>
+__device__ __forceinline__ void fa_reduce(const Prob &pr, int rhs0, unsigned act, const double (&a)[NR][4],
+                                          double *sig) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int nsb = pr.nsb[KA];
+    const size_t bs = (size_t)pr.nrhs * PSTRIDE;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        if (j % nw == w && (act >> j & 1)) {
+            const double *col = pr.part + (size_t)(rhs0 + j) * PSTRIDE;
+            double x = 0.0;
+            x += a[j][0];
+            x += a[j][1];
+            x += a[j][2];
+            x += a[j][3];
+            for (int b = lane + 256; b < nsb; b += 64) x += col[(size_t)b * bs];
+            x = wave_sum(x);
+            if (lane == 0) sig[j] = x;
+        }
+    }
+}
+
 // t = D q; r -= alpha t; x_lo += alpha q(s); partial |r|^2 (of the stored r)
-template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false, bool NT = false>
+// FA: phase A's reduction is completed here (alpha from sigma of fa_reduce;
+// a field whose sigma is not finite and positive is skipped, as the finish
+// marks it broken down) and the |r|^2 partials go to slot 1, beside phase A's
+// in slot 0, for phaseAB_finish.
+template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false, bool NT = false, bool FA = false>
 __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     constexpr int XP = XPrec<P>::value;
     typedef typename real_of<XP>::type RX;
     typedef typename LdsSpinor<P>::word W;
     __shared__ W xy[XY ? NR * LdsWords<P>::value * 256 : 1];
+    __shared__ double sig[NR];
     int sb, grp, s;
     stencil_tile<XY>(pr, KB, t, sb, grp, s);
     const int rhs0 = grp * NR;
-    const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
+    unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
     double part[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) part[j] = 0.0;
     const Geom g = pr.g;
     const int np = g.S[2];
     FieldPtr fq{pr.q, g.V, pr.nrhs}, fr{pr.r, g.V, pr.nrhs}, fx{pr.x_lo, g.V, pr.nrhs};
-    if (XY && act) stage_plane<P, NR>(fq, rhs0, act, s, g.V, xy, np);
+    if constexpr (FA) {
+        if (act) {   // uniform over the block
+            double a[NR][4];
+            fa_issue<NR>(pr, rhs0, act, a);
+            if constexpr (XY) {
+                stage_plane<P, NR>(fq, rhs0, act, s, g.V, xy, np, [&]() { fa_reduce<NR>(pr, rhs0, act, a, sig); });
+            } else {
+                fa_reduce<NR>(pr, rhs0, act, a, sig);
+                __syncthreads();
+            }
+#pragma unroll
+            for (int j = 0; j < NR; ++j)
+                if ((act >> j & 1) && !finite_pos(sig[j])) act &= ~(1u << j);
+        }
+    } else if (XY && act) {
+        stage_plane<P, NR>(fq, rhs0, act, s, g.V, xy, np);
+    }
     if (act && s < g.V) {
         const void *U = R12 ? pr.U12 : pr.U_lo;
         cx<R> acc[NR][12];
@@ -322,7 +397,8 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
-                const R a = (R)pr.sc[rhs0 + j].alpha;
+                const double al = FA ? pr.sc[rhs0 + j].rho / sig[j] : pr.sc[rhs0 + j].alpha;
+                const R a = (R)al;
                 cx<R> q[12], o[12], r[12];
                 if constexpr (XY) LdsSpinor<P>::get(xy, np, j, threadIdx.x, q);
                 else Spinor<P>::load(fq, rhs0 + j, s, q);
@@ -337,7 +413,7 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
                 part[j] = n;
                 cx<RX> x[12];
                 Spinor<XP>::template load<NT>(fx, rhs0 + j, s, x);
-                const RX ax = (RX)pr.sc[rhs0 + j].alpha;
+                const RX ax = (RX)al;
 #pragma unroll
                 for (int k = 0; k < 12; ++k) x[k] = {x[k].re + ax * (RX)q[k].re, x[k].im + ax * (RX)q[k].im};
                 Spinor<XP>::template store<NT>(fx, rhs0 + j, s, x);
@@ -349,8 +425,22 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
         if (threadIdx.x == 0)
 #pragma unroll
             for (int j = 0; j < NR; ++j)
-                if (act >> j & 1) part_at(pr, sb, rhs0 + j, 0) = part[j];
+                if (act >> j & 1) part_at(pr, sb, rhs0 + j, FA ? 1 : 0) = part[j];
     }
+}
+
+// the scalar updates after phase B of an active field (c0: its record before)
+__device__ __forceinline__ void phaseB_update(const Prob &pr, Scal &c, const Scal &c0, double rho) {
+    const int iters = c0.iters + 1, since_ru = c0.since_ru + 1;
+    c.rho_old = c0.rho;
+    c.rho = rho;
+    c.beta = rho / c0.rho;
+    c.iters = iters;
+    c.since_ru = since_ru;
+    if (!(rho < 1e300)) c.state = ST_BREAKDOWN;   // NaN or Inf
+    else if (rho <= c0.stop2 || iters >= pr.max_iter || (pr.ru_every > 0 && since_ru >= pr.ru_every))
+        c.state = ST_FROZEN;                       // wants a reliable update
+    else c.pending_p = 1;
 }
 
 __device__ __forceinline__ void phaseB_finish(const Prob &pr) {
@@ -359,19 +449,35 @@ __device__ __forceinline__ void phaseB_finish(const Prob &pr) {
     Scal c0;
     if (i < pr.nrhs) c0 = pr.sc[i];
     sum_all(pr, pr.nsb[KB], 1, sums);
-    if (i < pr.nrhs && c0.state == ST_ACTIVE) {
+    if (i < pr.nrhs && c0.state == ST_ACTIVE) phaseB_update(pr, pr.sc[i], c0, sums[i]);
+}
+
+// After an FA phase B: phase A's finish (sigma, alpha, breakdown) from slot 0,
+// then phase B's from slot 1, with the results phaseA_finish followed by
+// phaseB_finish give.
+__device__ __forceinline__ void phaseAB_finish(const Prob &pr) {
+    __shared__ double sa[MAX_SUMS], sbb[MAX_SUMS];
+    const int i = threadIdx.x;
+    Scal c0;
+    if (i < pr.nrhs) c0 = pr.sc[i];
+    sum_all(pr, pr.nsb[KA], 1, sa, 0);
+    sum_all(pr, pr.nsb[KB], 1, sbb, 1);
+    if (i < pr.nrhs) {
         Scal &c = pr.sc[i];
-        const double rho = sums[i];
-        const int iters = c0.iters + 1, since_ru = c0.since_ru + 1;
-        c.rho_old = c0.rho;
-        c.rho = rho;
-        c.beta = rho / c0.rho;
-        c.iters = iters;
-        c.since_ru = since_ru;
-        if (!(rho < 1e300)) c.state = ST_BREAKDOWN;   // NaN or Inf
-        else if (rho <= c0.stop2 || iters >= pr.max_iter || (pr.ru_every > 0 && since_ru >= pr.ru_every))
-            c.state = ST_FROZEN;                       // wants a reliable update
-        else c.pending_p = 1;
+        bool live = c0.state == ST_ACTIVE;
+        if (live) {
+            const double sigma = sa[i];
+            c.sigma = sigma;
+            if (!finite_pos(sigma)) {
+                c.state = ST_BREAKDOWN;
+                live = false;
+            } else {
+                c.alpha = c0.rho / sigma;
+            }
+        }
+        c.pending_p = 0;
+        c.restart = 0;
+        if (live) phaseB_update(pr, c, c0, sbb[i]);
     }
 }
 
