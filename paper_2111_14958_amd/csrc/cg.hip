@@ -39,11 +39,13 @@ namespace wd {
 // R12: links from the reconstruct-12 copy (FP32 storage).  NT: nontemporal
 // streaming accesses (FP64 solves larger than the MALL).  k_phaseB completes
 // phase A's reduction in its blocks (phaseB_tile with FA), so phase A has no
-// finish launch of its own.
+// finish launch of its own.  k_phaseA forms the direction as q = D^dagger r +
+// beta q (phaseA_tile with QR): solves that launch it (LaunchSet::qrec) have
+// no phase C.
 template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KA)
-    phaseA_tile<P, NR, ORD, XY, R12, NT>(pr, t_);
+    phaseA_tile<P, NR, ORD, XY, R12, NT, true>(pr, t_);
 }
 
 template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false>
@@ -420,6 +422,7 @@ static void launch_eo(int kind, const KindShape &k, hipStream_t st, const Prob *
 void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob) {
     const KindShape &k = ls.k[kind];
     if (k.grid <= 0) return;
+    if (kind == KC && ls.qrec) return;   // phase A forms the direction in q
     const bool reduces = kind == KA || kind == KB || kind == KR2 || kind == KN || kind == KS2 || kind == KS4 ||
                          kind == KS5;
     const bool eo_kind = kind == KA || kind == KB || kind == KR2 || kind == KEA1 || kind == KEB1 || kind == KER2A;
@@ -599,6 +602,8 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
         pr.nt[k] = pr.nsb[k] * pr.ng[k];
         ks.grid = pr.nt[k];
     }
+    // phase A by k_phaseA (not even-odd, not z-marching) carries the direction as q
+    ls.qrec = !ls.eo && ls.k[KA].xy != 2;
 }
 
 // The persistent kernel runs phases A and B with one block shape: phase B's,
@@ -607,6 +612,7 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
 // its own (set-up, after reliable updates) keeps the shape of plan_shapes.
 void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner, int max_cus) {
     const int blk = max_cus > 0 ? 1024 : ls.k[KB].block;
+    ls.qrec = 0;   // the persistent kernel keeps p and phase C
     int nr = max_cus > 0 ? 1 : ls.k[KB].nr;
     if (inner == WD_F64 && nr > 2) nr = 2;
     const int kinds[2] = {KA, KB};
@@ -780,7 +786,7 @@ static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const 
     if (!rc) {
         for (int it = 0; it < K; ++it) {
             const int kinds[3] = {KA, KB, KC};
-            for (int q = 0; q < 3; ++q) {
+            for (int q = 0; q < (ls.qrec ? 2 : 3); ++q) {
                 t_ev_start = ev[6 * it + 2 * q];
                 t_ev_stop = ev[6 * it + 2 * q + 1];
                 launch_kind_tiles(kinds[q], inner, ls.k[kinds[q]], st, dprob, 1);
@@ -800,13 +806,15 @@ static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const 
         }
         std::lock_guard<std::mutex> lk(g_prof_mu);
         for (int it = 0; it < K; ++it) {
-            int nact = 0, nc = 0;
+            int nact = 0, nc = 0, nq = 0;
             for (int i = 0; i < nrhs; ++i) {
                 nact += it < d[i];
                 nc += it < d[i] - froze[i];
+                nq += it < d[i] && !(it == 0 && before[i].restart);   // phase A reads the old q
             }
-            const double bytes[3] = {G + nact * 2.0 * S, G + nact * (3.0 * S + 2.0 * SX), nc * 3.0 * S};
-            const int cnt[3] = {nact, nact, nc};
+            const double bytes[3] = {G + nact * 2.0 * S + (ls.qrec ? nq * S : 0.0), G + nact * (3.0 * S + 2.0 * SX),
+                                     nc * 3.0 * S};
+            const int cnt[3] = {nact, nact, ls.qrec ? 0 : nc};
             for (int k = 0; k < 3; ++k) {
                 if (cnt[k] == 0) continue;
                 float ms = 0;

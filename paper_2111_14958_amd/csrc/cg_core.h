@@ -232,7 +232,12 @@ __device__ __forceinline__ unsigned rhs_mask(const Prob &pr, int rhs0, int want)
 // q = D^dagger p for active rhs; partial |q|^2 (of the stored q)
 // XY: plane-blocked (one xy-plane per block, x/y neighbours from LDS).
 // R12: the links are the gauge's reconstruct-12 copy pr.U12 (two rows per link).
-template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false, bool NT = false>
+// QR: the direction is carried as q alone.  Since p = r + beta p_old, its image
+// q = D^dagger p is D^dagger r + beta q_old: the stencil reads r and each site
+// adds beta times its own old q (q = D^dagger r after a restart), so neither p
+// nor a pass forming it (phase C) is needed.  Only the site's own q is read,
+// so q is updated in place.
+template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false, bool NT = false, bool QR = false>
 __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     typedef typename LdsSpinor<P>::word W;
@@ -246,7 +251,7 @@ __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
     for (int j = 0; j < NR; ++j) part[j] = 0.0;
     const Geom g = pr.g;
     const int np = g.S[2];
-    FieldPtr fp{pr.p, g.V, pr.nrhs}, fq{pr.q, g.V, pr.nrhs};
+    FieldPtr fp{QR ? pr.r : pr.p, g.V, pr.nrhs}, fq{pr.q, g.V, pr.nrhs};
     if (XY && act) stage_plane<P, NR>(fp, rhs0, act, s, g.V, xy, np);
     if (act && s < g.V) {
         const void *U = R12 ? pr.U12 : pr.U_lo;
@@ -260,6 +265,16 @@ __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
                 if constexpr (XY) LdsSpinor<P>::get(xy, np, j, threadIdx.x, self);
                 else Spinor<P>::load(fp, rhs0 + j, s, self);
                 wilson_finish<R>((R)pr.diag, self, acc[j], o);
+                if constexpr (QR) {
+                    const Scal &c = pr.sc[rhs0 + j];
+                    if (!c.restart) {
+                        const R b = (R)c.beta;
+                        cx<R> qo[12];
+                        Spinor<P>::template load<NT>(fq, rhs0 + j, s, qo);
+#pragma unroll
+                        for (int k = 0; k < 12; ++k) o[k] = {o[k].re + b * qo[k].re, o[k].im + b * qo[k].im};
+                    }
+                }
                 Spinor<P>::template store<NT>(fq, rhs0 + j, s, o);
                 double n = 0;
 #pragma unroll
