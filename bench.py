@@ -102,8 +102,8 @@ def main():
     src = wdgen.mixed_sources(dims, cfg["n_point"], cfg["n_gauss"], cfg["src_seed"])
     dU = torch.from_numpy(U).to(dev)
     dsrc = torch.from_numpy(src).to(dev)
-    # links: the complete copies plus two-row (reconstruct-12) FP32/FP16 copies,
-    # which phases A and B of the lower-precision CG read
+    # links: the complete copies plus a two-row (reconstruct-12) FP32 copy, which
+    # the FP32 operator and phases A and B of the FP32-inner CG read
     g = wd.Gauge(dU, dims, -1, recon12=True)
     sol = torch.zeros_like(dsrc)
 

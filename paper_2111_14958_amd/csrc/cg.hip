@@ -41,7 +41,7 @@ namespace wd {
 // phase A's reduction in its blocks (phaseB_tile with FA), so phase A has no
 // finish launch of its own.  k_phaseA forms the direction as q = D^dagger r +
 // beta q (phaseA_tile with QR): solves that launch it (LaunchSet::qrec) have
-// no phase C.
+// no phase C; so do the even-odd phase-A kernels.
 template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KA)
@@ -96,12 +96,12 @@ __global__ __launch_bounds__(256) void k_norm(const Prob *__restrict__ probs, in
 template <int P, int NR, bool DAG>
 __global__ __launch_bounds__(256) void k_eo_hop1(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(DAG ? KEA1 : KEB1)
-    eo_hop1_tile<P, NR, DAG>(pr, t_);
+    eo_hop1_tile<P, NR, DAG, true>(pr, t_);
 }
 template <int P, int NR>
 __global__ __launch_bounds__(256) void k_eo_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KA)
-    eo_phaseA_tile<P, NR>(pr, t_);
+    eo_phaseA_tile<P, NR, true>(pr, t_);
 }
 template <int P, int NR>
 __global__ __launch_bounds__(256) void k_eo_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
@@ -602,8 +602,9 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
         pr.nt[k] = pr.nsb[k] * pr.ng[k];
         ks.grid = pr.nt[k];
     }
-    // phase A by k_phaseA (not even-odd, not z-marching) carries the direction as q
-    ls.qrec = !ls.eo && ls.k[KA].xy != 2;
+    // phase A by k_phaseA or the even-odd kernels (not z-marching) carries the
+    // direction as q
+    ls.qrec = ls.eo || ls.k[KA].xy != 2;
 }
 
 // The persistent kernel runs phases A and B with one block shape: phase B's,

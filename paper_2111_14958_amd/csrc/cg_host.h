@@ -21,7 +21,7 @@ struct KindShape {
 struct LaunchSet {
     KindShape k[NKIND];
     int eo = 0;   // even-odd preconditioned solve: A, B, R2 are Schur kernels
-    int qrec = 0; // phase A forms the direction q = D^dagger r + beta q: no p, no phase C
+    int qrec = 0; // phase A forms the direction q = D^dagger r + beta q (Dhat for even-odd): no p, no phase C
 };
 
 // Byte offsets of the pieces of a solve workspace.

@@ -40,8 +40,9 @@ __device__ __forceinline__ void eo_tile(const Prob &pr, int K, int t, int &sb, i
 }
 
 // First half hop, onto the odd sites: tmp_o = H_oe v_e (H^dagger with DAG).
-// v: p for phase A (DAG), q for phase B.
-template <int P, int NR, bool DAG>
+// v: p for phase A (DAG), q for phase B.  QR: phase A hops r, as it forms the
+// direction as q = Dhat^dagger r + beta q (see phaseA_tile).
+template <int P, int NR, bool DAG, bool QR = false>
 __device__ __forceinline__ void eo_hop1_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     constexpr int K = DAG ? KEA1 : KEB1;
@@ -52,7 +53,7 @@ __device__ __forceinline__ void eo_hop1_tile(const Prob &pr, int t) {
     if (!act || k >= pr.vf) return;
     const Geom g = pr.g;
     const int s = eo_site(g, k, 1);
-    FieldPtr fin{DAG ? pr.p : pr.q, pr.vf, pr.nrhs}, fo{pr.tmp, pr.vf, pr.nrhs};
+    FieldPtr fin{DAG ? (QR ? pr.r : pr.p) : pr.q, pr.vf, pr.nrhs}, fo{pr.tmp, pr.vf, pr.nrhs};
     cx<R> acc[NR][12];
     hopping<P, DAG, NR, 1, false, true>(g, s, pr.U_lo, fin, rhs0, act, acc);
 #pragma unroll
@@ -60,8 +61,9 @@ __device__ __forceinline__ void eo_hop1_tile(const Prob &pr, int t) {
         if (act >> j & 1) Spinor<P>::store(fo, rhs0 + j, k, acc[j]);
 }
 
-// Phase A, second half: q_e = A p_e - c H^dagger_eo tmp_o, partial |q|^2
-template <int P, int NR>
+// Phase A, second half: q_e = A p_e - c H^dagger_eo tmp_o, partial |q|^2.
+// QR: with r in place of p, plus beta times the old q_e (not after a restart).
+template <int P, int NR, bool QR = false>
 __device__ __forceinline__ void eo_phaseA_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     int sb, grp, k;
@@ -74,7 +76,7 @@ __device__ __forceinline__ void eo_phaseA_tile(const Prob &pr, int t) {
     if (act && k < pr.vf) {
         const Geom g = pr.g;
         const int s = eo_site(g, k, 0);
-        FieldPtr ft{pr.tmp, pr.vf, pr.nrhs}, fp{pr.p, pr.vf, pr.nrhs}, fq{pr.q, pr.vf, pr.nrhs};
+        FieldPtr ft{pr.tmp, pr.vf, pr.nrhs}, fp{QR ? pr.r : pr.p, pr.vf, pr.nrhs}, fq{pr.q, pr.vf, pr.nrhs};
         cx<R> acc[NR][12];
         hopping<P, true, NR, 1, false, true>(g, s, pr.U_lo, ft, rhs0, act, acc);
         const R a = (R)pr.diag, c = (R)pr.eo_c;
@@ -85,6 +87,16 @@ __device__ __forceinline__ void eo_phaseA_tile(const Prob &pr, int t) {
                 Spinor<P>::load(fp, rhs0 + j, k, v);
 #pragma unroll
                 for (int m = 0; m < 12; ++m) o[m] = {fma(-c, acc[j][m].re, a * v[m].re), fma(-c, acc[j][m].im, a * v[m].im)};
+                if constexpr (QR) {
+                    const Scal &sc = pr.sc[rhs0 + j];
+                    if (!sc.restart) {
+                        const R b = (R)sc.beta;
+                        cx<R> qo[12];
+                        Spinor<P>::load(fq, rhs0 + j, k, qo);
+#pragma unroll
+                        for (int m = 0; m < 12; ++m) o[m] = {o[m].re + b * qo[m].re, o[m].im + b * qo[m].im};
+                    }
+                }
                 Spinor<P>::store(fq, rhs0 + j, k, o);
                 double n = 0;
 #pragma unroll

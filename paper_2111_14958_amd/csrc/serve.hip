@@ -139,7 +139,7 @@ static LaunchSet server_launch(int inner, int eo, const int grid[NKIND]) {
     server_shapes(inner, blk, nr);
     LaunchSet ls;
     ls.eo = eo;
-    ls.qrec = !eo;   // k_phaseA: the direction is carried as q
+    ls.qrec = 1;   // k_phaseA and the even-odd phase A carry the direction as q
     for (int k = 0; k < NKIND; ++k) {
         const bool stencil = k == KA || k == KB || k == KR2 || k == KEA1 || k == KEB1 || k == KER2A;
         ls.k[k].block = blk;
