@@ -427,11 +427,12 @@ FAMILY_DSLASH, FAMILY_CG_A, FAMILY_CG_B, FAMILY_CG_R = 0, 1, 2, 3
 
 def shape_set(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int, block: int,
               rhs_per_thread: int = 1, xcd_remap: int = 1, hop_order: int = 1, rhs_loop: int = 1,
-              strip: int = 0, group_major: int = 0, xy_lds: int = 0, max_blocks_per_cu: int = 0):
+              strip: int = 0, group_major: int = 0, xy_lds: int = 0, max_blocks_per_cu: int = 0,
+              rhs_pass: int = 0):
     r = TuneResult(block=block, rhs_per_thread=rhs_per_thread, xcd_remap=xcd_remap,
                    hop_order=hop_order, rhs_loop=rhs_loop,
                    site_order=strip | (group_major << 16) | ((1 if xy_lds else 0) << 17) |
-                   (max_blocks_per_cu << 18) | ((1 if xy_lds == 2 else 0) << 24))
+                   (max_blocks_per_cu << 18) | ((1 if xy_lds == 2 else 0) << 24) | (rhs_pass << 25))
     _check(lib().wd_shape_set(g.handle, prec, nrhs, 1 if dagger else 0, family, ctypes.byref(r)),
            "wd_shape_set")
 
@@ -445,6 +446,7 @@ def shape_get(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int) -> dict
     out["group_major"] = (r.site_order >> 16) & 1
     out["xy_lds"] = (1 + ((r.site_order >> 24) & 1)) if (r.site_order >> 17) & 1 else 0
     out["max_blocks_per_cu"] = (r.site_order >> 18) & 0x3F
+    out["rhs_pass"] = (r.site_order >> 25) & 0x3F
     return out
 
 

@@ -550,7 +550,7 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.remap = st[k]->remap;
             ks.ordered = (k == KA || k == KB) && st[k]->ordered == 3 ? 3 : 1;
             const int strip = (st[k]->strip > 0 && st[k]->strip < g->dims[2]) ? st[k]->strip : 0;
-            ks.order = strip | (st[k]->gmajor ? 1 << 16 : 0);
+            ks.order = strip | (st[k]->gmajor ? 1 << 16 : 0) | (st[k]->fpass << 24);
             // plane-blocked phases A and B: one xy-plane of 64..256 sites per
             // block (the partial-sum buffer holds one entry per 64 sites)
             ks.xy = (k == KA || k == KB || k == KR2) && st[k]->xylds && np >= 64 && np <= 256 && !pr.eo;

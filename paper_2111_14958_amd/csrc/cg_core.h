@@ -177,12 +177,27 @@ __device__ __forceinline__ int find_prob(const Prob *probs, int nprob, int K, in
 // Tile t of stencil kind K: its site block, its rhs group and this thread's
 // site (g.V when the thread has no site).  XY: a site block is one xy-plane
 // (Lx Ly <= blockDim.x sites), as the plane-blocked variant needs.
+// Passes (fp = (od >> 24) & 63 > 0): the site blocks are cut into eight
+// chunks, one per XCD's tile range, and a chunk is walked in passes of fp rhs
+// groups, site-block-major within a pass.  A pass holds fewer fields per
+// plane, so the planes whose spinors its blocks share lie closer together in
+// the XCD's L2; the links are read once per pass.
 template <bool XY = false>
 __device__ __forceinline__ void stencil_tile(const Prob &pr, int K, int t, int &sb, int &grp, int &s) {
     const int od = pr.sorder[K];
+    const int fp = (od >> 24) & 63;
     if ((od >> 16) & 1) {
         grp = t / pr.nsb[K];
         sb = t - grp * pr.nsb[K];
+    } else if (fp > 0 && fp < pr.ng[K]) {
+        const int nsb = pr.nsb[K], ng = pr.ng[K];
+        const int sc = (nsb + 7) >> 3;                  // site blocks per chunk
+        const int c = t / (sc * ng), u = t - c * sc * ng;
+        const int sbc = min(sc, nsb - c * sc);          // site blocks of this chunk
+        const int pass = u / (sbc * fp), v = u - pass * sbc * fp;
+        const int g0 = pass * fp, gp = min(fp, ng - g0);   // groups of this pass
+        sb = c * sc + v / gp;
+        grp = g0 + v % gp;
     } else {
         sb = t / pr.ng[K];
         grp = t - sb * pr.ng[K];

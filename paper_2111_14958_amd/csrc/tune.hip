@@ -45,7 +45,8 @@ static bool g_loaded = false;
 // wd_tune_result.site_order: strip | group-major << 16 | plane-blocked << 17 |
 // blocks-per-CU cap << 18 | z-marching << 24 (z-marching: xylds 2)
 int encode_order(const Shape &s) {
-    return s.strip | (s.gmajor << 16) | ((s.xylds ? 1 : 0) << 17) | (s.occ << 18) | ((s.xylds == 2) << 24);
+    return s.strip | (s.gmajor << 16) | ((s.xylds ? 1 : 0) << 17) | (s.occ << 18) | ((s.xylds == 2) << 24) |
+           (s.fpass << 25);
 }
 
 Shape default_shape(int prec, int nrhs, int fam) {
@@ -234,8 +235,11 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     const int zm = (sh->site_order >> 24) & 1;
     const int strip = sh->site_order & 0xffff, gmajor = (sh->site_order >> 16) & 1,
               xylds = (sh->site_order >> 17) & 1 ? 1 + zm : 0, occ = (sh->site_order >> 18) & 0x3f;
-    WD_CHECK(sh->site_order >= 0 && (sh->site_order >> 25) == 0 && occ <= 8, WD_EINVAL, "site_order 0x%x",
+    const int fpass = (sh->site_order >> 25) & 0x3f;
+    WD_CHECK(sh->site_order >= 0 && (sh->site_order >> 31) == 0 && occ <= 8, WD_EINVAL, "site_order 0x%x",
              sh->site_order);
+    WD_CHECK(fpass == 0 || ((family == FAM_CG_A || family == FAM_CG_B) && !gmajor && !zm), WD_EINVAL,
+             "passes of rhs groups: CG phase A/B kernels in site-block-major order only");
     WD_CHECK(!zm || ((sh->site_order >> 17) & 1), WD_EINVAL, "z-marching needs the plane-blocked bit");
     WD_CHECK(!xylds || g->dims[0] * g->dims[1] <= 256, WD_EINVAL, "plane-blocked LDS variant: Lx*Ly <= 256");
     WD_CHECK(!(xylds && family == FAM_CG_R && sh->rhs_per_thread != 1), WD_EINVAL,
@@ -253,6 +257,7 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     s.gmajor = gmajor;
     s.xylds = xylds;
     s.occ = occ;
+    s.fpass = fpass;
     shape_store(k, s);
     return WD_OK;
 }

@@ -50,6 +50,8 @@ struct Shape {
     int gmajor = 0;          // tiles ordered rhs-group-major (1) or site-block-major (0)
     int xylds = 0;           // plane-blocked: one xy-plane per block, x/y neighbours from LDS
     int occ = 0;             // plane-blocked operator: at most occ blocks per CU (0: no limit)
+    int fpass = 0;           // CG phases: each eighth of the site blocks is walked in passes of
+                             // fpass rhs groups (0: all groups of a site block together)
 };
 
 // Key of the launch-shape table: lattice, precision, rhs count, dagger, and

@@ -278,6 +278,39 @@ def test_plane_blocked_phase_kernels(inner, dims):
     assert rel(sols[2], sols[0]) <= kappa(m0) * 2 * TOL
 
 
+@pytest.mark.parametrize("inner", [wd.F64, wd.F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("xy,block", [(1, 256), (0, 64)], ids=["planes", "sites"])
+def test_rhs_pass_tile_order_is_bitwise_neutral(inner, xy, block):
+    """Walking each eighth of the site blocks in passes of a few rhs groups
+    (rhs_pass) only reorders the tiles: every tile forms the same partial sums,
+    which the finish adds in site-block order, so the solution is bitwise the
+    one of the default order.  30 site blocks (30 planes, or 30 blocks of 64
+    sites) make chunks of 4 with a short last one; 5 fields in passes of 2 or 3
+    leave a short last pass."""
+    dims, m0 = (8, 8, 5, 6), 0.1
+    U = wdgen.gauge_field(dims, 0.5, 411)
+    eta = wdgen.mixed_sources(dims, 3, 2, 412)
+    nrhs = eta.shape[0]
+    g = wd.Gauge(dev(U), dims)
+    p = wd.cg_default_params(inner=inner, reliable_every=0 if inner == wd.F64 else 50)
+    sols = {}
+    for fp in (0, 1, 2, 3):
+        say("cg rhs passes", inner, "xy", xy, "pass", fp)
+        for fam, dag in ((wd.FAMILY_CG_A, True), (wd.FAMILY_CG_B, False)):
+            wd.shape_set(g, inner, nrhs, dag, fam, block, 1, 1, 3, 1, 0, 0, xy, 0, fp)
+            assert wd.shape_get(g, inner, nrhs, dag, fam)["rhs_pass"] == fp
+        x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+        assert rc == wd.WD_OK, reps
+        sols[fp] = host(x)
+    _check_solution(U, eta, sols[0], dims, m0)
+    for fp in (1, 2, 3):
+        assert np.array_equal(sols[fp], sols[0]), fp
+    # passes are a CG phase A/B order only
+    with pytest.raises(wd.WDError) as e:
+        wd.shape_set(g, inner, nrhs, False, wd.FAMILY_DSLASH, 256, 1, 1, 1, 1, 0, 0, 0, 0, 2)
+    assert e.value.code == wd.WD_EINVAL
+
+
 @pytest.mark.parametrize("inner", [wd.F32, wd.F16N], ids=["f32", "f16n"])
 @pytest.mark.parametrize("dims,chunks", [((8, 8, 6, 6), (1, 2, 3, 6, 0)), ((16, 8, 5, 4), (1, 2, 5, 0)),
                                          ((8, 16, 2, 6), (1, 2)), ((14, 14, 14, 4), (4, 7))],
