@@ -198,12 +198,12 @@ def main():
         kernel_symbol = "wd::k_%s<1, %d, %d, %s, true, false>" % (dom_name[3:], nr, 3 if sh["hop_order"] == 3 else 1,
                                                     "true" if xy else "false")
     else:
-        kernel_symbol = "wd::k_phaseC<1>"
+        kernel_symbol = dom_name
     traffic, traffic_note = pmc_traffic() if dom_name == "cg_phaseB" else (None, "not measured")
     per_launch = {k: {"launches": v["launches"],
                       "avg_us": 1e3 * v["total_ms"] / max(v["launches"], 1),
                       "GBps": v["bytes_total"] / max(v["total_ms"], 1e-12) / 1e6}
-                  for k, v in prof.items()}
+                  for k, v in prof.items() if v["launches"] > 0}
 
     # -------- the same solve with the complete 18-real links (context)
     gfull = wd.Gauge(dU, dims, -1)
@@ -223,7 +223,8 @@ def main():
                       "max_true_rel_res": max(r["true_rel_res"] for r in rfs),
                       "err_vs_fp64_cg_solution": ((sol - x64).reshape(nrhs, -1).norm(dim=1) /
                                                   x64.reshape(nrhs, -1).norm(dim=1)).max().item(),
-                      "kernels_avg_us": {k: 1e3 * v["total_ms"] / max(v["launches"], 1) for k, v in proff.items()}}
+                      "kernels_avg_us": {k: 1e3 * v["total_ms"] / max(v["launches"], 1) for k, v in proff.items()
+                                         if v["launches"] > 0}}
     del gfull
     log(f"complete links: {full_value:.2f} solves/s")
 

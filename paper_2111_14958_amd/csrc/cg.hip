@@ -609,11 +609,10 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
 
 // The persistent kernel runs phases A and B with one block shape: phase B's,
 // or 1024 threads and one rhs per thread when it is limited to max_cus compute
-// units.  Its phase C tiles follow from its block size; phase C launched on
-// its own (set-up, after reliable updates) keeps the shape of plan_shapes.
+// units.  Its phase A forms the direction as q (no p and no phase C).
 void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner, int max_cus) {
     const int blk = max_cus > 0 ? 1024 : ls.k[KB].block;
-    ls.qrec = 0;   // the persistent kernel keeps p and phase C
+    ls.qrec = 1;   // the persistent kernel's phase A carries the direction as q too
     int nr = max_cus > 0 ? 1 : ls.k[KB].nr;
     if (inner == WD_F64 && nr > 2) nr = 2;
     const int kinds[2] = {KA, KB};

@@ -1,12 +1,13 @@
-// Persistent CG chunk kernel: K iterations of phases A, B and C (the CG of
-// arXiv 2111.14958, Sec. 2, carried in the solution space) in one launch.
+// Persistent CG chunk kernel: K iterations of phases A and B (the CG of
+// arXiv 2111.14958, Sec. 2, carried in the solution space, with the search
+// direction kept as q = D^dagger p) in one launch.
 //
 // The grid is sized so that every block is resident at once (occupancy x CU
 // count, or one 1024-thread block on each of max_cus compute units).  Blocks
 // sweep the tiles of a phase (XCD by XCD in contiguous ranges when the grid is
 // whole XCD rounds), then meet at a grid barrier.  The last block to arrive performs the phase's
 // fixed-order reduction (alpha or beta and the convergence tests) and releases
-// the others, so a CG iteration costs three grid-wide synchronisations and no
+// the others, so a CG iteration costs two grid-wide synchronisations and no
 // kernel launches.  Every wait is bounded: a block that waits longer than the
 // limit sets an abort flag, every other waiter sees it and exits, and the host
 // reports the failure; no wave can spin forever.
@@ -85,8 +86,8 @@ __global__ __launch_bounds__(BLK) void k_persistent(const Prob *__restrict__ pro
     const unsigned nblk = gridDim.x;
     unsigned e = 0;
     for (int it = 0; it < K; ++it) {
-        {   // phase A
-            FOR_MY_TILES(pr.nt[KA], t) phaseA_tile<P, NR, 1>(pr, t);
+        {   // phase A: the direction q = D^dagger r + beta q (no p, no phase C)
+            FOR_MY_TILES(pr.nt[KA], t) phaseA_tile<P, NR, 1, false, false, false, true>(pr, t);
         }
         if (bar_arrive(b, nblk, e)) {
             phaseA_finish(pr);
@@ -104,13 +105,6 @@ __global__ __launch_bounds__(BLK) void k_persistent(const Prob *__restrict__ pro
         } else if (bar_wait(b, e)) {
             return;
         }
-        ++e;
-        {   // phase C: tiles of blockDim.x sites and one rhs
-            const int ntc = (int)((pr.vf + blockDim.x - 1) / blockDim.x) * pr.nrhs;
-            FOR_MY_TILES(ntc, t) phaseC_tile<P>(pr, t);
-        }
-        if (bar_arrive(b, nblk, e)) bar_release(b, e);
-        else if (bar_wait(b, e)) return;
         ++e;
     }
 }
@@ -171,7 +165,7 @@ static int launch_persistent_cus(hipStream_t st, const Prob *d, int K, void *bar
 int record_persistent_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob,
                             int K, void *bar, int max_cus) {
     WD_CHECK(nprob == 1, WD_EINVAL, "the persistent kernel serves one problem");
-    const KindShape &ka = ls.k[KA], &kb = ls.k[KB], &kc = ls.k[KC];
+    const KindShape &ka = ls.k[KA], &kb = ls.k[KB];
     WD_CHECK(ka.block == kb.block && ka.nr == kb.nr, WD_EINVAL,
              "persistent kernel needs one block shape for phases A and B");
     if (max_cus > 0) {
@@ -182,7 +176,7 @@ int record_persistent_chunk(int inner, const LaunchSet &ls, hipStream_t st, cons
         }
         return fail(WD_EINVAL, "no compute-unit-limited kernel for precision %d", inner);
     }
-    const int max_tiles = std::max(ka.grid, std::max(kb.grid, kc.grid * kc.block / ka.block));
+    const int max_tiles = std::max(ka.grid, kb.grid);
     const int blk = ka.block;
     switch (inner * 4 + ka.nr) {
     case P64 * 4 + 1: return launch_persistent<P64, 1>(blk, st, d, K, bar, max_tiles);
