@@ -4,8 +4,10 @@
 //
 // A solve runs
 //   init   eta64 <- src, x64 <- x0 or 0, x_lo <- 0, scalars <- host record,
-//          N (|eta|^2), R2 (r = eta - D x64, true-residual test), C (p = r)
-//   chunk  K x [A, B, C], then R1 (x64 += x_lo), R2, C, summary   (one graph)
+//          N (|eta|^2), R2 (r = eta - D x64, true-residual test)
+//          (and C, p = r, with a z-marching phase A)
+//   chunk  K x [A, B], then R1 (x64 += x_lo), R2, summary   (one graph; with a
+//          z-marching phase A, which reads p: K x [A, B, C], then R1, R2, C)
 // and replays the chunk graph until no right-hand side is active, reading back
 // one counter per replay.  BiCGSTAB (bicgstab_core.h) uses the same driver with
 // the chunk K x [S1, S2, S3, S4, S5], then R1, R2, summary.

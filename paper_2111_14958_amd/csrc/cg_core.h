@@ -4,16 +4,19 @@
 // solution space (x = D^dagger chi):
 //     q = D^dagger p;  alpha = rho / |q|^2;  x += alpha q;  r -= alpha D q;
 //     rho' = |r|^2;    beta = rho' / rho;    p = r + beta p
-// so r is the residual of D x = eta itself.  One iteration is three phases:
-//     A  q = D^dagger p                     + partial sums of |q|^2   -> alpha
+// so r is the residual of D x = eta itself.  The direction is kept as its
+// image q alone (q' = D^dagger r + beta q equals D^dagger p'), and one
+// iteration is two phases:
+//     A  q = D^dagger r + beta q           + partial sums of |q|^2   -> alpha
 //     B  t = D q, r -= alpha t, x += alpha q + partial sums of |r|^2   -> beta
-//     C  p = r + beta p
-// Every scalar lives in device memory, one record per right-hand side; a
-// one-block launch after each reducing phase sums the per-block partials in a
-// fixed order and updates the scalars, so nothing returns to the host inside
+// (phase C, p = r + beta p, with phase A reading p, remains for the z-marching
+// phase-A kernel).  Every scalar lives in device memory, one record per
+// right-hand side.  Phase B's blocks complete phase A's reduction themselves,
+// and a one-block launch after phase B sums the per-block partials of both in
+// a fixed order and updates the scalars, so nothing returns to the host inside
 // an iteration and reductions are bitwise reproducible.
 //
-// Mixed precision: p, q, r and x_lo are stored in the inner precision (FP16N
+// Mixed precision: q, r, x_lo (and p) are stored in the inner precision (FP16N
 // keeps x_lo in FP32).  A reliable update (R1, R2) accumulates x64 += x_lo and
 // recomputes r = eta - D x64 with FP64 links and FP64 arithmetic; the solve
 // ends only when that true residual satisfies |r| <= tol |eta|.
@@ -316,6 +319,10 @@ __device__ __forceinline__ void phaseA_finish(const Prob &pr) {
     const int i = threadIdx.x;
     Scal c0;
     if (i < pr.nrhs) c0 = pr.sc[i];
+    if (!__syncthreads_or(i < pr.nrhs && c0.state == ST_ACTIVE)) {   // nothing to sum
+        if (i < pr.nrhs) pr.sc[i].pending_p = pr.sc[i].restart = 0;
+        return;
+    }
     sum_all(pr, pr.nsb[KA], 1, sums);
     if (i < pr.nrhs) {
         Scal &c = pr.sc[i];
@@ -478,8 +485,43 @@ __device__ __forceinline__ void phaseB_finish(const Prob &pr) {
     const int i = threadIdx.x;
     Scal c0;
     if (i < pr.nrhs) c0 = pr.sc[i];
+    if (!__syncthreads_or(i < pr.nrhs && c0.state == ST_ACTIVE)) return;   // nothing to sum
     sum_all(pr, pr.nsb[KB], 1, sums);
     if (i < pr.nrhs && c0.state == ST_ACTIVE) phaseB_update(pr, pr.sc[i], c0, sums[i]);
+}
+
+// Phase A's (slot 0) and phase B's (slot 1) sums of every field in one memory
+// round trip: wave w takes fields i = w, w + nw, ... and loads the first four
+// blocks of both columns before adding either, each in sum_all's order (so
+// the values are the ones sum_all returns, and fa_reduce's sigma).
+__device__ __forceinline__ void sum_ab(const Prob &pr, double *sa, double *sb) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const size_t bs = (size_t)pr.nrhs * PSTRIDE;
+    const int na = pr.nsb[KA], nb = pr.nsb[KB];
+    for (int i = w; i < pr.nrhs; i += nw) {
+        const double *ca = pr.part + (size_t)i * PSTRIDE, *cb = ca + 1;
+        double a[4], b[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a[k] = lane + 64 * k < na ? ca[(size_t)(lane + 64 * k) * bs] : 0.0;
+            b[k] = lane + 64 * k < nb ? cb[(size_t)(lane + 64 * k) * bs] : 0.0;
+        }
+        double x = 0.0, y = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            x += a[k];
+            y += b[k];
+        }
+        for (int j = lane + 256; j < na; j += 64) x += ca[(size_t)j * bs];
+        for (int j = lane + 256; j < nb; j += 64) y += cb[(size_t)j * bs];
+        x = wave_sum(x);
+        y = wave_sum(y);
+        if (lane == 0) {
+            sa[i] = x;
+            sb[i] = y;
+        }
+    }
+    __syncthreads();
 }
 
 // After an FA phase B: phase A's finish (sigma, alpha, breakdown) from slot 0,
@@ -490,8 +532,11 @@ __device__ __forceinline__ void phaseAB_finish(const Prob &pr) {
     const int i = threadIdx.x;
     Scal c0;
     if (i < pr.nrhs) c0 = pr.sc[i];
-    sum_all(pr, pr.nsb[KA], 1, sa, 0);
-    sum_all(pr, pr.nsb[KB], 1, sbb, 1);
+    if (!__syncthreads_or(i < pr.nrhs && c0.state == ST_ACTIVE)) {   // nothing to sum
+        if (i < pr.nrhs) pr.sc[i].pending_p = pr.sc[i].restart = 0;
+        return;
+    }
+    sum_ab(pr, sa, sbb);
     if (i < pr.nrhs) {
         Scal &c = pr.sc[i];
         bool live = c0.state == ST_ACTIVE;

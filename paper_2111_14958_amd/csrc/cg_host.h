@@ -50,7 +50,7 @@ void launch_eo_split(const Prob *d, int64_t vf, int nrhs, const void *src, void 
 void launch_eo_source(const Prob *d, int64_t vf, int nrhs, hipStream_t st);
 void launch_eo_merge(const Prob *d, int64_t vf, int nrhs, void *sol, hipStream_t st);
 int cg_status_of(int state);
-// Record one persistent chunk kernel (K iterations of phases A, B, C with grid
+// Record one persistent chunk kernel (K iterations of phases A and B with grid
 // barriers) on `st`; `bar` is 256 bytes of device scratch for the barrier.
 // max_cus > 0: one 1024-thread block on each of max_cus compute units.
 int record_persistent_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob,
