@@ -278,6 +278,33 @@ def test_plane_blocked_phase_kernels(inner, dims):
     assert rel(sols[2], sols[0]) <= kappa(m0) * 2 * TOL
 
 
+@pytest.mark.parametrize("inner", [wd.F32, wd.F16N], ids=["f32", "f16n"])
+@pytest.mark.parametrize("block", [64, 256])
+def test_four_rhs_per_thread_phase_kernels(inner, block):
+    """Site-blocked phases A and B with four right-hand sides per thread (the
+    most the FP32/FP16 kernels take), over 6 fields: one full group of four and
+    a ragged one of two.  Phase B completes phase A's reduction for all four
+    fields of its tile (waves 0..3 of a 256-thread block, or one wave for all
+    four in a 64-thread block)."""
+    dims, m0 = (8, 8, 4, 6), 0.1
+    U = wdgen.gauge_field(dims, 0.5, 421)
+    eta = wdgen.mixed_sources(dims, 4, 2, 422)
+    nrhs = eta.shape[0]
+    g = wd.Gauge(dev(U), dims)
+    p = wd.cg_default_params(inner=inner, reliable_every=50)
+    say("cg 4 rhs per thread", inner, block)
+    x0, _, rc0 = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    assert rc0 == wd.WD_OK
+    for fam, dag in ((wd.FAMILY_CG_A, True), (wd.FAMILY_CG_B, False)):
+        wd.shape_set(g, inner, nrhs, dag, fam, block, 4, 1, 3, 1, 4, 0, 0)
+        assert wd.shape_get(g, inner, nrhs, dag, fam)["rhs_per_thread"] == 4
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    assert rc == wd.WD_OK, reps
+    x = host(x)
+    _check_solution(U, eta, x, dims, m0)
+    assert rel(x, host(x0)) <= kappa(m0) * 2 * TOL
+
+
 @pytest.mark.parametrize("inner", [wd.F64, wd.F32], ids=["f64", "f32"])
 @pytest.mark.parametrize("xy,block", [(1, 256), (0, 64)], ids=["planes", "sites"])
 def test_rhs_pass_tile_order_is_bitwise_neutral(inner, xy, block):
