@@ -57,8 +57,12 @@ Shape default_shape(int prec, int nrhs, int fam) {
     s.rloop = 1;
     s.strip = 4;
     if (fam == FAM_DSLASH) {
-        s.nr = (prec == WD_F64 || nrhs < 2) ? 1 : 2;
+        // one rhs per thread: at 14^4 x 16 rhs it beat two with FP16 storage
+        // (33 vs 38 us, lexicographic plane order) and in FP32 on the
+        // reconstruct-12 links (45 vs 48.5 us; 50 vs 49 us on complete links)
+        s.nr = 1;
         s.xylds = 1;
+        if (prec == WD_F16N) s.strip = 0;
     } else if (fam == FAM_CG_R) {
         s.nr = 1;
         s.xylds = 1;
