@@ -248,7 +248,7 @@ typedef struct {
                              0: compiler order                                    */
     int32_t rhs_loop;     /* rhs groups one block handles one after the other    */
     int32_t site_order;   /* strip | group_major << 16 | xy_lds << 17 | occ << 18
-                             | z_march << 24.
+                             | z_march << 24 | rhs_pass << 25.
                              strip = W > 0: sites are processed in strips of W
                              z-planes, t-major inside a strip (0: lexicographic);
                              group_major = 1: tiles are ordered rhs-group-major
@@ -258,7 +258,12 @@ typedef struct {
                              z_march = 1 (with xy_lds = 1; CG phases A and B in
                              FP32/FP16N storage): a block walks a column of
                              xy-planes along z with two planes in LDS, and strip
-                             is then the number of z-chunks (0: automatic)     */
+                             is then the number of z-chunks (0: automatic);
+                             rhs_pass = n in 1..63 (CG phases A and B, not with
+                             group_major or z_march): the site blocks are cut
+                             into eight chunks, one per XCD's tile range, each
+                             walked in passes of n rhs groups (0: all at once);
+                             results are bitwise the same for every order    */
     double  us;           /* median time of one application, microseconds        */
     double  gbps;         /* algorithmic bytes / time                             */
 } wd_tune_result;
@@ -291,7 +296,7 @@ int wd_tune_cg(const wd_gauge *g, double m0, int32_t inner, const void *src_dev,
 
 /* kernel families of the shape table */
 #define WD_FAMILY_DSLASH 0   /* wd_dslash / wd_dslash_dag                       */
-#define WD_FAMILY_CG_A   1   /* CG phase A: q = D^dagger p and |q|^2           */
+#define WD_FAMILY_CG_A   1   /* CG phase A: q = D^dagger r + beta q, |q|^2     */
 #define WD_FAMILY_CG_B   2   /* CG phase B: D q, r and x updates, |r|^2        */
 #define WD_FAMILY_CG_R   3   /* reliable update r = eta - D x (FP64)           */
 /* Set the launch shape of one kernel family for (g's lattice, prec, nrhs,
@@ -312,14 +317,16 @@ int wd_shape_get(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
  * launch the kernels of each chunk one by one (instead of replaying the chunk
  * graph) and launch every phase-A/B/C tile kernel with HIP start/stop events
  * on the solve's stream, recorded at the kernel's own begin and end (the
- * one-block reduction launch after A and B is not included).  Launched one by
+ * one-block reduction launch after B is not included).  Launched one by
  * one, the kernels run somewhat slower than inside the graph.  bytes_total sums the algorithmic bytes of those launches (links
  * once, every spinor of every active right-hand side once per read or write).
  * Meant for measurement runs; CG (WD_METHOD_CGNE) without the persistent
  * kernel only. */
 typedef struct {
-    char    name[32];       /* "cg_phaseA" (q = D^dagger p), "cg_phaseB" (D q + updates),
-                               "cg_phaseC" (p = r + beta p)                              */
+    char    name[32];       /* "cg_phaseA" (q = D^dagger r + beta q), "cg_phaseB" (D q +
+                               updates), "cg_phaseC" (p = r + beta p: only in solves
+                               whose phase A reads p, i.e. z-marching phase A; 0
+                               launches otherwise)                                    */
     int64_t launches;
     double  total_ms;       /* summed event time                                    */
     double  bytes_total;    /* summed algorithmic bytes                             */
