@@ -337,6 +337,28 @@ int wd_profile_reset(void);
 /* copy up to max_n entries into out, *n = number of entries available */
 int wd_profile_read(wd_kernel_stat *out, int32_t max_n, int32_t *n);
 
+/* Chunk graphs of the CG solvers: *built = graphs captured since the library
+ * was loaded, *cached = graphs held now (at most 32, least recently used ones
+ * are dropped).  A solve replays the graph of its key (workspace address,
+ * lattice, rhs count, inner precision, chunk length, method and every field
+ * of every kernel's launch shape) and captures a new one when none matches. */
+int wd_cg_graph_stats(int64_t *built, int32_t *cached);
+
+/* --------------------------------------------------------- bandwidth probe */
+/* The memory ceiling the operator's bandwidth is measured against (the naive
+ * roofline P = min(peak flops, bandwidth x intensity) of Sec. 3.1 needs the
+ * attainable bandwidth): one streaming kernel with 16-byte coalesced accesses.
+ *   WD_STREAM_READ   reads `bytes` of src_dev (dst_dev: 16 bytes the kernel may
+ *                    write, so that no load can be dropped)
+ *   WD_STREAM_COPY   copies `bytes` from src_dev to dst_dev (no overlap)
+ *   WD_STREAM_WRITE  writes `bytes` of a constant pattern to dst_dev (src_dev unused)
+ * bytes and both pointers must be multiples of 16 (WD_EINVAL otherwise).
+ * Asynchronous on `stream`. */
+#define WD_STREAM_READ  0
+#define WD_STREAM_COPY  1
+#define WD_STREAM_WRITE 2
+int wd_stream(int32_t kind, const void *src_dev, void *dst_dev, size_t bytes, void *stream);
+
 /* ----------------------------------------------------------------- serving */
 typedef struct wd_server wd_server;
 
@@ -366,13 +388,18 @@ typedef struct {
     uint64_t steps;             /* scheduling steps run                           */
     uint64_t arena_high_water;  /* largest number of arena bytes in use           */
     int32_t  active, pending;
+    uint64_t arena_capacity;    /* arena bytes left for requests once the server's
+                                   own tables are carved out: the largest footprint
+                                   wd_serve_submit accepts                        */
 } wd_serve_stats;
 
 /* Device bytes a request occupies in the arena while it is resident. */
 size_t wd_serve_footprint(const wd_request *req);
 /* Start the scheduler thread.  The arena is used as a first-fit heap. */
 int wd_serve_create(const wd_serve_config *cfg, wd_server **out);
-/* Queue a request; returns at once.  WD_ETOOBIG if it can never fit the arena.
+/* Queue a request; returns at once.  WD_ETOOBIG if its footprint exceeds the
+ * arena capacity (wd_serve_stats.arena_capacity), so it could never be admitted;
+ * every accepted request is admitted once enough of the arena is free.
  * The caller keeps gauge_dev/src_dev/sol_dev alive until the ticket is done. */
 int wd_serve_submit(wd_server *s, const wd_request *req, uint64_t *ticket);
 /* *done = 1 and reps[nrhs] filled once the request is finished, else *done = 0.

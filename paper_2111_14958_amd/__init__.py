@@ -23,6 +23,7 @@ F64, F32, F16N = 0, 1, 2
 METHOD_CGNE, METHOD_BICGSTAB = 0, 1
 PRECOND_NONE, PRECOND_EO = 0, 1
 PACKED = 1
+STREAM_READ, STREAM_COPY, STREAM_WRITE = 0, 1, 2
 GAUGE_RECON12 = 1 << 8   # wd_gauge_create: also keep a two-row (reconstruct-12) FP32 copy
 GAUGE_F64, GAUGE_F32, GAUGE_F16 = 1, 2, 4
 
@@ -38,7 +39,7 @@ EXPORTS = [
     "wd_coo_create", "wd_coo_destroy", "wd_coo_info", "wd_coo_export", "wd_coo_spmv",
     "wd_cg_default_params", "wd_cg_workspace_bytes", "wd_cg_solve", "wd_cg_solve_batch",
     "wd_tune_dslash", "wd_tune_lookup", "wd_tune_cg", "wd_shape_set", "wd_shape_get",
-    "wd_profile_enable", "wd_profile_reset", "wd_profile_read",
+    "wd_profile_enable", "wd_profile_reset", "wd_profile_read", "wd_cg_graph_stats", "wd_stream",
     "wd_serve_footprint", "wd_serve_create", "wd_serve_submit", "wd_serve_poll",
     "wd_serve_stats_get", "wd_serve_destroy",
 ]
@@ -100,7 +101,7 @@ class ServeStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
                 ("completed", ctypes.c_uint64), ("steps", ctypes.c_uint64),
                 ("arena_high_water", ctypes.c_uint64), ("active", ctypes.c_int32),
-                ("pending", ctypes.c_int32)]
+                ("pending", ctypes.c_int32), ("arena_capacity", ctypes.c_uint64)]
 
 
 _lib = None
@@ -150,6 +151,8 @@ def lib():
             "wd_profile_enable": ([I32], ctypes.c_int),
             "wd_profile_reset": ([], ctypes.c_int),
             "wd_profile_read": ([ctypes.POINTER(KernelStat), I32, ctypes.POINTER(I32)], ctypes.c_int),
+            "wd_cg_graph_stats": ([ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(I32)], ctypes.c_int),
+            "wd_stream": ([I32, P, P, SZ, P], ctypes.c_int),
             "wd_serve_footprint": ([ctypes.POINTER(Request)], SZ),
             "wd_serve_create": ([ctypes.POINTER(ServeConfig), ctypes.POINTER(P)], ctypes.c_int),
             "wd_serve_submit": ([P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -468,6 +471,20 @@ def profile_read() -> dict:
         out[k.name.decode()] = {"launches": k.launches, "total_ms": k.total_ms,
                                 "bytes_total": k.bytes_total}
     return out
+
+
+def cg_graph_stats():
+    """(chunk graphs captured since load, graphs cached now)"""
+    built, cached = ctypes.c_int64(0), ctypes.c_int32(0)
+    _check(lib().wd_cg_graph_stats(ctypes.byref(built), ctypes.byref(cached)), "wd_cg_graph_stats")
+    return built.value, cached.value
+
+
+def stream(kind: int, src, dst, nbytes: int):
+    """One streaming kernel (STREAM_READ / STREAM_COPY / STREAM_WRITE) over nbytes
+    of the GPU tensors src and dst (src may be None for STREAM_WRITE)."""
+    _check(lib().wd_stream(kind, None if src is None else _ptr(src), _ptr(dst), int(nbytes), _stream()),
+           "wd_stream")
 
 
 @dataclass

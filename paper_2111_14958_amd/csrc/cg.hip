@@ -682,12 +682,16 @@ void init_scalars(std::vector<Scal> &sc, int nrhs) {
 }
 
 // ------------------------------------------------------------ graph cache
+// Every field of every kernel kind's launch shape is part of the key (the hop
+// order, the LDS size, the link copy and the streaming hint select different
+// kernels), so a changed shape never replays a graph of the old kernels.
 struct GraphKey {
     const void *ws;
     int dims[4], nrhs, inner, K, persistent, method, max_cus;
-    int shp[NKIND][5];
+    KindShape shp[NKIND];
     bool operator<(const GraphKey &o) const { return memcmp(this, &o, sizeof(*this)) < 0; }
 };
+static_assert(sizeof(KindShape) == 10 * sizeof(int), "KindShape must be plain ints (compared bytewise)");
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
@@ -698,6 +702,7 @@ struct GraphEntry {
 static std::mutex g_graph_mu;
 static std::map<GraphKey, GraphEntry> g_graphs;
 static uint64_t g_graph_clock = 0;
+static int64_t g_graphs_built = 0;   // chunk graphs captured since the library was loaded
 static std::map<int, hipStream_t> g_capture_streams;
 
 static hipStream_t capture_stream() {
@@ -744,6 +749,7 @@ static int get_graph(const GraphKey &key, F record, hipGraphExec_t *out) {
     }
     e.last_use = ++g_graph_clock;
     g_graphs[key] = e;
+    ++g_graphs_built;
     *out = e.exec;
     return WD_OK;
 }
@@ -904,13 +910,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     key.persistent = persistent;
     key.max_cus = p.max_cus;
     key.method = p.method | (eo << 4);
-    for (int k = 0; k < NKIND; ++k) {
-        key.shp[k][0] = ls.k[k].block;
-        key.shp[k][1] = ls.k[k].nr;
-        key.shp[k][2] = ls.k[k].remap;
-        key.shp[k][3] = ls.k[k].grid;
-        key.shp[k][4] = ls.k[k].order | (ls.k[k].xy << 18) | (ls.k[k].r12 << 20) | (ls.k[k].nt << 21);
-    }
+    for (int k = 0; k < NKIND; ++k) key.shp[k] = ls.k[k];
     hipGraphExec_t exec = nullptr;
     int rec_rc = WD_OK;
     rc = get_graph(key, [&](hipStream_t cs) {
@@ -1193,6 +1193,15 @@ int wd_tune_cg(const wd_gauge *g, double m0, int32_t inner, const void *src, int
     best->rhs_loop = bests.rloop;
     best->site_order = encode_order(bests);
     best->us = best_ms * 1e3;
+    return WD_OK;
+}
+
+int wd_cg_graph_stats(int64_t *built, int32_t *cached) {
+    clear_error();
+    WD_CHECK(built && cached, WD_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    *built = g_graphs_built;
+    *cached = (int32_t)g_graphs.size();
     return WD_OK;
 }
 

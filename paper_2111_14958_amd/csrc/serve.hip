@@ -170,6 +170,7 @@ struct wd_server {
     wd_serve_stats stats{};
     // per (inner precision, even-odd) group: max_slots Prob records
     size_t table_off[6] = {0, 0, 0, 0, 0, 0};
+    size_t table_bytes = 0;             // arena bytes the six tables occupy
     std::vector<wd::Prob> table[6];     // host staging of the tables (alive until the step syncs)
     int chunk = 25;
 };
@@ -345,6 +346,16 @@ static void scheduler(wd_server *s) {
                     admitted.push_back(sl);
                     it = s->pending.erase(it);
                     s->stats.admitted++;
+                } else if (s->active.empty() && admitted.empty() && nslots < s->cfg.max_slots) {
+                    // the arena is empty and still too small (submit's capacity
+                    // check rules this out): fail the request rather than wait
+                    // for space that can never appear
+                    std::vector<wd_cg_report> reps(it->req.nrhs);
+                    memset(reps.data(), 0, sizeof(wd_cg_report) * it->req.nrhs);
+                    for (auto &r : reps) r.status = WD_ETOOBIG;
+                    s->done[it->ticket] = reps;
+                    s->stats.completed++;
+                    it = s->pending.erase(it);
                 } else {
                     // keep the order fair: a request that has waited long enough
                     // stops later requests from overtaking it
@@ -470,6 +481,7 @@ int wd_serve_create(const wd_serve_config *cfg, wd_server **out) {
             return fail(WD_ETOOBIG, "arena too small for the request tables");
         }
     }
+    s->table_bytes = s->arena.used;
     s->arena.high = s->arena.used;
     (void)hipSetDevice(cfg->device);
     const hipError_t e = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking);
@@ -492,7 +504,9 @@ int wd_serve_submit(wd_server *s, const wd_request *req, uint64_t *ticket) {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->error) return fail(s->error, "server stopped after a runtime error");
     WD_CHECK(!s->stop, WD_EINVAL, "server is shutting down");
-    const size_t capacity = s->arena.size - 3 * al256s(sizeof(Prob) * s->cfg.max_slots);
+    // what is left of the arena once the request tables are carved out: a
+    // request of at most this footprint fits as soon as nothing else is resident
+    const size_t capacity = s->arena.size - s->table_bytes;
     if (need > capacity)
         return fail(WD_ETOOBIG, "request needs %zu bytes, the arena offers %zu", need, capacity);
     Pending p;
@@ -528,6 +542,7 @@ int wd_serve_stats_get(wd_server *s, wd_serve_stats *st) {
     std::lock_guard<std::mutex> lk(s->mu);
     *st = s->stats;
     st->arena_high_water = s->arena.high;
+    st->arena_capacity = s->arena.size - s->table_bytes;
     st->pending = (int32_t)s->pending.size();
     return WD_OK;
 }

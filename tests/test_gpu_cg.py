@@ -179,6 +179,43 @@ def test_nan_source_breaks_down():
     assert reps[0]["status"] == wd.WD_EBREAKDOWN and reps[1]["status"] == wd.WD_OK
 
 
+def test_graph_cache_keys_on_the_hop_order():
+    """A solve whose phase kernels differ only in the hop order captures a graph
+    of its own on the same workspace (the old order's graph is not replayed),
+    and going back replays the cached one."""
+    import torch
+    dims, m0, nrhs = (8, 8, 8, 8), 0.05, 2
+    U = wdgen.gauge_field(dims, 0.5, 1021)
+    eta = wdgen.gaussian_source(dims, nrhs, 2021)
+    g = wd.Gauge(dev(U), dims)
+    p = wd.cg_default_params(inner=wd.F32, reliable_every=50)
+    ws = torch.empty(wd.cg_workspace_bytes(g, nrhs, p), dtype=torch.uint8, device="cuda")
+    base = {fam: wd.shape_get(g, wd.F32, nrhs, fam == wd.FAMILY_CG_A, fam)
+            for fam in (wd.FAMILY_CG_A, wd.FAMILY_CG_B)}
+    sols = {}
+    try:
+        for order in (3, 1, 3):
+            for fam, sh in base.items():
+                wd.shape_set(g, wd.F32, nrhs, fam == wd.FAMILY_CG_A, fam, sh["block"],
+                             rhs_per_thread=sh["rhs_per_thread"], xcd_remap=sh["xcd_remap"], hop_order=order,
+                             strip=sh["strip"], xy_lds=sh["xy_lds"])
+            say("graph key hop order", order)
+            before = wd.cg_graph_stats()[0]
+            x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p, ws=ws)
+            assert rc == wd.WD_OK
+            built = wd.cg_graph_stats()[0] - before
+            sols.setdefault(order, []).append((host(x), built))
+    finally:
+        for fam, sh in base.items():
+            wd.shape_set(g, wd.F32, nrhs, fam == wd.FAMILY_CG_A, fam, sh["block"],
+                         rhs_per_thread=sh["rhs_per_thread"], xcd_remap=sh["xcd_remap"],
+                         hop_order=sh["hop_order"], strip=sh["strip"], xy_lds=sh["xy_lds"])
+    assert sols[1][0][1] == 1                 # the new hop order captured its own graph
+    assert sols[3][1][1] == 0                 # back to order 3: the cached graph is replayed
+    assert np.array_equal(sols[3][0][0], sols[3][1][0])
+    _check_solution(U, eta, sols[1][0][0], dims, m0)
+
+
 def test_workspace_too_small():
     dims = (4, 4, 4, 4)
     U = wdgen.gauge_field(dims, 0.3, 1001)

@@ -1,8 +1,12 @@
 """GPU operator parity: wd_dslash / wd_dslash_dag against the FP64 CPU oracle.
 
-Tolerances (global |GPU - oracle| / |oracle|): FP64 1e-13, FP32 1e-6, FP16N 2e-3
-(half storage carries 11 significant bits, unit roundoff 4.9e-4; the bound allows
-a few roundings of the inputs and the output).  Packing is checked bit for bit.
+Two checks per case:
+* global |GPU - oracle| / |oracle| against the unrounded FP64 inputs: FP64 1e-13,
+  FP32 1e-6, FP16N 2e-3 (half storage carries 11 significant bits, unit roundoff
+  4.9e-4; the bound allows a few roundings of the inputs and the output);
+* every site on its own (sitecheck), with the oracle fed the links and fields the
+  GPU holds (FP32- or FP16-rounded), so a single wrong component anywhere fails.
+Packing is checked bit for bit.
 """
 import numpy as np
 import pytest
@@ -11,11 +15,13 @@ import oracle
 import paper_2111_14958_amd as wd
 import wdgen
 from gpu_util import dev, host, rel, say, field_set
+import sitecheck
 
 pytestmark = pytest.mark.gpu
 
 TOL = {wd.F64: 1e-13, wd.F32: 1e-6, wd.F16N: 2e-3}
 NAMES = {wd.F64: "f64", wd.F32: "f32", wd.F16N: "f16n"}
+SITE_BOUND = {wd.F64: sitecheck.F64_BOUND, wd.F32: sitecheck.F32_BOUND, wd.F16N: sitecheck.F16N_BOUND}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -34,6 +40,19 @@ def _oracle_input(psi, prec):
         return oracle.round_f32(psi)
     c, n = oracle.fp16n_encode(psi.reshape(psi.shape[0], -1, 4, 3).astype(np.complex64))
     return oracle.fp16n_decode(c, n).astype(np.complex128).reshape(psi.shape)
+
+
+def _oracle_links(U, prec):
+    """The links the GPU reads in `prec` (the complete copy of a gauge made without
+    reconstruct-12)."""
+    return {wd.F64: lambda u: u, wd.F32: sitecheck.links_f32, wd.F16N: sitecheck.links_f16}[prec](U)
+
+
+def check_per_site(got, U, psi, dims, m0, t_sign, dag, prec, what):
+    """every site of got against the oracle on the GPU-held inputs"""
+    pin = _oracle_input(psi, prec)
+    want = oracle.dirac(_oracle_links(U, prec), pin, dims, m0, t_sign, dagger=dag)
+    return sitecheck.assert_sites(got, want, pin, m0, SITE_BOUND[prec], what)
 
 
 CASES = [
@@ -58,6 +77,7 @@ def test_dslash_matches_oracle(dims, m0, eps, nrhs, prec):
             want = oracle.dirac(U, psi, dims, m0, t_sign, dagger=dag)
             err = rel(got, want)
             assert err <= TOL[prec], f"{NAMES[prec]} dag={dag} t_sign={t_sign}: rel err {err:.3e}"
+            check_per_site(got, U, psi, dims, m0, t_sign, dag, prec, f"{NAMES[prec]} dag={dag} t_sign={t_sign}")
         g.close()
 
 

@@ -11,9 +11,16 @@
     be <= tol and agree with the residual the library reports; the solution
     agrees with the FP64 CG solution within kappa(D) (2 tol), the bound on the
     error of two solutions that both meet tol.
+* The same 16 fields solved in one persistent launch per chunk (grid barriers,
+  every block sweeping several tiles per phase), FP32 inner and FP64, with the
+  default phase shapes and with site blocks of 4 (FP32) or 2 (FP64) right-hand
+  sides per thread: oracle residuals, and agreement with the kernel-per-phase
+  solution.
 * 64 right-hand sides, the most one call takes, solve like single fields; 65
   are refused.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -21,6 +28,7 @@ import oracle
 import paper_2111_14958_amd as wd
 import wdgen
 from gpu_util import dev, host, rel, say
+from test_gpu_dslash import check_per_site
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
@@ -59,6 +67,8 @@ def test_bench_operator_16_fields(bench_fields, prec):
         for i in range(src.shape[0]):
             err = rel(got[i], want[i])
             assert err <= OP_TOL[prec], (prec, dag, i, err)
+        # and every site of every field against the oracle on the GPU-held inputs
+        check_per_site(got, U, src, dims, m0, -1, dag, prec, f"14^4 x 16 prec {prec} dagger {dag}")
 
 
 @pytest.mark.parametrize("recon12", [True, False], ids=["recon12", "complete-links"])
@@ -84,6 +94,51 @@ def test_bench_cg_workload(bench_fields, recon12):
     assert np.all(oracle.true_residual(U, src, x64, dims, m0) <= tol * 1.0000001)
     for i in range(src.shape[0]):
         assert rel(x[i], x64[i]) <= kappa(m0) * 2 * tol, i
+
+
+_PER_PHASE = {}
+
+
+def _shape_raw(g, prec, nrhs, dag, fam):
+    r = wd.TuneResult()
+    assert wd.lib().wd_shape_get(g.handle, prec, nrhs, dag, fam, ctypes.byref(r)) == 0
+    return r
+
+
+@pytest.mark.parametrize("inner,nr", [(wd.F32, 0), (wd.F32, 4), (wd.F64, 0), (wd.F64, 2)],
+                         ids=["f32-default", "f32-4rhs", "f64-default", "f64-2rhs"])
+def test_persistent_kernel_benchmark_workload(bench_fields, inner, nr):
+    cfg, U, src = bench_fields
+    dims, m0, tol = cfg["dims"], cfg["m0"], cfg["tol"]
+    nrhs = src.shape[0]
+    g = wd.Gauge(dev(U), dims, recon12=True)
+    ru = 0 if inner == wd.F64 else 50
+    if inner not in _PER_PHASE:
+        say("per-phase reference 14^4 x 16", inner)
+        x0, _, rc0 = wd.cg_solve_batch(g, m0, dev(src), params=wd.cg_default_params(
+            tol=tol, inner=inner, reliable_every=ru, persistent=0))
+        assert rc0 == wd.WD_OK
+        _PER_PHASE[inner] = host(x0)
+    keep = [(dag, fam, _shape_raw(g, inner, nrhs, dag, fam)) for dag, fam in ((1, wd.FAMILY_CG_A),
+                                                                             (0, wd.FAMILY_CG_B))]
+    try:
+        if nr:
+            for dag, fam, _ in keep:
+                wd.shape_set(g, inner, nrhs, bool(dag), fam, 256, rhs_per_thread=nr, hop_order=1, strip=4)
+        say("persistent 14^4 x 16", inner, "rhs per thread", nr or "default")
+        x, reps, rc = wd.cg_solve_batch(g, m0, dev(src), params=wd.cg_default_params(
+            tol=tol, inner=inner, reliable_every=ru, persistent=1))
+    finally:
+        for dag, fam, r in keep:
+            assert wd.lib().wd_shape_set(g.handle, inner, nrhs, dag, fam, ctypes.byref(r)) == 0
+    assert rc == wd.WD_OK, reps
+    x = host(x)
+    res = oracle.true_residual(U, src, x, dims, m0)
+    assert np.all(res <= tol * 1.0000001), res
+    for r, o in zip(reps, res):
+        assert abs(r["true_rel_res"] - o) <= 1e-3 * tol + 1e-6 * o, (r["true_rel_res"], o)
+    for i in range(nrhs):
+        assert rel(x[i], _PER_PHASE[inner][i]) <= kappa(m0) * 2 * tol, i
 
 
 def test_rhs_count_limits():

@@ -34,6 +34,20 @@ def _requests():
     return out
 
 
+def _big_requests():
+    """The serving workload's largest volumes beside small ones: 14^4 and
+    16^3 x 32 with 12 right-hand sides at m0 0.02 (the hardest conditioning the
+    stream draws), one of them even-odd preconditioned, and three small requests."""
+    out = []
+    specs = [((14, 14, 14, 14), 12, 0.02, 0), ((16, 16, 16, 32), 12, 0.02, 1),
+             ((4, 4, 4, 4), 3, 0.2, 0), ((8, 8, 8, 8), 5, 0.07, 1), ((12, 12, 12, 12), 1, 0.11, 0)]
+    for i, (dims, nrhs, m0, eo) in enumerate(specs):
+        U = wdgen.gauge_field(dims, 0.5, 11_000 + i)
+        src = wdgen.gaussian_source(dims, nrhs, 61_000 + i)
+        out.append(dict(dims=dims, nrhs=nrhs, m0=m0, U=U, src=src, inner=wd.F32, eo=eo))
+    return out
+
+
 def _run(reqs, arena_bytes, max_slots=8, chunk=10):
     import torch
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
@@ -75,6 +89,81 @@ def test_serve_mix_matches_oracle_and_alone():
         xa, repa, _ = _run([reqs[i]], 64 << 20)
         assert np.array_equal(xa[0], xs[i])
         assert [e["iters"] for e in repa[0]] == [e["iters"] for e in reps[i]]
+
+
+def test_serve_mix_at_the_largest_volumes():
+    """Grouped launches with many tiles per request (14^4 and 16^3 x 32 at 12
+    right-hand sides) give oracle-accepted results that are bitwise the same
+    alone and in the mix."""
+    reqs = _big_requests()
+    say("serve big mix", [r["dims"] for r in reqs])
+    xs, reps, st = _run(reqs, 3 << 30, chunk=25)
+    assert st["completed"] == len(reqs)
+    for r, x, rep in zip(reqs, xs, reps):
+        assert all(e["status"] == 0 for e in rep), (r["dims"], rep)
+        res = oracle.true_residual(r["U"], r["src"], x, r["dims"], r["m0"])
+        assert np.all(res <= TOL * 1.0000001), (r["dims"], res)
+        for e, o in zip(rep, res):
+            assert abs(e["true_rel_res"] - o) <= 1e-3 * TOL + 1e-6 * o
+    for i in (0, 1):
+        say("serve big alone", reqs[i]["dims"])
+        xa, repa, _ = _run([reqs[i]], 2 << 30, chunk=25)
+        assert np.array_equal(xa[0], xs[i]), reqs[i]["dims"]
+        assert [e["iters"] for e in repa[0]] == [e["iters"] for e in reps[i]]
+
+
+def test_serve_largest_accepted_request_completes():
+    """A request whose footprint equals the arena's capacity is accepted and
+    completes; one slightly larger is refused at submission (it could never be
+    admitted)."""
+    import torch
+    small = dict(dims=(4, 4, 4, 4), nrhs=1, m0=0.1)
+    large = dict(dims=(4, 4, 4, 4), nrhs=2, m0=0.1)
+    U = wdgen.gauge_field(small["dims"], 0.3, 12_001)
+    dU = dev(U)
+    p = wd.cg_default_params(inner=wd.F32)
+    fps = []
+    for r in (small, large):
+        req = wd.Request()
+        req.dims[:] = list(r["dims"])
+        req.t_sign, req.nrhs, req.m0 = -1, r["nrhs"], r["m0"]
+        req.gauge_dev = req.src_dev = 1
+        req.sol_dev = 2
+        req.params = p
+        fps.append(wd.Server.footprint(req))
+    # the bytes the server keeps for itself, from a probe server's capacity
+    probe_arena = torch.empty(1 << 22, dtype=torch.uint8, device="cuda")
+    probe = wd.Server(probe_arena, max_slots=4)
+    own = probe_arena.numel() - probe.stats()["arena_capacity"]
+    probe.close()
+    assert own > 0
+    for arena_bytes, accept in ((own + fps[0], (True, False)), (own + fps[1] - 256, (True, False)),
+                                (own + fps[1], (True, True))):
+        say("serve capacity", arena_bytes, accept)
+        arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+        srv = wd.Server(arena, max_slots=4)
+        assert srv.stats()["arena_capacity"] == arena_bytes - own
+        for r, ok in zip((small, large), accept):
+            src = wdgen.gaussian_source(r["dims"], r["nrhs"], 62_000 + r["nrhs"])
+            dsrc = dev(src)
+            sol = torch.zeros_like(dsrc)
+            req = wd.Server.request(r["dims"], r["nrhs"], r["m0"], dU, dsrc, sol, p)
+            if not ok:
+                with pytest.raises(wd.WDError) as e:
+                    srv.submit(req)
+                assert e.value.code == wd.WD_ETOOBIG
+                continue
+            t = srv.submit(req, keep=(dsrc, sol))
+            t0 = time.time()
+            rep = None
+            while rep is None:
+                rep = srv.poll(t)
+                assert time.time() - t0 < 60, "an accepted request was never completed"
+                time.sleep(0.002)
+            assert all(e["status"] == 0 for e in rep), rep
+            res = oracle.true_residual(U, src, host(sol), r["dims"], r["m0"])
+            assert np.all(res <= TOL * 1.0000001)
+        srv.close()
 
 
 def test_serve_admission_respects_arena():
