@@ -390,17 +390,33 @@ def main():
         i_g = cfg["n_point"]   # first Gaussian source
         iters_needed = reps64[i_g]["iters"]
         n_it = min(args.cpu_iters, iters_needed)
-        log(f"cpu oracle: {n_it} CG iterations on one 14^4 field")
-        t0 = time.perf_counter()
-        oracle.cg(U, src[i_g:i_g + 1], dims, m0, tol=1e-300, max_iter=n_it)
-        t_cpu = time.perf_counter() - t0
-        per_iter = t_cpu / n_it
-        cpu = {"value": 1.0 / (per_iter * iters_needed), "unit": "solves/s", "cores": 1,
+        threads_all = oracle.set_threads(0)   # OMP_NUM_THREADS, else every host core
+        runs = {}
+        for nt in sorted({1, threads_all}):
+            oracle.set_threads(nt)
+            log(f"cpu oracle: {n_it} CG iterations on one 14^4 field, {nt} thread(s)")
+            t0 = time.perf_counter()
+            oracle.cg(U, src[i_g:i_g + 1], dims, m0, tol=1e-300, max_iter=n_it)
+            t_cpu = time.perf_counter() - t0
+            runs[nt] = {"solves_per_s": 1.0 / (t_cpu / n_it * iters_needed), "seconds": t_cpu}
+        oracle.set_threads(threads_all)
+        model = "unknown"
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        cpu = {"value": runs[threads_all]["solves_per_s"], "unit": "solves/s", "cores": threads_all,
                "kind": "oracle",
-               "sample": f"FP64 C oracle CG (single thread) on 1 Gaussian field of this 14^4 "
-                         f"workload: {n_it} iterations timed ({t_cpu:.1f} s), scaled to the "
-                         f"{iters_needed} iterations the FP64 solve needs",
-               "seconds": t_cpu}
+               "sample": f"FP64 C oracle CG on 1 Gaussian field of this 14^4 workload: {n_it} iterations "
+                         f"timed ({runs[threads_all]['seconds']:.1f} s on {threads_all} threads; the "
+                         f"operator's site loop is OpenMP-parallel, dot products sequential), scaled to "
+                         f"the {iters_needed} iterations the FP64 solve needs",
+               "seconds": runs[threads_all]["seconds"],
+               "one_thread_solves_per_s": runs[1]["solves_per_s"], "one_thread_seconds": runs[1]["seconds"],
+               "cpu_model": model, "host_cpus_visible": os.cpu_count()}
 
     out = {
         "metric": METRIC,

@@ -34,13 +34,33 @@
  *  paper (Sec. 2), which sums duplicate entries.
  *
  * Sums are sequential in site order, FP64, no fused-multiply-add assumptions.
+ * The operator's loop over sites may run on several host threads (OpenMP):
+ * every site is computed by the same statements whichever thread runs it, so
+ * the result does not depend on the thread count.  Dot products and norms stay
+ * sequential.
  */
 #include <complex.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
+
+/* Host threads for the operator's site loop (n <= 0 leaves the setting);
+ * returns the count now in force (1 without OpenMP). */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* gamma_mu[alpha][beta], DeGrand-Rossi basis */
 static cplx G[4][4][4];
@@ -94,6 +114,7 @@ void oracle_dirac(const cplx *U, const int L[4], int t_sign, double m0,
                 Pb[mu][a][b] = id + sgn * G[mu][a][b];
             }
 
+#pragma omp parallel for schedule(static)
     for (long s = 0; s < V; ++s) {
         int c[4];
         long rem = s;
