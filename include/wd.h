@@ -66,7 +66,7 @@ enum {
     WD_ENOMEM = -4,      /* workspace too small or device allocation failed         */
     WD_ENOTCONV = -5,    /* max_iter reached before the true residual met tol       */
     WD_EBREAKDOWN = -6,  /* NaN/Inf or <q,q> <= 0 inside CG                         */
-    WD_ETOOBIG = -7,     /* request larger than the server arena                    */
+    WD_ETOOBIG = -7,     /* request larger than the server arena or static scratch  */
     WD_ENOTFOUND = -8    /* unknown server ticket                                   */
 };
 
@@ -136,6 +136,21 @@ int wd_dslash(const wd_gauge *g, double m0, int32_t prec, const void *in_dev, vo
               int32_t nrhs, uint32_t flags, void *stream);
 int wd_dslash_dag(const wd_gauge *g, double m0, int32_t prec, const void *in_dev,
                   void *out_dev, int32_t nrhs, uint32_t flags, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): wd_dslash (dagger = 0)
+ * or wd_dslash_dag (dagger = 1) on canonical complex128 in/out, with the packed
+ * temporaries kept in a static device array of WD_NOALLOC_SCRATCH_BYTES that
+ * the library holds on every device it runs on until the process ends, instead
+ * of buffers allocated per call.  The call allocates nothing.  Both packed
+ * fields (each rounded up to 256 bytes) must fit the array: 2 * nrhs * V *
+ * (192 | 96 | 52) bytes for FP64 | FP32 | FP16N, else WD_ETOOBIG.  Every call on
+ * one device shares that device's array, so calls that overlap on one device
+ * (other streams, other threads) race; calls ordered on one stream do not.
+ * dagger other than 0/1 is WD_EINVAL.  Asynchronous on `stream`. */
+#define WD_NOALLOC_SCRATCH_BYTES (64u << 20)
+int wd_dslash_noalloc(const wd_gauge *g, double m0, int32_t prec, int32_t dagger,
+                      const void *in_dev, void *out_dev, int32_t nrhs, void *stream);
 
 /* ------------------------------------------- coordinate-format operator */
 /* The operator stored explicitly as in Sec. 2 of the paper: arrays Val, Row,

@@ -35,7 +35,7 @@ EXPORTS = [
     "wd_version", "wd_strerror", "wd_last_error_detail", "wd_device_info",
     "wd_gauge_create", "wd_gauge_destroy", "wd_gauge_info",
     "wd_spinor_bytes", "wd_pack_spinor", "wd_unpack_spinor",
-    "wd_dslash", "wd_dslash_dag",
+    "wd_dslash", "wd_dslash_dag", "wd_dslash_noalloc",
     "wd_coo_create", "wd_coo_destroy", "wd_coo_info", "wd_coo_export", "wd_coo_spmv",
     "wd_cg_default_params", "wd_cg_workspace_bytes", "wd_cg_solve", "wd_cg_solve_batch",
     "wd_tune_dslash", "wd_tune_lookup", "wd_tune_cg", "wd_shape_set", "wd_shape_get",
@@ -131,6 +131,7 @@ def lib():
             "wd_unpack_spinor": ([P, I32, P, P, I32, P], ctypes.c_int),
             "wd_dslash": ([P, D, I32, P, P, I32, U32, P], ctypes.c_int),
             "wd_dslash_dag": ([P, D, I32, P, P, I32, U32, P], ctypes.c_int),
+            "wd_dslash_noalloc": ([P, D, I32, I32, P, P, I32, P], ctypes.c_int),
             "wd_coo_create": ([P, D, I32, I32, P, ctypes.POINTER(P)], ctypes.c_int),
             "wd_coo_destroy": ([P], ctypes.c_int),
             "wd_coo_info": ([P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -293,6 +294,21 @@ def dslash(g: Gauge, m0: float, psi, prec: int = F64, dagger: bool = False,
     fn = lib().wd_dslash_dag if dagger else lib().wd_dslash
     _check(fn(g.handle, float(m0), prec, _ptr(psi), _ptr(out), nrhs,
               PACKED if packed else 0, _stream()), "wd_dslash_dag" if dagger else "wd_dslash")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # WD_NOALLOC_SCRATCH_BYTES
+
+
+def dslash_noalloc(g: Gauge, m0: float, psi, prec: int = F64, dagger: bool = False, out=None):
+    """wd_dslash_noalloc: out = D psi (or D^dagger psi) on canonical complex128
+    fields, the packed temporaries held in the library's static device scratch."""
+    torch = _torch()
+    _require_cuda(psi, torch.complex128, "psi")
+    nrhs = psi.numel() // (g.sites * 12)
+    out = torch.empty_like(psi) if out is None else out
+    _check(lib().wd_dslash_noalloc(g.handle, float(m0), prec, 1 if dagger else 0, _ptr(psi),
+                                   _ptr(out), nrhs, _stream()), "wd_dslash_noalloc")
     return out
 
 

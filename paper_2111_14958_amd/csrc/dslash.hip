@@ -8,6 +8,7 @@
 // optionally remapped so each XCD works through one contiguous range of them.
 // `order` = strip width | group-major << 16.
 #include <algorithm>
+#include <mutex>
 
 #include "wd_device.h"
 #include "wd_host.h"
@@ -246,8 +247,36 @@ int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void 
     return WD_OK;
 }
 
+// Device memory of wd_dslash_noalloc: the packed input and output of one call.
+// Host code never passes the name itself to a kernel (on the host it is a
+// stand-in, not a device address); it uses the address hipGetSymbolAddress
+// returns for the current device, taken once per device.
+static __device__ __align__(256) unsigned char scratch[WD_NOALLOC_SCRATCH_BYTES];
+
+static int scratch_ptr(unsigned char **out) {
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static unsigned char *ptr[MAX_DEVICES];
+    int dev = 0;
+    WD_HIP(hipGetDevice(&dev));
+    WD_CHECK(dev >= 0 && dev < MAX_DEVICES, WD_ENODEV, "device ordinal %d beyond %d", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(WD_EHIP, "hipGetSymbolAddress of the static scratch on device %d: %s", dev,
+                        hipGetErrorString(e));
+        ptr[dev] = (unsigned char *)p;
+    }
+    *out = ptr[dev];
+    return WD_OK;
+}
+
+// scratch_a/scratch_b: where the canonical path keeps the packed in/out; null =
+// allocate them on the stream
 static int dslash_entry(const wd_gauge *g, double m0, int32_t prec, const void *in, void *out,
-                        int32_t nrhs, uint32_t flags, void *stream, bool dag) {
+                        int32_t nrhs, uint32_t flags, void *stream, bool dag, bool noalloc = false) {
     clear_error();
     WD_CHECK(g && in && out, WD_EINVAL, "null argument");
     WD_CHECK(prec >= 0 && prec <= 2, WD_EINVAL, "unknown precision %d", prec);
@@ -265,6 +294,20 @@ static int dslash_entry(const wd_gauge *g, double m0, int32_t prec, const void *
 
     // canonical complex128 in/out: pack, apply, unpack through temporaries
     const size_t nb = spinor_bytes(prec, g->V, nrhs);
+    if (noalloc) {
+        // the two packed buffers, each at a 256-byte boundary, in the static scratch
+        const size_t nba = (nb + 255) & ~(size_t)255;
+        WD_CHECK(2 * nba <= (size_t)WD_NOALLOC_SCRATCH_BYTES, WD_ETOOBIG,
+                 "%d fields of %lld sites in precision %d need %zu bytes of scratch, the static scratch holds %zu",
+                 nrhs, (long long)g->V, prec, 2 * nba, (size_t)WD_NOALLOC_SCRATCH_BYTES);
+        unsigned char *sp = nullptr;
+        rc = scratch_ptr(&sp);
+        if (rc) return rc;
+        rc = launch_pack_spinor(prec, in, sp, (int)g->V, nrhs, st);
+        if (!rc) rc = launch_dslash(g, m0, prec, dag, sp, sp + nba, nrhs, sh, st);
+        if (!rc) rc = launch_unpack_spinor(prec, sp + nba, out, (int)g->V, nrhs, st);
+        return rc;
+    }
     void *a = nullptr, *b = nullptr;
     WD_HIP(hipMallocAsync(&a, nb, st));
     hipError_t e = hipMallocAsync(&b, nb, st);
@@ -290,5 +333,13 @@ int wd_dslash(const wd_gauge *g, double m0, int32_t prec, const void *in_dev, vo
 int wd_dslash_dag(const wd_gauge *g, double m0, int32_t prec, const void *in_dev, void *out_dev,
                   int32_t nrhs, uint32_t flags, void *stream) {
     return wd::dslash_entry(g, m0, prec, in_dev, out_dev, nrhs, flags, stream, true);
+}
+int wd_dslash_noalloc(const wd_gauge *g, double m0, int32_t prec, int32_t dagger, const void *in_dev,
+                      void *out_dev, int32_t nrhs, void *stream) {
+    if (dagger != 0 && dagger != 1) {
+        wd::clear_error();
+        return wd::fail(WD_EINVAL, "dagger must be 0 or 1, not %d", dagger);
+    }
+    return wd::dslash_entry(g, m0, prec, in_dev, out_dev, nrhs, 0u, stream, dagger == 1, true);
 }
 }

@@ -198,7 +198,7 @@ const char *wd_strerror(int code) {
     case WD_ENOMEM: return "out of memory / workspace too small";
     case WD_ENOTCONV: return "not converged within max_iter";
     case WD_EBREAKDOWN: return "CG breakdown (NaN/Inf or non-positive curvature)";
-    case WD_ETOOBIG: return "request larger than the server arena";
+    case WD_ETOOBIG: return "request larger than the server arena or the static scratch";
     case WD_ENOTFOUND: return "unknown ticket";
     }
     return "unknown error";
