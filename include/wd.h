@@ -260,7 +260,10 @@ typedef struct {
     int32_t rhs_per_thread;
     int32_t xcd_remap;    /* 1: tiles mapped to XCDs in contiguous ranges        */
     int32_t hop_order;    /* 1: hops one at a time, 2: a direction's two hops together,
-                             0: compiler order                                    */
+                             3: two hops in flight, 4: 3 with the own spinor loaded
+                             first, 5: 3 with the hops that read memory (z, t) before
+                             the ones that read LDS (x, y; plane blocks, one rhs per
+                             thread), 0: compiler order                           */
     int32_t rhs_loop;     /* rhs groups one block handles one after the other    */
     int32_t site_order;   /* strip | group_major << 16 | xy_lds << 17 | occ << 18
                              | z_march << 24 | rhs_pass << 25.
@@ -285,7 +288,9 @@ typedef struct {
 
 /* Time every candidate launch shape of the operator for (g, prec, nrhs, dagger)
  * on scratch data, reject candidates whose output differs from the reference
- * shape, and store the fastest in the in-process table (and in the cache file
+ * shape's by more than rounding (shapes that sum the hops in another order round
+ * differently: per component FP64 1e-12, FP32 2e-5 of the largest component,
+ * FP16N two half ulps of the site norm), and store the fastest in the in-process table (and in the cache file
  * named by WD_TUNE_CACHE, if set).  Later calls with the same key use it.
  * Synchronises `stream`. */
 int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger,
@@ -298,7 +303,8 @@ int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
  * whole CG (Fig. 1): one launch shape for phases A and B (families
  * WD_FAMILY_CG_A and WD_FAMILY_CG_B) of g's lattice, inner precision `inner`
  * and nrhs fields.  Every candidate (plane or site blocks, 1 or 2 rhs per
- * thread, hop order 1 or 3, z-strips of 0/2/4/7 planes) runs `iters` (1..1000)
+ * thread, hop order 1, 3 or 5 (5: plane blocks, one rhs per thread), z-strips of
+ * 0/2/4/7 planes) runs `iters` (1..1000)
  * CG iterations from the nrhs canonical fields src_dev (as wd_cg_solve_batch
  * takes them) with the mass m0; the median of three runs is kept; a candidate
  * whose iterate differs from the first candidate's by more than 1e-3 relative
@@ -317,8 +323,11 @@ int wd_tune_cg(const wd_gauge *g, double m0, int32_t inner, const void *src_dev,
 /* Set the launch shape of one kernel family for (g's lattice, prec, nrhs,
  * dagger) by hand -- e.g. to sweep the block size of the whole CG as the paper
  * does for its workgroup size (Sec. 3.1, Fig. 1).  block in {64,128,256},
- * rhs_per_thread in {1,2,4}, hop_order 0..4, rhs_loop >= 1, site_order as in
- * wd_tune_result. */
+ * rhs_per_thread in {1,2,4}, hop_order 0..5 (CG phases: 1, 3 or 5), rhs_loop >= 1,
+ * site_order as in wd_tune_result; z_march = 1 for the operator kernel (FP32 and
+ * FP16N storage): a block walks a column of xy-planes along z, strip is then the
+ * (even) number of z-chunks, alternate chunks walk downward, and group_major
+ * selects the tile order (0: chunk, rhs, t; 1: rhs, t, chunk). */
 int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, int32_t family,
                  const wd_tune_result *shape);
 /* The launch shape a kernel family uses for the key (set, tuned or default);

@@ -339,14 +339,37 @@ static void launch_AB_o(int nr, int xy, int lds, int r12, int nt, int grid, int 
         else WD_TIMED_LAUNCH((k_phaseA<P, 4, ORD, false>), gr, bl, st, d, n, remap);
     }
 }
+// hop order 5 (the memory hops z and t first, then the LDS hops x and y):
+// plane-blocked variants with one rhs per thread
+template <int P, bool B>
+static void launch_AB_o5(int r12, int nt, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    const dim3 gr(grid), bl(blk);
+    if (r12) {
+        if constexpr (P == P32) {
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, 5, true, true>), gr, bl, st, d, n, remap);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 1, 5, true, true>), gr, bl, st, d, n, remap);
+        }
+    } else if (nt) {
+        if constexpr (P == P64) {
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, 5, true, false, true>), gr, bl, st, d, n, remap);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 1, 5, true, false, true>), gr, bl, st, d, n, remap);
+        }
+    } else {
+        if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, 5, true>), gr, bl, st, d, n, remap);
+        else WD_TIMED_LAUNCH((k_phaseA<P, 1, 5, true>), gr, bl, st, d, n, remap);
+    }
+}
+
 template <int P>
 static void launch_A(const KindShape &k, hipStream_t st, const Prob *d, int n) {
-    if (k.ordered == 3) launch_AB_o<P, 3, false>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
+    if (k.ordered == 5) launch_AB_o5<P, false>(k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
+    else if (k.ordered == 3) launch_AB_o<P, 3, false>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
     else launch_AB_o<P, 1, false>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
 }
 template <int P>
 static void launch_B(const KindShape &k, hipStream_t st, const Prob *d, int n) {
-    if (k.ordered == 3) launch_AB_o<P, 3, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
+    if (k.ordered == 5) launch_AB_o5<P, true>(k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
+    else if (k.ordered == 3) launch_AB_o<P, 3, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
     else launch_AB_o<P, 1, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
 }
 template <int P>
@@ -550,7 +573,7 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.block = st[k]->block;
             ks.nr = st[k]->nr;
             ks.remap = st[k]->remap;
-            ks.ordered = (k == KA || k == KB) && st[k]->ordered == 3 ? 3 : 1;
+            ks.ordered = (k == KA || k == KB) && (st[k]->ordered == 3 || st[k]->ordered == 5) ? st[k]->ordered : 1;
             const int strip = (st[k]->strip > 0 && st[k]->strip < g->dims[2]) ? st[k]->strip : 0;
             ks.order = strip | (st[k]->gmajor ? 1 << 16 : 0) | (st[k]->fpass << 24);
             // plane-blocked phases A and B: one xy-plane of 64..256 sites per
@@ -589,6 +612,8 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
                 ks.r12 = 1;
                 if (ks.nr > 2) ks.nr = 2;
             }
+            // hop order 5 exists for plane blocks with one rhs per thread
+            if (ks.ordered == 5 && !(ks.xy == 1 && ks.nr == 1)) ks.ordered = 3;
         } else {
             ks.block = 256;
             ks.nr = 1;
@@ -1118,9 +1143,10 @@ int wd_tune_cg(const wd_gauge *g, double m0, int32_t inner, const void *src, int
         if (xy && (np < 64 || np > 256)) continue;
         for (int nr = 1; nr <= 2; ++nr) {
             if (xy && nr == 2 && inner == WD_F64) continue;
-            for (int ord : {3, 1})
+            for (int ord : {5, 3, 1})
                 for (int strip : {4, 0, 2, 7}) {
                     if (strip >= Lz) continue;
+                    if (ord == 5 && !(xy && nr == 1)) continue;   // memory hops first: plane blocks
                     Shape s = default_shape(inner, nrhs, FAM_CG_B);
                     s.block = 256;
                     s.nr = nr;
@@ -1183,8 +1209,8 @@ int wd_tune_cg(const wd_gauge *g, double m0, int32_t inner, const void *src, int
         shape_store(kb, keep_b);
         return rc ? rc : fail(WD_EHIP, "no CG launch shape could be timed");
     }
-    shape_store(ka, bests);
-    shape_store(kb, bests);
+    shape_store_persist(ka, bests, best_ms * 1e3);
+    shape_store_persist(kb, bests, best_ms * 1e3);
     memset(best, 0, sizeof(*best));
     best->block = bests.block;
     best->rhs_per_thread = bests.nr;

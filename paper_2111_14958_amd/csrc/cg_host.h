@@ -10,7 +10,7 @@ namespace wd {
 
 struct KindShape {
     int block = 256, nr = 1, remap = 0, grid = 0;
-    int ordered = 1;   // hop order of phases A and B: 1 or 3 (pipelined)
+    int ordered = 1;   // hop order of phases A and B: 1, 3 (pipelined) or 5 (pipelined, memory hops first)
     int order = 0;     // stencil kinds: processing order, strip | group-major << 16 | plane-blocked << 17
     int xy = 0;        // phases A and B: 1 plane-blocked variant (x/y neighbours from LDS),
                        // 2 z-marching columns of planes (zm_tile)

@@ -124,6 +124,95 @@ __global__ __launch_bounds__(256) void k_dslash_xy(Geom g, double diag, const vo
     }
 }
 
+// z-marching variant: a block walks a column of xy-planes along z (one rhs,
+// one t, the planes of z-chunk c), so every spinor is read from memory about
+// once by its own block instead of once per neighbouring plane.  Per plane:
+// the next plane's own spinors are loaded first (they are the z neighbours on
+// that side), one barrier, x and y neighbours from LDS (two plane buffers),
+// t neighbours from memory, the z hop from the other side carried in registers
+// (march_hopping).  Even chunks walk upward, odd chunks downward (nchunk is
+// even), so the two blocks meeting at a chunk boundary load the planes there
+// at the same time, both at the start or both at the end of their walks.
+// Tile order 0: chunk-major, then rhs, then t (an XCD's contiguous range of
+// tiles holds whole t-rings of a few rhs of one chunk); 1: rhs-major, then t,
+// then chunk (whole t-rings and both chunks of fewer rhs).  With those on one
+// XCD and walking in step, the t neighbours and the boundary planes a block
+// reads were loaded by another block of that XCD moments before.
+// blockDim.x = Lx Ly.
+template <int P, bool DAG, bool DOWN, bool R12, int ORD>
+__device__ __forceinline__ void zm_walk(const Geom &g, double diag, const void *U, const FieldPtr &in,
+                                        const FieldPtr &out, int rhs, int tt, int z0, int z1,
+                                        typename LdsSpinor<P>::word *buf0, typename LdsSpinor<P>::word *buf1) {
+    typedef typename real_of<P>::type R;
+    const int np = g.S[2], Lz = g.L[2];
+    const int i = threadIdx.x;
+    const int tb = np * Lz * tt + i;   // this thread's site on plane 0 of the t-slice
+    const int zf = DOWN ? z1 - 1 : z0;
+    cx<R> self[12], carry[12];
+    {   // the z hop into the first plane from the plane on the far side
+        const int zb = DOWN ? (zf + 1 == Lz ? 0 : zf + 1) : (zf == 0 ? Lz - 1 : zf - 1);
+        const int sb = tb + np * zb;
+        cx<R> u[9], v[12], h[6], w[6];
+        Link<P>::template load<R12>(U, g, 2, DOWN ? tb + np * zf : sb, false, u);
+        Spinor<P>::load(in, rhs, sb, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) carry[k] = {R(0), R(0)};
+        constexpr int SF = DAG ? +1 : -1;
+        if constexpr (DOWN) {
+            project<2, SF>(v, h);
+            link_mul(u, h, w);
+            accumulate<2, SF>(w, carry);
+        } else {
+            project<2, -SF>(v, h);
+            link_adj_mul(u, h, w);
+            accumulate<2, -SF>(w, carry);
+        }
+        Spinor<P>::load(in, rhs, tb + np * zf, self);
+        LdsSpinor<P>::put(buf0, np, 0, i, self);
+    }
+    const int nz = z1 - z0;
+    for (int k = 0; k < nz; ++k) {
+        const int z = DOWN ? zf - k : zf + k;
+        const int zn = DOWN ? (z == 0 ? Lz - 1 : z - 1) : (z + 1 == Lz ? 0 : z + 1);
+        const int s = tb + np * z, sn = tb + np * zn;
+        typename LdsSpinor<P>::word *cur = (k & 1) ? buf1 : buf0;
+        cx<R> nxt[12], acc[12], o[12];
+        Spinor<P>::load(in, rhs, sn, nxt);
+        __syncthreads();   // plane z is complete in its buffer
+        march_hopping<P, DAG, DOWN, R12, ORD>(g, s, sn, U, in, rhs, cur, s - i, np, nxt, carry, acc);
+        LdsSpinor<P>::get(cur, np, 0, i, self);
+        wilson_finish<R>((R)diag, self, acc, o);
+        Spinor<P>::store(out, rhs, s, o);
+        // the other buffer was last read before this step's barrier
+        if (k + 1 < nz) LdsSpinor<P>::put((k & 1) ? buf0 : buf1, np, 0, i, nxt);
+    }
+}
+
+template <int P, bool DAG, bool R12 = false, int ORD = 3>
+__global__ __launch_bounds__(256) void k_dslash_zm(Geom g, double diag, const void *__restrict__ U, FieldPtr in,
+                                                   FieldPtr out, int nchunk, int remap, int order) {
+    typedef typename LdsSpinor<P>::word W;
+    extern __shared__ uint4 lds_raw[];
+    const int np = g.S[2], Lz = g.L[2], Lt = g.L[3];
+    W *buf0 = (W *)lds_raw, *buf1 = buf0 + (LdsSpinor<P>::BYTES / 16) * np;
+    const int b = remap ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    int rhs, tt, c;
+    if (order == 0) {
+        tt = b % Lt;
+        const int q = b / Lt;
+        rhs = q % in.nrhs;
+        c = q / in.nrhs;
+    } else {
+        c = b % nchunk;
+        const int q = b / nchunk;
+        tt = q % Lt;
+        rhs = q / Lt;
+    }
+    const int z0 = (c * Lz) / nchunk, z1 = ((c + 1) * Lz) / nchunk;
+    if (c & 1) zm_walk<P, DAG, true, R12, ORD>(g, diag, U, in, out, rhs, tt, z0, z1, buf0, buf1);
+    else zm_walk<P, DAG, false, R12, ORD>(g, diag, U, in, out, rhs, tt, z0, z1, buf0, buf1);
+}
+
 // LDS bytes of the plane-blocked variant
 static size_t xy_lds_bytes(int prec, int nr, int np) {
     return (size_t)nr * (prec == WD_F64 ? 192 : 96) * np;
@@ -134,10 +223,11 @@ static void launch_xy(int nr, int ord, dim3 grid, int np, size_t lds, hipStream_
                       const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int od) {
     const dim3 block(np);
     if (nr == 1) {
-        if (ord == 3) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 3, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+        if (ord == 5) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 5, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+        else if (ord == 3) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 3, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
         else hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 1, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
-    } else {
-        if (ord == 3) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 2, 3, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+    } else {   // hop order 5 exists for one rhs per thread: 3 here
+        if (ord == 3 || ord == 5) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 2, 3, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
         else hipLaunchKernelGGL((k_dslash_xy<P, DAG, 2, 1, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
     }
 }
@@ -165,7 +255,8 @@ static void launch_nr(int nr, int ordered, int rl, dim3 grid, dim3 block, hipStr
                       const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int od) {
     if (ordered == 1) launch_nr_o<P, DAG, 1, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
     else if (ordered == 2) launch_nr_o<P, DAG, 2, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
-    else if (ordered == 3) launch_nr_o<P, DAG, 3, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
+    else if (ordered == 3 || ordered == 5)   // site blocks read every neighbour from memory: 5 is 3
+        launch_nr_o<P, DAG, 3, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
     else if (ordered == 4) launch_nr_o<P, DAG, 4, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
     else launch_nr_o<P, DAG, 0, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
 }
@@ -195,6 +286,32 @@ int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void 
     const int np = g.L[0] * g.L[1];
     // FP32 with a reconstruct-12 copy: every shape reads the two-row links
     const bool r12 = prec == WD_F32 && gg->U12[WD_F32] != nullptr;
+    if (sh.xylds == 2 && np <= 256 && prec != WD_F64 && g.L[2] >= 2) {
+        // z-marching columns: nchunk (even, at most Lz) chunks per column
+        int nch = sh.strip >= 2 ? sh.strip & ~1 : 2;
+        if (nch > g.L[2]) nch = g.L[2] & ~1;
+        const size_t lds = 2 * (size_t)(prec == WD_F64 ? 192 : 96) * np;
+        FieldPtr fi{(void *)in, g.V, nrhs}, fo{out, g.V, nrhs};
+        const void *U = r12 ? gg->U12[WD_F32] : gg->U[prec];
+        const dim3 grid(nch * g.L[3] * nrhs), block(np);
+        const int ord = sh.gmajor;
+        const double diag = 4.0 + m0;
+        switch (prec * 2 + (dag ? 1 : 0)) {
+        case 2:
+            if (r12) hipLaunchKernelGGL((k_dslash_zm<P32, false, true>), grid, block, lds, st, g, diag, U, fi, fo, nch, sh.remap, ord);
+            else hipLaunchKernelGGL((k_dslash_zm<P32, false>), grid, block, lds, st, g, diag, U, fi, fo, nch, sh.remap, ord);
+            break;
+        case 3:
+            if (r12) hipLaunchKernelGGL((k_dslash_zm<P32, true, true>), grid, block, lds, st, g, diag, U, fi, fo, nch, sh.remap, ord);
+            else hipLaunchKernelGGL((k_dslash_zm<P32, true>), grid, block, lds, st, g, diag, U, fi, fo, nch, sh.remap, ord);
+            break;
+        case 4: hipLaunchKernelGGL((k_dslash_zm<P16, false>), grid, block, lds, st, g, diag, U, fi, fo, nch, sh.remap, ord); break;
+        case 5: hipLaunchKernelGGL((k_dslash_zm<P16, true>), grid, block, lds, st, g, diag, U, fi, fo, nch, sh.remap, ord); break;
+        default: return fail(WD_EINVAL, "unknown precision %d", prec);
+        }
+        WD_HIP(hipGetLastError());
+        return WD_OK;
+    }
     if (sh.xylds && np <= 256) {   // else the site-blocked kernel below
         const int nrx = prec == WD_F64 ? 1 : std::min(nr, 2);
         const int ngx = (nrhs + nrx - 1) / nrx;
@@ -205,7 +322,7 @@ int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void 
         FieldPtr fi{(void *)in, g.V, nrhs}, fo{out, g.V, nrhs};
         const void *U = r12 ? gg->U12[WD_F32] : gg->U[prec];
         const dim3 grid((g.V / np) * ngx);
-        const int ord = sh.ordered == 3 ? 3 : 1;
+        const int ord = sh.ordered == 3 || sh.ordered == 5 ? sh.ordered : 1;
         switch (prec * 2 + (dag ? 1 : 0)) {
         case 0: launch_xy<P64, false>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
         case 1: launch_xy<P64, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;

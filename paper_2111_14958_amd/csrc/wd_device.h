@@ -500,6 +500,10 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
         if constexpr (ORDERED == 2 && FWD) after_acc(nbi[H], lsi[H]);
         if constexpr (ORDERED == 2 && FWD) after_acc(nbi[H + 1], lsi[H + 1]);
         if constexpr ((ORDERED == 3 || ORDERED == 4) && H + 1 < 8) after_acc(nbi[H + 1], lsi[H + 1]);
+        // ORDERED 5: as 3 in the sequence z+ z- t+ t- x+ x- y+ y- (the hops that
+        // read memory first, close in time to the neighbouring blocks' loads of
+        // their own planes; the LDS hops last)
+        if constexpr (ORDERED == 5 && H != 3) after_acc(nbi[H == 7 ? 0 : H + 1], lsi[H == 7 ? 0 : H + 1]);
         if constexpr (ORDERED == 4 && H == 0) after_first(nbi[0]);
         if constexpr (ZM && MU == 2 && !FWD) return;   // carried in from the previous plane
         const int nb = nbi[H];
@@ -528,14 +532,116 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
             }
         }
     };
+    if constexpr (ORDERED == 5) {
+        hop(IntC<4>{});
+        hop(IntC<5>{});
+        hop(IntC<6>{});
+        hop(IntC<7>{});
+        hop(IntC<0>{});
+        hop(IntC<1>{});
+        hop(IntC<2>{});
+        hop(IntC<3>{});
+    } else {
+        hop(IntC<0>{});
+        hop(IntC<1>{});
+        hop(IntC<2>{});
+        hop(IntC<3>{});
+        hop(IntC<4>{});
+        hop(IntC<5>{});
+        hop(IntC<6>{});
+        hop(IntC<7>{});
+    }
+}
+
+// Hopping sum of Eq. (1) at site s for a block that walks a column of
+// xy-planes along z (one rhs, one t).  The block's LDS holds plane z (`xy`,
+// first site plane0, np sites: the x and y neighbours); the thread holds its
+// own spinor (read back from `xy`) and `nxt`, its site's spinor on the next plane of the walk
+// (z + 1 upward, z - 1 downward), which is its z neighbour on that side; the
+// z hop from the other side arrives in `carry`, formed on the previous plane.
+// sn is the site of nxt.  The t neighbours come from memory.
+//   upward:   acc = carry + ... + (1 + SF g_z) U_z(s) nxt,
+//             carry <- (1 + SB g_z) U_z(s)^dag self   (the backward hop of sn)
+//   downward: acc = carry + ... + (1 + SB g_z) U_z(sn)^dag nxt,
+//             carry <- (1 + SF g_z) U_z(sn) self      (the forward hop of sn)
+// Both use the one link between the two planes.  Loads are issued hop by hop,
+// one (ORD 1) or two (ORD 3) hops in flight, as in hopping().
+template <int P, bool DAG, bool DOWN, bool R12 = false, int ORD = 3>
+__device__ __forceinline__ void march_hopping(const Geom &g, int s, int sn, const void *U, const FieldPtr &in,
+                                              int rhs, const typename LdsSpinor<P>::word *xy, int plane0, int np,
+                                              const cx<typename real_of<P>::type> nxt[12],
+                                              cx<typename real_of<P>::type> carry[12],
+                                              cx<typename real_of<P>::type> acc[12]) {
+    typedef typename real_of<P>::type R;
+    constexpr int SF = DAG ? +1 : -1;
+    constexpr int SB = -SF;
+    int c[4];
+    site_coords(g, s, c);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = carry[k];
+    // neighbour and link site of the x, y and t hops: h = 0..5 is x+, x-, y+, y-, t+, t-
+    int nbi[6], lsi[6];
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+        const int mu = h == 2 ? 3 : h;
+        nbi[2 * h] = c[mu] == g.L[mu] - 1 ? s - (g.L[mu] - 1) * g.S[mu] : s + g.S[mu];
+        nbi[2 * h + 1] = c[mu] == 0 ? s + (g.L[mu] - 1) * g.S[mu] : s - g.S[mu];
+        lsi[2 * h] = s;
+        lsi[2 * h + 1] = nbi[2 * h + 1];
+    }
+    int zl = DOWN ? sn : s;   // site of the z link
+    auto after_acc = [&](int &a, int &b) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) asm volatile("" : "+v"(a), "+v"(b) : "v"(acc[k].re), "v"(acc[k].im));
+    };
+    auto hop = [&](auto hc) {
+        constexpr int H = decltype(hc)::value;
+        constexpr int MU = H < 4 ? H / 2 : 3;
+        constexpr bool FWD = (H % 2) == 0;
+        constexpr int S = FWD ? SF : SB;
+        if constexpr (ORD == 1) after_acc(nbi[H], lsi[H]);
+        else if constexpr (H + 1 < 6) after_acc(nbi[H + 1], lsi[H + 1]);
+        else after_acc(zl, zl);
+        cx<R> u[9], p[12], h[6], w[6];
+        Link<P>::template load<R12>(U, g, MU, lsi[H], MU == 3 && c[3] == (FWD ? g.L[3] - 1 : 0), u);
+        if constexpr (MU < 2) LdsSpinor<P>::get(xy, np, 0, nbi[H] - plane0, p);
+        else Spinor<P>::load(in, rhs, nbi[H], p);
+        project<MU, S>(p, h);
+        if constexpr (FWD) link_mul(u, h, w);
+        else link_adj_mul(u, h, w);
+        accumulate<MU, S>(w, acc);
+    };
     hop(IntC<0>{});
     hop(IntC<1>{});
     hop(IntC<2>{});
     hop(IntC<3>{});
     hop(IntC<4>{});
     hop(IntC<5>{});
-    hop(IntC<6>{});
-    hop(IntC<7>{});
+    {   // the z hop towards the next plane, and the carry for it (own spinor from LDS)
+        if constexpr (ORD == 1) after_acc(zl, zl);
+        cx<R> u[9], h[6], w[6], self[12];
+        Link<P>::template load<R12>(U, g, 2, zl, false, u);
+        LdsSpinor<P>::get(xy, np, 0, s - plane0, self);
+        if constexpr (DOWN) {
+            project<2, SB>(nxt, h);
+            link_adj_mul(u, h, w);
+            accumulate<2, SB>(w, acc);
+            project<2, SF>(self, h);
+            link_mul(u, h, w);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) carry[k] = {R(0), R(0)};
+            accumulate<2, SF>(w, carry);
+        } else {
+            project<2, SF>(nxt, h);
+            link_mul(u, h, w);
+            accumulate<2, SF>(w, acc);
+            project<2, SB>(self, h);
+            link_adj_mul(u, h, w);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) carry[k] = {R(0), R(0)};
+            accumulate<2, SB>(w, carry);
+        }
+    }
 }
 
 // Apply D (or D^dagger): o = diag * psi(s) - 1/2 acc, with diag = 4 + m0.

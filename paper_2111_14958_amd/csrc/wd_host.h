@@ -66,6 +66,8 @@ struct ShapeKey {
 };
 Shape shape_lookup(const ShapeKey &k);      // tuned entry or the default
 void shape_store(const ShapeKey &k, const Shape &s);
+// shape_store, and append the entry to the cache file WD_TUNE_CACHE names (if any)
+void shape_store_persist(const ShapeKey &k, const Shape &s, double us);
 Shape default_shape(int prec, int nrhs, int fam = FAM_DSLASH);
 int encode_order(const Shape &s);           // wd_tune_result.site_order of a shape
 

@@ -419,7 +419,7 @@ def test_cg_autotuner(inner):
     g = wd.Gauge(dev(U), dims)
     say("cg autotune", inner)
     best = wd.tune_cg(g, m0, inner, dev(eta), iters=20)
-    assert best["block"] == 256 and best["rhs_per_thread"] in (1, 2) and best["hop_order"] in (1, 3)
+    assert best["block"] == 256 and best["rhs_per_thread"] in (1, 2) and best["hop_order"] in (1, 3, 5)
     assert best["strip"] in (0, 2, 4) and best["us"] > 0
     for fam, dag in ((wd.FAMILY_CG_A, True), (wd.FAMILY_CG_B, False)):
         got = wd.shape_get(g, inner, eta.shape[0], dag, fam)

@@ -176,7 +176,7 @@ def test_packed_mode_matches_canonical():
         assert np.array_equal(host(wd.unpack_spinor(g, pout, prec, 4)), canon)
 
 
-def test_autotuner_keeps_results_identical():
+def test_autotuner_keeps_results_to_rounding():
     dims, m0 = (8, 8, 8, 12), 0.05
     U, psi = field_set(dims, 0.5, 51, 5, 52)
     g = wd.Gauge(dev(U), dims)
@@ -188,7 +188,11 @@ def test_autotuner_keeps_results_identical():
         assert best["us"] > 0 and best["gbps"] > 0
         assert wd.tune_lookup(g, prec, 5) == {**best, "us": 0.0, "gbps": 0.0}
         after = host(wd.dslash(g, m0, dev(psi), prec))
-        assert np.array_equal(before, after)
+        # the tuned shape may sum the hops in another order than the default
+        # (hop order 5 takes the memory hops first): equal to rounding, and
+        # deterministic once chosen
+        assert rel(after, before) <= TOL[prec]
+        assert np.array_equal(after, host(wd.dslash(g, m0, dev(psi), prec)))
 
 
 def test_dslash_argument_errors():
