@@ -13,7 +13,8 @@ Workload (one step = one full batched solve, every step of the hot path):
 Prints ONE JSON line: value = right-hand-side solves per second.  Beside it:
 the plain FP64 CG on the same GPU (the "mixed vs FP64" ratio), the roofline of
 the dominant kernel measured with HIP events (the library's profiling mode),
-the stand-alone operator bandwidth, a device copy ceiling and the CPU oracle.
+the stand-alone operator bandwidth and HBM traffic, the streaming-kernel ceilings,
+the persistent kernel at the same shape and the CPU oracle.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -34,28 +35,31 @@ HBM_PEAK_GBPS = 8000.0
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "k_phaseB_f32_14x4_16rhs_pmc.md")
 # sources that define the phase-B kernel; the counter figures hold only for them
 KERNEL_SOURCES = ("wd_device.h", "cg_core.h", "cg.hip")
+# the stand-alone operator's counter summary and the sources of its kernels
+PMC_DSLASH = os.path.join(ROOT, "profiles", "k_dslash_xy_14x4_16rhs_pmc.md")
+DSLASH_SOURCES = ("wd_device.h", "dslash.hip")
 
 
-def kernel_sources_sha256():
+def kernel_sources_sha256(sources=KERNEL_SOURCES):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2111_14958_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def pmc_traffic():
-    """HBM-side bytes per phase-B launch from the committed counter summary, or
-    None when it is missing or was taken on other kernel sources."""
+def pmc_traffic(path=PMC_SUMMARY, sources=KERNEL_SOURCES, key="traffic_bytes_per_launch"):
+    """HBM-side bytes per launch from a committed counter summary, or None when
+    it is missing or was taken on other kernel sources."""
     try:
-        text = open(PMC_SUMMARY).read()
+        text = open(path).read()
     except OSError:
         return None, "no counter summary"
     sha = re.search(r"kernel_sources_sha256: ([0-9a-f]+)", text)
-    val = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text)
+    val = re.search(re.escape(key) + r": ([0-9.eE+]+)", text)
     if not sha or not val:
         return None, "counter summary unreadable"
-    if sha.group(1) != kernel_sources_sha256():
+    if sha.group(1) != kernel_sources_sha256(sources):
         return None, "kernel changed since the counters were taken"
     return float(val.group(1)), "FETCH_SIZE x2 + WRITE_SIZE (copy-calibrated), per launch"
 
@@ -228,6 +232,27 @@ def main():
     del gfull
     log(f"complete links: {full_value:.2f} solves/s")
 
+    # ---- the same batch in one persistent launch per chunk (grid barriers)
+    p_pers = wd.cg_default_params(tol=tol, inner=wd.F32, reliable_every=50, persistent=1)
+    solve(p_pers)   # graph capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    repsp, rcp = solve(p_pers)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    it_p = max(r["iters"] for r in repsp)
+    ka = complete_links["kernels_avg_us"]
+    per_it_graph = ka.get("cg_phaseA", 0.0) + ka.get("cg_phaseB", 0.0)
+    persistent = {"solves_per_s": nrhs / tp, "converged": rcp == wd.WD_OK, "iters_max": it_p,
+                  "us_per_iteration": 1e6 * tp / it_p,
+                  "graph_path_phase_A_plus_B_us": per_it_graph,
+                  # the persistent kernel reads the complete FP32 links, so it is
+                  # compared with the graph path's phases on the complete links;
+                  # two grid barriers per iteration
+                  "barrier_us_estimate": (1e6 * tp / it_p - per_it_graph) / 2,
+                  "max_true_rel_res": max(r["true_rel_res"] for r in repsp)}
+    log(f"persistent: {nrhs / tp:.2f} solves/s")
+
     # ------------------------------------------ stand-alone operator, 16 rhs
     dslash = {}
     for prec, name in ((wd.F32, "f32"), (wd.F64, "f64"), (wd.F16N, "f16n")):
@@ -265,9 +290,16 @@ def main():
         cold_us = sorted(cold)[len(cold) // 2]
         del flush
         dslash[name] = {"us": us, "GBps": alg / (us * 1e-6) / 1e9, "link_bytes_per_site": link,
+                        "alg_bytes_per_launch": alg,
                         "GFLOPs": 1368.0 * V * nrhs / (us * 1e-6) / 1e9,
                         "frac_hbm": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS,
-                        "cold_us_median": cold_us, "cold_GBps": alg / (cold_us * 1e-6) / 1e9}
+                        "cold_us_median": cold_us, "cold_GBps": alg / (cold_us * 1e-6) / 1e9,
+                        "cold_frac_hbm": alg / (cold_us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
+        for mode in ("hot", "cold"):
+            tb, note = pmc_traffic(PMC_DSLASH, DSLASH_SOURCES, f"traffic_{name}_{mode}")
+            dslash[name][f"traffic_{mode}_bytes_per_launch"] = tb
+            dslash[name][f"traffic_{mode}_over_algorithmic"] = tb / alg if tb else None
+        dslash[name]["traffic_note"] = note
         del pin, pout
 
     # ------------------------- the paper's coordinate-format operator (Sec. 2)
@@ -295,20 +327,30 @@ def main():
                      "bytes_per_site": alg / V, "nnz": c.nnz}
         c.close()
 
-    # ----------------------------------------------------- copy ceiling
-    a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbps = 2 * a.numel() * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del a, b
+    # ------------------------------------ memory ceiling: the streaming kernels
+    # wd_stream read / copy / write with 16-byte coalesced accesses; 128 MiB stays
+    # in the 256 MB MALL when repeated (the operator's 125 MB working set does
+    # too), 4 GiB streams from HBM
+    stream = {}
+    buf_a = torch.empty(4 << 30, dtype=torch.uint8, device=dev)
+    buf_b = torch.empty(4 << 30, dtype=torch.uint8, device=dev)
+    for label, nbytes, n_rep in (("128MiB_repeated", 128 << 20, 20), ("4GiB", 4 << 30, 5)):
+        row = {}
+        for kind, kname, fac in ((wd.STREAM_READ, "read", 1), (wd.STREAM_COPY, "copy", 2),
+                                 (wd.STREAM_WRITE, "write", 1)):
+            for _ in range(2):
+                wd.stream(kind, buf_a, buf_b, nbytes)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(n_rep):
+                wd.stream(kind, buf_a, buf_b, nbytes)
+            e1.record()
+            torch.cuda.synchronize()
+            row[kname + "_GBps"] = fac * nbytes * n_rep / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        stream[label] = row
+    del buf_a, buf_b
+    copy_gbps = stream["4GiB"]["copy_GBps"]
 
     # ------ 8^4, 12^4, 14^4 single field: operator alone and CG, FP64 and FP32 (context)
     single = {}
@@ -325,14 +367,25 @@ def main():
             pout = wd.empty_packed(g2, prec, 1)
             for _ in range(3):
                 wd.dslash(g2, sfcfg["m0"], pin, prec, packed=True, nrhs=1, out=pout)
+            torch.cuda.synchronize()
+            # 100 applications captured in one graph and replayed: the time per
+            # application is the kernel's (plus the graph's gap between kernels),
+            # not the host's call rate
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                for _ in range(100):
+                    wd.dslash(g2, sfcfg["m0"], pin, prec, packed=True, nrhs=1, out=pout)
+            graph.replay()
+            torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            for _ in range(200):
-                wd.dslash(g2, sfcfg["m0"], pin, prec, packed=True, nrhs=1, out=pout)
+            for _ in range(5):
+                graph.replay()
             e1.record()
             torch.cuda.synchronize()
-            us = e0.elapsed_time(e1) * 1e3 / 200
+            us = e0.elapsed_time(e1) * 1e3 / 500
+            del graph
             alg = V2 * ({wd.F64: 576, wd.F32: 192}[prec] + 2 * {wd.F64: 192, wd.F32: 96}[prec])
             pc = wd.cg_default_params(tol=sfcfg["tol"], inner=prec, reliable_every=0 if prec == wd.F64 else 50)
             sol2 = torch.zeros_like(s2)
@@ -462,6 +515,8 @@ def main():
             "dslash_16rhs": dslash,
             "coo_spmv_1rhs": coo,
             "copy_GBps": copy_gbps,
+            "stream": stream,
+            "persistent_cg_16rhs": persistent,
             "single_field": single,
             "lat16x3x32_12rhs": big,
         },

@@ -5,6 +5,8 @@
     python -m paper_2111_14958_amd.experiments serve   # open-loop serving latency
     python -m paper_2111_14958_amd.experiments serve eo   # the same, even-odd preconditioned
     python -m paper_2111_14958_amd.experiments solve   # one profiled 14^4 x 16 solve
+    python -m paper_2111_14958_amd.experiments dslash f32|f64|f16n hot|cold [reps]
+                                                       # the 14^4 x 16 operator alone
 
 Fig. 1 of the paper times the whole CG at 14^4 while varying the SYCL
 workgroup size with the number of compute units fixed; here the block size of
@@ -171,7 +173,7 @@ def solve():
     """One mixed-precision solve of the 14^4 x 16 benchmark workload (reconstruct-12
     links, as the benchmark) with the
     library's profiling mode on (every chunk kernel launched on its own,
-    bracketed by events), then one 256 MiB device copy of known size: the
+    bracketed by events), then one 256 MiB streaming copy of known size: the
     program that hardware-counter runs profile (the copy calibrates the byte
     counters).  Prints the per-kernel statistics as JSON."""
     import torch
@@ -195,14 +197,57 @@ def solve():
     prof = wd.profile_read()
     a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
+    wd.stream(wd.STREAM_COPY, a, b, a.numel())
     torch.cuda.synchronize()
     print(json.dumps({"solve": "14^4 x 16 mixed", "rc": rc, "iters": max(r["iters"] for r in reps),
                       "kernels": prof, "copy_bytes_each_way": a.numel()}), flush=True)
 
 
+def dslash(prec_name="f32", mode="hot", reps=20):
+    """The stand-alone operator on the 14^4 x 16 benchmark fields (reconstruct-12
+    gauge, as the benchmark; default launch shapes): `reps` applications back to
+    back (mode hot: fields and links stay in the 256 MB MALL) or each after a
+    1 GiB buffer is written (mode cold), then one 256 MiB streaming copy of
+    known size that calibrates the byte counters: the program that the
+    operator's hardware-counter runs profile.  Prints the timing as JSON."""
+    import torch
+
+    import paper_2111_14958_amd as wd
+    import wdgen
+    prec = {"f64": wd.F64, "f32": wd.F32, "f16n": wd.F16N}[prec_name]
+    reps = int(reps)
+    cfg = wdgen.CONFIGS["lat14x4_16rhs"]
+    dims, nrhs = cfg["dims"], cfg["n_point"] + cfg["n_gauss"]
+    U = wdgen.gauge_field(dims, cfg["eps"], cfg["gauge_seed"])
+    src = wdgen.mixed_sources(dims, cfg["n_point"], cfg["n_gauss"], cfg["src_seed"])
+    g = wd.Gauge(torch.from_numpy(U).cuda(), dims, recon12=True)
+    pin = wd.pack_spinor(g, torch.from_numpy(src).cuda(), prec)
+    pout = wd.empty_packed(g, prec, nrhs)
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda") if mode == "cold" else None
+    times = []
+    for _ in range(reps):
+        if flush is not None:
+            flush.fill_(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        wd.dslash(g, cfg["m0"], pin, prec, packed=True, nrhs=nrhs, out=pout)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e3)
+    a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    wd.stream(wd.STREAM_COPY, a, b, a.numel())
+    torch.cuda.synchronize()
+    print(json.dumps({"dslash": "14^4 x 16", "prec": prec_name, "mode": mode, "reps": reps,
+                      "shape": wd.shape_get(g, prec, nrhs, False, wd.FAMILY_DSLASH),
+                      "median_us": sorted(times)[len(times) // 2], "copy_bytes_each_way": a.numel()}),
+          flush=True)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "serve" and sys.argv[2:] == ["eo"]:
         serve(eo=True)
+    elif sys.argv[1] == "dslash":
+        dslash(*sys.argv[2:])
     else:
         {"fig1": fig1, "fig2": fig2, "serve": serve, "solve": solve}[sys.argv[1]]()
