@@ -44,16 +44,21 @@ namespace wd {
 // finish launch of its own.  k_phaseA forms the direction as q = D^dagger r +
 // beta q (phaseA_tile with QR): solves that launch it (LaunchSet::qrec) have
 // no phase C; so do the even-odd phase-A kernels.
+// par >= 0: the fused finish (LaunchSet::fused): iteration parity par of the
+// chunk, first = 1 for the chunk's first iteration (see phaseA_tile); -1: the
+// three-launch iteration with k_finish after phase B.
 template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false>
-__global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
+__global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap, int par,
+                                                int first) {
     WD_KERNEL_PROLOGUE(KA)
-    phaseA_tile<P, NR, ORD, XY, R12, NT, true>(pr, t_);
+    phaseA_tile<P, NR, ORD, XY, R12, NT, true>(pr, t_, par, first);
 }
 
 template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false>
-__global__ __launch_bounds__(256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
+__global__ __launch_bounds__(256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap, int par,
+                                                int /*first*/) {
     WD_KERNEL_PROLOGUE(KB)
-    phaseB_tile<P, NR, ORD, XY, R12, NT, true>(pr, t_);
+    phaseB_tile<P, NR, ORD, XY, R12, NT, true>(pr, t_, par);
 }
 
 // z-marching phases A and B (zm_tile); dynamic LDS of two plane buffers
@@ -180,10 +185,19 @@ void launch_eo_merge(const Prob *d, int64_t vf, int nrhs, void *sol, hipStream_t
 // device-scope release fence in every block, which on a multi-XCD GPU writes
 // back the XCD's L2 each time: the whole CG ran 1.4x slower that way.)
 // kind | FIN_AB: phase B's finish after k_phaseB, which also completes phase A's.
-constexpr int FIN_AB = 0x100;
+// kind | FIN_TRAIL | parity << 12: the finish of the last iteration of a chunk
+// run with the fused finish (K iterations, parity K & 1): the records that
+// iteration's phase A wrote (pr.sc2 for an odd K, else pr.sc) and its phase A
+// partials (slot 0 for an odd K, else slot 2) give the final records in pr.sc.
+constexpr int FIN_AB = 0x100, FIN_TRAIL = 0x200;
 __global__ __launch_bounds__(1024) void k_finish(const Prob *__restrict__ probs, int nprob, int kind) {
     for (int j = 0; j < nprob; ++j) {
         const Prob &pr = probs[j];
+        if (kind & FIN_TRAIL) {
+            const int pk = (kind >> 12) & 1;
+            phaseAB_finish(pr, pk ? pr.sc2 : pr.sc, pr.sc, pk ? 0 : 2);
+            continue;
+        }
         switch (kind) {
         case KA: phaseA_finish(pr); break;
         case KB: phaseB_finish(pr); break;
@@ -260,55 +274,55 @@ static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
 // the plane-blocked (XY) variants exist for up to 2 rhs per thread (1 in FP64)
 // reconstruct-12 variants: FP32 storage, plane or site blocks, 1 or 2 rhs per thread
 template <int P, int ORD, bool B>
-static void launch_AB_r12(int nr, int xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+static void launch_AB_r12(int nr, int xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap, int par, int first) {
     const dim3 gr(grid), bl(blk);
     if constexpr (P == P32) {
         if (xy) {
             if (nr == 2) {
-                if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, true, true>), gr, bl, st, d, n, remap);
-                else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, true, true>), gr, bl, st, d, n, remap);
+                if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, true, true>), gr, bl, st, d, n, remap, par, first);
+                else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, true, true>), gr, bl, st, d, n, remap, par, first);
             } else {
-                if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, true, true>), gr, bl, st, d, n, remap);
-                else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, true, true>), gr, bl, st, d, n, remap);
+                if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, true, true>), gr, bl, st, d, n, remap, par, first);
+                else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, true, true>), gr, bl, st, d, n, remap, par, first);
             }
         } else if (nr == 2) {
-            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, false, true>), gr, bl, st, d, n, remap);
-            else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, false, true>), gr, bl, st, d, n, remap);
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, false, true>), gr, bl, st, d, n, remap, par, first);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, false, true>), gr, bl, st, d, n, remap, par, first);
         } else {
-            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, false, true>), gr, bl, st, d, n, remap);
-            else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, false, true>), gr, bl, st, d, n, remap);
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, false, true>), gr, bl, st, d, n, remap, par, first);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, false, true>), gr, bl, st, d, n, remap, par, first);
         }
     }
 }
 
 // nontemporal-stream variants: FP64, plane blocks (1 rhs per thread) or site blocks (1 or 2)
 template <int P, int ORD, bool B>
-static void launch_AB_nt(int nr, int xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+static void launch_AB_nt(int nr, int xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap, int par, int first) {
     const dim3 gr(grid), bl(blk);
     if constexpr (P == P64) {
         if (xy) {
-            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, true, false, true>), gr, bl, st, d, n, remap);
-            else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, true, false, true>), gr, bl, st, d, n, remap);
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, true, false, true>), gr, bl, st, d, n, remap, par, first);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, true, false, true>), gr, bl, st, d, n, remap, par, first);
         } else if (nr == 2) {
-            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, false, false, true>), gr, bl, st, d, n, remap);
-            else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, false, false, true>), gr, bl, st, d, n, remap);
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, false, false, true>), gr, bl, st, d, n, remap, par, first);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, false, false, true>), gr, bl, st, d, n, remap, par, first);
         } else {
-            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, false, false, true>), gr, bl, st, d, n, remap);
-            else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, false, false, true>), gr, bl, st, d, n, remap);
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, false, false, true>), gr, bl, st, d, n, remap, par, first);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, false, false, true>), gr, bl, st, d, n, remap, par, first);
         }
     }
 }
 
 template <int P, int ORD, bool B>
 static void launch_AB_o(int nr, int xy, int lds, int r12, int nt, int grid, int blk, hipStream_t st, const Prob *d,
-                        int n, int remap) {
+                        int n, int remap, int par, int first) {
     const dim3 gr(grid), bl(blk);
     if (r12) {
-        launch_AB_r12<P, ORD, B>(nr, xy, grid, blk, st, d, n, remap);
+        launch_AB_r12<P, ORD, B>(nr, xy, grid, blk, st, d, n, remap, par, first);
         return;
     }
     if (nt) {
-        launch_AB_nt<P, ORD, B>(nr, xy, grid, blk, st, d, n, remap);
+        launch_AB_nt<P, ORD, B>(nr, xy, grid, blk, st, d, n, remap, par, first);
         return;
     }
     if (xy == 2) {
@@ -320,57 +334,59 @@ static void launch_AB_o(int nr, int xy, int lds, int r12, int nt, int grid, int 
     }
     if (xy) {
         if (nr == 2 && P != P64) {
-            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, true>), gr, bl, st, d, n, remap);
-            else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, true>), gr, bl, st, d, n, remap);
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, true>), gr, bl, st, d, n, remap, par, first);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, true>), gr, bl, st, d, n, remap, par, first);
         } else {
-            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, true>), gr, bl, st, d, n, remap);
-            else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, true>), gr, bl, st, d, n, remap);
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, true>), gr, bl, st, d, n, remap, par, first);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, true>), gr, bl, st, d, n, remap, par, first);
         }
         return;
     }
     if (nr == 1) {
-        if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, false>), gr, bl, st, d, n, remap);
-        else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, false>), gr, bl, st, d, n, remap);
+        if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, ORD, false>), gr, bl, st, d, n, remap, par, first);
+        else WD_TIMED_LAUNCH((k_phaseA<P, 1, ORD, false>), gr, bl, st, d, n, remap, par, first);
     } else if (nr == 2) {
-        if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, false>), gr, bl, st, d, n, remap);
-        else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, false>), gr, bl, st, d, n, remap);
+        if (B) WD_TIMED_LAUNCH((k_phaseB<P, 2, ORD, false>), gr, bl, st, d, n, remap, par, first);
+        else WD_TIMED_LAUNCH((k_phaseA<P, 2, ORD, false>), gr, bl, st, d, n, remap, par, first);
     } else {
-        if (B) WD_TIMED_LAUNCH((k_phaseB<P, 4, ORD, false>), gr, bl, st, d, n, remap);
-        else WD_TIMED_LAUNCH((k_phaseA<P, 4, ORD, false>), gr, bl, st, d, n, remap);
+        if (B) WD_TIMED_LAUNCH((k_phaseB<P, 4, ORD, false>), gr, bl, st, d, n, remap, par, first);
+        else WD_TIMED_LAUNCH((k_phaseA<P, 4, ORD, false>), gr, bl, st, d, n, remap, par, first);
     }
 }
 // hop order 5 (the memory hops z and t first, then the LDS hops x and y):
 // plane-blocked variants with one rhs per thread
 template <int P, bool B>
-static void launch_AB_o5(int r12, int nt, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+static void launch_AB_o5(int r12, int nt, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap, int par, int first) {
     const dim3 gr(grid), bl(blk);
     if (r12) {
         if constexpr (P == P32) {
-            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, 5, true, true>), gr, bl, st, d, n, remap);
-            else WD_TIMED_LAUNCH((k_phaseA<P, 1, 5, true, true>), gr, bl, st, d, n, remap);
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, 5, true, true>), gr, bl, st, d, n, remap, par, first);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 1, 5, true, true>), gr, bl, st, d, n, remap, par, first);
         }
     } else if (nt) {
         if constexpr (P == P64) {
-            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, 5, true, false, true>), gr, bl, st, d, n, remap);
-            else WD_TIMED_LAUNCH((k_phaseA<P, 1, 5, true, false, true>), gr, bl, st, d, n, remap);
+            if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, 5, true, false, true>), gr, bl, st, d, n, remap, par, first);
+            else WD_TIMED_LAUNCH((k_phaseA<P, 1, 5, true, false, true>), gr, bl, st, d, n, remap, par, first);
         }
     } else {
-        if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, 5, true>), gr, bl, st, d, n, remap);
-        else WD_TIMED_LAUNCH((k_phaseA<P, 1, 5, true>), gr, bl, st, d, n, remap);
+        if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, 5, true>), gr, bl, st, d, n, remap, par, first);
+        else WD_TIMED_LAUNCH((k_phaseA<P, 1, 5, true>), gr, bl, st, d, n, remap, par, first);
     }
 }
 
 template <int P>
-static void launch_A(const KindShape &k, hipStream_t st, const Prob *d, int n) {
-    if (k.ordered == 5) launch_AB_o5<P, false>(k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
-    else if (k.ordered == 3) launch_AB_o<P, 3, false>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
-    else launch_AB_o<P, 1, false>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
+static void launch_A(const KindShape &k, hipStream_t st, const Prob *d, int n, int par, int first) {
+    if (k.ordered == 5) launch_AB_o5<P, false>(k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, first);
+    else if (k.ordered == 3)
+        launch_AB_o<P, 3, false>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, first);
+    else launch_AB_o<P, 1, false>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, first);
 }
 template <int P>
-static void launch_B(const KindShape &k, hipStream_t st, const Prob *d, int n) {
-    if (k.ordered == 5) launch_AB_o5<P, true>(k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
-    else if (k.ordered == 3) launch_AB_o<P, 3, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
-    else launch_AB_o<P, 1, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap);
+static void launch_B(const KindShape &k, hipStream_t st, const Prob *d, int n, int par) {
+    if (k.ordered == 5) launch_AB_o5<P, true>(k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, 0);
+    else if (k.ordered == 3)
+        launch_AB_o<P, 3, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, 0);
+    else launch_AB_o<P, 1, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, 0);
 }
 template <int P>
 static void launch_R2(int nr, int xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
@@ -396,7 +412,8 @@ static void launch_bicg(int kind, const KindShape &k, hipStream_t st, const Prob
     }
 }
 
-static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream_t st, const Prob *d, int nprob);
+static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream_t st, const Prob *d, int nprob,
+                              int par = -1, int first = 0);
 
 static void launch_finish(int kind, hipStream_t st, const Prob *d, int nprob) {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, d, nprob, kind);
@@ -444,7 +461,8 @@ static void launch_eo(int kind, const KindShape &k, hipStream_t st, const Prob *
     }
 }
 
-void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob) {
+void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, int par,
+                 int first) {
     const KindShape &k = ls.k[kind];
     if (k.grid <= 0) return;
     if (kind == KC && ls.qrec) return;   // phase A forms the direction in q
@@ -456,22 +474,43 @@ void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const
         else if (inner == P32) launch_eo<P32>(kind, k, st, d, nprob);
         else launch_eo<P16>(kind, k, st, d, nprob);
     } else {
-        launch_kind_tiles(kind, inner, k, st, d, nprob);
+        launch_kind_tiles(kind, inner, k, st, d, nprob, par, first);
     }
-    if (reduces) launch_finish_after(kind, ls, st, d, nprob);
+    // with the fused finish, phase A finishes the previous iteration and a
+    // trailing finish the chunk's last (launch_iterations)
+    if (reduces && !(par >= 0 && (kind == KA || kind == KB))) launch_finish_after(kind, ls, st, d, nprob);
 }
 
-static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream_t st, const Prob *d, int nprob) {
+void launch_iterations(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, int K) {
+    if (ls.fused) {
+        for (int it = 0; it < K; ++it) {
+            launch_kind(KA, inner, ls, st, d, nprob, it & 1, it == 0);
+            launch_kind(KB, inner, ls, st, d, nprob, it & 1, 0);
+        }
+        hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, d, nprob, KB | FIN_AB | FIN_TRAIL | ((K & 1) << 12));
+        return;
+    }
+    for (int it = 0; it < K; ++it) {
+        if (ls.eo) launch_kind(KEA1, inner, ls, st, d, nprob);
+        launch_kind(KA, inner, ls, st, d, nprob);
+        if (ls.eo) launch_kind(KEB1, inner, ls, st, d, nprob);
+        launch_kind(KB, inner, ls, st, d, nprob);
+        launch_kind(KC, inner, ls, st, d, nprob);
+    }
+}
+
+static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream_t st, const Prob *d, int nprob,
+                              int par, int first) {
     switch (kind) {
     case KA:
-        if (inner == P64) launch_A<P64>(k, st, d, nprob);
-        else if (inner == P32) launch_A<P32>(k, st, d, nprob);
-        else launch_A<P16>(k, st, d, nprob);
+        if (inner == P64) launch_A<P64>(k, st, d, nprob, par, first);
+        else if (inner == P32) launch_A<P32>(k, st, d, nprob, par, first);
+        else launch_A<P16>(k, st, d, nprob, par, first);
         break;
     case KB:
-        if (inner == P64) launch_B<P64>(k, st, d, nprob);
-        else if (inner == P32) launch_B<P32>(k, st, d, nprob);
-        else launch_B<P16>(k, st, d, nprob);
+        if (inner == P64) launch_B<P64>(k, st, d, nprob, par);
+        else if (inner == P32) launch_B<P32>(k, st, d, nprob, par);
+        else launch_B<P16>(k, st, d, nprob, par);
         break;
     case KC:
         if (inner == P64 && k.nt) WD_TIMED_LAUNCH((k_phaseC<P64, true>), dim3(k.grid), dim3(k.block), st, d, nprob, 0);
@@ -519,6 +558,7 @@ WsLayout ws_layout(int64_t V, int nrhs, int inner, int method, int eo) {
     const int64_t Vf = eo ? V / 2 : V;   // sites of a vector
     L.prob = o; o += al256(sizeof(Prob));
     L.scal = o; o += al256(sizeof(Scal) * nrhs);
+    L.scal2 = o; o += al256(sizeof(Scal) * nrhs);
     L.bar = o; o += 256;
     L.summary = o; o += 256;
     L.part = o; o += al256((size_t)((V + 63) / 64) * nrhs * PSTRIDE * sizeof(double));
@@ -632,6 +672,9 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
     // phase A by k_phaseA or the even-odd kernels (not z-marching) carries the
     // direction as q
     ls.qrec = ls.eo || ls.k[KA].xy != 2;
+    // phase A completes the previous iteration's finish: plane or site blocks
+    // with phase A's reduction inside phase B (not even-odd, not z-marching)
+    ls.fused = !ls.eo && ls.k[KA].xy != 2 && ls.k[KB].xy != 2;
 }
 
 // The persistent kernel runs phases A and B with one block shape: phase B's,
@@ -640,6 +683,7 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
 void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner, int max_cus) {
     const int blk = max_cus > 0 ? 1024 : ls.k[KB].block;
     ls.qrec = 1;   // the persistent kernel's phase A carries the direction as q too
+    ls.fused = 0;  // it finishes each iteration at its own grid barriers
     int nr = max_cus > 0 ? 1 : ls.k[KB].nr;
     if (inner == WD_F64 && nr > 2) nr = 2;
     const int kinds[2] = {KA, KB};
@@ -685,6 +729,7 @@ void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_par
     pr.eta64 = ws + L.eta64;
     pr.part = (double *)(ws + L.part);
     pr.sc = (Scal *)(ws + L.scal);
+    pr.sc2 = (Scal *)(ws + L.scal2);
     pr.v = ws + L.q;
     pr.rh = L.rh ? ws + L.rh : nullptr;
     pr.sv = L.sv ? ws + L.sv : nullptr;
@@ -822,11 +867,15 @@ static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const 
             for (int q = 0; q < (ls.qrec ? 2 : 3); ++q) {
                 t_ev_start = ev[6 * it + 2 * q];
                 t_ev_stop = ev[6 * it + 2 * q + 1];
-                launch_kind_tiles(kinds[q], inner, ls.k[kinds[q]], st, dprob, 1);
+                if (ls.fused)   // the sequence launch_iterations records
+                    launch_kind_tiles(kinds[q], inner, ls.k[kinds[q]], st, dprob, 1, it & 1, q == 0 && it == 0);
+                else launch_kind_tiles(kinds[q], inner, ls.k[kinds[q]], st, dprob, 1);
                 t_ev_start = t_ev_stop = nullptr;
-                if (kinds[q] != KC) launch_finish_after(kinds[q], ls, st, dprob, 1);
+                if (kinds[q] != KC && !ls.fused) launch_finish_after(kinds[q], ls, st, dprob, 1);
             }
         }
+        if (ls.fused)
+            hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, st, dprob, 1, KB | FIN_AB | FIN_TRAIL | ((K & 1) << 12));
         if (hipMemcpyAsync(after.data(), dscal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             rc = fail(WD_EHIP, "profiling copy failed");
@@ -948,14 +997,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
             return;
         }
         if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, K, w + L.bar + 64, p.max_cus);
-        else
-            for (int it = 0; it < K; ++it) {
-                if (eo) launch_kind(KEA1, p.inner, ls, cs, dprob, 1);
-                launch_kind(KA, p.inner, ls, cs, dprob, 1);
-                if (eo) launch_kind(KEB1, p.inner, ls, cs, dprob, 1);
-                launch_kind(KB, p.inner, ls, cs, dprob, 1);
-                launch_kind(KC, p.inner, ls, cs, dprob, 1);
-            }
+        else launch_iterations(p.inner, ls, cs, dprob, 1, K);
         launch_kind(KR1, p.inner, ls, cs, dprob, 1);
         if (eo) launch_kind(KER2A, p.inner, ls, cs, dprob, 1);
         launch_kind(KR2, p.inner, ls, cs, dprob, 1);

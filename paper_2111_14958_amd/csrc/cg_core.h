@@ -86,6 +86,8 @@ struct alignas(16) Prob {
     void *x64, *eta64;        // FP64 packed vectors
     double *part;             // [nsb][nrhs][PSTRIDE] partial sums of the current phase
     Scal *sc;                 // [nrhs]
+    Scal *sc2;                // [nrhs] second record per field: with the fused finish, the phase-A
+                              // launches of a chunk read one and write the other (iteration parity)
     void *rh, *v, *sv, *tv;   // BiCGSTAB: shadow residual r_hat, v = D p, s, t = D s
     BScal *bs;                // BiCGSTAB scalars [nrhs]
     void *eta_o;              // even-odd: odd half of the source (FP64)
@@ -238,12 +240,66 @@ __device__ __forceinline__ void stage_plane(const FieldPtr &f, int rhs0, unsigne
 
 // bit j set: rhs rhs0 + j is in state `want`
 template <int NR>
-__device__ __forceinline__ unsigned rhs_mask(const Prob &pr, int rhs0, int want) {
+__device__ __forceinline__ unsigned rhs_mask(const Prob &pr, const Scal *sc, int rhs0, int want) {
     unsigned m = 0;
 #pragma unroll
     for (int j = 0; j < NR; ++j)
-        if (rhs0 + j < pr.nrhs && pr.sc[rhs0 + j].state == want) m |= 1u << j;
+        if (rhs0 + j < pr.nrhs && sc[rhs0 + j].state == want) m |= 1u << j;
     return m;
+}
+template <int NR>
+__device__ __forceinline__ unsigned rhs_mask(const Prob &pr, int rhs0, int want) {
+    return rhs_mask<NR>(pr, pr.sc, rhs0, want);
+}
+
+// The finish of one iteration for one field (c0: its record before): phase
+// A's sum sigma gives alpha (or a breakdown), phase B's sum rho the next beta,
+// the counters and the state, as phaseA_finish then phaseB_finish do.  Only
+// the fields the finish changes, as scalars (no record is copied through
+// memory); store_fin writes them with the unchanged ones.
+struct Fin {
+    double sigma, alpha, rho_old, rho, beta;
+    int state, iters, since_ru, pending_p;
+};
+__device__ __forceinline__ Fin cg_transition(const Prob &pr, const Scal &c0, double sigma, double rho) {
+    Fin f{c0.sigma, c0.alpha, c0.rho_old, c0.rho, c0.beta, c0.state, c0.iters, c0.since_ru, 0};
+    if (c0.state != ST_ACTIVE) return f;
+    f.sigma = sigma;
+    if (!finite_pos(sigma)) {
+        f.state = ST_BREAKDOWN;
+        return f;
+    }
+    f.alpha = c0.rho / sigma;
+    f.iters = c0.iters + 1;
+    f.since_ru = c0.since_ru + 1;
+    f.rho_old = c0.rho;
+    f.rho = rho;
+    f.beta = rho / c0.rho;
+    if (!(rho < 1e300)) f.state = ST_BREAKDOWN;   // NaN or Inf
+    else if (rho <= c0.stop2 || f.iters >= pr.max_iter || (pr.ru_every > 0 && f.since_ru >= pr.ru_every))
+        f.state = ST_FROZEN;                        // wants a reliable update
+    else f.pending_p = 1;
+    return f;
+}
+// the record after the finish: c0's fields with f's changes; restart cleared
+// (phase A formed the direction)
+__device__ __forceinline__ void store_fin(Scal &d, const Scal &c0, const Fin &f) {
+    d.rho = f.rho;
+    d.rho_old = f.rho_old;
+    d.alpha = f.alpha;
+    d.beta = f.beta;
+    d.sigma = f.sigma;
+    d.eta2 = c0.eta2;
+    d.stop2 = c0.stop2;
+    d.true2 = c0.true2;
+    d.state = f.state;
+    d.iters = f.iters;
+    d.since_ru = f.since_ru;
+    d.n_ru = c0.n_ru;
+    d.pending_p = f.pending_p;
+    d.restart = 0;
+    d.zero_src = c0.zero_src;
+    d.pad = c0.pad;
 }
 
 // ------------------------------------------------------------------ phase A
@@ -255,22 +311,102 @@ __device__ __forceinline__ unsigned rhs_mask(const Prob &pr, int rhs0, int want)
 // adds beta times its own old q (q = D^dagger r after a restart), so neither p
 // nor a pass forming it (phase C) is needed.  Only the site's own q is read,
 // so q is updated in place.
+//
+// Fused finish (par >= 0, with QR): the launch also completes the finish of the
+// iteration before it, so an iteration is two launches.  Every block sums, for
+// its own fields and in the finish's fixed order, phase A's partials of the
+// previous iteration (slot 2 for par 0, slot 0 for par 1) and phase B's (slot
+// 1), and applies the same transition (cg_transition) to the records it reads
+// from pr.sc (par 0) or pr.sc2 (par 1); the site block 0 of each field group
+// writes the results to the other array, which no block of this launch reads.
+// So every block gets the same alpha, beta and state, bitwise equal to what
+// k_finish would have recorded.  first = 1 (the chunk's first iteration): the
+// records are final already (the reliable update or the trailing finish of the
+// chunk before wrote them) and are copied unchanged.  Partials go to slot 0
+// (par 0) or 2 (par 1).
 template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false, bool NT = false, bool QR = false>
-__device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
+__device__ __forceinline__ void phaseA_tile(const Prob &pr, int t, int par = -1, int first = 0) {
     typedef typename real_of<P>::type R;
     typedef typename LdsSpinor<P>::word W;
     __shared__ W xy[XY ? NR * LdsWords<P>::value * 256 : 1];
+    __shared__ double fsig[NR], frho[NR], fbeta[NR];
+    __shared__ int fact[NR], frestart[NR];
     int sb, grp, s;
     stencil_tile<XY>(pr, KA, t, sb, grp, s);
     const int rhs0 = grp * NR;
-    const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
+    const bool fused = QR && par >= 0;   // uniform over the launch
+    const bool fin = fused && !first;
+    const Scal *sin = fused && par ? pr.sc2 : pr.sc;
+    Scal *sout = par ? pr.sc : pr.sc2;
+    const int wslot = fused && par ? 2 : 0;
+    // fields that iterate before this launch's finish (uniform over the block)
+    const unsigned act0 = rhs_mask<NR>(pr, sin, rhs0, ST_ACTIVE);
     double part[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) part[j] = 0.0;
     const Geom g = pr.g;
     const int np = g.S[2];
     FieldPtr fp{QR ? pr.r : pr.p, g.V, pr.nrhs}, fq{pr.q, g.V, pr.nrhs};
-    if (XY && act) stage_plane<P, NR>(fp, rhs0, act, s, g.V, xy, np);
+    // the fields of this launch's records that the finish's decision reads,
+    // loaded early by the thread that decides, so the staging covers the latency
+    Scal c0[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        c0[j] = Scal{};
+        if (fused && threadIdx.x == 0 && rhs0 + j < pr.nrhs) {
+            const Scal &m = sin[rhs0 + j];
+            c0[j].state = m.state;
+            c0[j].rho = m.rho;
+            c0[j].stop2 = m.stop2;
+            c0[j].iters = m.iters;
+            c0[j].since_ru = m.since_ru;
+            c0[j].beta = m.beta;
+            c0[j].restart = m.restart;
+        }
+    }
+    double as[NR][4], ar[NR][4];
+    if (fin && act0) {
+        col_issue<NR>(pr, rhs0, act0, as, par ? 0 : 2, pr.nsb[KA]);
+        col_issue<NR>(pr, rhs0, act0, ar, 1, pr.nsb[KB]);
+    }
+    auto reduce = [&]() {
+        if (fin && act0) {
+            col_reduce<NR>(pr, rhs0, act0, as, fsig, par ? 0 : 2, pr.nsb[KA]);
+            col_reduce<NR>(pr, rhs0, act0, ar, frho, 1, pr.nsb[KB]);
+        }
+    };
+    // the plane is staged for the fields active before the finish (a field
+    // that the finish freezes is staged for nothing, once per reliable update)
+    if (XY && act0) stage_plane<P, NR>(fp, rhs0, act0, s, g.V, xy, np, reduce);
+    else if (fin && act0) {
+        reduce();
+        __syncthreads();
+    }
+    // thread 0 applies the finish and shares the decision through LDS (one
+    // barrier); site block 0 of the group stores the records at the end
+    unsigned act = act0;
+    if (fused) {
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int j = 0; j < NR; ++j) {
+                const bool live = act0 >> j & 1;
+                if (fin) {
+                    const Fin f = cg_transition(pr, c0[j], live ? fsig[j] : 0.0, live ? frho[j] : 0.0);
+                    fact[j] = live && f.state == ST_ACTIVE;
+                    fbeta[j] = f.beta;
+                    frestart[j] = 0;
+                } else {
+                    fact[j] = live;
+                    fbeta[j] = c0[j].beta;
+                    frestart[j] = c0[j].restart;
+                }
+            }
+        __syncthreads();
+        act = 0;
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            if (fact[j]) act |= 1u << j;
+    }
     if (act && s < g.V) {
         const void *U = R12 ? pr.U12 : pr.U_lo;
         cx<R> acc[NR][12];
@@ -284,9 +420,8 @@ __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
                 else Spinor<P>::load(fp, rhs0 + j, s, self);
                 wilson_finish<R>((R)pr.diag, self, acc[j], o);
                 if constexpr (QR) {
-                    const Scal &c = pr.sc[rhs0 + j];
-                    if (!c.restart) {
-                        const R b = (R)c.beta;
+                    if (!(fused ? frestart[j] : pr.sc[rhs0 + j].restart)) {
+                        const R b = (R)(fused ? fbeta[j] : pr.sc[rhs0 + j].beta);
                         cx<R> qo[12];
                         Spinor<P>::template load<NT>(fq, rhs0 + j, s, qo);
 #pragma unroll
@@ -306,8 +441,22 @@ __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t) {
         if (threadIdx.x == 0)
 #pragma unroll
             for (int j = 0; j < NR; ++j)
-                if (act >> j & 1) part_at(pr, sb, rhs0 + j, 0) = part[j];
+                if (act >> j & 1) part_at(pr, sb, rhs0 + j, wslot) = part[j];
     }
+    // the group's records after the finish (or copied unchanged in the chunk's
+    // first iteration), from the complete records read again
+    if (fused && sb == 0 && threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < NR; ++j)
+            if (rhs0 + j < pr.nrhs) {
+                const Scal full = sin[rhs0 + j];
+                if (fin) {
+                    const bool live = act0 >> j & 1;
+                    store_fin(sout[rhs0 + j], full, cg_transition(pr, full, live ? fsig[j] : 0.0, live ? frho[j] : 0.0));
+                } else {
+                    sout[rhs0 + j] = full;
+                }
+            }
 }
 
 // The finish functions run in one block; thread i updates the scalars of
@@ -347,15 +496,15 @@ __device__ __forceinline__ void phaseA_finish(const Prob &pr) {
 // latency then covers them); fa_reduce completes the sums into sig[j] (LDS,
 // read after the block's next barrier).
 template <int NR>
-__device__ __forceinline__ void fa_issue(const Prob &pr, int rhs0, unsigned act, double (&a)[NR][4]) {
+__device__ __forceinline__ void col_issue(const Prob &pr, int rhs0, unsigned act, double (&a)[NR][4], int slot,
+                                          int nsb) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int nsb = pr.nsb[KA];
     const size_t bs = (size_t)pr.nrhs * PSTRIDE;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         a[j][0] = a[j][1] = a[j][2] = a[j][3] = 0.0;
         if (j % nw == w && (act >> j & 1)) {
-            const double *col = pr.part + (size_t)(rhs0 + j) * PSTRIDE;
+            const double *col = pr.part + (size_t)(rhs0 + j) * PSTRIDE + slot;
             if (lane < nsb) a[j][0] = col[(size_t)lane * bs];
             if (lane + 64 < nsb) a[j][1] = col[(size_t)(lane + 64) * bs];
             if (lane + 128 < nsb) a[j][2] = col[(size_t)(lane + 128) * bs];
@@ -365,15 +514,14 @@ __device__ __forceinline__ void fa_issue(const Prob &pr, int rhs0, unsigned act,
 }
 
 template <int NR>
-__device__ __forceinline__ void fa_reduce(const Prob &pr, int rhs0, unsigned act, const double (&a)[NR][4],
-                                          double *sig) {
+__device__ __forceinline__ void col_reduce(const Prob &pr, int rhs0, unsigned act, const double (&a)[NR][4],
+                                           double *out, int slot, int nsb) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int nsb = pr.nsb[KA];
     const size_t bs = (size_t)pr.nrhs * PSTRIDE;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j % nw == w && (act >> j & 1)) {
-            const double *col = pr.part + (size_t)(rhs0 + j) * PSTRIDE;
+            const double *col = pr.part + (size_t)(rhs0 + j) * PSTRIDE + slot;
             double x = 0.0;
             x += a[j][0];
             x += a[j][1];
@@ -381,9 +529,19 @@ __device__ __forceinline__ void fa_reduce(const Prob &pr, int rhs0, unsigned act
             x += a[j][3];
             for (int b = lane + 256; b < nsb; b += 64) x += col[(size_t)b * bs];
             x = wave_sum(x);
-            if (lane == 0) sig[j] = x;
+            if (lane == 0) out[j] = x;
         }
     }
+}
+
+template <int NR>
+__device__ __forceinline__ void fa_issue(const Prob &pr, int rhs0, unsigned act, double (&a)[NR][4], int slot = 0) {
+    col_issue<NR>(pr, rhs0, act, a, slot, pr.nsb[KA]);
+}
+template <int NR>
+__device__ __forceinline__ void fa_reduce(const Prob &pr, int rhs0, unsigned act, const double (&a)[NR][4],
+                                          double *sig, int slot = 0) {
+    col_reduce<NR>(pr, rhs0, act, a, sig, slot, pr.nsb[KA]);
 }
 
 // t = D q; r -= alpha t; x_lo += alpha q(s); partial |r|^2 (of the stored r)
@@ -391,8 +549,11 @@ __device__ __forceinline__ void fa_reduce(const Prob &pr, int rhs0, unsigned act
 // a field whose sigma is not finite and positive is skipped, as the finish
 // marks it broken down) and the |r|^2 partials go to slot 1, beside phase A's
 // in slot 0, for phaseAB_finish.
+// par >= 0 (with FA; the fused finish, see phaseA_tile): the records are those
+// the phase-A launch of iteration parity par wrote (pr.sc2 for par 0, pr.sc for
+// 1) and phase A's partials are in slot 0 (par 0) or 2 (par 1).
 template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false, bool NT = false, bool FA = false>
-__device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
+__device__ __forceinline__ void phaseB_tile(const Prob &pr, int t, int par = -1) {
     typedef typename real_of<P>::type R;
     constexpr int XP = XPrec<P>::value;
     typedef typename real_of<XP>::type RX;
@@ -402,7 +563,9 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
     int sb, grp, s;
     stencil_tile<XY>(pr, KB, t, sb, grp, s);
     const int rhs0 = grp * NR;
-    unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
+    const Scal *sc = par < 0 ? pr.sc : (par ? pr.sc : pr.sc2);
+    const int aslot = par > 0 ? 2 : 0;
+    unsigned act = rhs_mask<NR>(pr, sc, rhs0, ST_ACTIVE);
     double part[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) part[j] = 0.0;
@@ -412,11 +575,12 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
     if constexpr (FA) {
         if (act) {   // uniform over the block
             double a[NR][4];
-            fa_issue<NR>(pr, rhs0, act, a);
+            fa_issue<NR>(pr, rhs0, act, a, aslot);
             if constexpr (XY) {
-                stage_plane<P, NR>(fq, rhs0, act, s, g.V, xy, np, [&]() { fa_reduce<NR>(pr, rhs0, act, a, sig); });
+                stage_plane<P, NR>(fq, rhs0, act, s, g.V, xy, np,
+                                   [&]() { fa_reduce<NR>(pr, rhs0, act, a, sig, aslot); });
             } else {
-                fa_reduce<NR>(pr, rhs0, act, a, sig);
+                fa_reduce<NR>(pr, rhs0, act, a, sig, aslot);
                 __syncthreads();
             }
 #pragma unroll
@@ -434,7 +598,7 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t) {
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
-                const double al = FA ? pr.sc[rhs0 + j].rho / sig[j] : pr.sc[rhs0 + j].alpha;
+                const double al = FA ? sc[rhs0 + j].rho / sig[j] : sc[rhs0 + j].alpha;
                 const R a = (R)al;
                 cx<R> q[12], o[12], r[12];
                 if constexpr (XY) LdsSpinor<P>::get(xy, np, j, threadIdx.x, q);
@@ -494,12 +658,12 @@ __device__ __forceinline__ void phaseB_finish(const Prob &pr) {
 // round trip: wave w takes fields i = w, w + nw, ... and loads the first four
 // blocks of both columns before adding either, each in sum_all's order (so
 // the values are the ones sum_all returns, and fa_reduce's sigma).
-__device__ __forceinline__ void sum_ab(const Prob &pr, double *sa, double *sb) {
+__device__ __forceinline__ void sum_ab(const Prob &pr, double *sa, double *sb, int aslot = 0) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const size_t bs = (size_t)pr.nrhs * PSTRIDE;
     const int na = pr.nsb[KA], nb = pr.nsb[KB];
     for (int i = w; i < pr.nrhs; i += nw) {
-        const double *ca = pr.part + (size_t)i * PSTRIDE, *cb = ca + 1;
+        const double *ca = pr.part + (size_t)i * PSTRIDE + aslot, *cb = pr.part + (size_t)i * PSTRIDE + 1;
         double a[4], b[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -524,37 +688,24 @@ __device__ __forceinline__ void sum_ab(const Prob &pr, double *sa, double *sb) {
     __syncthreads();
 }
 
-// After an FA phase B: phase A's finish (sigma, alpha, breakdown) from slot 0,
-// then phase B's from slot 1, with the results phaseA_finish followed by
-// phaseB_finish give.
-__device__ __forceinline__ void phaseAB_finish(const Prob &pr) {
+// After an FA phase B: phase A's finish (sigma, alpha, breakdown) from its
+// slot (0 or 2), then phase B's from slot 1, with the results phaseA_finish
+// followed by phaseB_finish give.  The records are read from sin and written
+// to sout (the same array in the three-launch iteration; with the fused
+// finish, the chunk's last records into pr.sc).
+__device__ __forceinline__ void phaseAB_finish(const Prob &pr, const Scal *sin, Scal *sout, int aslot) {
     __shared__ double sa[MAX_SUMS], sbb[MAX_SUMS];
     const int i = threadIdx.x;
     Scal c0;
-    if (i < pr.nrhs) c0 = pr.sc[i];
+    if (i < pr.nrhs) c0 = sin[i];
     if (!__syncthreads_or(i < pr.nrhs && c0.state == ST_ACTIVE)) {   // nothing to sum
-        if (i < pr.nrhs) pr.sc[i].pending_p = pr.sc[i].restart = 0;
+        if (i < pr.nrhs) store_fin(sout[i], c0, cg_transition(pr, c0, 0.0, 0.0));
         return;
     }
-    sum_ab(pr, sa, sbb);
-    if (i < pr.nrhs) {
-        Scal &c = pr.sc[i];
-        bool live = c0.state == ST_ACTIVE;
-        if (live) {
-            const double sigma = sa[i];
-            c.sigma = sigma;
-            if (!finite_pos(sigma)) {
-                c.state = ST_BREAKDOWN;
-                live = false;
-            } else {
-                c.alpha = c0.rho / sigma;
-            }
-        }
-        c.pending_p = 0;
-        c.restart = 0;
-        if (live) phaseB_update(pr, c, c0, sbb[i]);
-    }
+    sum_ab(pr, sa, sbb, aslot);
+    if (i < pr.nrhs) store_fin(sout[i], c0, cg_transition(pr, c0, sa[i], sbb[i]));
 }
+__device__ __forceinline__ void phaseAB_finish(const Prob &pr) { phaseAB_finish(pr, pr.sc, pr.sc, 0); }
 
 // ---------------------------------------------- z-marching phases A and B
 // A tile is a column of xy-planes: one t, one rhs, the planes z0 <= z < z1 of

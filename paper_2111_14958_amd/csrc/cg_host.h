@@ -22,11 +22,13 @@ struct LaunchSet {
     KindShape k[NKIND];
     int eo = 0;   // even-odd preconditioned solve: A, B, R2 are Schur kernels
     int qrec = 0; // phase A forms the direction q = D^dagger r + beta q (Dhat for even-odd): no p, no phase C
+    int fused = 0; // phase A completes the previous iteration's finish (launch_iterations): two launches
+                   // per iteration and one trailing finish per chunk
 };
 
 // Byte offsets of the pieces of a solve workspace.
 struct WsLayout {
-    size_t prob, scal, bar, summary, part, eta64, x64, xlo, r, p, q;
+    size_t prob, scal, scal2, bar, summary, part, eta64, x64, xlo, r, p, q;
     size_t bscal, rh, sv, tv;   // BiCGSTAB only (0 otherwise)
     size_t eta_o, tmp, w64;     // even-odd only (0 otherwise)
     size_t total;
@@ -38,7 +40,14 @@ void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner, in
 void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_params &p, char *ws,
                const WsLayout &L);
 void init_scalars(std::vector<Scal> &sc, int nrhs);
-void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob);
+// One kernel kind of a CG iteration (and the finish after it).  par >= 0, first:
+// phase A or B of a fused-finish iteration (see launch_iterations).
+void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, int par = -1,
+                 int first = 0);
+// K CG iterations: with ls.fused, phases A and B per iteration (A finishing the
+// iteration before it) and one trailing finish; else A, B (with its finish)
+// and C, with the even-odd hops where ls.eo.
+void launch_iterations(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, int K);
 void launch_summary(hipStream_t st, const Prob *d, int nprob, int *out, const int *abort_flag);
 void launch_zero(void *p, size_t bytes, hipStream_t st);
 int check_params(const wd_cg_params *p);

@@ -140,6 +140,7 @@ static LaunchSet server_launch(int inner, int eo, const int grid[NKIND]) {
     LaunchSet ls;
     ls.eo = eo;
     ls.qrec = 1;   // k_phaseA and the even-odd phase A carry the direction as q
+    ls.fused = !eo;   // site blocks, phase A's reduction in phase B: phase A finishes the iteration before it
     for (int k = 0; k < NKIND; ++k) {
         const bool stencil = k == KA || k == KB || k == KR2 || k == KEA1 || k == KEB1 || k == KER2A;
         ls.k[k].block = blk;
@@ -253,13 +254,7 @@ static int step_group(wd_server *s, int gkey, const std::vector<Slot *> &grp) {
     Prob *dt = (Prob *)arena_ptr(s, s->table_off[gkey]);
     const int n = (int)table.size();
     WD_HIP(hipMemcpyAsync(dt, table.data(), sizeof(Prob) * n, hipMemcpyHostToDevice, s->st));
-    for (int it = 0; it < s->chunk; ++it) {
-        if (eo) launch_kind(KEA1, inner, ls, s->st, dt, n);
-        launch_kind(KA, inner, ls, s->st, dt, n);
-        if (eo) launch_kind(KEB1, inner, ls, s->st, dt, n);
-        launch_kind(KB, inner, ls, s->st, dt, n);
-        launch_kind(KC, inner, ls, s->st, dt, n);
-    }
+    launch_iterations(inner, ls, s->st, dt, n, s->chunk);
     launch_kind(KR1, inner, ls, s->st, dt, n);
     if (eo) launch_kind(KER2A, inner, ls, s->st, dt, n);
     launch_kind(KR2, inner, ls, s->st, dt, n);
