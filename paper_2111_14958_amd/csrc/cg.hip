@@ -11,6 +11,7 @@
 // and replays the chunk graph until no right-hand side is active, reading back
 // one counter per replay.  BiCGSTAB (bicgstab_core.h) uses the same driver with
 // the chunk K x [S1, S2, S3, S4, S5], then R1, R2, summary.
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -587,6 +588,11 @@ WsLayout ws_layout(int64_t V, int nrhs, int inner, int method, int eo) {
 }
 
 // Launch shapes of every kernel kind for one problem (tiles start at 0).
+bool unfused_requested() {
+    const char *v = getenv("WD_CG_UNFUSED");
+    return v && *v && strcmp(v, "0") != 0;
+}
+
 void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr) {
     const int V = (int)g->V;
     const int np = g->dims[0] * g->dims[1];
@@ -673,8 +679,10 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
     // direction as q
     ls.qrec = ls.eo || ls.k[KA].xy != 2;
     // phase A completes the previous iteration's finish: plane or site blocks
-    // with phase A's reduction inside phase B (not even-odd, not z-marching)
-    ls.fused = !ls.eo && ls.k[KA].xy != 2 && ls.k[KB].xy != 2;
+    // with phase A's reduction inside phase B (not even-odd, not z-marching).
+    // WD_CG_UNFUSED=1 selects the three-launch iteration instead (the same
+    // arithmetic; kept for comparisons).
+    ls.fused = !ls.eo && ls.k[KA].xy != 2 && ls.k[KB].xy != 2 && !unfused_requested();
 }
 
 // The persistent kernel runs phases A and B with one block shape: phase B's,
@@ -983,7 +991,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     key.K = K;
     key.persistent = persistent;
     key.max_cus = p.max_cus;
-    key.method = p.method | (eo << 4);
+    key.method = p.method | (eo << 4) | (ls.fused << 5);
     for (int k = 0; k < NKIND; ++k) key.shp[k] = ls.k[k];
     hipGraphExec_t exec = nullptr;
     int rec_rc = WD_OK;

@@ -48,6 +48,8 @@ void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const
 // iteration before it) and one trailing finish; else A, B (with its finish)
 // and C, with the even-odd hops where ls.eo.
 void launch_iterations(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, int K);
+// WD_CG_UNFUSED set (and not "0"): solves and the server use the three-launch iteration
+bool unfused_requested();
 void launch_summary(hipStream_t st, const Prob *d, int nprob, int *out, const int *abort_flag);
 void launch_zero(void *p, size_t bytes, hipStream_t st);
 int check_params(const wd_cg_params *p);

@@ -140,7 +140,8 @@ static LaunchSet server_launch(int inner, int eo, const int grid[NKIND]) {
     LaunchSet ls;
     ls.eo = eo;
     ls.qrec = 1;   // k_phaseA and the even-odd phase A carry the direction as q
-    ls.fused = !eo;   // site blocks, phase A's reduction in phase B: phase A finishes the iteration before it
+    ls.fused = !eo && !unfused_requested();   // site blocks, phase A's reduction in phase B: phase A
+                                              // finishes the iteration before it
     for (int k = 0; k < NKIND; ++k) {
         const bool stencil = k == KA || k == KB || k == KR2 || k == KEA1 || k == KEB1 || k == KER2A;
         ls.k[k].block = blk;
