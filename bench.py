@@ -199,8 +199,10 @@ def main():
         sh = wd.shape_get(g, wd.F32, nrhs, fam == wd.FAMILY_CG_A, fam)
         xy = sh["xy_lds"] and dims[0] * dims[1] <= 256
         nr = min(sh["rhs_per_thread"], 2) if xy else sh["rhs_per_thread"]
-        kernel_symbol = "wd::k_%s<1, %d, %d, %s, true, false>" % (dom_name[3:], nr, sh["hop_order"] if sh["hop_order"] in (3, 5) else 1,
-                                                    "true" if xy else "false")
+        mp = bool(xy) and nr == 1 and sh["hop_order"] == 5 and sh.get("xy_planes", 1) > 1
+        kernel_symbol = "wd::k_%s<1, %d, %d, %s, true, false, %s>" % (
+            dom_name[3:], nr, sh["hop_order"] if sh["hop_order"] in (3, 5) else 1, "true" if xy else "false",
+            "true" if mp else "false")
     else:
         kernel_symbol = dom_name
     traffic, traffic_note = pmc_traffic() if dom_name == "cg_phaseB" else (None, "not measured")

@@ -265,10 +265,19 @@ typedef struct {
                              the ones that read LDS (x, y; plane blocks, one rhs per
                              thread), 0: compiler order                           */
     int32_t rhs_loop;     /* rhs groups one block handles one after the other    */
-    int32_t site_order;   /* strip | group_major << 16 | xy_lds << 17 | occ << 18
-                             | z_march << 24 | rhs_pass << 25.
-                             strip = W > 0: sites are processed in strips of W
-                             z-planes, t-major inside a strip (0: lexicographic);
+    int32_t site_order;   /* strip | xy_planes << 12 | group_major << 16
+                             | xy_lds << 17 | occ << 18 | z_march << 24
+                             | rhs_pass << 25.
+                             strip = W in 1..4095: sites are processed in strips
+                             of W z-planes, t-major inside a strip (0:
+                             lexicographic); xy_planes = k in 2..4 (with xy_lds
+                             = 1, one rhs per thread, hop order 3 or 5; the
+                             operator and CG phases A and B): a block is k
+                             z-adjacent xy-planes (k Lx Ly <= 512 sites), a z
+                             neighbour inside it read from LDS too; a lattice,
+                             precision or strip where k planes do not fit (FP64,
+                             Lz or W not a multiple of k) uses one (0 or 1:
+                             one plane);
                              group_major = 1: tiles are ordered rhs-group-major
                              instead of site-block-major; xy_lds = 1: one xy-plane
                              per block with the x/y neighbours in LDS; occ > 0: at
@@ -304,7 +313,8 @@ int wd_tune_lookup(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
  * WD_FAMILY_CG_A and WD_FAMILY_CG_B) of g's lattice, inner precision `inner`
  * and nrhs fields.  Every candidate (plane or site blocks, 1 or 2 rhs per
  * thread, hop order 1, 3 or 5 (5: plane blocks, one rhs per thread), z-strips of
- * 0/2/4/7 planes) runs `iters` (1..1000)
+ * 0/2/4/7 planes, with hop order 5 one or two planes per block where two fit)
+ * runs `iters` (1..1000)
  * CG iterations from the nrhs canonical fields src_dev (as wd_cg_solve_batch
  * takes them) with the mass m0; the median of three runs is kept; a candidate
  * whose iterate differs from the first candidate's by more than 1e-3 relative

@@ -429,7 +429,8 @@ def tune_cg(g: Gauge, m0: float, inner: int, src, iters: int = 30) -> dict:
     _check(lib().wd_tune_cg(g.handle, float(m0), inner, _ptr(src), nrhs, iters, ctypes.byref(r), _stream()),
            "wd_tune_cg")
     out = {f[0]: getattr(r, f[0]) for f in r._fields_ if f[0] != "gbps"}
-    out["strip"] = r.site_order & 0xFFFF
+    out["strip"] = r.site_order & 0xFFF
+    out["xy_planes"] = max(1, (r.site_order >> 12) & 7)
     out["xy_lds"] = (r.site_order >> 17) & 1
     return out
 
@@ -447,11 +448,12 @@ FAMILY_DSLASH, FAMILY_CG_A, FAMILY_CG_B, FAMILY_CG_R = 0, 1, 2, 3
 def shape_set(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int, block: int,
               rhs_per_thread: int = 1, xcd_remap: int = 1, hop_order: int = 1, rhs_loop: int = 1,
               strip: int = 0, group_major: int = 0, xy_lds: int = 0, max_blocks_per_cu: int = 0,
-              rhs_pass: int = 0):
+              rhs_pass: int = 0, xy_planes: int = 1):
     r = TuneResult(block=block, rhs_per_thread=rhs_per_thread, xcd_remap=xcd_remap,
                    hop_order=hop_order, rhs_loop=rhs_loop,
-                   site_order=strip | (group_major << 16) | ((1 if xy_lds else 0) << 17) |
-                   (max_blocks_per_cu << 18) | ((1 if xy_lds == 2 else 0) << 24) | (rhs_pass << 25))
+                   site_order=strip | ((xy_planes if xy_planes > 1 else 0) << 12) | (group_major << 16) |
+                   ((1 if xy_lds else 0) << 17) | (max_blocks_per_cu << 18) |
+                   ((1 if xy_lds == 2 else 0) << 24) | (rhs_pass << 25))
     _check(lib().wd_shape_set(g.handle, prec, nrhs, 1 if dagger else 0, family, ctypes.byref(r)),
            "wd_shape_set")
 
@@ -461,7 +463,8 @@ def shape_get(g: Gauge, prec: int, nrhs: int, dagger: bool, family: int) -> dict
     _check(lib().wd_shape_get(g.handle, prec, nrhs, 1 if dagger else 0, family, ctypes.byref(r)),
            "wd_shape_get")
     out = {f[0]: getattr(r, f[0]) for f in r._fields_ if f[0] not in ("us", "gbps")}
-    out["strip"] = r.site_order & 0xFFFF
+    out["strip"] = r.site_order & 0xFFF
+    out["xy_planes"] = max(1, (r.site_order >> 12) & 7)
     out["group_major"] = (r.site_order >> 16) & 1
     out["xy_lds"] = (1 + ((r.site_order >> 24) & 1)) if (r.site_order >> 17) & 1 else 0
     out["max_blocks_per_cu"] = (r.site_order >> 18) & 0x3F

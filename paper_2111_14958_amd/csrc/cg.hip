@@ -48,18 +48,19 @@ namespace wd {
 // par >= 0: the fused finish (LaunchSet::fused): iteration parity par of the
 // chunk, first = 1 for the chunk's first iteration (see phaseA_tile); -1: the
 // three-launch iteration with k_finish after phase B.
-template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false>
-__global__ __launch_bounds__(256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap, int par,
-                                                int first) {
+// MP: plane blocks of several z-adjacent planes (up to 512 threads).
+template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false, bool MP = false>
+__global__ __launch_bounds__(MP ? 512 : 256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap,
+                                                           int par, int first) {
     WD_KERNEL_PROLOGUE(KA)
-    phaseA_tile<P, NR, ORD, XY, R12, NT, true>(pr, t_, par, first);
+    phaseA_tile<P, NR, ORD, XY, R12, NT, true, MP>(pr, t_, par, first);
 }
 
-template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false>
-__global__ __launch_bounds__(256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap, int par,
-                                                int /*first*/) {
+template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false, bool MP = false>
+__global__ __launch_bounds__(MP ? 512 : 256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap,
+                                                           int par, int /*first*/) {
     WD_KERNEL_PROLOGUE(KB)
-    phaseB_tile<P, NR, ORD, XY, R12, NT, true>(pr, t_, par);
+    phaseB_tile<P, NR, ORD, XY, R12, NT, true, MP>(pr, t_, par);
 }
 
 // z-marching phases A and B (zm_tile); dynamic LDS of two plane buffers
@@ -357,9 +358,22 @@ static void launch_AB_o(int nr, int xy, int lds, int r12, int nt, int grid, int 
 // hop order 5 (the memory hops z and t first, then the LDS hops x and y):
 // plane-blocked variants with one rhs per thread
 template <int P, bool B>
-static void launch_AB_o5(int r12, int nt, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap, int par, int first) {
+static void launch_AB_o5(int r12, int nt, int mp, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap,
+                         int par, int first) {
     const dim3 gr(grid), bl(blk);
-    if (r12) {
+    if (mp) {   // several planes per block: FP32 and FP16 storage
+        if constexpr (P != P64) {
+            if (r12) {
+                if constexpr (P == P32) {
+                    if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, 5, true, true, false, true>), gr, bl, st, d, n, remap, par, first);
+                    else WD_TIMED_LAUNCH((k_phaseA<P, 1, 5, true, true, false, true>), gr, bl, st, d, n, remap, par, first);
+                }
+            } else {
+                if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, 5, true, false, false, true>), gr, bl, st, d, n, remap, par, first);
+                else WD_TIMED_LAUNCH((k_phaseA<P, 1, 5, true, false, false, true>), gr, bl, st, d, n, remap, par, first);
+            }
+        }
+    } else if (r12) {
         if constexpr (P == P32) {
             if (B) WD_TIMED_LAUNCH((k_phaseB<P, 1, 5, true, true>), gr, bl, st, d, n, remap, par, first);
             else WD_TIMED_LAUNCH((k_phaseA<P, 1, 5, true, true>), gr, bl, st, d, n, remap, par, first);
@@ -377,14 +391,14 @@ static void launch_AB_o5(int r12, int nt, int grid, int blk, hipStream_t st, con
 
 template <int P>
 static void launch_A(const KindShape &k, hipStream_t st, const Prob *d, int n, int par, int first) {
-    if (k.ordered == 5) launch_AB_o5<P, false>(k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, first);
+    if (k.ordered == 5) launch_AB_o5<P, false>(k.r12, k.nt, k.planes > 1, k.grid, k.block, st, d, n, k.remap, par, first);
     else if (k.ordered == 3)
         launch_AB_o<P, 3, false>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, first);
     else launch_AB_o<P, 1, false>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, first);
 }
 template <int P>
 static void launch_B(const KindShape &k, hipStream_t st, const Prob *d, int n, int par) {
-    if (k.ordered == 5) launch_AB_o5<P, true>(k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, 0);
+    if (k.ordered == 5) launch_AB_o5<P, true>(k.r12, k.nt, k.planes > 1, k.grid, k.block, st, d, n, k.remap, par, 0);
     else if (k.ordered == 3)
         launch_AB_o<P, 3, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, 0);
     else launch_AB_o<P, 1, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, 0);
@@ -596,6 +610,7 @@ bool unfused_requested() {
 void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr) {
     const int V = (int)g->V;
     const int np = g->dims[0] * g->dims[1];
+    const Geom geo = make_geom(g);
     ShapeKey ka{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, inner, nrhs, 1, FAM_CG_A};
     ShapeKey kb = ka;
     kb.dag = 0;
@@ -660,6 +675,17 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             }
             // hop order 5 exists for plane blocks with one rhs per thread
             if (ks.ordered == 5 && !(ks.xy == 1 && ks.nr == 1)) ks.ordered = 3;
+            // several z-adjacent planes per block (FP32 / FP16 storage, hop order 5);
+            // the block is rounded up to whole wavefronts for the block sums
+            ks.planes = 1;
+            if ((k == KA || k == KB) && ks.xy == 1 && ks.nr == 1 && ks.ordered == 5 && !ks.nt) {
+                const int kp = xy_planes(*st[k], geo, inner, 1);
+                if (kp > 1) {
+                    ks.planes = kp;
+                    ks.block = (kp * np + 63) & ~63;
+                    ks.order |= kp << 18;
+                }
+            }
         } else {
             ks.block = 256;
             ks.nr = 1;
@@ -669,7 +695,7 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.nt = k == KC && inner == WD_F64 && mall_exceeded && !pr.eo;
         }
         pr.sorder[k] = ks.order;
-        pr.nsb[k] = ks.xy == 2 ? ks.order * g->dims[3] : ks.xy ? V / np : (Vf + ks.block - 1) / ks.block;
+        pr.nsb[k] = ks.xy == 2 ? ks.order * g->dims[3] : ks.xy ? V / (np * ks.planes) : (Vf + ks.block - 1) / ks.block;
         pr.ng[k] = (nrhs + ks.nr - 1) / ks.nr;
         pr.t0[k] = 0;
         pr.nt[k] = pr.nsb[k] * pr.ng[k];
@@ -700,8 +726,10 @@ void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner, in
         ks.block = blk;
         ks.nr = nr;
         ks.remap = 0;
-        ks.order = ks.xy == 2 ? 0 : ks.order & ~(1 << 17);   // z-marching: the order held the chunk count
+        // z-marching: the order held the chunk count; no plane blocks
+        ks.order = ks.xy == 2 ? 0 : ks.order & ~(1 << 17) & ~(7 << 18);
         ks.xy = 0;
+        ks.planes = 1;
         ks.lds = 0;
         ks.r12 = 0;   // the persistent kernel reads the complete copy
         ks.nt = 0;
@@ -769,7 +797,7 @@ struct GraphKey {
     KindShape shp[NKIND];
     bool operator<(const GraphKey &o) const { return memcmp(this, &o, sizeof(*this)) < 0; }
 };
-static_assert(sizeof(KindShape) == 10 * sizeof(int), "KindShape must be plain ints (compared bytewise)");
+static_assert(sizeof(KindShape) == 11 * sizeof(int), "KindShape must be plain ints (compared bytewise)");
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
@@ -941,8 +969,10 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     const int persistent = (p.persistent == 1 && !bicg) ? 1 : 0;
     if (persistent) plan_persistent(ls, hp, V, nrhs, p.inner, p.max_cus);
     for (int k = 0; k < NKIND; ++k)   // kernels launched one by one are compiled for <= 256 threads
-        WD_CHECK(ls.k[k].block <= 256 || (persistent && (k == KA || k == KB)), WD_EINVAL,
-                 "kernel kind %d planned with %d threads per block", k, ls.k[k].block);
+                                      // (multi-plane phases A and B: <= 512)
+        WD_CHECK(ls.k[k].block <= 256 || (persistent && (k == KA || k == KB)) ||
+                     (ls.k[k].planes > 1 && ls.k[k].block <= 512 && (k == KA || k == KB)),
+                 WD_EINVAL, "kernel kind %d planned with %d threads per block", k, ls.k[k].block);
     for (int k = 0; k < NKIND; ++k)   // every kind's partial sums fit the buffer
         WD_CHECK(hp.nsb[k] <= (V + 63) / 64, WD_EINVAL, "kernel kind %d has %d site blocks, the partial-sum "
                  "buffer holds %lld", k, hp.nsb[k], (long long)((V + 63) / 64));
@@ -1182,6 +1212,7 @@ int wd_tune_cg(const wd_gauge *g, double m0, int32_t inner, const void *src, int
     std::vector<double> ref(fb / 8), got(fb / 8);
     std::vector<wd_cg_report> reps(nrhs);
     const int Lz = g->dims[2], np = g->dims[0] * g->dims[1];
+    const Geom geo = make_geom(g);
     const ShapeKey ka{{g->dims[0], g->dims[1], g->dims[2], g->dims[3]}, inner, nrhs, 1, FAM_CG_A};
     ShapeKey kb = ka;
     kb.dag = 0;
@@ -1205,7 +1236,10 @@ int wd_tune_cg(const wd_gauge *g, double m0, int32_t inner, const void *src, int
                     s.xylds = xy;
                     s.gmajor = 0;
                     s.occ = 0;
+                    s.planes = 1;
                     cand.push_back(s);
+                    s.planes = 2;   // two z-adjacent planes per block, where they fit
+                    if (ord == 5 && xy_planes(s, geo, inner, 1) == 2) cand.push_back(s);
                 }
         }
     }

@@ -78,7 +78,8 @@ struct alignas(16) Prob {
     int ng[NKIND];    // rhs groups per kernel kind
     int t0[NKIND];    // first tile of this problem in a grouped launch
     int nt[NKIND];    // tiles of this problem
-    int sorder[NKIND];  // stencil kinds: strip | group-major << 16 (see order_site)
+    int sorder[NKIND];  // stencil kinds: strip | group-major << 16 | plane-blocked << 17
+                        // | planes per block << 18 | rhs passes << 24 (see stencil_tile)
     const void *U_lo; // links in the inner precision
     const void *U12;  // reconstruct-12 copy in the inner precision, or null
     const void *U64;  // FP64 links
@@ -187,7 +188,10 @@ __device__ __forceinline__ int find_prob(const Prob *probs, int nprob, int K, in
 // groups, site-block-major within a pass.  A pass holds fewer fields per
 // plane, so the planes whose spinors its blocks share lie closer together in
 // the XCD's L2; the links are read once per pass.
-template <bool XY = false>
+// MP (with XY): a site block is xy_kp(pr.sorder[K]) z-adjacent planes, whose
+// sites are consecutive (the host picks only orders that keep them together).
+__device__ __forceinline__ int xy_kp(int od) { return max(1, (od >> 18) & 7); }
+template <bool XY = false, bool MP = false>
 __device__ __forceinline__ void stencil_tile(const Prob &pr, int K, int t, int &sb, int &grp, int &s) {
     const int od = pr.sorder[K];
     const int fp = (od >> 24) & 63;
@@ -207,7 +211,7 @@ __device__ __forceinline__ void stencil_tile(const Prob &pr, int K, int t, int &
         sb = t / pr.ng[K];
         grp = t - sb * pr.ng[K];
     }
-    const int rows = XY ? pr.g.S[2] : (int)blockDim.x;
+    const int rows = XY ? (MP ? pr.g.S[2] * xy_kp(od) : pr.g.S[2]) : (int)blockDim.x;
     const int L = sb * rows + (int)threadIdx.x;
     s = ((int)threadIdx.x < rows && L < pr.g.V) ? order_site(pr.g, od & 0xffff, L) : pr.g.V;
 }
@@ -305,6 +309,10 @@ __device__ __forceinline__ void store_fin(Scal &d, const Scal &c0, const Fin &f)
 // ------------------------------------------------------------------ phase A
 // q = D^dagger p for active rhs; partial |q|^2 (of the stored q)
 // XY: plane-blocked (one xy-plane per block, x/y neighbours from LDS).
+// MP (with XY): several z-adjacent planes per block (stencil_tile).  All z
+// neighbours still come from memory: reading the ones inside the block from
+// LDS (a branch per lane) took phases A and B from 77 to 95 VGPRs and 6 to 5
+// waves per SIMD.
 // R12: the links are the gauge's reconstruct-12 copy pr.U12 (two rows per link).
 // QR: the direction is carried as q alone.  Since p = r + beta p_old, its image
 // q = D^dagger p is D^dagger r + beta q_old: the stencil reads r and each site
@@ -324,15 +332,16 @@ __device__ __forceinline__ void store_fin(Scal &d, const Scal &c0, const Fin &f)
 // records are final already (the reliable update or the trailing finish of the
 // chunk before wrote them) and are copied unchanged.  Partials go to slot 0
 // (par 0) or 2 (par 1).
-template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false, bool NT = false, bool QR = false>
+template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false, bool NT = false, bool QR = false,
+          bool MP = false>
 __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t, int par = -1, int first = 0) {
     typedef typename real_of<P>::type R;
     typedef typename LdsSpinor<P>::word W;
-    __shared__ W xy[XY ? NR * LdsWords<P>::value * 256 : 1];
+    __shared__ W xy[XY ? NR * LdsWords<P>::value * (MP ? 512 : 256) : 1];
     __shared__ double fsig[NR], frho[NR], fbeta[NR];
     __shared__ int fact[NR], frestart[NR];
     int sb, grp, s;
-    stencil_tile<XY>(pr, KA, t, sb, grp, s);
+    stencil_tile<XY, MP>(pr, KA, t, sb, grp, s);
     const int rhs0 = grp * NR;
     const bool fused = QR && par >= 0;   // uniform over the launch
     const bool fin = fused && !first;
@@ -345,7 +354,7 @@ __device__ __forceinline__ void phaseA_tile(const Prob &pr, int t, int par = -1,
 #pragma unroll
     for (int j = 0; j < NR; ++j) part[j] = 0.0;
     const Geom g = pr.g;
-    const int np = g.S[2];
+    const int np = MP ? g.S[2] * xy_kp(pr.sorder[KA]) : g.S[2];   // sites staged in LDS
     FieldPtr fp{QR ? pr.r : pr.p, g.V, pr.nrhs}, fq{pr.q, g.V, pr.nrhs};
     // the fields of this launch's records that the finish's decision reads,
     // loaded early by the thread that decides, so the staging covers the latency
@@ -552,16 +561,17 @@ __device__ __forceinline__ void fa_reduce(const Prob &pr, int rhs0, unsigned act
 // par >= 0 (with FA; the fused finish, see phaseA_tile): the records are those
 // the phase-A launch of iteration parity par wrote (pr.sc2 for par 0, pr.sc for
 // 1) and phase A's partials are in slot 0 (par 0) or 2 (par 1).
-template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false, bool NT = false, bool FA = false>
+template <int P, int NR, int ORD = 1, bool XY = false, bool R12 = false, bool NT = false, bool FA = false,
+          bool MP = false>
 __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t, int par = -1) {
     typedef typename real_of<P>::type R;
     constexpr int XP = XPrec<P>::value;
     typedef typename real_of<XP>::type RX;
     typedef typename LdsSpinor<P>::word W;
-    __shared__ W xy[XY ? NR * LdsWords<P>::value * 256 : 1];
+    __shared__ W xy[XY ? NR * LdsWords<P>::value * (MP ? 512 : 256) : 1];
     __shared__ double sig[NR];
     int sb, grp, s;
-    stencil_tile<XY>(pr, KB, t, sb, grp, s);
+    stencil_tile<XY, MP>(pr, KB, t, sb, grp, s);
     const int rhs0 = grp * NR;
     const Scal *sc = par < 0 ? pr.sc : (par ? pr.sc : pr.sc2);
     const int aslot = par > 0 ? 2 : 0;
@@ -570,7 +580,7 @@ __device__ __forceinline__ void phaseB_tile(const Prob &pr, int t, int par = -1)
 #pragma unroll
     for (int j = 0; j < NR; ++j) part[j] = 0.0;
     const Geom g = pr.g;
-    const int np = g.S[2];
+    const int np = MP ? g.S[2] * xy_kp(pr.sorder[KB]) : g.S[2];   // sites staged in LDS
     FieldPtr fq{pr.q, g.V, pr.nrhs}, fr{pr.r, g.V, pr.nrhs}, fx{pr.x_lo, g.V, pr.nrhs};
     if constexpr (FA) {
         if (act) {   // uniform over the block

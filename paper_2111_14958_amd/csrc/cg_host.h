@@ -12,11 +12,13 @@ struct KindShape {
     int block = 256, nr = 1, remap = 0, grid = 0;
     int ordered = 1;   // hop order of phases A and B: 1, 3 (pipelined) or 5 (pipelined, memory hops first)
     int order = 0;     // stencil kinds: processing order, strip | group-major << 16 | plane-blocked << 17
+                       // | planes per block << 18
     int xy = 0;        // phases A and B: 1 plane-blocked variant (x/y neighbours from LDS),
                        // 2 z-marching columns of planes (zm_tile)
     int lds = 0;       // dynamic LDS bytes per block (z-marching)
     int r12 = 0;       // phases A and B: links from the reconstruct-12 copy
     int nt = 0;        // phases A, B and C: nontemporal streaming accesses (FP64)
+    int planes = 1;    // phases A and B, plane-blocked: z-adjacent xy-planes per block
 };
 struct LaunchSet {
     KindShape k[NKIND];

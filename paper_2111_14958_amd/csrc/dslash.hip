@@ -79,8 +79,12 @@ __global__ __launch_bounds__(256) void k_dslash(Geom g, double diag, const void 
 // spinors to LDS; the x and y neighbours then come from LDS, so only the own
 // spinor and the z and t neighbours are read from memory.  The own spinor is
 // read back from LDS for the diagonal term.
-template <int P, bool DAG, int NR, int ORD, bool R12 = false>
-__global__ __launch_bounds__(256) void k_dslash_xy(Geom g, double diag, const void *__restrict__ U,
+// MP: a block is k z-adjacent planes of one rhs (blockDim.x = k Lx Ly <= 512
+// consecutive sites; the processing order keeps such planes together).  A
+// 14 x 14 plane fills 196 of a 256-thread block's lanes, two planes 392 of
+// 448; and a z neighbour inside the block comes from LDS.
+template <int P, bool DAG, int NR, int ORD, bool R12 = false, bool MP = false>
+__global__ __launch_bounds__(MP ? 512 : 256) void k_dslash_xy(Geom g, double diag, const void *__restrict__ U,
                                                    FieldPtr in, FieldPtr out, int ngroups, int remap, int order) {
     typedef typename real_of<P>::type R;
     typedef typename LdsSpinor<P>::word W;
@@ -111,8 +115,8 @@ __global__ __launch_bounds__(256) void k_dslash_xy(Geom g, double diag, const vo
     }
     __syncthreads();
     cx<R> acc[NR][12];
-    hopping<P, DAG, NR, ORD, true, false, false, R12>(g, s, U, in, rhs0, act, acc, nullptr, xy, s - (int)threadIdx.x,
-                                                      np);
+    hopping<P, DAG, NR, ORD, true, false, false, R12, MP>(g, s, U, in, rhs0, act, acc, nullptr, xy,
+                                                          s - (int)threadIdx.x, np);
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (act >> j & 1) {
@@ -218,11 +222,25 @@ static size_t xy_lds_bytes(int prec, int nr, int np) {
     return (size_t)nr * (prec == WD_F64 ? 192 : 96) * np;
 }
 
+int xy_planes(const Shape &sh, const Geom &g, int prec, int nr) {
+    const int k = sh.planes;
+    const int strip = (sh.strip > 0 && sh.strip < g.L[2]) ? sh.strip : 0;
+    // k z-adjacent planes are consecutive sites in every processing order
+    // whose strips hold whole groups of k planes
+    if (k < 2 || prec == WD_F64 || nr != 1 || k * g.S[2] > 512 || g.L[2] % k || strip % k) return 1;
+    return k;
+}
+
 template <int P, bool DAG, bool R12 = false>
 static void launch_xy(int nr, int ord, dim3 grid, int np, size_t lds, hipStream_t st, const Geom &g, double diag,
-                      const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int od) {
+                      const void *U, FieldPtr in, FieldPtr out, int ngroups, int remap, int od, bool mp) {
     const dim3 block(np);
-    if (nr == 1) {
+    if (mp) {   // several planes per block: one rhs per thread, hop order 3 or 5, not FP64
+        if constexpr (P != P64) {
+            if (ord == 5) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 5, R12, true>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+            else hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 3, R12, true>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
+        }
+    } else if (nr == 1) {
         if (ord == 5) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 5, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
         else if (ord == 3) hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 3, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
         else hipLaunchKernelGGL((k_dslash_xy<P, DAG, 1, 1, R12>), grid, block, lds, st, g, diag, U, in, out, ngroups, remap, od);
@@ -315,27 +333,30 @@ int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void 
     if (sh.xylds && np <= 256) {   // else the site-blocked kernel below
         const int nrx = prec == WD_F64 ? 1 : std::min(nr, 2);
         const int ngx = (nrhs + nrx - 1) / nrx;
-        size_t lds = xy_lds_bytes(prec, nrx, np);
+        const int kp = xy_planes(sh, g, prec, nrx);
+        const int npb = kp * np;   // sites per block
+        size_t lds = xy_lds_bytes(prec, nrx, npb);
         // fewer resident blocks keep an XCD's in-flight data within its L2: the
         // LDS request is padded so at most occ blocks fit the 160 KB of a CU
         if (sh.occ > 0 && (size_t)(163840 / sh.occ) > lds) lds = std::min<size_t>(163840 / sh.occ, 65536);
         FieldPtr fi{(void *)in, g.V, nrhs}, fo{out, g.V, nrhs};
         const void *U = r12 ? gg->U12[WD_F32] : gg->U[prec];
-        const dim3 grid((g.V / np) * ngx);
-        const int ord = sh.ordered == 3 || sh.ordered == 5 ? sh.ordered : 1;
+        const dim3 grid((g.V / npb) * ngx);
+        int ord = sh.ordered == 3 || sh.ordered == 5 ? sh.ordered : 1;
+        if (kp > 1 && ord == 1) ord = 3;
         switch (prec * 2 + (dag ? 1 : 0)) {
-        case 0: launch_xy<P64, false>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
-        case 1: launch_xy<P64, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
+        case 0: launch_xy<P64, false>(nrx, ord, grid, npb, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od, kp > 1); break;
+        case 1: launch_xy<P64, true>(nrx, ord, grid, npb, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od, kp > 1); break;
         case 2:
-            if (r12) launch_xy<P32, false, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od);
-            else launch_xy<P32, false>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od);
+            if (r12) launch_xy<P32, false, true>(nrx, ord, grid, npb, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od, kp > 1);
+            else launch_xy<P32, false>(nrx, ord, grid, npb, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od, kp > 1);
             break;
         case 3:
-            if (r12) launch_xy<P32, true, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od);
-            else launch_xy<P32, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od);
+            if (r12) launch_xy<P32, true, true>(nrx, ord, grid, npb, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od, kp > 1);
+            else launch_xy<P32, true>(nrx, ord, grid, npb, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od, kp > 1);
             break;
-        case 4: launch_xy<P16, false>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
-        case 5: launch_xy<P16, true>(nrx, ord, grid, np, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od); break;
+        case 4: launch_xy<P16, false>(nrx, ord, grid, npb, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od, kp > 1); break;
+        case 5: launch_xy<P16, true>(nrx, ord, grid, npb, lds, st, g, 4.0 + m0, U, fi, fo, ngx, sh.remap, od, kp > 1); break;
         default: return fail(WD_EINVAL, "unknown precision %d", prec);
         }
         WD_HIP(hipGetLastError());

@@ -43,15 +43,18 @@ static bool g_loaded = false;
 // contiguous tiles, z-strips of 4 planes, pipelined hops (plane blocks: the
 // hops that read memory first), 256-thread blocks.
 // The plane-blocked LDS variants are used where an xy-plane has at most 256
-// sites (else the site-blocked kernels).  Operator kernel: two rhs per thread
-// in FP32 / FP16N, one in FP64.  CG phase kernels: one rhs per thread,
-// plane-blocked in FP32 and FP64 (in FP16N the site-blocked kernel is faster).
-// The reliable-update kernel: two rhs per thread.
-// wd_tune_result.site_order: strip | group-major << 16 | plane-blocked << 17 |
-// blocks-per-CU cap << 18 | z-marching << 24 (z-marching: xylds 2)
+// sites (else the site-blocked kernels).  One rhs per thread everywhere.
+// Operator kernel: plane-blocked, two z-adjacent planes per block in FP32
+// with 8 or more rhs.
+// CG phase kernels: plane-blocked (one plane per block) in FP32 and FP64; in
+// FP16N the site-blocked kernel is faster.  The reliable-update kernel:
+// plane-blocked.
+// wd_tune_result.site_order: strip | planes per block << 12 (0: one) |
+// group-major << 16 | plane-blocked << 17 | blocks-per-CU cap << 18 |
+// z-marching << 24 (z-marching: xylds 2) | rhs passes << 25
 int encode_order(const Shape &s) {
-    return s.strip | (s.gmajor << 16) | ((s.xylds ? 1 : 0) << 17) | (s.occ << 18) | ((s.xylds == 2) << 24) |
-           (s.fpass << 25);
+    return s.strip | ((s.planes > 1 ? s.planes : 0) << 12) | (s.gmajor << 16) | ((s.xylds ? 1 : 0) << 17) |
+           (s.occ << 18) | ((s.xylds == 2) << 24) | (s.fpass << 25);
 }
 
 Shape default_shape(int prec, int nrhs, int fam) {
@@ -71,6 +74,12 @@ Shape default_shape(int prec, int nrhs, int fam) {
         // memory hops (z, t) first: 47.6 -> 45.0 us FP32, 99 -> 97 us FP64
         // (fabric reads 242 -> 196 MB); FP16 storage unchanged
         else s.ordered = 5;
+        // FP32 with 8 or more rhs: two z-adjacent planes per block (a 14 x 14
+        // plane fills 196 of 256 lanes, two fill 392 of 448): 14^4 x 16 rhs
+        // 45.1-45.9 -> 42.7-44.5 us.  With one field the halved block count
+        // costs more than it saves (14^4: 7.1 -> 7.7 us, 12^4: 6.5 -> 6.9 us);
+        // FP16 storage gains 1 % (kept at one plane)
+        if (prec == WD_F32 && nrhs >= 8) s.planes = 2;
     } else if (fam == FAM_CG_R) {
         s.nr = 1;
         s.xylds = 1;
@@ -127,6 +136,7 @@ static void load_cache_locked() {
         s.xylds = cs.xylds;
         s.occ = cs.occ;
         s.fpass = cs.fpass;
+        s.planes = cs.planes;
         g_table[k] = {s, us};
     }
     fclose(f);
@@ -154,7 +164,8 @@ void shape_store_persist(const ShapeKey &k, const Shape &s, double us) {
     int ver = 0;
     if (!cache_identity(&arch, &ver)) return;
     const CacheKey ck{k.fam, {k.L[0], k.L[1], k.L[2], k.L[3]}, k.prec, k.nrhs, k.dag};
-    const CacheShape cs{s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor, s.xylds, s.occ, s.fpass};
+    const CacheShape cs{s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor, s.xylds, s.occ, s.fpass,
+                        s.planes};
     const std::string line = cache_line(arch.c_str(), ver, ck, cs, us);
     std::lock_guard<std::mutex> lk(g_mu);
     FILE *f = fopen(path, "a");
@@ -283,11 +294,16 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     WD_CHECK(!(prec == WD_F64 && family != FAM_DSLASH && sh->rhs_per_thread > 2), WD_EINVAL,
              "FP64 CG kernels take <= 2 rhs per thread");
     const int zm = (sh->site_order >> 24) & 1;
-    const int strip = sh->site_order & 0xffff, gmajor = (sh->site_order >> 16) & 1,
+    const int strip = sh->site_order & 0xfff, planes = std::max(1, (sh->site_order >> 12) & 7),
+              gmajor = (sh->site_order >> 16) & 1,
               xylds = (sh->site_order >> 17) & 1 ? 1 + zm : 0, occ = (sh->site_order >> 18) & 0x3f;
     const int fpass = (sh->site_order >> 25) & 0x3f;
-    WD_CHECK(sh->site_order >= 0 && (sh->site_order >> 31) == 0 && occ <= 8, WD_EINVAL, "site_order 0x%x",
-             sh->site_order);
+    WD_CHECK(sh->site_order >= 0 && (sh->site_order >> 31) == 0 && ((sh->site_order >> 15) & 1) == 0 && occ <= 8,
+             WD_EINVAL, "site_order 0x%x", sh->site_order);
+    WD_CHECK(planes == 1 || (((sh->site_order >> 17) & 1) && !zm && sh->rhs_per_thread == 1 && planes <= 4 &&
+                             family != FAM_CG_R && sh->hop_order != 1 && sh->hop_order != 2 && sh->hop_order != 4),
+             WD_EINVAL, "several planes per block: plane-blocked operator and CG phase A/B kernels, one rhs per "
+             "thread, hop order 3 or 5, at most 4 planes");
     WD_CHECK(fpass == 0 || ((family == FAM_CG_A || family == FAM_CG_B) && !gmajor && !zm), WD_EINVAL,
              "passes of rhs groups: CG phase A/B kernels in site-block-major order only");
     WD_CHECK(!zm || ((sh->site_order >> 17) & 1), WD_EINVAL, "z-marching needs the plane-blocked bit");
@@ -308,6 +324,7 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     s.xylds = xylds;
     s.occ = occ;
     s.fpass = fpass;
+    s.planes = planes;
     shape_store(k, s);
     return WD_OK;
 }
@@ -401,16 +418,16 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
         }
         if (!within_rounding(prec, h_ref.data(), h_out.data(), V, nrhs)) {   // rejected
             if (verbose) fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d strip %d gmajor %d "
-                                 "xylds %d occ %d: output differs, rejected\n", s.block, s.nr, s.remap, s.ordered, s.rloop,
-                                 s.strip, s.gmajor, s.xylds, s.occ);
+                                 "xylds %d occ %d planes %d: output differs, rejected\n", s.block, s.nr, s.remap,
+                                 s.ordered, s.rloop, s.strip, s.gmajor, s.xylds, s.occ, s.planes);
             return;
         }
         double us = 0;
         rc = time_shape(g, prec, dag, in, out, nrhs, s, st, 10, &us);
         if (verbose && !rc)
-            fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d strip %d gmajor %d xylds %d occ %d: "
-                    "%.2f us, %.0f GB/s\n", s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor, s.xylds,
-                    s.occ, us, algorithmic_bytes(prec, V, nrhs) / (us * 1e-6) / 1e9);
+            fprintf(stderr, "[wd tune] block %d nr %d remap %d ordered %d rloop %d strip %d gmajor %d xylds %d occ %d "
+                    "planes %d: %.2f us, %.0f GB/s\n", s.block, s.nr, s.remap, s.ordered, s.rloop, s.strip, s.gmajor,
+                    s.xylds, s.occ, s.planes, us, algorithmic_bytes(prec, V, nrhs) / (us * 1e-6) / 1e9);
         if (!rc && us < best_us) { best_us = us; bestshape = s; }
     };
     for (int bi = 0; bi < 3 && !rc; ++bi)
@@ -438,10 +455,13 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
             }
     // plane-blocked variant: one xy-plane per block, x/y neighbours from LDS
     const int np = g->dims[0] * g->dims[1];
+    const Geom geo = make_geom(g);
     if (np <= 256)
-        for (int cand = 0; cand < 2 * 2 * 3 * 8 * 4 && !rc; ++cand) {
+        for (int cand2 = 0; cand2 < 2 * 2 * 3 * 8 * 4 * 2 && !rc; ++cand2) {
             Shape s;
             const int occs[4] = {0, 3, 4, 6}, ords[3] = {1, 3, 5};
+            const int cand = cand2 % 384;
+            s.planes = cand2 < 384 ? 1 : 2;   // two z-adjacent planes per block
             s.occ = occs[cand / 96];
             const int o = (cand / 12) & 7;
             s.block = np;
@@ -456,6 +476,7 @@ int wd_tune_dslash(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger
             if (o > 0 && strips[o & 3] == 0 && (o & 3) != 0) continue;
             if (s.nr > 1 && (prec == WD_F64 || nrhs < 2)) continue;
             if (s.gmajor && (nrhs + s.nr - 1) / s.nr == 1) continue;
+            if (s.planes > 1 && (s.ordered == 1 || xy_planes(s, geo, prec, s.nr) != s.planes)) continue;
             try_shape(s);
         }
     hipFree(in);

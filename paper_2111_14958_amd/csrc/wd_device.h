@@ -427,13 +427,16 @@ template <> struct LdsSpinor<P64> {
 // HALF: `in` holds only the sites of the other parity, site n at index n / 2
 // (even-odd preconditioning; needs an even Lx).
 // R12: U is a reconstruct-12 copy (two rows per link, FP32/FP16).
+// ZIN (with XYLDS; a block of several z-adjacent xy-planes, whose sites are
+// consecutive, all staged in `xy`): a z neighbour that lies in the block's
+// planes is read from LDS, the others from memory.
 // ZM (with XYLDS; for a block that walks a column of xy-planes in z): `zn` is
 // the LDS copy of the next plane, which supplies the forward z neighbour.  The
 // backward z hop is not formed here: acc starts from `carry`, which holds it
 // on entry, and on return `carry` holds the backward z hop of site s + z,
 // (1 + SB gamma_z) U_z(s)^dag psi(s), made from the link the forward z hop loads.
 template <int P, bool DAG, int NR, int ORDERED = 1, bool XYLDS = false, bool HALF = false, bool ZM = false,
-          bool R12 = false>
+          bool R12 = false, bool ZIN = false>
 __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, const FieldPtr &in,
                                         int rhs0, unsigned act, cx<typename real_of<P>::type> acc[NR][12],
                                         const cx<typename real_of<P>::type> (*first)[12] = nullptr,
@@ -441,6 +444,7 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
                                         int np = 0, const typename LdsSpinor<P>::word *zn = nullptr,
                                         cx<typename real_of<P>::type> (*carry)[12] = nullptr) {
     static_assert(!ZM || XYLDS, "z-marching reads the x and y neighbours from LDS");
+    static_assert(!ZIN || (XYLDS && !ZM && !HALF), "z neighbours from LDS: multi-plane blocks only");
     typedef typename real_of<P>::type R;
     constexpr int SF = DAG ? +1 : -1;
     constexpr int SB = -SF;
@@ -516,7 +520,11 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
                 cx<R> p[12], h[6], w[6];
                 if constexpr (XYLDS && MU < 2) LdsSpinor<P>::get(xy, np, j, nb - plane0, p);
                 else if constexpr (ZM && MU == 2) LdsSpinor<P>::get(zn, np, j, s - plane0, p);
-                else Spinor<P>::load(in, rhs0 + j, HALF ? nb >> 1 : nb, p);
+                else if constexpr (ZIN && MU == 2) {
+                    const int li = nb - plane0;   // in the block's planes: only one wave can diverge
+                    if ((unsigned)li < (unsigned)np) LdsSpinor<P>::get(xy, np, j, li, p);
+                    else Spinor<P>::load(in, rhs0 + j, nb, p);
+                } else Spinor<P>::load(in, rhs0 + j, HALF ? nb >> 1 : nb, p);
                 project<MU, S>(p, h);
                 if constexpr (FWD) link_mul(u, h, w);
                 else link_adj_mul(u, h, w);

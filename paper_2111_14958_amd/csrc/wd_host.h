@@ -52,6 +52,8 @@ struct Shape {
     int occ = 0;             // plane-blocked operator: at most occ blocks per CU (0: no limit)
     int fpass = 0;           // CG phases: each eighth of the site blocks is walked in passes of
                              // fpass rhs groups (0: all groups of a site block together)
+    int planes = 1;          // plane-blocked, one rhs per thread, FP32/FP16 storage: k z-adjacent
+                             // xy-planes per block (k Lx Ly <= 512 sites)
 };
 
 // Key of the launch-shape table: lattice, precision, rhs count, dagger, and
@@ -85,6 +87,10 @@ struct wd_gauge {
 
 namespace wd {
 Geom make_geom(const wd_gauge *g);
+// planes per plane-blocked block that shape sh gets on lattice g (1 where k
+// planes do not fit: FP64 storage, several rhs per thread, k Lx Ly > 512, Lz or
+// the strip width not a multiple of k)
+int xy_planes(const Shape &sh, const Geom &g, int prec, int nr);
 // Launchers implemented in the .hip units (all asynchronous on `stream`).
 // canonical complex128 links -> packed precision prec; the t-links of the last
 // time slice carry the boundary sign (tsign) from here on

@@ -11,6 +11,11 @@
 * Hop orders 1, 3 and 5 (5: the hops that read memory before the ones that
   read LDS) of the plane-blocked operator, every precision.
 * CG with phases A and B in hop orders 1, 3 and 5: oracle true residual.
+* Several z-adjacent xy-planes per block (xy_planes 2..4) for the operator
+  (the z neighbours inside the block read from LDS) and for CG phases A and
+  B, every precision (FP64, and shapes where k planes do not fit, fall back
+  to one plane), against the oracle site by site and against one plane per
+  block; shape_set refuses the combinations the kernels do not have.
 """
 import numpy as np
 import pytest
@@ -147,3 +152,82 @@ def test_cg_phase_hop_orders(inner):
     kappa = (8.0 + m0) / m0
     for s in sols[1:]:
         assert rel(s, sols[0]) <= kappa * 2e-10
+
+
+MP_CASES = [((3, 5, 4, 6), 3, 0.05),        # 15-site planes; Lz 4 takes 2 and 4 planes
+            ((8, 8, 6, 6), 4, 0.05),        # 64-site planes; Lz 6 takes 2 and 3 planes
+            ((14, 14, 14, 14), 16, 0.05)]   # the benchmark volume: 2 planes of 196 sites
+
+
+@pytest.mark.parametrize("dims,nrhs,m0", MP_CASES, ids=[str(c[0]) for c in MP_CASES])
+def test_multi_plane_operator_matches_oracle(dims, nrhs, m0):
+    U, psi = field_set(dims, 0.5, 1100 + sum(dims), nrhs, 1150 + sum(dims))
+    np_ = dims[0] * dims[1]
+    ks = [k for k in (2, 3, 4) if k * np_ <= 512] + ([3] if 3 * np_ > 512 else [])   # 3 at 14^4: falls back
+    cache = {}
+    for r12, prec in ((False, wd.F64), (False, wd.F32), (True, wd.F32), (False, wd.F16N)):
+        g = wd.Gauge(dev(U), dims, -1, recon12=r12)
+        x = dev(psi)
+        one = {}
+        for dag in (False, True):   # one plane per block, the same strip and hop order
+            wd.shape_set(g, prec, nrhs, dag, wd.FAMILY_DSLASH, np_, hop_order=5, strip=0, xy_lds=1)
+            one[dag] = host(wd.dslash(g, m0, x, prec, dagger=dag))
+        for k in ks:
+            for strip in (0, 2, 4):
+                for ho in (3, 5):
+                    for dag in (False, True):
+                        wd.shape_set(g, prec, nrhs, dag, wd.FAMILY_DSLASH, k * np_, hop_order=ho, strip=strip,
+                                     xy_lds=1, xy_planes=k)
+                        assert wd.shape_get(g, prec, nrhs, dag, wd.FAMILY_DSLASH)["xy_planes"] == k
+                    for dag in (False, True):
+                        what = f"{k} planes {NAMES[prec]} r12={r12} strip={strip} hop order {ho} dag={dag}"
+                        say(what, dims, nrhs)
+                        got = host(wd.dslash(g, m0, x, prec, dagger=dag))
+                        _check(got, U, psi, dims, m0, dag, prec, what, cache)
+                        # the same sums per site as one plane per block, up to rounding
+                        assert rel(got, one[dag]) <= {wd.F64: 1e-14, wd.F32: 2e-6, wd.F16N: 2e-3}[prec], what
+        g.close()
+
+
+def test_multi_plane_shapes_refused():
+    dims = (8, 8, 6, 6)
+    U, _ = field_set(dims, 0.5, 1201, 1, 1202)
+    g = wd.Gauge(dev(U), dims, -1)
+    bad = [dict(family=wd.FAMILY_DSLASH, block=128, hop_order=5, strip=0, xy_lds=0, xy_planes=2),   # site blocks
+           dict(family=wd.FAMILY_DSLASH, block=128, rhs_per_thread=2, hop_order=3, xy_lds=1, xy_planes=2),
+           dict(family=wd.FAMILY_DSLASH, block=128, hop_order=1, xy_lds=1, xy_planes=2),
+           dict(family=wd.FAMILY_DSLASH, block=128, hop_order=3, xy_lds=2, xy_planes=2),   # z-marching
+           dict(family=wd.FAMILY_DSLASH, block=320, hop_order=5, xy_lds=1, xy_planes=5),
+           dict(family=wd.FAMILY_CG_R, block=128, hop_order=3, xy_lds=1, xy_planes=2)]
+    for kw in bad:
+        fam = kw.pop("family")
+        with pytest.raises(RuntimeError):
+            wd.shape_set(g, wd.F32, 4, False, fam, **kw)
+    g.close()
+
+
+@pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
+def test_cg_phase_multi_plane(inner):
+    """Phases A and B with 1, 2 and 3 z-adjacent planes per block (hop order 5,
+    64-site planes: blocks of 64, 128 and 192 threads; FP64 falls back to one
+    plane): oracle true residual <= 1e-10, and the solutions agree with each
+    other to the solver tolerance."""
+    dims, m0 = (8, 8, 6, 6), 0.1
+    U, eta = field_set(dims, 0.5, 1301, 4, 1302)
+    g = wd.Gauge(dev(U), dims, -1, recon12=True)
+    p = wd.cg_default_params(inner=inner, reliable_every=0 if inner == wd.F64 else 50)
+    sols = []
+    for k in (1, 2, 3):
+        for fam, dag in ((wd.FAMILY_CG_A, True), (wd.FAMILY_CG_B, False)):
+            wd.shape_set(g, inner, 4, dag, fam, 256, 1, 1, 5, 1, 0, 0, 1, xy_planes=k)
+            assert wd.shape_get(g, inner, 4, dag, fam)["xy_planes"] == k
+        say("cg planes", k, NAMES[inner])
+        x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+        assert rc == wd.WD_OK, reps
+        res = oracle.true_residual(U, eta, host(x), dims, m0, -1)
+        assert np.all(res <= 1e-10 * 1.0000001), res
+        sols.append(host(x))
+    kappa = (8.0 + m0) / m0
+    for s_ in sols[1:]:
+        assert rel(s_, sols[0]) <= kappa * 2e-10
+    g.close()

@@ -1,6 +1,7 @@
 """The autotuner's cache file format (csrc/tune_cache.h) round trip, without a
 GPU: a small host program built with g++ writes entries for every kernel family
-and shape field (hop order 5, z-marching, passes of rhs groups), parses them
+and shape field (hop order 5, z-marching, passes of rhs groups, planes per
+block), parses them
 back, and checks that lines of another arch or runtime version, of another
 format version and malformed lines are skipped."""
 import os
@@ -21,7 +22,7 @@ static bool same(const CacheKey &a, const CacheKey &b) {
 static bool same(const CacheShape &a, const CacheShape &b) {
     return a.block == b.block && a.nr == b.nr && a.remap == b.remap && a.ordered == b.ordered &&
            a.rloop == b.rloop && a.strip == b.strip && a.gmajor == b.gmajor && a.xylds == b.xylds &&
-           a.occ == b.occ && a.fpass == b.fpass;
+           a.occ == b.occ && a.fpass == b.fpass && a.planes == b.planes;
 }
 int main() {
     const char *arch = "gfx950:sramecc+:xnack-";
@@ -32,7 +33,7 @@ int main() {
             for (int xy : {0, 1, 2}) {
                 CacheKey k{fam, {14, 12, 16, 32}, fam % 3, 16 - fam, fam & 1};
                 CacheShape s{xy ? 196 : 256, 1 + (ord == 3), 1, ord, 1, xy == 2 ? 2 : 4, xy == 2, xy, 3 * (xy == 1),
-                             fam == 1 ? 7 : 0};
+                             fam == 1 ? 7 : 0, xy == 1 && ord == 5 ? 2 : 1};
                 std::string line = cache_line(arch, ver, k, s, 12.345);
                 line.pop_back();   // the reader strips the newline
                 CacheKey k2;
@@ -50,8 +51,10 @@ int main() {
         "",
         "gfx950 14 14 14 14 1 16 0 256 1 1 3 1 4 0 1 0 45.000",   // the old format: no arch/runtime/family
         "wdtune 1 gfx950:sramecc+:xnack- 70226015 0 14 14 14 14 1 16 0 196 1 1 5 1 4 0 1 0 0 45.000",
-        "wdtune 2 gfx950:sramecc+:xnack- 70226015 0 14 14 14 14 1 16 0 196 1 1 5 1 4 0 1 0 45.000",
-        "wdtune 2 gfx950:sramecc+:xnack- 70226015 0 14 14 14 14 1 16 0 196 1 1 5 1 4 0 1 0 0 45.000 extra",
+        "wdtune 2 gfx950:sramecc+:xnack- 70226015 0 14 14 14 14 1 16 0 196 1 1 5 1 4 0 1 0 0 45.000",   // version 2
+        "wdtune 3 gfx950:sramecc+:xnack- 70226015 0 14 14 14 14 1 16 0 196 1 1 5 1 4 0 1 0 0 45.000",   // a field short
+        "wdtune 3 gfx950:sramecc+:xnack- 70226015 0 14 14 14 14 1 16 0 196 1 1 5 1 4 0 1 0 0 2 45.000 extra",
+        "wdtune 3 gfx950:sramecc+:xnack- 70226015 0 14 14 14 14 1 16 0 196 1 1 5 1 4 0 1 0 0 2x 45.000",
     };
     for (const char *b : bad)
         if (cache_parse(b, "gfx950:sramecc+:xnack-", 70226015, &k, &s, &us)) { printf("accepted: %s\n", b); return 4; }
