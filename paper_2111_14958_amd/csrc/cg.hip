@@ -49,16 +49,25 @@ namespace wd {
 // chunk, first = 1 for the chunk's first iteration (see phaseA_tile); -1: the
 // three-launch iteration with k_finish after phase B.
 // MP: plane blocks of several z-adjacent planes (up to 512 threads).
+// Waves per SIMD asked of the register allocator: 3 for the FP64 kernels with
+// one rhs per thread (<= 168 VGPRs; left to the compiler it takes 172-182 for
+// some, which allows 2), except the two that would spill to reach it
+// (phase B with hop order 5, and site-blocked with hop order 3).
+template <int P, int NR, int ORD, bool XY, bool B>
+constexpr int phase_waves() {
+    return (P == P64 && NR == 1 && !(B && (ORD == 5 || (ORD == 3 && !XY)))) ? 3 : 1;
+}
+
 template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false, bool MP = false>
-__global__ __launch_bounds__(MP ? 512 : 256) void k_phaseA(const Prob *__restrict__ probs, int nprob, int remap,
-                                                           int par, int first) {
+__global__ __launch_bounds__(MP ? 512 : 256, (phase_waves<P, NR, ORD, XY, false>())) void k_phaseA(
+    const Prob *__restrict__ probs, int nprob, int remap, int par, int first) {
     WD_KERNEL_PROLOGUE(KA)
     phaseA_tile<P, NR, ORD, XY, R12, NT, true, MP>(pr, t_, par, first);
 }
 
 template <int P, int NR, int ORD, bool XY, bool R12 = false, bool NT = false, bool MP = false>
-__global__ __launch_bounds__(MP ? 512 : 256) void k_phaseB(const Prob *__restrict__ probs, int nprob, int remap,
-                                                           int par, int /*first*/) {
+__global__ __launch_bounds__(MP ? 512 : 256, (phase_waves<P, NR, ORD, XY, true>())) void k_phaseB(
+    const Prob *__restrict__ probs, int nprob, int remap, int par, int /*first*/) {
     WD_KERNEL_PROLOGUE(KB)
     phaseB_tile<P, NR, ORD, XY, R12, NT, true, MP>(pr, t_, par);
 }

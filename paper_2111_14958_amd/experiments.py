@@ -4,7 +4,7 @@
     python -m paper_2111_14958_amd.experiments fig2    # whole-CG speedup vs compute units
     python -m paper_2111_14958_amd.experiments serve   # open-loop serving latency
     python -m paper_2111_14958_amd.experiments serve eo   # the same, even-odd preconditioned
-    python -m paper_2111_14958_amd.experiments solve   # one profiled 14^4 x 16 solve
+    python -m paper_2111_14958_amd.experiments solve [f32|f64|f16n]   # one profiled 14^4 x 16 solve
     python -m paper_2111_14958_amd.experiments dslash f32|f64|f16n hot|cold [reps]
                                                        # the 14^4 x 16 operator alone
 
@@ -169,10 +169,10 @@ def serve(n_requests=600, rates=(0.25, 0.5, 1.0, 1.5, 2.0), pool=2, arena_gib=24
                           **res}), flush=True)
 
 
-def solve():
-    """One mixed-precision solve of the 14^4 x 16 benchmark workload (reconstruct-12
-    links, as the benchmark) with the
-    library's profiling mode on (every chunk kernel launched on its own,
+def solve(inner_name="f32"):
+    """One solve of the 14^4 x 16 benchmark workload (reconstruct-12 links, as the
+    benchmark; inner precision f32 (mixed, the benchmark's), f64 or f16n) with
+    the library's profiling mode on (every chunk kernel launched on its own,
     bracketed by events), then one 256 MiB streaming copy of known size: the
     program that hardware-counter runs profile (the copy calibrates the byte
     counters).  Prints the per-kernel statistics as JSON."""
@@ -186,7 +186,8 @@ def solve():
     src = wdgen.mixed_sources(dims, cfg["n_point"], cfg["n_gauss"], cfg["src_seed"])
     g = wd.Gauge(torch.from_numpy(U).cuda(), dims, recon12=True)   # as the benchmark
     dsrc = torch.from_numpy(src).cuda()
-    p = wd.cg_default_params(tol=cfg["tol"], inner=wd.F32, reliable_every=50)
+    inner = {"f64": wd.F64, "f32": wd.F32, "f16n": wd.F16N}[inner_name]
+    p = wd.cg_default_params(tol=cfg["tol"], inner=inner, reliable_every=0 if inner == wd.F64 else 50)
     sol = torch.zeros_like(dsrc)
     ws = torch.empty(wd.cg_workspace_bytes(g, dsrc.shape[0], p), dtype=torch.uint8, device="cuda")
     wd.profile_reset()
@@ -199,7 +200,7 @@ def solve():
     b = torch.empty_like(a)
     wd.stream(wd.STREAM_COPY, a, b, a.numel())
     torch.cuda.synchronize()
-    print(json.dumps({"solve": "14^4 x 16 mixed", "rc": rc, "iters": max(r["iters"] for r in reps),
+    print(json.dumps({"solve": "14^4 x 16, inner " + inner_name, "rc": rc, "iters": max(r["iters"] for r in reps),
                       "kernels": prof, "copy_bytes_each_way": a.numel()}), flush=True)
 
 
@@ -249,5 +250,7 @@ if __name__ == "__main__":
         serve(eo=True)
     elif sys.argv[1] == "dslash":
         dslash(*sys.argv[2:])
+    elif sys.argv[1] == "solve":
+        solve(*sys.argv[2:])
     else:
         {"fig1": fig1, "fig2": fig2, "serve": serve, "solve": solve}[sys.argv[1]]()
