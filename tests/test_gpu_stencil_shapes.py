@@ -164,6 +164,8 @@ def test_multi_plane_operator_matches_oracle(dims, nrhs, m0):
     U, psi = field_set(dims, 0.5, 1100 + sum(dims), nrhs, 1150 + sum(dims))
     np_ = dims[0] * dims[1]
     ks = [k for k in (2, 3, 4) if k * np_ <= 512] + ([3] if 3 * np_ > 512 else [])   # 3 at 14^4: falls back
+    # processing orders (strip, XCD remap, group-major); the benchmark volume takes the default one
+    orders = ((0, 1, 0), (2, 1, 0), (4, 1, 0), (2, 0, 1)) if np_ * dims[2] * dims[3] <= 8 ** 4 else ((4, 1, 0),)
     cache = {}
     for r12, prec in ((False, wd.F64), (False, wd.F32), (True, wd.F32), (False, wd.F16N)):
         g = wd.Gauge(dev(U), dims, -1, recon12=r12)
@@ -173,14 +175,15 @@ def test_multi_plane_operator_matches_oracle(dims, nrhs, m0):
             wd.shape_set(g, prec, nrhs, dag, wd.FAMILY_DSLASH, np_, hop_order=5, strip=0, xy_lds=1)
             one[dag] = host(wd.dslash(g, m0, x, prec, dagger=dag))
         for k in ks:
-            for strip in (0, 2, 4):
+            for strip, remap, gm in orders:
                 for ho in (3, 5):
                     for dag in (False, True):
-                        wd.shape_set(g, prec, nrhs, dag, wd.FAMILY_DSLASH, k * np_, hop_order=ho, strip=strip,
-                                     xy_lds=1, xy_planes=k)
+                        wd.shape_set(g, prec, nrhs, dag, wd.FAMILY_DSLASH, k * np_, xcd_remap=remap, hop_order=ho,
+                                     strip=strip, group_major=gm, xy_lds=1, xy_planes=k)
                         assert wd.shape_get(g, prec, nrhs, dag, wd.FAMILY_DSLASH)["xy_planes"] == k
                     for dag in (False, True):
-                        what = f"{k} planes {NAMES[prec]} r12={r12} strip={strip} hop order {ho} dag={dag}"
+                        what = (f"{k} planes {NAMES[prec]} r12={r12} strip={strip} remap={remap} group-major={gm} "
+                                f"hop order {ho} dag={dag}")
                         say(what, dims, nrhs)
                         got = host(wd.dslash(g, m0, x, prec, dagger=dag))
                         _check(got, U, psi, dims, m0, dag, prec, what, cache)
@@ -206,14 +209,19 @@ def test_multi_plane_shapes_refused():
     g.close()
 
 
+MP_CG_CASES = [((8, 8, 6, 6), 1301),     # 64-site planes: blocks of 64, 128 and 192 threads
+               ((10, 10, 6, 4), 1401)]   # 100-site planes: 200 and 300 sites in blocks of 256 and 320
+                                         # threads (the idle lanes of the last wave hold no site)
+
+
 @pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
-def test_cg_phase_multi_plane(inner):
-    """Phases A and B with 1, 2 and 3 z-adjacent planes per block (hop order 5,
-    64-site planes: blocks of 64, 128 and 192 threads; FP64 falls back to one
-    plane): oracle true residual <= 1e-10, and the solutions agree with each
-    other to the solver tolerance."""
-    dims, m0 = (8, 8, 6, 6), 0.1
-    U, eta = field_set(dims, 0.5, 1301, 4, 1302)
+@pytest.mark.parametrize("dims,seed", MP_CG_CASES, ids=[str(c[0]) for c in MP_CG_CASES])
+def test_cg_phase_multi_plane(inner, dims, seed):
+    """Phases A and B with 1, 2 and 3 z-adjacent planes per block (hop order 5;
+    FP64 falls back to one plane): oracle true residual <= 1e-10, and the
+    solutions agree with each other to the solver tolerance."""
+    m0 = 0.1
+    U, eta = field_set(dims, 0.5, seed, 4, seed + 1)
     g = wd.Gauge(dev(U), dims, -1, recon12=True)
     p = wd.cg_default_params(inner=inner, reliable_every=0 if inner == wd.F64 else 50)
     sols = []
