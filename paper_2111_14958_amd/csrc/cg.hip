@@ -99,10 +99,10 @@ __global__ __launch_bounds__(256) void k_ru1(const Prob *__restrict__ probs, int
     ru1_tile<P>(pr, t_);
 }
 
-template <int P, int NR, bool XY = false>
+template <int P, int NR, bool XY = false, bool ZX = false>
 __global__ __launch_bounds__(256) void k_ru2(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KR2)
-    ru2_tile<P, NR, XY>(pr, t_);
+    ru2_tile<P, NR, XY, ZX>(pr, t_);
 }
 
 __global__ __launch_bounds__(256) void k_norm(const Prob *__restrict__ probs, int nprob, int remap) {
@@ -412,12 +412,13 @@ static void launch_B(const KindShape &k, hipStream_t st, const Prob *d, int n, i
         launch_AB_o<P, 3, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, 0);
     else launch_AB_o<P, 1, true>(k.nr, k.xy, k.lds, k.r12, k.nt, k.grid, k.block, st, d, n, k.remap, par, 0);
 }
-template <int P>
+template <int P, bool ZX = false>
 static void launch_R2(int nr, int xy, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (xy) hipLaunchKernelGGL((k_ru2<P, 1, true>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else if (nr == 1) hipLaunchKernelGGL((k_ru2<P, 1>), dim3(grid), dim3(blk), 0, st, d, n, remap);
-    else hipLaunchKernelGGL((k_ru2<P, 2>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    if (xy) hipLaunchKernelGGL((k_ru2<P, 1, true, ZX>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else if (nr == 1) hipLaunchKernelGGL((k_ru2<P, 1, false, ZX>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    else hipLaunchKernelGGL((k_ru2<P, 2, false, ZX>), dim3(grid), dim3(blk), 0, st, d, n, remap);
 }
+
 
 template <int P, bool S4>
 static void launch_BS(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
@@ -503,6 +504,21 @@ void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const
     // with the fused finish, phase A finishes the previous iteration and a
     // trailing finish the chunk's last (launch_iterations)
     if (reduces && !(par >= 0 && (kind == KA || kind == KB))) launch_finish_after(kind, ls, st, d, nprob);
+}
+
+// The first true residual of a solve (R2).  x_zero: x64 is zero (no initial
+// guess), so r = eta is formed without the FP64 stencil (bitwise the same).
+void launch_first_residual(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, bool x_zero) {
+    if (!x_zero || ls.eo) {
+        launch_kind(KR2, inner, ls, st, d, nprob);
+        return;
+    }
+    const KindShape &k = ls.k[KR2];
+    if (k.grid <= 0) return;
+    if (inner == P64) launch_R2<P64, true>(k.nr, k.xy, k.grid, k.block, st, d, nprob, k.remap);
+    else if (inner == P32) launch_R2<P32, true>(k.nr, k.xy, k.grid, k.block, st, d, nprob, k.remap);
+    else launch_R2<P16, true>(k.nr, k.xy, k.grid, k.block, st, d, nprob, k.remap);
+    launch_finish(KR2, st, d, nprob);
 }
 
 void launch_iterations(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, int K) {
@@ -1015,7 +1031,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
         launch_eo_source(dprob, Vf, nrhs, st);
         launch_kind(KER2A, p.inner, ls, st, dprob, 1);
     }
-    launch_kind(KR2, p.inner, ls, st, dprob, 1);
+    launch_first_residual(p.inner, ls, st, dprob, 1, !p.use_x0);
     if (!bicg) launch_kind(KC, p.inner, ls, st, dprob, 1);
     const int *dabort = persistent ? (const int *)(w + L.bar + 128) : nullptr;
     launch_summary(st, dprob, 1, dsum, dabort);

@@ -860,7 +860,9 @@ __device__ __forceinline__ void ru1_tile(const Prob &pr, int t) {
 // r = eta - D x64 in FP64 with FP64 links; r_lo = r rounded to the inner
 // precision; partial |r|^2 in FP64 (frozen rhs).  XY: one xy-plane per block,
 // x64 of the plane staged in LDS (x and y neighbours and the site itself).
-template <int P, int NR, bool XY = false>
+// ZX: x64 is zero (the first residual of a solve without an initial guess):
+// D x64 is exactly zero, so r = eta without the stencil, bitwise the same.
+template <int P, int NR, bool XY = false, bool ZX = false>
 __device__ __forceinline__ void ru2_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     typedef typename LdsSpinor<P64>::word W;
@@ -875,18 +877,25 @@ __device__ __forceinline__ void ru2_tile(const Prob &pr, int t) {
     const Geom g = pr.g;
     const int np = g.S[2];
     FieldPtr fx{pr.x64, g.V, pr.nrhs}, fe{pr.eta64, g.V, pr.nrhs}, fr{pr.r, g.V, pr.nrhs};
-    if (XY && act) stage_plane<P64, NR>(fx, rhs0, act, s, g.V, xy, np);
+    if (!ZX && XY && act) stage_plane<P64, NR>(fx, rhs0, act, s, g.V, xy, np);
     if (act && s < g.V) {
         const void *U = pr.U64;
         cx<double> acc[NR][12];
-        hopping<P64, false, NR, XY ? 3 : 1, XY>(g, s, U, fx, rhs0, act, acc, nullptr, xy, s - (int)threadIdx.x, np);
+        if constexpr (!ZX)
+            hopping<P64, false, NR, XY ? 3 : 1, XY>(g, s, U, fx, rhs0, act, acc, nullptr, xy, s - (int)threadIdx.x,
+                                                    np);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
                 cx<double> x[12], e[12], o[12];
-                if constexpr (XY) LdsSpinor<P64>::get(xy, np, j, threadIdx.x, x);
-                else Spinor<P64>::load(fx, rhs0 + j, s, x);
-                wilson_finish<double>(pr.diag, x, acc[j], o);
+                if constexpr (ZX) {
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) o[k] = {0.0, 0.0};
+                } else {
+                    if constexpr (XY) LdsSpinor<P64>::get(xy, np, j, threadIdx.x, x);
+                    else Spinor<P64>::load(fx, rhs0 + j, s, x);
+                    wilson_finish<double>(pr.diag, x, acc[j], o);
+                }
                 Spinor<P64>::load(fe, rhs0 + j, s, e);
                 cx<R> rl[12];
                 double n = 0;

@@ -49,6 +49,8 @@ void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const
 // K CG iterations: with ls.fused, phases A and B per iteration (A finishing the
 // iteration before it) and one trailing finish; else A, B (with its finish)
 // and C, with the even-odd hops where ls.eo.
+// the first true residual of a solve; x_zero: x64 is zero (no stencil needed)
+void launch_first_residual(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, bool x_zero);
 void launch_iterations(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, int K);
 // WD_CG_UNFUSED set (and not "0"): solves and the server use the three-launch iteration
 bool unfused_requested();

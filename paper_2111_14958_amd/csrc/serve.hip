@@ -229,7 +229,7 @@ static int init_slot(wd_server *s, Slot &sl) {
         launch_eo_source(dp, vf, rq.nrhs, st);
         launch_kind(KER2A, inner, ls, st, dp, 1);
     }
-    launch_kind(KR2, inner, ls, st, dp, 1);
+    launch_first_residual(inner, ls, st, dp, 1, !rq.params.use_x0);
     launch_kind(KC, inner, ls, st, dp, 1);
     WD_HIP(hipGetLastError());
     return WD_OK;
