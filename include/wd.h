@@ -155,9 +155,10 @@ int wd_dslash_noalloc(const wd_gauge *g, double m0, int32_t prec, int32_t dagger
 /* ------------------------------------------- coordinate-format operator */
 /* The operator stored explicitly as in Sec. 2 of the paper: arrays Val, Row,
  * Col of the non-zero entries of D (or D^dagger), 49 per row (the diagonal,
- * then per direction x, y, z, t the 6 forward and 6 backward entries), rows
- * r = 12 site + 3 spin + colour stored one after the other; duplicate entries
- * of extent-2 lattices are kept.  Built on the device from the gauge handle's
+ * then per direction x, y, z, t the 6 forward and 6 backward entries) of the
+ * rows r = 12 site + 3 spin + colour; entry k of row r sits at index
+ * k * rows + r (entry 0 of every row first); duplicate entries of extent-2
+ * lattices are kept.  Built on the device from the gauge handle's
  * FP64 links; prec is WD_F64 (complex128 values) or WD_F32 (complex64).
  * Row and Col are int32.  The handle owns the arrays (nnz*(16 or 8) + nnz*8
  * bytes). */

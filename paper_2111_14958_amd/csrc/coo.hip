@@ -7,9 +7,12 @@
 // row: row r = 12 n + 3 alpha + a (site n, spin alpha, colour a) holds 49
 // entries -- the diagonal (4 + m0), then for mu = x, y, z, t the forward hop
 // (spin beta with (1 -+ gamma_mu)_{alpha beta} != 0, colours b) and the
-// backward hop.  Entries of one row are stored contiguously, so the product
-// can give each row to one thread and sum its 49 terms in storage order
-// without atomics; Row is kept as the format defines it (and for export).
+// backward hop.  Entry k of row r is stored at index k * rows + r (entry 0 of
+// every row, then entry 1, ...): the product gives each row to one thread,
+// which sums its 49 terms in entry order without atomics, and the threads of
+// a wavefront read consecutive values and column indices (a row-after-row
+// order would put a wavefront's loads 49 entries apart).  Row is kept as the
+// format defines it (and for export).
 // On lattices of extent 2 the forward and backward columns coincide; both
 // entries are kept and summed, like duplicate coordinate entries.
 #include "wd_device.h"
@@ -43,12 +46,13 @@ __global__ void k_coo_build(Geom g, double diag, const double2 *__restrict__ U64
     const int s = r / 12, al = (r % 12) / 3, a = r % 3;
     int c[4];
     site_coords(g, s, c);
-    const size_t base = (size_t)r * COO_PER_ROW;
+    const size_t rows = (size_t)12 * g.V;
     int k = 0;
     auto put = [&](int cc, double re, double im) {
-        val[base + k] = {(T)re, (T)im};
-        row[base + k] = r;
-        col[base + k] = cc;
+        const size_t e = (size_t)k * rows + r;
+        val[e] = {(T)re, (T)im};
+        row[e] = r;
+        col[e] = cc;
         ++k;
     };
     put(r, diag, 0.0);
@@ -83,24 +87,35 @@ __global__ void k_coo_build(Geom g, double diag, const double2 *__restrict__ U64
     }
 }
 
-// out[row] = sum over the row's entries of Val * in[Col], nrhs vectors.
+// out[row] = sum over the row's entries of Val * in[Col], nrhs vectors, up to
+// four at a time (each entry read once per group of four vectors).  Every sum
+// runs over the row's entries in entry order.
 template <typename T>
 __global__ void k_coo_spmv(const typename CVal<T>::type *__restrict__ val, const int *__restrict__ col,
                            const typename CVal<T>::type *__restrict__ in, typename CVal<T>::type *__restrict__ out,
                            int nrows, int nrhs) {
+    typedef typename CVal<T>::type C;
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrows) return;
-    const size_t base = (size_t)r * COO_PER_ROW;
-    for (int v = 0; v < nrhs; ++v) {
-        const typename CVal<T>::type *x = in + (size_t)v * nrows;
-        T sre = 0, sim = 0;
+    for (int v0 = 0; v0 < nrhs; v0 += 4) {
+        const int nv = min(4, nrhs - v0);
+        T sre[4] = {0, 0, 0, 0}, sim[4] = {0, 0, 0, 0};
         for (int k = 0; k < COO_PER_ROW; ++k) {
-            const typename CVal<T>::type a = val[base + k];
-            const typename CVal<T>::type b = x[col[base + k]];
-            sre += a.x * b.x - a.y * b.y;
-            sim += a.x * b.y + a.y * b.x;
+            const size_t e = (size_t)k * nrows + r;
+            const C a = val[e];
+            const int c = col[e];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j < nv) {
+                    const C b = in[(size_t)(v0 + j) * nrows + c];
+                    sre[j] += a.x * b.x - a.y * b.y;
+                    sim[j] += a.x * b.y + a.y * b.x;
+                }
+            }
         }
-        out[(size_t)v * nrows + r] = {sre, sim};
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j < nv) out[(size_t)(v0 + j) * nrows + r] = {sre[j], sim[j]};
     }
 }
 

@@ -27,7 +27,8 @@ def test_coo_entries_bit_exact(dims, dagger):
     V = wdgen.volume(dims)
     assert c.nnz == 588 * V and c.rows == 12 * V
     val, row, col = (host(t) for t in c.export())
-    assert np.all(np.diff(row) >= 0)            # stored row by row
+    rows = 12 * V                                 # entry k of row r at k * rows + r
+    assert np.array_equal(row.reshape(49, rows), np.broadcast_to(np.arange(rows), (49, rows)))
     ov, orow, ocol = oracle.coo(U, dims, 0.07, dagger=dagger)
     a = _sorted(val, row.astype(np.int64), col.astype(np.int64))
     b = _sorted(ov, orow, ocol)
@@ -40,11 +41,11 @@ def test_coo_product_matches_oracle(prec, tol):
     import torch
     dims, m0 = (8, 8, 8, 8), 0.05
     U = wdgen.gauge_field(dims, 0.5, 9)
-    psi = wdgen.gaussian_source(dims, 3, 10)
+    psi = wdgen.gaussian_source(dims, 6, 10)   # two groups of vectors: 4 and 2
     say("coo spmv", prec)
     g = wd.Gauge(dev(U), dims)
     c = wd.Coo(g, m0, prec)
-    x = dev(psi).reshape(3, -1)
+    x = dev(psi).reshape(6, -1)
     if prec == wd.F32:
         x = x.to(torch.complex64)
     got = host(c.spmv(x)).reshape(psi.shape)
