@@ -599,7 +599,7 @@ WsLayout ws_layout(int64_t V, int nrhs, int inner, int method, int eo) {
     L.prob = o; o += al256(sizeof(Prob));
     L.scal = o; o += al256(sizeof(Scal) * nrhs);
     L.scal2 = o; o += al256(sizeof(Scal) * nrhs);
-    L.bar = o; o += 256;
+    L.bar = o; o += BAR_BYTES;
     L.summary = o; o += 256;
     L.part = o; o += al256((size_t)((V + 63) / 64) * nrhs * PSTRIDE * sizeof(double));
     L.eta64 = o; o += al256(spinor_bytes(WD_F64, Vf, nrhs));
@@ -1007,7 +1007,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     init_scalars(sc, nrhs);
     WD_HIP(hipMemcpyAsync((void *)dprob, &hp, sizeof(hp), hipMemcpyHostToDevice, st));
     WD_HIP(hipMemcpyAsync(w + L.scal, sc.data(), sizeof(Scal) * nrhs, hipMemcpyHostToDevice, st));
-    WD_HIP(hipMemsetAsync(w + L.bar, 0, 256, st));
+    WD_HIP(hipMemsetAsync(w + L.bar, 0, BAR_BYTES, st));
     // fields
     const int64_t Vf = hp.vf;
     int rc = WD_OK;
@@ -1033,7 +1033,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     }
     launch_first_residual(p.inner, ls, st, dprob, 1, !p.use_x0);
     if (!bicg) launch_kind(KC, p.inner, ls, st, dprob, 1);
-    const int *dabort = persistent ? (const int *)(w + L.bar + 128) : nullptr;
+    const int *dabort = persistent ? (const int *)(w + L.bar + BAR_ABORT) : nullptr;
     launch_summary(st, dprob, 1, dsum, dabort);
     WD_HIP(hipGetLastError());
 
@@ -1059,7 +1059,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
             launch_summary(cs, dprob, 1, dsum, dabort);
             return;
         }
-        if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, K, w + L.bar + 64, p.max_cus);
+        if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, K, w + L.bar, p.max_cus);
         else launch_iterations(p.inner, ls, cs, dprob, 1, K);
         launch_kind(KR1, p.inner, ls, cs, dprob, 1);
         if (eo) launch_kind(KER2A, p.inner, ls, cs, dprob, 1);

@@ -28,6 +28,12 @@ struct LaunchSet {
                    // per iteration and one trailing finish per chunk
 };
 
+// The persistent kernel's grid-barrier words, each on a 256-byte line of its
+// own (the line every waiting block polls is not the one the arrivals update):
+// the released generation, the abort flag and the arrival counter.
+constexpr size_t BAR_GEN = 0, BAR_ABORT = 256, BAR_COUNT = 512;
+constexpr size_t BAR_BYTES = 768;
+
 // Byte offsets of the pieces of a solve workspace.
 struct WsLayout {
     size_t prob, scal, scal2, bar, summary, part, eta64, x64, xlo, r, p, q;
@@ -46,11 +52,11 @@ void init_scalars(std::vector<Scal> &sc, int nrhs);
 // phase A or B of a fused-finish iteration (see launch_iterations).
 void launch_kind(int kind, int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, int par = -1,
                  int first = 0);
+// the first true residual of a solve; x_zero: x64 is zero (no stencil needed)
+void launch_first_residual(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, bool x_zero);
 // K CG iterations: with ls.fused, phases A and B per iteration (A finishing the
 // iteration before it) and one trailing finish; else A, B (with its finish)
 // and C, with the even-odd hops where ls.eo.
-// the first true residual of a solve; x_zero: x64 is zero (no stencil needed)
-void launch_first_residual(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, bool x_zero);
 void launch_iterations(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob, int K);
 // WD_CG_UNFUSED set (and not "0"): solves and the server use the three-launch iteration
 bool unfused_requested();
@@ -66,7 +72,7 @@ void launch_eo_source(const Prob *d, int64_t vf, int nrhs, hipStream_t st);
 void launch_eo_merge(const Prob *d, int64_t vf, int nrhs, void *sol, hipStream_t st);
 int cg_status_of(int state);
 // Record one persistent chunk kernel (K iterations of phases A and B with grid
-// barriers) on `st`; `bar` is 256 bytes of device scratch for the barrier.
+// barriers) on `st`; `bar` is BAR_BYTES of device scratch for the barrier.
 // max_cus > 0: one 1024-thread block on each of max_cus compute units.
 int record_persistent_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob,
                             int K, void *bar, int max_cus = 0);

@@ -45,12 +45,15 @@ __device__ __forceinline__ void bar_release(const Barrier &b, unsigned e) {
 }
 
 // Wait for barrier e to be released; returns nonzero if the launch aborted.
+// The generation is polled with relaxed loads and acquired once, by the fence
+// after the loop: an acquiring load at device scope invalidates the XCD's L2
+// on every poll, under the blocks of that XCD that are still computing.
 __device__ __forceinline__ int bar_wait(const Barrier &b, unsigned e) {
     __shared__ int aborted;
     if (threadIdx.x == 0) {
         const unsigned long long t0 = wall_clock64();
         int ab = 0;
-        while (__hip_atomic_load(b.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < e + 1) {
+        while (__hip_atomic_load(b.gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < e + 1) {
             if (__hip_atomic_load(b.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ab = 1; break; }
             if (wall_clock64() - t0 > b.limit) {
                 __hip_atomic_store(b.abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -109,14 +112,20 @@ __global__ __launch_bounds__(BLK) void k_persistent(const Prob *__restrict__ pro
     }
 }
 
+// zero the barrier words (a kernel: no memset node in the chunk graph)
 __global__ void k_bar_reset(unsigned *p) {
-    if (threadIdx.x < 32) p[threadIdx.x] = 0u;   // count, gen, abort (128 bytes)
+    if (threadIdx.x == 0) {
+        p[BAR_GEN / 4] = 0u;
+        p[BAR_ABORT / 4] = 0u;
+        p[BAR_COUNT / 4] = 0u;
+    }
 }
 
 static void make_barrier(Barrier &b, void *bar, int khz) {
-    b.count = (unsigned *)bar;
-    b.gen = (unsigned *)((char *)bar + 32);
-    b.abort = (int *)((char *)bar + 64);
+    char *c = (char *)bar;
+    b.count = (unsigned *)(c + BAR_COUNT);
+    b.gen = (unsigned *)(c + BAR_GEN);
+    b.abort = (int *)(c + BAR_ABORT);
     b.limit = (unsigned long long)khz * 1000ull * 2ull;   // two seconds
 }
 

@@ -209,7 +209,7 @@ static int init_slot(wd_server *s, Slot &sl) {
     init_scalars(sl.sc, rq.nrhs);
     WD_HIP(hipMemcpyAsync(w + L.prob, &sl.prob, sizeof(Prob), hipMemcpyHostToDevice, st));
     WD_HIP(hipMemcpyAsync(w + L.scal, sl.sc.data(), sizeof(Scal) * rq.nrhs, hipMemcpyHostToDevice, st));
-    WD_HIP(hipMemsetAsync(w + L.bar, 0, 256, st));
+    WD_HIP(hipMemsetAsync(w + L.bar, 0, BAR_BYTES, st));
     const Prob *dp = (const Prob *)(w + L.prob);
     if (eo) {
         launch_eo_split(dp, vf, rq.nrhs, rq.src_dev, w + L.eta64, w + L.eta_o, st);
