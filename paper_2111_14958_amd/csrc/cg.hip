@@ -972,6 +972,27 @@ static int profiled_chunk(int inner, const LaunchSet &ls, hipStream_t st, const 
     return rc;
 }
 
+// Pinned host staging for the solve driver's small copies (problem record,
+// scalar records, chunk summary), one buffer per host thread, kept for the
+// life of the thread: copies from pageable memory go through the runtime's
+// own staging and left the GPU idle for tens of microseconds each, and a
+// pinned allocation per solve costs as much.  A solve reuses the buffer only
+// after the previous solve on the thread has synchronised its stream (a solve
+// that returned an error early may leave a copy in flight, which reads the
+// buffer only for that failed solve).
+static char *host_stage(size_t bytes) {
+    thread_local char *buf = nullptr;
+    thread_local size_t cap = 0;
+    if (cap < bytes) {
+        if (buf) (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        if (hipHostMalloc((void **)&buf, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        cap = bytes;
+    }
+    return buf;
+}
+
 // The solve driver shared by wd_cg_solve and wd_cg_solve_batch.
 int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, const wd_cg_params &p,
            void *ws, size_t ws_bytes, wd_cg_report *reps, hipStream_t st) {
@@ -1005,8 +1026,14 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     // upload the problem record and the initial scalars
     std::vector<Scal> sc;
     init_scalars(sc, nrhs);
-    WD_HIP(hipMemcpyAsync((void *)dprob, &hp, sizeof(hp), hipMemcpyHostToDevice, st));
-    WD_HIP(hipMemcpyAsync(w + L.scal, sc.data(), sizeof(Scal) * nrhs, hipMemcpyHostToDevice, st));
+    // staging: problem record, scalar records, summary (pinned, see host_stage)
+    const size_t st_scal = (sizeof(Prob) + 255) & ~size_t(255), st_sum = st_scal + ((sizeof(Scal) * nrhs + 255) & ~size_t(255));
+    char *stage = host_stage(st_sum + 256);
+    WD_CHECK(stage, WD_ENOMEM, "pinned host staging of %zu bytes", st_sum + 256);
+    memcpy(stage, &hp, sizeof(hp));
+    memcpy(stage + st_scal, sc.data(), sizeof(Scal) * nrhs);
+    WD_HIP(hipMemcpyAsync((void *)dprob, stage, sizeof(hp), hipMemcpyHostToDevice, st));
+    WD_HIP(hipMemcpyAsync(w + L.scal, stage + st_scal, sizeof(Scal) * nrhs, hipMemcpyHostToDevice, st));
     WD_HIP(hipMemsetAsync(w + L.bar, 0, BAR_BYTES, st));
     // fields
     const int64_t Vf = hp.vf;
@@ -1070,8 +1097,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     if (rc) return rc;
     if (rec_rc) return rec_rc;
 
-    int *hsum = nullptr;
-    WD_HIP(hipHostMalloc((void **)&hsum, 64, hipHostMallocDefault));
+    int *hsum = (int *)(stage + st_sum);
     WD_HIP(hipMemcpyAsync(hsum, dsum, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     WD_HIP(hipStreamSynchronize(st));
     // every chunk either converges a field or spends K iterations of it
@@ -1081,10 +1107,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
         hipError_t e = hipSuccess;
         if (prof) {
             rc = profiled_chunk(p.inner, ls, st, dprob, K, nrhs, V, w + L.scal, ls.k[KB].r12 != 0);
-            if (rc) {
-                (void)hipHostFree(hsum);
-                return rc;
-            }
+            if (rc) return rc;
             launch_kind(KR1, p.inner, ls, st, dprob, 1);
             launch_kind(KR2, p.inner, ls, st, dprob, 1);
             launch_kind(KC, p.inner, ls, st, dprob, 1);
@@ -1094,16 +1117,9 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
         }
         if (e == hipSuccess) e = hipMemcpyAsync(hsum, dsum, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) {
-            (void)hipHostFree(hsum);
-            return fail(WD_EHIP, "chunk replay failed: %s", hipGetErrorString(e));
-        }
-        if (persistent && hsum[1] != 0) {
-            (void)hipHostFree(hsum);
-            return fail(WD_EHIP, "persistent kernel grid barrier timed out");
-        }
+        if (e != hipSuccess) return fail(WD_EHIP, "chunk replay failed: %s", hipGetErrorString(e));
+        if (persistent && hsum[1] != 0) return fail(WD_EHIP, "persistent kernel grid barrier timed out");
     }
-    (void)hipHostFree(hsum);
     // solution out (even-odd: x_o from x_e), scalars back
     if (eo) {
         launch_eo_merge(dprob, Vf, nrhs, sol, st);
@@ -1112,8 +1128,9 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
         rc = launch_unpack_spinor(WD_F64, w + L.x64, sol, (int)V, nrhs, st);
         if (rc) return rc;
     }
-    WD_HIP(hipMemcpyAsync(sc.data(), w + L.scal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st));
+    WD_HIP(hipMemcpyAsync(stage + st_scal, w + L.scal, sizeof(Scal) * nrhs, hipMemcpyDeviceToHost, st));
     WD_HIP(hipStreamSynchronize(st));
+    memcpy(sc.data(), stage + st_scal, sizeof(Scal) * nrhs);
     int first_bad = WD_OK;
     for (int i = 0; i < nrhs; ++i) {
         if (sc[i].zero_src) WD_HIP(hipMemsetAsync((char *)sol + (size_t)i * V * 192, 0, (size_t)V * 192, st));
