@@ -789,6 +789,7 @@ void fill_prob(Prob &pr, const wd_gauge *g, double m0, int nrhs, const wd_cg_par
     pr.x64 = ws + L.x64;
     pr.eta64 = ws + L.eta64;
     pr.part = (double *)(ws + L.part);
+    pr.psb = (int)((g->V + 63) / 64);   // the buffer's site blocks per column (ws_layout)
     pr.sc = (Scal *)(ws + L.scal);
     pr.sc2 = (Scal *)(ws + L.scal2);
     pr.v = ws + L.q;

@@ -85,7 +85,9 @@ struct alignas(16) Prob {
     const void *U64;  // FP64 links
     void *x_lo, *r, *p, *q;   // inner-precision vectors (x_lo: FP32 for FP16N)
     void *x64, *eta64;        // FP64 packed vectors
-    double *part;             // [nsb][nrhs][PSTRIDE] partial sums of the current phase
+    double *part;             // [PSTRIDE][nrhs][psb] partial sums: column (slot, field) holds the
+                              // site blocks' partials one after the other
+    int psb;                  // site blocks a column has room for ((V + 63) / 64)
     Scal *sc;                 // [nrhs]
     Scal *sc2;                // [nrhs] second record per field: with the fused finish, the phase-A
                               // launches of a chunk read one and write the other (iteration parity)
@@ -144,31 +146,35 @@ __device__ __forceinline__ void block_sum(double v[NR]) {
 // blocks are loaded together (absent ones as 0, which leaves the sum
 // unchanged), so up to 256 site blocks cost one memory round trip.
 constexpr int MAX_SUMS = 64 * 3;
+// The partials of slot k of field i, site block after site block (a
+// wavefront reading 64 consecutive blocks reads 512 contiguous bytes).
+__device__ __forceinline__ const double *part_col(const Prob &pr, int i, int k) {
+    return pr.part + ((size_t)k * pr.nrhs + i) * pr.psb;
+}
+__device__ __forceinline__ double &part_at(const Prob &pr, int sb, int i, int k) {
+    return pr.part[((size_t)k * pr.nrhs + i) * pr.psb + sb];
+}
+
 // Partials k0 .. k0 + nk - 1 of each entry are summed.
 __device__ __forceinline__ void sum_all(const Prob &pr, int nsb, int nk, double *sums, int k0 = 0) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const size_t bs = (size_t)pr.nrhs * PSTRIDE;   // stride between site blocks
     for (int job = w; job < pr.nrhs * nk; job += nw) {
         const int i = job / nk, k = job - i * nk;
-        const double *col = pr.part + (size_t)i * PSTRIDE + k0 + k;
-        const double a0 = lane < nsb ? col[(size_t)lane * bs] : 0.0;
-        const double a1 = lane + 64 < nsb ? col[(size_t)(lane + 64) * bs] : 0.0;
-        const double a2 = lane + 128 < nsb ? col[(size_t)(lane + 128) * bs] : 0.0;
-        const double a3 = lane + 192 < nsb ? col[(size_t)(lane + 192) * bs] : 0.0;
+        const double *col = part_col(pr, i, k0 + k);
+        const double a0 = lane < nsb ? col[lane] : 0.0;
+        const double a1 = lane + 64 < nsb ? col[lane + 64] : 0.0;
+        const double a2 = lane + 128 < nsb ? col[lane + 128] : 0.0;
+        const double a3 = lane + 192 < nsb ? col[lane + 192] : 0.0;
         double x = 0.0;
         x += a0;
         x += a1;
         x += a2;
         x += a3;
-        for (int b = lane + 256; b < nsb; b += 64) x += col[(size_t)b * bs];
+        for (int b = lane + 256; b < nsb; b += 64) x += col[b];
         x = wave_sum(x);
         if (lane == 0) sums[job] = x;
     }
     __syncthreads();
-}
-
-__device__ __forceinline__ double &part_at(const Prob &pr, int sb, int i, int k) {
-    return pr.part[((size_t)sb * pr.nrhs + i) * PSTRIDE + k];
 }
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < 1e300; }
@@ -508,16 +514,15 @@ template <int NR>
 __device__ __forceinline__ void col_issue(const Prob &pr, int rhs0, unsigned act, double (&a)[NR][4], int slot,
                                           int nsb) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const size_t bs = (size_t)pr.nrhs * PSTRIDE;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         a[j][0] = a[j][1] = a[j][2] = a[j][3] = 0.0;
         if (j % nw == w && (act >> j & 1)) {
-            const double *col = pr.part + (size_t)(rhs0 + j) * PSTRIDE + slot;
-            if (lane < nsb) a[j][0] = col[(size_t)lane * bs];
-            if (lane + 64 < nsb) a[j][1] = col[(size_t)(lane + 64) * bs];
-            if (lane + 128 < nsb) a[j][2] = col[(size_t)(lane + 128) * bs];
-            if (lane + 192 < nsb) a[j][3] = col[(size_t)(lane + 192) * bs];
+            const double *col = part_col(pr, rhs0 + j, slot);
+            if (lane < nsb) a[j][0] = col[lane];
+            if (lane + 64 < nsb) a[j][1] = col[lane + 64];
+            if (lane + 128 < nsb) a[j][2] = col[lane + 128];
+            if (lane + 192 < nsb) a[j][3] = col[lane + 192];
         }
     }
 }
@@ -526,17 +531,16 @@ template <int NR>
 __device__ __forceinline__ void col_reduce(const Prob &pr, int rhs0, unsigned act, const double (&a)[NR][4],
                                            double *out, int slot, int nsb) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const size_t bs = (size_t)pr.nrhs * PSTRIDE;
 #pragma unroll
     for (int j = 0; j < NR; ++j) {
         if (j % nw == w && (act >> j & 1)) {
-            const double *col = pr.part + (size_t)(rhs0 + j) * PSTRIDE + slot;
+            const double *col = part_col(pr, rhs0 + j, slot);
             double x = 0.0;
             x += a[j][0];
             x += a[j][1];
             x += a[j][2];
             x += a[j][3];
-            for (int b = lane + 256; b < nsb; b += 64) x += col[(size_t)b * bs];
+            for (int b = lane + 256; b < nsb; b += 64) x += col[b];
             x = wave_sum(x);
             if (lane == 0) out[j] = x;
         }
@@ -670,15 +674,14 @@ __device__ __forceinline__ void phaseB_finish(const Prob &pr) {
 // the values are the ones sum_all returns, and fa_reduce's sigma).
 __device__ __forceinline__ void sum_ab(const Prob &pr, double *sa, double *sb, int aslot = 0) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const size_t bs = (size_t)pr.nrhs * PSTRIDE;
     const int na = pr.nsb[KA], nb = pr.nsb[KB];
     for (int i = w; i < pr.nrhs; i += nw) {
-        const double *ca = pr.part + (size_t)i * PSTRIDE + aslot, *cb = pr.part + (size_t)i * PSTRIDE + 1;
+        const double *ca = part_col(pr, i, aslot), *cb = part_col(pr, i, 1);
         double a[4], b[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            a[k] = lane + 64 * k < na ? ca[(size_t)(lane + 64 * k) * bs] : 0.0;
-            b[k] = lane + 64 * k < nb ? cb[(size_t)(lane + 64 * k) * bs] : 0.0;
+            a[k] = lane + 64 * k < na ? ca[lane + 64 * k] : 0.0;
+            b[k] = lane + 64 * k < nb ? cb[lane + 64 * k] : 0.0;
         }
         double x = 0.0, y = 0.0;
 #pragma unroll
@@ -686,8 +689,8 @@ __device__ __forceinline__ void sum_ab(const Prob &pr, double *sa, double *sb, i
             x += a[k];
             y += b[k];
         }
-        for (int j = lane + 256; j < na; j += 64) x += ca[(size_t)j * bs];
-        for (int j = lane + 256; j < nb; j += 64) y += cb[(size_t)j * bs];
+        for (int j = lane + 256; j < na; j += 64) x += ca[j];
+        for (int j = lane + 256; j < nb; j += 64) y += cb[j];
         x = wave_sum(x);
         y = wave_sum(y);
         if (lane == 0) {
