@@ -272,8 +272,9 @@ typedef struct {
                              strip = W in 1..4095: sites are processed in strips
                              of W z-planes, t-major inside a strip (0:
                              lexicographic); xy_planes = k in 2..4 (with xy_lds
-                             = 1, one rhs per thread, hop order 3 or 5; the
-                             operator and CG phases A and B): a block is k
+                             = 1, one rhs per thread; the operator with hop
+                             order 3 or 5, CG phases A and B with hop order
+                             5): a block is k
                              z-adjacent xy-planes (k Lx Ly <= 512 sites), a z
                              neighbour inside it read from LDS too; a lattice,
                              precision or strip where k planes do not fit (FP64,

@@ -419,7 +419,6 @@ static void launch_R2(int nr, int xy, int grid, int blk, hipStream_t st, const P
     else hipLaunchKernelGGL((k_ru2<P, 2, false, ZX>), dim3(grid), dim3(blk), 0, st, d, n, remap);
 }
 
-
 template <int P, bool S4>
 static void launch_BS(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
     if (nr == 1) hipLaunchKernelGGL((k_bi_stencil<P, 1, S4>), dim3(grid), dim3(blk), 0, st, d, n, remap);

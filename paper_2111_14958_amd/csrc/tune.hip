@@ -301,9 +301,9 @@ int wd_shape_set(const wd_gauge *g, int32_t prec, int32_t nrhs, int32_t dagger, 
     WD_CHECK(sh->site_order >= 0 && (sh->site_order >> 31) == 0 && ((sh->site_order >> 15) & 1) == 0 && occ <= 8,
              WD_EINVAL, "site_order 0x%x", sh->site_order);
     WD_CHECK(planes == 1 || (((sh->site_order >> 17) & 1) && !zm && sh->rhs_per_thread == 1 && planes <= 4 &&
-                             family != FAM_CG_R && sh->hop_order != 1 && sh->hop_order != 2 && sh->hop_order != 4),
-             WD_EINVAL, "several planes per block: plane-blocked operator and CG phase A/B kernels, one rhs per "
-             "thread, hop order 3 or 5, at most 4 planes");
+                             family != FAM_CG_R && (sh->hop_order == 5 || (sh->hop_order == 3 && family == FAM_DSLASH))),
+             WD_EINVAL, "several planes per block: plane-blocked operator (hop order 3 or 5) and CG phase A/B "
+             "kernels (hop order 5), one rhs per thread, at most 4 planes");
     WD_CHECK(fpass == 0 || ((family == FAM_CG_A || family == FAM_CG_B) && !gmajor && !zm), WD_EINVAL,
              "passes of rhs groups: CG phase A/B kernels in site-block-major order only");
     WD_CHECK(!zm || ((sh->site_order >> 17) & 1), WD_EINVAL, "z-marching needs the plane-blocked bit");

@@ -201,7 +201,9 @@ def test_multi_plane_shapes_refused():
            dict(family=wd.FAMILY_DSLASH, block=128, hop_order=1, xy_lds=1, xy_planes=2),
            dict(family=wd.FAMILY_DSLASH, block=128, hop_order=3, xy_lds=2, xy_planes=2),   # z-marching
            dict(family=wd.FAMILY_DSLASH, block=320, hop_order=5, xy_lds=1, xy_planes=5),
-           dict(family=wd.FAMILY_CG_R, block=128, hop_order=3, xy_lds=1, xy_planes=2)]
+           dict(family=wd.FAMILY_CG_R, block=128, hop_order=3, xy_lds=1, xy_planes=2),
+           dict(family=wd.FAMILY_CG_B, block=128, hop_order=3, xy_lds=1, xy_planes=2),   # CG: hop order 5 only
+           dict(family=wd.FAMILY_DSLASH, block=128, hop_order=0, xy_lds=1, xy_planes=2)]
     for kw in bad:
         fam = kw.pop("family")
         with pytest.raises(RuntimeError):
