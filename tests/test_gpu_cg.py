@@ -167,6 +167,30 @@ def test_initial_guess_zero_source_and_max_iter():
     assert reps3[0]["iters"] == 5 and reps3[0]["true_rel_res"] > TOL
 
 
+@pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
+def test_first_residual_without_stencil_is_bitwise_the_same(inner):
+    """Without an initial guess the first residual is r = eta, formed without
+    the FP64 stencil; an explicit zero initial guess runs the stencil on x = 0.
+    Both give bitwise the same solutions and reports."""
+    dims, m0 = (8, 8, 6, 6), 0.1
+    U, eta = field_set(dims, 0.5, 1501, 3, 1502)
+    g = wd.Gauge(dev(U), dims, -1, recon12=True)
+    p = wd.cg_default_params(inner=inner, reliable_every=0 if inner == wd.F64 else 50)
+    say("first residual", inner)
+    x0, r0, rc0 = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+    p.use_x0 = 1
+    x1, r1, rc1 = wd.cg_solve_batch(g, m0, dev(eta), sol=torch_zeros_like(dev(eta)), params=p)
+    assert rc0 == rc1 == wd.WD_OK
+    assert np.array_equal(host(x0), host(x1))
+    for a, b in zip(r0, r1):
+        assert a["iters"] == b["iters"] and a["true_rel_res"] == b["true_rel_res"]
+
+
+def torch_zeros_like(t):
+    import torch
+    return torch.zeros_like(t)
+
+
 def test_nan_source_breaks_down():
     dims, m0 = (4, 4, 4, 4), 0.1
     U = wdgen.gauge_field(dims, 0.3, 1001)
