@@ -184,7 +184,12 @@ typedef struct {
     int32_t use_x0;         /* 1: sol_dev holds the initial guess on entry              */
     int32_t persistent;     /* 0: one kernel per CG phase, 1: one persistent kernel per
                                chunk with grid barriers, -1: library default             */
-    int32_t chunk;          /* CG iterations per graph replay, 0 = library default     */
+    int32_t chunk;          /* CG iterations per graph replay (the host checks for
+                               convergence between replays).  0 = library default:
+                               reliable_every (or 50), and for CG a replay cut
+                               short, in multiples of 8, once the fields' decrease of
+                               |r|^2 says they need fewer; the results do not depend
+                               on the replay lengths                                  */
     int32_t method;         /* WD_METHOD_CGNE (default) or WD_METHOD_BICGSTAB           */
     int32_t precondition;   /* WD_PRECOND_NONE (default) or WD_PRECOND_EO               */
     int32_t max_cus;        /* 0: all compute units.  n > 0: the CG iterations run on n

@@ -224,17 +224,53 @@ __global__ __launch_bounds__(1024) void k_finish(const Prob *__restrict__ probs,
 }
 
 // out[0] = right-hand sides still active or frozen over all problems,
-// out[1] = the persistent kernel's abort flag (0 when there is none)
+// out[1] = the persistent kernel's abort flag (0 when there is none),
+// out[2] = for one CG problem, an estimate of the iterations its active fields
+// still need: |r|^2 of each is extrapolated at its rate of decrease since the
+// previous summary (log-linear) down to the stopping value; -1 when unknown
+// (another method, several problems, a field without such a history).  The
+// previous summary's |r|^2 and iteration count of each field sit 256 bytes
+// after out (SumHist; the summary area has room for MAX_RHS of them) and are
+// replaced.  One block of MAX_RHS threads.
+struct SumHist {
+    double rho;
+    int iters, pad;
+};
 __global__ void k_summary(const Prob *__restrict__ probs, int nprob, int *out, const int *abort_flag) {
-    if (threadIdx.x != 0) return;
-    int live = 0;
-    for (int j = 0; j < nprob; ++j)
-        for (int i = 0; i < probs[j].nrhs; ++i) {
-            const int st = probs[j].sc[i].state;
-            live += (st == ST_ACTIVE || st == ST_FROZEN);
+    __shared__ int unknown, need;
+    const int i = threadIdx.x;
+    if (i == 0) {
+        int live = 0;
+        for (int j = 0; j < nprob; ++j)
+            for (int f = 0; f < probs[j].nrhs; ++f) {
+                const int st = probs[j].sc[f].state;
+                live += (st == ST_ACTIVE || st == ST_FROZEN);
+            }
+        out[0] = live;
+        out[1] = abort_flag ? *abort_flag : 0;
+        unknown = nprob != 1 || probs[0].method != METHOD_CGNE;
+        need = 0;
+    }
+    __syncthreads();
+    if (nprob == 1 && probs[0].method == METHOD_CGNE && i < probs[0].nrhs) {
+        const Scal &c = probs[0].sc[i];
+        SumHist *h = (SumHist *)((char *)out + 256) + i;
+        const SumHist prev = *h;
+        if (c.state == ST_ACTIVE) {
+            if (!(c.rho > c.stop2)) {
+                atomicMax(&need, 1);
+            } else if (c.stop2 > 0.0 && c.iters > prev.iters && prev.rho > c.rho) {
+                const double rate = log(prev.rho / c.rho) / (double)(c.iters - prev.iters);
+                const double n = log(c.rho / c.stop2) / rate;
+                atomicMax(&need, n < 1e6 ? (int)ceil(n) : 1000000);
+            } else {
+                atomicOr(&unknown, 1);
+            }
         }
-    out[0] = live;
-    out[1] = abort_flag ? *abort_flag : 0;
+        *h = SumHist{c.rho, c.iters, 0};
+    }
+    __syncthreads();
+    if (i == 0) out[2] = unknown ? -1 : need;
 }
 
 // BiCGSTAB stages (bicgstab_core.h)
@@ -579,7 +615,7 @@ static void launch_kind_tiles(int kind, int inner, const KindShape &k, hipStream
 }
 
 void launch_summary(hipStream_t st, const Prob *d, int nprob, int *out, const int *abort_flag) {
-    hipLaunchKernelGGL(k_summary, dim3(1), dim3(64), 0, st, d, nprob, out, abort_flag);
+    hipLaunchKernelGGL(k_summary, dim3(1), dim3(MAX_RHS), 0, st, d, nprob, out, abort_flag);
 }
 
 void launch_zero(void *p, size_t bytes, hipStream_t st) {
@@ -599,7 +635,7 @@ WsLayout ws_layout(int64_t V, int nrhs, int inner, int method, int eo) {
     L.scal = o; o += al256(sizeof(Scal) * nrhs);
     L.scal2 = o; o += al256(sizeof(Scal) * nrhs);
     L.bar = o; o += BAR_BYTES;
-    L.summary = o; o += 256;
+    L.summary = o; o += 256 + al256(sizeof(SumHist) * MAX_RHS);
     L.part = o; o += al256((size_t)((V + 63) / 64) * nrhs * PSTRIDE * sizeof(double));
     L.eta64 = o; o += al256(spinor_bytes(WD_F64, Vf, nrhs));
     L.x64 = o; o += al256(spinor_bytes(WD_F64, Vf, nrhs));
@@ -1070,55 +1106,69 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
     for (int d = 0; d < 4; ++d) key.dims[d] = g->dims[d];
     key.nrhs = nrhs;
     key.inner = p.inner;
-    key.K = K;
     key.persistent = persistent;
     key.max_cus = p.max_cus;
     key.method = p.method | (eo << 4) | (ls.fused << 5);
     for (int k = 0; k < NKIND; ++k) key.shp[k] = ls.k[k];
-    hipGraphExec_t exec = nullptr;
-    int rec_rc = WD_OK;
-    rc = get_graph(key, [&](hipStream_t cs) {
-        if (bicg) {
-            for (int it = 0; it < K; ++it)
-                for (int k = KS1; k <= KS5; ++k) launch_kind(k, p.inner, ls, cs, dprob, 1);
+    // the graph of a chunk of Kc iterations (cached per length)
+    auto chunk_graph = [&](int Kc, hipGraphExec_t *exec) -> int {
+        key.K = Kc;
+        int rec_rc = WD_OK;
+        const int r = get_graph(key, [&](hipStream_t cs) {
+            if (bicg) {
+                for (int it = 0; it < Kc; ++it)
+                    for (int k = KS1; k <= KS5; ++k) launch_kind(k, p.inner, ls, cs, dprob, 1);
+                launch_kind(KR1, p.inner, ls, cs, dprob, 1);
+                launch_kind(KR2, p.inner, ls, cs, dprob, 1);
+                launch_summary(cs, dprob, 1, dsum, dabort);
+                return;
+            }
+            if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, Kc, w + L.bar, p.max_cus);
+            else launch_iterations(p.inner, ls, cs, dprob, 1, Kc);
             launch_kind(KR1, p.inner, ls, cs, dprob, 1);
+            if (eo) launch_kind(KER2A, p.inner, ls, cs, dprob, 1);
             launch_kind(KR2, p.inner, ls, cs, dprob, 1);
+            launch_kind(KC, p.inner, ls, cs, dprob, 1);
             launch_summary(cs, dprob, 1, dsum, dabort);
-            return;
-        }
-        if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, K, w + L.bar, p.max_cus);
-        else launch_iterations(p.inner, ls, cs, dprob, 1, K);
-        launch_kind(KR1, p.inner, ls, cs, dprob, 1);
-        if (eo) launch_kind(KER2A, p.inner, ls, cs, dprob, 1);
-        launch_kind(KR2, p.inner, ls, cs, dprob, 1);
-        launch_kind(KC, p.inner, ls, cs, dprob, 1);
-        launch_summary(cs, dprob, 1, dsum, dabort);
-    }, &exec);
-    if (rc) return rc;
-    if (rec_rc) return rec_rc;
+        }, exec);
+        return r ? r : rec_rc;
+    };
 
     int *hsum = (int *)(stage + st_sum);
-    WD_HIP(hipMemcpyAsync(hsum, dsum, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    WD_HIP(hipMemcpyAsync(hsum, dsum, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
     WD_HIP(hipStreamSynchronize(st));
-    // every chunk either converges a field or spends K iterations of it
-    const int max_chunks = p.max_iter / K + 2 * (p.max_iter / (K * 4) + 4);
+    // Chunks of K iterations, except where the library picks the length
+    // (p.chunk == 0): once the summary estimates that the active fields need
+    // fewer, the chunk is cut to that many plus 3, rounded up to a multiple of
+    // 8 (a few graph lengths), so a solve does not idle through most of a
+    // chunk after its fields converge.  Chunk boundaries only decide when the
+    // host looks: the results are bitwise the same for any lengths.
+    const bool adaptive = p.chunk == 0;
+    // every chunk of K either converges a field or spends K iterations of it
+    const int64_t budget = (int64_t)K * (p.max_iter / K + 2 * (p.max_iter / (K * 4) + 4));
     const bool prof = g_prof_on.load() != 0 && !persistent && !bicg && !eo;
-    for (int c = 0; c < max_chunks && hsum[0] > 0; ++c) {
+    int Kc = K;
+    for (int64_t run = 0; run < budget && hsum[0] > 0; run += Kc) {
         hipError_t e = hipSuccess;
         if (prof) {
-            rc = profiled_chunk(p.inner, ls, st, dprob, K, nrhs, V, w + L.scal, ls.k[KB].r12 != 0);
+            rc = profiled_chunk(p.inner, ls, st, dprob, Kc, nrhs, V, w + L.scal, ls.k[KB].r12 != 0);
             if (rc) return rc;
             launch_kind(KR1, p.inner, ls, st, dprob, 1);
             launch_kind(KR2, p.inner, ls, st, dprob, 1);
             launch_kind(KC, p.inner, ls, st, dprob, 1);
             launch_summary(st, dprob, 1, dsum, dabort);
         } else {
+            hipGraphExec_t exec = nullptr;
+            rc = chunk_graph(Kc, &exec);
+            if (rc) return rc;
             e = hipGraphLaunch(exec, st);
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(hsum, dsum, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hsum, dsum, 3 * sizeof(int), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return fail(WD_EHIP, "chunk replay failed: %s", hipGetErrorString(e));
         if (persistent && hsum[1] != 0) return fail(WD_EHIP, "persistent kernel grid barrier timed out");
+        const int need = hsum[2];
+        Kc = (adaptive && need >= 0 && need + 3 < K) ? std::min(K, std::max(8, (need + 3 + 7) / 8 * 8)) : K;
     }
     // solution out (even-odd: x_o from x_e), scalars back
     if (eo) {

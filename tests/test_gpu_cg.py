@@ -234,10 +234,40 @@ def test_graph_cache_keys_on_the_hop_order():
             wd.shape_set(g, wd.F32, nrhs, fam == wd.FAMILY_CG_A, fam, sh["block"],
                          rhs_per_thread=sh["rhs_per_thread"], xcd_remap=sh["xcd_remap"],
                          hop_order=sh["hop_order"], strip=sh["strip"], xy_lds=sh["xy_lds"])
-    assert sols[1][0][1] == 1                 # the new hop order captured its own graph
-    assert sols[3][1][1] == 0                 # back to order 3: the cached graph is replayed
+    # the new hop order captured its own graphs (one per chunk length the solve used)
+    assert sols[1][0][1] == sols[3][0][1] >= 1
+    assert sols[3][1][1] == 0                 # back to order 3: the cached graphs are replayed
     assert np.array_equal(sols[3][0][0], sols[3][1][0])
     _check_solution(U, eta, sols[1][0][0], dims, m0)
+
+
+@pytest.mark.parametrize("inner", [wd.F64, wd.F32], ids=["f64", "f32"])
+def test_adaptive_chunk_lengths_are_bitwise_neutral(inner):
+    """With the library's chunk length (chunk = 0) the last replays are cut to
+    the iterations the fields are estimated to need; the solutions and reports
+    are bitwise those of fixed chunks of 50 and of 7 iterations, and the solve
+    captured a shorter graph than 50."""
+    import torch
+    dims, m0, nrhs = (8, 8, 8, 8), 0.05, 4
+    U, eta = field_set(dims, 0.5, 1601, nrhs, 1602)
+    g = wd.Gauge(dev(U), dims, -1, recon12=True)
+    ru = 0 if inner == wd.F64 else 50
+    out = {}
+    for chunk in (0, 50, 7):
+        p = wd.cg_default_params(inner=inner, reliable_every=ru, chunk=chunk)
+        ws = torch.empty(wd.cg_workspace_bytes(g, nrhs, p), dtype=torch.uint8, device="cuda")
+        say("chunk length", chunk, inner)
+        before = wd.cg_graph_stats()[0]
+        x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p, ws=ws)
+        assert rc == wd.WD_OK, reps
+        out[chunk] = (host(x), [(r["iters"], r["true_rel_res"], r["reliable_updates"]) for r in reps],
+                      wd.cg_graph_stats()[0] - before)
+    assert max(r[0] for r in out[0][1]) > 50          # more than one chunk
+    assert out[0][2] >= 2                              # a length of 50 and a shorter one
+    for chunk in (50, 7):
+        assert np.array_equal(out[0][0], out[chunk][0]), chunk
+        assert out[0][1] == out[chunk][1], chunk
+    _check_solution(U, eta, out[0][0], dims, m0)
 
 
 def test_workspace_too_small():
