@@ -335,7 +335,9 @@ int wd_tune_cg(const wd_gauge *g, double m0, int32_t inner, const void *src_dev,
 /* kernel families of the shape table */
 #define WD_FAMILY_DSLASH 0   /* wd_dslash / wd_dslash_dag                       */
 #define WD_FAMILY_CG_A   1   /* CG phase A: q = D^dagger r + beta q, |q|^2     */
-#define WD_FAMILY_CG_B   2   /* CG phase B: D q, r and x updates, |r|^2        */
+#define WD_FAMILY_CG_B   2   /* CG phase B: D q, r and x updates, |r|^2; also
+                                 BiCGSTAB's two stencil stages (its plane-blocked
+                                 bit; they take hop order 5, one rhs per thread) */
 #define WD_FAMILY_CG_R   3   /* reliable update r = eta - D x (FP64)           */
 /* Set the launch shape of one kernel family for (g's lattice, prec, nrhs,
  * dagger) by hand -- e.g. to sweep the block size of the whole CG as the paper

@@ -66,29 +66,39 @@ __device__ __forceinline__ void bi1_tile(const Prob &pr, int t) {
 // ------------------------------------------- S2 / S4, stencil plus reductions
 // S2: out = v = D p, partials <r_hat, v> (2 numbers).
 // S4: out = t = D s, partials <t, s> (2) and <t, t> (1).
-template <int P, int NR, bool S4>
+// XY: one xy-plane per block, its input spinors staged in LDS (the x and y
+// hops and the site's own spinor read them there); ORD: hop order as in the
+// CG phases (5 = the memory hops z and t first); R12: links from the
+// reconstruct-12 copy.
+template <int P, int NR, bool S4, int ORD = 1, bool XY = false, bool R12 = false>
 __device__ __forceinline__ void bi_stencil_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
+    typedef typename LdsSpinor<P>::word W;
+    __shared__ W xy[XY ? NR * LdsWords<P>::value * 256 : 1];
     const int K = S4 ? KS4 : KS2;
     int sb, grp, s;
-    stencil_tile(pr, K, t, sb, grp, s);
+    stencil_tile<XY>(pr, K, t, sb, grp, s);
     const int rhs0 = grp * NR;
     const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
     double part[3 * NR];
 #pragma unroll
     for (int j = 0; j < 3 * NR; ++j) part[j] = 0.0;
     const Geom g = pr.g;
+    const int np = g.S[2];   // sites of a plane
+    FieldPtr fin{S4 ? pr.sv : pr.p, g.V, pr.nrhs}, fout{S4 ? pr.tv : pr.v, g.V, pr.nrhs};
+    if (XY && act) stage_plane<P, NR>(fin, rhs0, act, s, g.V, xy, np);   // act is uniform over the block
     if (act && s < g.V) {
-        FieldPtr fin{S4 ? pr.sv : pr.p, g.V, pr.nrhs}, fout{S4 ? pr.tv : pr.v, g.V, pr.nrhs};
         FieldPtr fh{pr.rh, g.V, pr.nrhs};
-        const void *U = pr.U_lo;
+        const void *U = R12 ? pr.U12 : pr.U_lo;
         cx<R> acc[NR][12];
-        hopping<P, false, NR, 1>(g, s, U, fin, rhs0, act, acc);
+        hopping<P, false, NR, ORD, XY, false, false, R12>(g, s, U, fin, rhs0, act, acc, nullptr, xy,
+                                                          s - (int)threadIdx.x, np);
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
                 cx<R> self[12], o[12], a[12];
-                Spinor<P>::load(fin, rhs0 + j, s, self);
+                if constexpr (XY) LdsSpinor<P>::get(xy, np, j, threadIdx.x, self);
+                else Spinor<P>::load(fin, rhs0 + j, s, self);
                 wilson_finish<R>((R)pr.diag, self, acc[j], o);
                 Spinor<P>::store(fout, rhs0 + j, s, o);
                 if (S4) {

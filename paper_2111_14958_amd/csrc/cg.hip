@@ -280,11 +280,11 @@ __global__ __launch_bounds__(256) void k_bi1(const Prob *__restrict__ probs, int
     bi1_tile<P>(pr, t_);
 }
 
-template <int P, int NR, bool S4>
+template <int P, int NR, bool S4, int ORD = 1, bool XY = false, bool R12 = false>
 __global__ __launch_bounds__(256) void k_bi_stencil(const Prob *__restrict__ probs, int nprob, int remap) {
     constexpr int K = S4 ? KS4 : KS2;
     WD_KERNEL_PROLOGUE(K)
-    bi_stencil_tile<P, NR, S4>(pr, t_);
+    bi_stencil_tile<P, NR, S4, ORD, XY, R12>(pr, t_);
 }
 
 template <int P>
@@ -455,9 +455,18 @@ static void launch_R2(int nr, int xy, int grid, int blk, hipStream_t st, const P
     else hipLaunchKernelGGL((k_ru2<P, 2, false, ZX>), dim3(grid), dim3(blk), 0, st, d, n, remap);
 }
 
+// plane blocks (xy): hop order 5, one rhs per thread, the reconstruct-12
+// links in FP32 when the gauge has them
 template <int P, bool S4>
-static void launch_BS(int nr, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
-    if (nr == 1) hipLaunchKernelGGL((k_bi_stencil<P, 1, S4>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+static void launch_BS(int nr, int xy, int r12, int grid, int blk, hipStream_t st, const Prob *d, int n, int remap) {
+    if (xy) {
+        if constexpr (P == P32)
+            if (r12) {
+                hipLaunchKernelGGL((k_bi_stencil<P, 1, S4, 5, true, true>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+                return;
+            }
+        hipLaunchKernelGGL((k_bi_stencil<P, 1, S4, 5, true>), dim3(grid), dim3(blk), 0, st, d, n, remap);
+    } else if (nr == 1) hipLaunchKernelGGL((k_bi_stencil<P, 1, S4>), dim3(grid), dim3(blk), 0, st, d, n, remap);
     else if (nr == 2) hipLaunchKernelGGL((k_bi_stencil<P, 2, S4>), dim3(grid), dim3(blk), 0, st, d, n, remap);
     else hipLaunchKernelGGL((k_bi_stencil<P, 4, S4>), dim3(grid), dim3(blk), 0, st, d, n, remap);
 }
@@ -465,9 +474,9 @@ template <int P>
 static void launch_bicg(int kind, const KindShape &k, hipStream_t st, const Prob *d, int n) {
     switch (kind) {
     case KS1: hipLaunchKernelGGL(k_bi1<P>, dim3(k.grid), dim3(k.block), 0, st, d, n, 0); break;
-    case KS2: launch_BS<P, false>(k.nr, k.grid, k.block, st, d, n, k.remap); break;
+    case KS2: launch_BS<P, false>(k.nr, k.xy, k.r12, k.grid, k.block, st, d, n, k.remap); break;
     case KS3: hipLaunchKernelGGL(k_bi3<P>, dim3(k.grid), dim3(k.block), 0, st, d, n, 0); break;
-    case KS4: launch_BS<P, true>(k.nr, k.grid, k.block, st, d, n, k.remap); break;
+    case KS4: launch_BS<P, true>(k.nr, k.xy, k.r12, k.grid, k.block, st, d, n, k.remap); break;
     case KS5: hipLaunchKernelGGL(k_bi5<P>, dim3(k.grid), dim3(k.block), 0, st, d, n, 0); break;
     }
 }
@@ -699,7 +708,8 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.order = strip | (st[k]->gmajor ? 1 << 16 : 0) | (st[k]->fpass << 24);
             // plane-blocked phases A and B: one xy-plane of 64..256 sites per
             // block (the partial-sum buffer holds one entry per 64 sites)
-            ks.xy = (k == KA || k == KB || k == KR2) && st[k]->xylds && np >= 64 && np <= 256 && !pr.eo;
+            ks.xy = (k == KA || k == KB || k == KR2 || k == KS2 || k == KS4) && st[k]->xylds && np >= 64 &&
+                    np <= 256 && !pr.eo;
             if (pr.eo) {   // the half-lattice kernels: site blocks, lexicographic order
                 ks.order = 0;
                 if (ks.nr > 2) ks.nr = 2;
@@ -713,7 +723,7 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             // z-marching columns of planes (FP32 and FP16 storage, one rhs per
             // tile); strip = number of z-chunks, by default enough for about
             // three tiles per compute unit with chunks of at least two planes
-            if (ks.xy && st[k]->xylds == 2 && inner != WD_F64 && g->dims[2] >= 2) {
+            if (ks.xy && st[k]->xylds == 2 && inner != WD_F64 && g->dims[2] >= 2 && k != KS2 && k != KS4) {
                 const int Lz = g->dims[2], Lt = g->dims[3];
                 int nzc = st[k]->strip > 0 ? std::min(st[k]->strip, Lz)
                                            : std::min((768 + Lt * nrhs - 1) / (Lt * nrhs), Lz / 2);
@@ -732,6 +742,13 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             if ((k == KA || k == KB) && pr.U12 && !pr.eo && ks.xy != 2) {
                 ks.r12 = 1;
                 if (ks.nr > 2) ks.nr = 2;
+            }
+            // BiCGSTAB's stencils on plane blocks: hop order 5, one rhs per
+            // thread, the reconstruct-12 links where the gauge has them (FP32)
+            if ((k == KS2 || k == KS4) && ks.xy == 1) {
+                ks.nr = 1;
+                ks.ordered = 5;
+                ks.r12 = pr.U12 != nullptr;
             }
             // hop order 5 exists for plane blocks with one rhs per thread
             if (ks.ordered == 5 && !(ks.xy == 1 && ks.nr == 1)) ks.ordered = 3;

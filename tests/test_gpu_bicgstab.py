@@ -112,6 +112,35 @@ def test_batch_equals_single_fields():
         assert rel(host(xi)[0], xb[i]) <= kappa(m0) * 2 * TOL
 
 
+@pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
+def test_plane_blocked_stencils(inner):
+    """The two stencil stages on xy-plane blocks (hop order 5; the
+    reconstruct-12 links in FP32) against the site-blocked ones (hop order 1,
+    complete links).  The 10 x 10 planes fill one and a half wavefronts of a
+    256-thread block and the lattice is anisotropic.  Both solutions pass the
+    oracle's residual check and agree within the condition-number bound; in
+    FP64 without reliable updates both iterate the same recurrence, so their
+    iteration counts agree to rounding."""
+    dims, m0 = (10, 10, 6, 4), 0.1
+    U = wdgen.gauge_field(dims, 0.5, 1011)
+    eta = wdgen.mixed_sources(dims, 3, 2, 1012)
+    nrhs = eta.shape[0]
+    g = wd.Gauge(dev(U), dims, recon12=inner == wd.F32)
+    sols, iters = {}, {}
+    for xy in (0, 1):
+        say("bicgstab stencil blocks", inner, "xy", xy)
+        wd.shape_set(g, inner, nrhs, False, wd.FAMILY_CG_B, 256, 1, 1, 5 if xy else 1, 1, 0, 0, xy)
+        x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=_params(inner))
+        assert rc == wd.WD_OK, reps
+        sols[xy] = host(x)
+        iters[xy] = [r["iters"] for r in reps]
+        _check_solution(U, eta, sols[xy], dims, m0)
+    for i in range(nrhs):
+        assert rel(sols[1][i], sols[0][i]) <= kappa(m0) * 2 * TOL, i
+        if inner == wd.F64:
+            assert abs(iters[1][i] - iters[0][i]) <= max(2, iters[0][i] // 20), (iters, i)
+
+
 def test_lat14x4_1rhs_f32():
     """The paper's 14^4 lattice, one Gaussian source, FP32 inner iterations."""
     dims, m0 = (14, 14, 14, 14), 0.05

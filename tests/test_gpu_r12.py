@@ -103,9 +103,10 @@ def test_r12_operator_matches_oracle(dims, t_sign):
 
 
 def test_r12_gauge_serves_every_solver():
-    """Kernels without a two-row variant (even-odd, BiCGSTAB, the persistent
-    kernel, FP16 storage) keep reading the complete copies of a reconstruct-12
-    gauge."""
+    """Every solver takes a reconstruct-12 gauge: kernels without a two-row
+    variant (even-odd, the persistent kernel, FP16 storage) keep reading its
+    complete copies, BiCGSTAB's plane-blocked stencils (8 x 8 planes here) read
+    the two-row links."""
     dims, m0 = (8, 8, 4, 6), 0.1
     U = wdgen.gauge_field(dims, 0.5, 511)
     eta = wdgen.mixed_sources(dims, 2, 1, 512)
