@@ -90,9 +90,10 @@ typedef struct wd_gauge wd_gauge;
 #define WD_GAUGE_F32  (1u << WD_F32)
 #define WD_GAUGE_F16  (1u << WD_F16N)
 /* Reconstruct-12: beside the FP32 copy, keep one with rows 0 and 1 of each link
- * only (12 reals instead of 18); the FP32 operator (wd_dslash, wd_dslash_dag) and
+ * only (12 reals instead of 18); the FP32 operator (wd_dslash, wd_dslash_dag),
  * the kernels of phases A and B of CG with FP32 inner iterations (plane or site
- * blocks, not even-odd, not the persistent or z-marching kernels) read it and
+ * blocks and the even-odd half-lattice hops; not the persistent or z-marching
+ * kernels, not the server) and BiCGSTAB's plane-blocked stencils read it and
  * rebuild row 2 as the complex conjugate of the
  * cross product of rows 0 and 1, which holds for SU(3) matrices (unitary, det 1).
  * That cuts a third of their link bytes.  (With FP16 storage the rebuilt row

@@ -111,20 +111,20 @@ __global__ __launch_bounds__(256) void k_norm(const Prob *__restrict__ probs, in
 }
 
 // Even-odd preconditioning (eo_core.h)
-template <int P, int NR, bool DAG>
+template <int P, int NR, bool DAG, bool R12 = false>
 __global__ __launch_bounds__(256) void k_eo_hop1(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(DAG ? KEA1 : KEB1)
-    eo_hop1_tile<P, NR, DAG, true>(pr, t_);
+    eo_hop1_tile<P, NR, DAG, true, R12>(pr, t_);
 }
-template <int P, int NR>
+template <int P, int NR, bool R12 = false>
 __global__ __launch_bounds__(256) void k_eo_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KA)
-    eo_phaseA_tile<P, NR, true>(pr, t_);
+    eo_phaseA_tile<P, NR, true, R12>(pr, t_);
 }
-template <int P, int NR>
+template <int P, int NR, bool R12 = false>
 __global__ __launch_bounds__(256) void k_eo_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KB)
-    eo_phaseB_tile<P, NR>(pr, t_);
+    eo_phaseB_tile<P, NR, R12>(pr, t_);
 }
 template <int NR>
 __global__ __launch_bounds__(256) void k_eo_ru2a(const Prob *__restrict__ probs, int nprob, int remap) {
@@ -497,11 +497,38 @@ static void launch_finish_after(int kind, const LaunchSet &ls, hipStream_t st, c
     launch_finish(kind == KB && fa ? (KB | FIN_AB) : kind, st, d, nprob);
 }
 
+// the FP32 half-lattice hops of phases A and B on the reconstruct-12 links
+static void launch_eo_r12(int kind, const KindShape &k, hipStream_t st, const Prob *d, int n) {
+    const dim3 gr(k.grid), bl(k.block);
+    const bool two = k.nr >= 2;
+    switch (kind) {
+    case KEA1:
+        if (two) hipLaunchKernelGGL((k_eo_hop1<P32, 2, true, true>), gr, bl, 0, st, d, n, k.remap);
+        else hipLaunchKernelGGL((k_eo_hop1<P32, 1, true, true>), gr, bl, 0, st, d, n, k.remap);
+        break;
+    case KEB1:
+        if (two) hipLaunchKernelGGL((k_eo_hop1<P32, 2, false, true>), gr, bl, 0, st, d, n, k.remap);
+        else hipLaunchKernelGGL((k_eo_hop1<P32, 1, false, true>), gr, bl, 0, st, d, n, k.remap);
+        break;
+    case KA:
+        if (two) hipLaunchKernelGGL((k_eo_phaseA<P32, 2, true>), gr, bl, 0, st, d, n, k.remap);
+        else hipLaunchKernelGGL((k_eo_phaseA<P32, 1, true>), gr, bl, 0, st, d, n, k.remap);
+        break;
+    case KB:
+        if (two) hipLaunchKernelGGL((k_eo_phaseB<P32, 2, true>), gr, bl, 0, st, d, n, k.remap);
+        else hipLaunchKernelGGL((k_eo_phaseB<P32, 1, true>), gr, bl, 0, st, d, n, k.remap);
+        break;
+    }
+}
 // even-odd kernels of the stencil kinds (1 or 2 rhs per thread)
 template <int P>
 static void launch_eo(int kind, const KindShape &k, hipStream_t st, const Prob *d, int n) {
     const dim3 gr(k.grid), bl(k.block);
     const bool two = k.nr >= 2;
+    if (P == P32 && k.r12 && (kind == KEA1 || kind == KEB1 || kind == KA || kind == KB)) {
+        launch_eo_r12(kind, k, st, d, n);
+        return;
+    }
     switch (kind) {
     case KEA1:
         if (two) hipLaunchKernelGGL((k_eo_hop1<P, 2, true>), gr, bl, 0, st, d, n, k.remap);
@@ -738,8 +765,9 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
                 ks.nt = 1;
                 if (ks.nr > 2) ks.nr = 2;
             }
-            // reconstruct-12 links for phases A and B (FP32; plane or site blocks, <= 2 rhs per thread)
-            if ((k == KA || k == KB) && pr.U12 && !pr.eo && ks.xy != 2) {
+            // reconstruct-12 links for phases A and B (FP32; plane or site blocks, <= 2 rhs per thread;
+            // even-odd: both half-lattice hops of each phase)
+            if ((k == KA || k == KB || (pr.eo && (k == KEA1 || k == KEB1))) && pr.U12 && ks.xy != 2) {
                 ks.r12 = 1;
                 if (ks.nr > 2) ks.nr = 2;
             }

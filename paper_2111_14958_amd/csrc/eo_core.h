@@ -41,8 +41,9 @@ __device__ __forceinline__ void eo_tile(const Prob &pr, int K, int t, int &sb, i
 
 // First half hop, onto the odd sites: tmp_o = H_oe v_e (H^dagger with DAG).
 // v: p for phase A (DAG), q for phase B.  QR: phase A hops r, as it forms the
-// direction as q = Dhat^dagger r + beta q (see phaseA_tile).
-template <int P, int NR, bool DAG, bool QR = false>
+// direction as q = Dhat^dagger r + beta q (see phaseA_tile).  R12 (here and in
+// the second halves of phases A and B): links from the reconstruct-12 copy.
+template <int P, int NR, bool DAG, bool QR = false, bool R12 = false>
 __device__ __forceinline__ void eo_hop1_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     constexpr int K = DAG ? KEA1 : KEB1;
@@ -55,7 +56,7 @@ __device__ __forceinline__ void eo_hop1_tile(const Prob &pr, int t) {
     const int s = eo_site(g, k, 1);
     FieldPtr fin{DAG ? (QR ? pr.r : pr.p) : pr.q, pr.vf, pr.nrhs}, fo{pr.tmp, pr.vf, pr.nrhs};
     cx<R> acc[NR][12];
-    hopping<P, DAG, NR, 1, false, true>(g, s, pr.U_lo, fin, rhs0, act, acc);
+    hopping<P, DAG, NR, 1, false, true, false, R12>(g, s, R12 ? pr.U12 : pr.U_lo, fin, rhs0, act, acc);
 #pragma unroll
     for (int j = 0; j < NR; ++j)
         if (act >> j & 1) Spinor<P>::store(fo, rhs0 + j, k, acc[j]);
@@ -63,7 +64,7 @@ __device__ __forceinline__ void eo_hop1_tile(const Prob &pr, int t) {
 
 // Phase A, second half: q_e = A p_e - c H^dagger_eo tmp_o, partial |q|^2.
 // QR: with r in place of p, plus beta times the old q_e (not after a restart).
-template <int P, int NR, bool QR = false>
+template <int P, int NR, bool QR = false, bool R12 = false>
 __device__ __forceinline__ void eo_phaseA_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     int sb, grp, k;
@@ -78,7 +79,7 @@ __device__ __forceinline__ void eo_phaseA_tile(const Prob &pr, int t) {
         const int s = eo_site(g, k, 0);
         FieldPtr ft{pr.tmp, pr.vf, pr.nrhs}, fp{QR ? pr.r : pr.p, pr.vf, pr.nrhs}, fq{pr.q, pr.vf, pr.nrhs};
         cx<R> acc[NR][12];
-        hopping<P, true, NR, 1, false, true>(g, s, pr.U_lo, ft, rhs0, act, acc);
+        hopping<P, true, NR, 1, false, true, false, R12>(g, s, R12 ? pr.U12 : pr.U_lo, ft, rhs0, act, acc);
         const R a = (R)pr.diag, c = (R)pr.eo_c;
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
@@ -116,7 +117,7 @@ __device__ __forceinline__ void eo_phaseA_tile(const Prob &pr, int t) {
 
 // Phase B, second half: t_e = A q_e - c H_eo tmp_o; r -= alpha t; x_lo += alpha q;
 // partial |r|^2
-template <int P, int NR>
+template <int P, int NR, bool R12 = false>
 __device__ __forceinline__ void eo_phaseB_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     constexpr int XP = XPrec<P>::value;
@@ -134,7 +135,7 @@ __device__ __forceinline__ void eo_phaseB_tile(const Prob &pr, int t) {
         FieldPtr ft{pr.tmp, pr.vf, pr.nrhs}, fq{pr.q, pr.vf, pr.nrhs}, fr{pr.r, pr.vf, pr.nrhs},
             fx{pr.x_lo, pr.vf, pr.nrhs};
         cx<R> acc[NR][12];
-        hopping<P, false, NR, 1, false, true>(g, s, pr.U_lo, ft, rhs0, act, acc);
+        hopping<P, false, NR, 1, false, true, false, R12>(g, s, R12 ? pr.U12 : pr.U_lo, ft, rhs0, act, acc);
         const R a = (R)pr.diag, c = (R)pr.eo_c;
 #pragma unroll
         for (int j = 0; j < NR; ++j) {

@@ -1,5 +1,6 @@
-"""Reconstruct-12 links (WD_GAUGE_RECON12): the FP32 operator and phases A and
-B of CG with FP32 inner iterations read a two-row FP32 copy of the links and
+"""Reconstruct-12 links (WD_GAUGE_RECON12): the FP32 operator, phases A and B
+of CG with FP32 inner iterations (also their even-odd half-lattice hops) and
+BiCGSTAB's plane-blocked stencils read a two-row FP32 copy of the links and
 rebuild the third row from the first two.
 
 The operator on such a gauge matches the oracle's D and D^dagger in every launch
@@ -104,9 +105,9 @@ def test_r12_operator_matches_oracle(dims, t_sign):
 
 def test_r12_gauge_serves_every_solver():
     """Every solver takes a reconstruct-12 gauge: kernels without a two-row
-    variant (even-odd, the persistent kernel, FP16 storage) keep reading its
-    complete copies, BiCGSTAB's plane-blocked stencils (8 x 8 planes here) read
-    the two-row links."""
+    variant (the persistent kernel, FP16 storage) keep reading its complete
+    copies; BiCGSTAB's plane-blocked stencils (8 x 8 planes here) and the
+    even-odd half-lattice hops read the two-row links."""
     dims, m0 = (8, 8, 4, 6), 0.1
     U = wdgen.gauge_field(dims, 0.5, 511)
     eta = wdgen.mixed_sources(dims, 2, 1, 512)
@@ -121,6 +122,31 @@ def test_r12_gauge_serves_every_solver():
     say("r12 gauge operator")
     got = host(wd.dslash(g12, m0, dev(eta), wd.F32))
     assert rel(got, oracle.dirac(U, eta, dims, m0, -1)) <= 1e-6
+
+
+@pytest.mark.parametrize("t_sign", [-1, 1], ids=["antiperiodic", "periodic"])
+def test_r12_even_odd_solve(t_sign):
+    """Even-odd CG with FP32 inner iterations on a reconstruct-12 gauge: the
+    half-lattice hops of phases A and B (both halves of each) read the two-row
+    links.  The oracle's operator checks the solution; it agrees with the
+    solve on the complete links within kappa(D) (2 tol) and is not bitwise
+    that solve's (the rebuilt third rows round differently), which shows the
+    two-row copy was read."""
+    dims, m0 = (8, 6, 4, 6), 0.1   # even Lx
+    U = wdgen.gauge_field(dims, 0.5, 531)
+    eta = wdgen.mixed_sources(dims, 3, 2, 532)
+    say("r12 even-odd", t_sign)
+    p = wd.cg_default_params(inner=wd.F32, precondition=wd.PRECOND_EO)
+    sols = []
+    for r12 in (True, False):
+        g = wd.Gauge(dev(U), dims, recon12=r12, t_sign=t_sign)
+        x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+        assert rc == wd.WD_OK, (r12, reps)
+        sols.append(host(x))
+        assert np.all(oracle.true_residual(U, eta, sols[-1], dims, m0, t_sign) <= TOL * 1.0000001), r12
+    for i in range(eta.shape[0]):
+        assert rel(sols[0][i], sols[1][i]) <= kappa(m0) * 2 * TOL, i
+    assert np.any(sols[0] != sols[1])
 
 
 def test_r12_refuses_links_outside_su3():
