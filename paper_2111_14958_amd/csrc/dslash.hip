@@ -279,17 +279,7 @@ static void launch_nr(int nr, int ordered, int rl, dim3 grid, dim3 block, hipStr
     else launch_nr_o<P, DAG, 0, R12>(nr, grid, block, st, g, diag, U, in, out, ngroups, remap, rl, od);
 }
 
-Geom make_geom(const wd_gauge *gg) {
-    Geom g;
-    for (int d = 0; d < 4; ++d) g.L[d] = gg->dims[d];
-    g.S[0] = 1;
-    g.S[1] = g.L[0];
-    g.S[2] = g.L[0] * g.L[1];
-    g.S[3] = g.L[0] * g.L[1] * g.L[2];
-    g.V = (int)gg->V;
-    g.tsign = gg->tsign;
-    return g;
-}
+Geom make_geom(const wd_gauge *gg) { return geom_of(gg->dims, gg->tsign); }
 
 int launch_dslash(const wd_gauge *gg, double m0, int prec, bool dag, const void *in, void *out,
                   int nrhs, const Shape &sh, hipStream_t st) {

@@ -93,19 +93,58 @@ template <typename R> __device__ __forceinline__ cx<R> cjmul(cx<R> a, cx<R> b) {
 template <typename R> __device__ __forceinline__ R norm2(cx<R> a) { return a.re * a.re + a.im * a.im; }
 
 // ------------------------------------------------------------------ geometry
+// Division by a lattice extent without the integer divide sequence (about 20
+// vector instructions): division by an invariant integer through
+// multiplication (Granlund and Montgomery, 1994).  For a divisor
+// 1 <= d < 2^31 let l = ceil(log2 d) and M = floor(2^(32+l) / d) + 1.  Then
+// e = M d - 2^(32+l) lies in (0, d], d <= 2^l, so n M / 2^(32+l) exceeds n / d
+// by less than 1/d and floor(n M / 2^(32+l)) = floor(n / d) for n < 2^32.
+// M = 2^32 + m with m = floor(2^32 (2^l - d) / d) + 1 < 2^32, hence
+// floor(n M / 2^32) = mulhi(n, m) + n, which stays below 2^32 for n < 2^31
+// (mulhi(n, m) < n): n / d = (mulhi(n, m) + n) >> l for 0 <= n < 2^31.
+struct FastDiv {
+    uint32_t m, l;
+};
+__host__ __device__ inline FastDiv fastdiv_make(uint32_t d) {
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    return FastDiv{(uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1), l};
+}
+__host__ __device__ __forceinline__ int fastdiv(int n, FastDiv f) {
+    const uint32_t u = (uint32_t)n;
+    return (int)(((uint32_t)(((uint64_t)u * f.m) >> 32) + u) >> f.l);
+}
+
 struct Geom {
     int L[4];     // Lx, Ly, Lz, Lt
     int S[4];     // strides 1, Lx, Lx*Ly, Lx*Ly*Lz
     int V;        // sites
     int tsign;    // time boundary sign, carried by the t-links of the last slice
+    FastDiv dL[3];   // division by Lx, Ly, Lz
+    FastDiv dP;      // division by the sites of an xy-plane, Lx Ly
 };
+// the geometry of a dims[0] x dims[1] x dims[2] x dims[3] lattice
+__host__ __device__ inline Geom geom_of(const int dims[4], int tsign) {
+    Geom g;
+    for (int d = 0; d < 4; ++d) g.L[d] = dims[d];
+    g.S[0] = 1;
+    g.S[1] = g.L[0];
+    g.S[2] = g.L[0] * g.L[1];
+    g.S[3] = g.L[0] * g.L[1] * g.L[2];
+    g.V = g.S[3] * g.L[3];
+    g.tsign = tsign;
+    for (int d = 0; d < 3; ++d) g.dL[d] = fastdiv_make((uint32_t)g.L[d]);
+    g.dP = fastdiv_make((uint32_t)g.S[2]);
+    return g;
+}
 
+// coordinates of site 0 <= s < V
 __device__ __forceinline__ void site_coords(const Geom &g, int s, int c[4]) {
-    int r = s;
-    c[0] = r % g.L[0]; r /= g.L[0];
-    c[1] = r % g.L[1]; r /= g.L[1];
-    c[2] = r % g.L[2];
-    c[3] = r / g.L[2];
+    const int q0 = fastdiv(s, g.dL[0]), q1 = fastdiv(q0, g.dL[1]), q2 = fastdiv(q1, g.dL[2]);
+    c[0] = s - q0 * g.L[0];
+    c[1] = q0 - q1 * g.L[1];
+    c[2] = q1 - q2 * g.L[2];
+    c[3] = q2;
 }
 
 // ------------------------------------------------------------- spinor views
@@ -677,8 +716,8 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 // xy-plane stays contiguous, so a wavefront's accesses remain coalesced.
 __host__ __device__ __forceinline__ int order_site(const Geom &g, int strip, int L) {
     if (strip <= 0) return L;
-    const int P = g.S[2];                 // sites per xy-plane
-    const int q = L / P, off = L - q * P; // plane number in the order, offset
+    const int P = g.S[2];                           // sites per xy-plane
+    const int q = fastdiv(L, g.dP), off = L - q * P; // plane number in the order, offset
     const int per = strip * g.L[3];       // planes of a full strip
     const int zb = q / per, qq = q - zb * per;
     const int w = g.L[2] - zb * strip < strip ? g.L[2] - zb * strip : strip;   // last strip may be narrower

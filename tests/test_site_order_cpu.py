@@ -25,10 +25,7 @@ int main() {
                            {6,4,9,3}};
     int bad = 0, checked = 0;
     for (auto &d : dims) {
-        wd::Geom g;
-        for (int k = 0; k < 4; ++k) g.L[k] = d[k];
-        g.S[0] = 1; g.S[1] = d[0]; g.S[2] = d[0] * d[1]; g.S[3] = d[0] * d[1] * d[2];
-        g.V = d[0] * d[1] * d[2] * d[3];
+        const wd::Geom g = wd::geom_of(d, -1);
         const int P = g.S[2];
         for (int W = 0; W <= d[2] + 1; ++W) {
             std::vector<int> seen(g.V, 0);
@@ -54,6 +51,59 @@ def test_processing_orders_are_permutations(tmp_path):
     exe = tmp_path / "order"
     src.write_text(PROGRAM)
     subprocess.run(["hipcc", "-x", "hip", "--offload-arch=gfx950", "-std=c++17", "-O1", "-w",
+                    "-I", CSRC, str(src), "-o", str(exe)], check=True, capture_output=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "bad 0" in r.stdout
+
+
+FASTDIV = r"""
+#include "wd_device.h"
+#include <stdio.h>
+#include <stdint.h>
+// every divisor up to 4200 against every dividend up to 70000, then a
+// pseudo-random sample of large dividends and divisors, and the extremes
+int main() {
+    long bad = 0, checked = 0;
+    auto check = [&](int n, int d, wd::FastDiv f) {
+        ++checked;
+        if (wd::fastdiv(n, f) != n / d) {
+            if (bad < 5) printf("n %d d %d got %d\n", n, d, wd::fastdiv(n, f));
+            ++bad;
+        }
+    };
+    for (int d = 1; d <= 4200; ++d) {
+        const wd::FastDiv f = wd::fastdiv_make(d);
+        for (int n = 0; n < 70000; ++n) check(n, d, f);
+        check(2147483647, d, f);
+        check(2147483647 - d, d, f);
+    }
+    uint64_t x = 88172645463325252ull;
+    for (int i = 0; i < 4000000; ++i) {
+        x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+        const int d = 1 + (int)((x >> 33) % ((i & 1) ? 2147483646u : 100000u));
+        const int n = (int)((x & 0x7fffffff) >> (i % 24));
+        check(n, d, wd::fastdiv_make(d));
+    }
+    const int ds[] = {1, 2, 3, 1073741823, 1073741824, 1073741825, 2147483646, 2147483647};
+    for (int d : ds)
+        for (int n : {0, 1, d - 1, d, 2147483646, 2147483647})
+            if (n >= 0) check(n, d, wd::fastdiv_make(d));
+    printf("checked %ld bad %ld\n", checked, bad);
+    return bad != 0;
+}
+"""
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not found")
+def test_fastdiv_matches_integer_division(tmp_path):
+    """The kernels divide by lattice extents with a multiply-high, an add and
+    a shift (division by invariant integers); the host build of the same
+    functions against C's integer division."""
+    src = tmp_path / "fastdiv.cpp"
+    exe = tmp_path / "fastdiv"
+    src.write_text(FASTDIV)
+    subprocess.run(["hipcc", "-x", "hip", "--offload-arch=gfx950", "-std=c++17", "-O2", "-w",
                     "-I", CSRC, str(src), "-o", str(exe)], check=True, capture_output=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
