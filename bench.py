@@ -243,15 +243,16 @@ def main():
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     it_p = max(r["iters"] for r in repsp)
-    ka = complete_links["kernels_avg_us"]
-    per_it_graph = ka.get("cg_phaseA", 0.0) + ka.get("cg_phaseB", 0.0)
+    per_it_graph = sum(1e3 * prof[k]["total_ms"] / max(prof[k]["launches"], 1)
+                       for k in ("cg_phaseA", "cg_phaseB") if k in prof)
     persistent = {"solves_per_s": nrhs / tp, "converged": rcp == wd.WD_OK, "iters_max": it_p,
                   "us_per_iteration": 1e6 * tp / it_p,
                   "graph_path_phase_A_plus_B_us": per_it_graph,
-                  # the persistent kernel reads the complete FP32 links, so it is
-                  # compared with the graph path's phases on the complete links;
-                  # two grid barriers per iteration
-                  "barrier_us_estimate": (1e6 * tp / it_p - per_it_graph) / 2,
+                  # one 1024-thread block per compute unit, site blocks, the
+                  # reconstruct-12 links as the graph path; against the graph
+                  # path's plane-blocked phases, per grid barrier (two per
+                  # iteration): an upper bound of the barrier's cost
+                  "overhead_us_per_barrier": (1e6 * tp / it_p - per_it_graph) / 2,
                   "max_true_rel_res": max(r["true_rel_res"] for r in repsp)}
     log(f"persistent: {nrhs / tp:.2f} solves/s")
 

@@ -92,8 +92,8 @@ typedef struct wd_gauge wd_gauge;
 /* Reconstruct-12: beside the FP32 copy, keep one with rows 0 and 1 of each link
  * only (12 reals instead of 18); the FP32 operator (wd_dslash, wd_dslash_dag),
  * the kernels of phases A and B of CG with FP32 inner iterations (plane or site
- * blocks and the even-odd half-lattice hops; not the persistent or z-marching
- * kernels, not the server) and BiCGSTAB's plane-blocked stencils read it and
+ * blocks, the even-odd half-lattice hops and the persistent kernel's phases;
+ * not the z-marching kernels, not the server) and BiCGSTAB's plane-blocked stencils read it and
  * rebuild row 2 as the complex conjugate of the
  * cross product of rows 0 and 1, which holds for SU(3) matrices (unitary, det 1).
  * That cuts a third of their link bytes.  (With FP16 storage the rebuilt row
@@ -205,7 +205,11 @@ typedef struct {
  * updates and the final FP64 residual still run on the whole device.  Results
  * are identical (bitwise) for every n.  Returns WD_EHIP if the kernel would fit
  * twice on a compute unit.  FP32 or FP16N inner iterations only.  Not for the
- * server. */
+ * server.  With persistent = 1 and max_cus = 0, FP32 and FP16N solves whose
+ * phase shapes take one rhs per thread (the defaults) use this launch on every
+ * compute unit, and the same bits as max_cus = n; FP64 (and shapes with several
+ * rhs per thread) run phase B's block size instead, as many blocks as are
+ * resident at once. */
 
 /* Krylov method of wd_cg_solve / wd_cg_solve_batch.
  * WD_METHOD_CGNE: CG on the normal equations D D^dagger chi = eta, x = D^dagger chi

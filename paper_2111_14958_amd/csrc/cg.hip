@@ -816,14 +816,22 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
     ls.fused = !ls.eo && ls.k[KA].xy != 2 && ls.k[KB].xy != 2 && !unfused_requested();
 }
 
-// The persistent kernel runs phases A and B with one block shape: phase B's,
-// or 1024 threads and one rhs per thread when it is limited to max_cus compute
-// units.  Its phase A forms the direction as q (no p and no phase C).
+// The persistent kernel runs phases A and B with one block shape, site blocks
+// and one hop at a time.  FP32 and FP16 storage with one rhs per thread (the
+// default shapes), or a launch limited to max_cus compute units: one
+// 1024-thread block per compute unit (all of them, or max_cus), the
+// reconstruct-12 links in FP32 where the gauge has them.  Otherwise (FP64,
+// several rhs per thread): phase B's block size, as many blocks as are
+// resident at once, complete links.  Its phase A forms the direction as q (no
+// p and no phase C).  ls.pcus: the compute-unit limit of the first kind of
+// launch (0 for the second).
 void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner, int max_cus) {
-    const int blk = max_cus > 0 ? 1024 : ls.k[KB].block;
+    const bool cus = max_cus > 0 || (inner != WD_F64 && ls.k[KB].nr == 1);
+    ls.pcus = max_cus > 0 ? max_cus : cus ? (1 << 30) : 0;
+    const int blk = cus ? 1024 : ls.k[KB].block;
     ls.qrec = 1;   // the persistent kernel's phase A carries the direction as q too
     ls.fused = 0;  // it finishes each iteration at its own grid barriers
-    int nr = max_cus > 0 ? 1 : ls.k[KB].nr;
+    int nr = cus ? 1 : ls.k[KB].nr;
     if (inner == WD_F64 && nr > 2) nr = 2;
     const int kinds[2] = {KA, KB};
     for (int k : kinds) {
@@ -831,12 +839,13 @@ void plan_persistent(LaunchSet &ls, Prob &pr, int64_t V, int nrhs, int inner, in
         ks.block = blk;
         ks.nr = nr;
         ks.remap = 0;
+        ks.ordered = 1;
         // z-marching: the order held the chunk count; no plane blocks
         ks.order = ks.xy == 2 ? 0 : ks.order & ~(1 << 17) & ~(7 << 18);
         ks.xy = 0;
         ks.planes = 1;
         ks.lds = 0;
-        ks.r12 = 0;   // the persistent kernel reads the complete copy
+        ks.r12 = cus && inner == WD_F32 && pr.U12 != nullptr;
         ks.nt = 0;
         pr.sorder[k] = ks.order;
         pr.nsb[k] = (int)((V + blk - 1) / blk);
@@ -1168,7 +1177,7 @@ int cg_run(const wd_gauge *g, double m0, const void *src, void *sol, int nrhs, c
                 launch_summary(cs, dprob, 1, dsum, dabort);
                 return;
             }
-            if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, Kc, w + L.bar, p.max_cus);
+            if (persistent) rec_rc = record_persistent_chunk(p.inner, ls, cs, dprob, 1, Kc, w + L.bar, ls.pcus);
             else launch_iterations(p.inner, ls, cs, dprob, 1, Kc);
             launch_kind(KR1, p.inner, ls, cs, dprob, 1);
             if (eo) launch_kind(KER2A, p.inner, ls, cs, dprob, 1);

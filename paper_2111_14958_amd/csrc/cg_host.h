@@ -26,6 +26,8 @@ struct LaunchSet {
     int qrec = 0; // phase A forms the direction q = D^dagger r + beta q (Dhat for even-odd): no p, no phase C
     int fused = 0; // phase A completes the previous iteration's finish (launch_iterations): two launches
                    // per iteration and one trailing finish per chunk
+    int pcus = 0;  // persistent kernel: one 1024-thread block on each of min(pcus, CUs) compute units
+                   // (0: phase B's blocks, as many as are resident at once)
 };
 
 // The persistent kernel's grid-barrier words, each on a 256-byte line of its
@@ -73,7 +75,8 @@ void launch_eo_merge(const Prob *d, int64_t vf, int nrhs, void *sol, hipStream_t
 int cg_status_of(int state);
 // Record one persistent chunk kernel (K iterations of phases A and B with grid
 // barriers) on `st`; `bar` is BAR_BYTES of device scratch for the barrier.
-// max_cus > 0: one 1024-thread block on each of max_cus compute units.
+// max_cus > 0: one 1024-thread block on each of min(max_cus, CUs) compute
+// units (ls.pcus after plan_persistent).
 int record_persistent_chunk(int inner, const LaunchSet &ls, hipStream_t st, const Prob *d, int nprob,
                             int K, void *bar, int max_cus = 0);
 

@@ -82,15 +82,17 @@ __device__ __forceinline__ int bar_wait(const Barrier &b, unsigned e) {
     for (int t = lo_ + i_; t < hi_; t += per_)
 
 // BLK is the block size the kernel is compiled for: 256, or 1024 for the
-// compute-unit-limited launch (one block fills a compute unit).
-template <int P, int NR, int BLK = 256>
+// launch with one block per compute unit (FP32 and FP16 storage).  R12: links
+// from the reconstruct-12 copy (FP32).  The phase tiles take one hop at a time
+// (pipelining two hops, hop order 3, timed the same at 14^4 x 16).
+template <int P, int NR, int BLK = 256, bool R12 = false>
 __global__ __launch_bounds__(BLK) void k_persistent(const Prob *__restrict__ probs, int K, Barrier b) {
     const Prob &pr = probs[0];
     const unsigned nblk = gridDim.x;
     unsigned e = 0;
     for (int it = 0; it < K; ++it) {
         {   // phase A: the direction q = D^dagger r + beta q (no p, no phase C)
-            FOR_MY_TILES(pr.nt[KA], t) phaseA_tile<P, NR, 1, false, false, false, true>(pr, t);
+            FOR_MY_TILES(pr.nt[KA], t) phaseA_tile<P, NR, 1, false, R12, false, true>(pr, t);
         }
         if (bar_arrive(b, nblk, e)) {
             phaseA_finish(pr);
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(BLK) void k_persistent(const Prob *__restrict__ pro
         }
         ++e;
         {   // phase B
-            FOR_MY_TILES(pr.nt[KB], t) phaseB_tile<P, NR, 1>(pr, t);
+            FOR_MY_TILES(pr.nt[KB], t) phaseB_tile<P, NR, 1, false, R12>(pr, t);
         }
         if (bar_arrive(b, nblk, e)) {
             phaseB_finish(pr);
@@ -154,19 +156,19 @@ static int launch_persistent(int blk, hipStream_t st, const Prob *d, int K, void
 // for one such block only (checked), so every block runs on a compute unit of
 // its own: the launch uses exactly that many compute units.  All blocks are
 // resident at once, which the grid barriers need.
-template <int P>
+template <int P, bool R12>
 static int launch_persistent_cus(hipStream_t st, const Prob *d, int K, void *bar, int max_cus) {
     int dev = 0, ncu = 0, per_cu = 0, khz = 0;
     WD_HIP(hipGetDevice(&dev));
     WD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     WD_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-    WD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<P, 1, 1024>, 1024, 0));
+    WD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persistent<P, 1, 1024, R12>, 1024, 0));
     WD_CHECK(per_cu == 1, WD_EHIP, "the compute-unit-limited kernel fits %d times on a compute unit", per_cu);
     const int nblk = max_cus < ncu ? max_cus : ncu;
     Barrier b;
     make_barrier(b, bar, khz);
     hipLaunchKernelGGL(k_bar_reset, dim3(1), dim3(64), 0, st, (unsigned *)bar);
-    hipLaunchKernelGGL((k_persistent<P, 1, 1024>), dim3(nblk), dim3(1024), 0, st, d, K, b);
+    hipLaunchKernelGGL((k_persistent<P, 1, 1024, R12>), dim3(nblk), dim3(1024), 0, st, d, K, b);
     WD_HIP(hipGetLastError());
     return WD_OK;
 }
@@ -178,10 +180,13 @@ int record_persistent_chunk(int inner, const LaunchSet &ls, hipStream_t st, cons
     WD_CHECK(ka.block == kb.block && ka.nr == kb.nr, WD_EINVAL,
              "persistent kernel needs one block shape for phases A and B");
     if (max_cus > 0) {
-        WD_CHECK(ka.block == 1024 && ka.nr == 1, WD_EINVAL, "compute-unit-limited kernel needs 1024 threads, 1 rhs");
+        WD_CHECK(ka.block == 1024 && ka.nr == 1 && (!ka.r12 || inner == P32), WD_EINVAL,
+                 "kernel with a block per compute unit: 1024 threads, 1 rhs");
         switch (inner) {
-        case P32: return launch_persistent_cus<P32>(st, d, K, bar, max_cus);
-        case P16: return launch_persistent_cus<P16>(st, d, K, bar, max_cus);
+        case P32:
+            return ka.r12 ? launch_persistent_cus<P32, true>(st, d, K, bar, max_cus)
+                          : launch_persistent_cus<P32, false>(st, d, K, bar, max_cus);
+        case P16: return launch_persistent_cus<P16, false>(st, d, K, bar, max_cus);
         }
         return fail(WD_EINVAL, "no compute-unit-limited kernel for precision %d", inner);
     }

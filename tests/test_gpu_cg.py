@@ -313,8 +313,9 @@ def test_persistent_kernel_matches_oracle(inner):
 def test_compute_unit_limited_persistent_kernel(inner):
     """The persistent kernel confined to n compute units (one 1024-thread block
     each) gives the same bits for every n, including grids that are not whole
-    XCD rounds and n above the device's compute units; the oracle accepts the
-    solution and it agrees with the kernel-per-phase path."""
+    XCD rounds and n above the device's compute units, and so does the default
+    persistent launch (that kernel on every compute unit); the oracle accepts
+    the solution and it agrees with the kernel-per-phase path."""
     dims, m0 = (8, 8, 8, 12), 0.05   # 6144 sites: 6 site blocks of 1024 per rhs
     U = wdgen.gauge_field(dims, 0.5, 1013)
     eta = wdgen.mixed_sources(dims, 2, 1, 2013)
@@ -327,6 +328,12 @@ def test_compute_unit_limited_persistent_kernel(inner):
         assert rc == wd.WD_OK, reps
         sols[n] = host(x)
         assert np.array_equal(sols[n], sols[1]), n
+    # without max_cus the persistent kernel takes the same launch on every compute unit
+    say("cg persistent default launch", inner)
+    x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=wd.cg_default_params(
+        inner=inner, reliable_every=50, persistent=1))
+    assert rc == wd.WD_OK, reps
+    assert np.array_equal(host(x), sols[1])
     _check_solution(U, eta, sols[1], dims, m0)
     x0, _, rc0 = wd.cg_solve_batch(g, m0, dev(eta), params=wd.cg_default_params(inner=inner, reliable_every=50))
     assert rc0 == wd.WD_OK

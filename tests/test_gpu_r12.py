@@ -105,9 +105,9 @@ def test_r12_operator_matches_oracle(dims, t_sign):
 
 def test_r12_gauge_serves_every_solver():
     """Every solver takes a reconstruct-12 gauge: kernels without a two-row
-    variant (the persistent kernel, FP16 storage) keep reading its complete
-    copies; BiCGSTAB's plane-blocked stencils (8 x 8 planes here) and the
-    even-odd half-lattice hops read the two-row links."""
+    variant (FP16 storage) keep reading its complete copies; BiCGSTAB's
+    plane-blocked stencils (8 x 8 planes here), the even-odd half-lattice hops
+    and the persistent kernel's phases read the two-row links."""
     dims, m0 = (8, 8, 4, 6), 0.1
     U = wdgen.gauge_field(dims, 0.5, 511)
     eta = wdgen.mixed_sources(dims, 2, 1, 512)
@@ -147,6 +147,30 @@ def test_r12_even_odd_solve(t_sign):
     for i in range(eta.shape[0]):
         assert rel(sols[0][i], sols[1][i]) <= kappa(m0) * 2 * TOL, i
     assert np.any(sols[0] != sols[1])
+
+
+def test_r12_persistent_kernel():
+    """The persistent kernel (FP32 inner, one 1024-thread block per compute
+    unit) reads the two-row links of a reconstruct-12 gauge: the oracle checks
+    the solution, it agrees with the persistent solve on the complete links
+    within kappa(D) (2 tol) and is not bitwise that one, and confining the
+    launch to 5 compute units gives the same bits."""
+    dims, m0 = (8, 8, 4, 6), 0.1
+    U = wdgen.gauge_field(dims, 0.5, 541)
+    eta = wdgen.mixed_sources(dims, 2, 2, 542)
+    say("r12 persistent")
+    sols = {}
+    for r12, n in ((True, 0), (True, 5), (False, 0)):
+        g = wd.Gauge(dev(U), dims, recon12=r12)
+        p = wd.cg_default_params(inner=wd.F32, reliable_every=50, persistent=1, max_cus=n)
+        x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=p)
+        assert rc == wd.WD_OK, (r12, n, reps)
+        sols[r12, n] = host(x)
+        assert np.all(oracle.true_residual(U, eta, sols[r12, n], dims, m0) <= TOL * 1.0000001), (r12, n)
+    assert np.array_equal(sols[True, 0], sols[True, 5])
+    for i in range(eta.shape[0]):
+        assert rel(sols[True, 0][i], sols[False, 0][i]) <= kappa(m0) * 2 * TOL, i
+    assert np.any(sols[True, 0] != sols[False, 0])
 
 
 def test_r12_refuses_links_outside_su3():
