@@ -301,8 +301,11 @@ def fp16n_encode(psi_f32: np.ndarray):
     """Half storage with a per-site FP32 norm for spinors [..., V, 4, 3].
 
     norm = max |component| over the 24 real numbers of the site (FP32);
-    code = half(v / norm) with the quotient rounded to FP32 first, then to half,
-    both round-to-nearest-even.  A site that is all zero gets norm 0, codes 0.
+    inv = 1 / norm rounded to FP32; code = half(v * inv) with the product
+    rounded to FP32 first, then to half, all round-to-nearest-even (one
+    division per site instead of one per component).  Where 1 / norm
+    overflows FP32 (norm < 2^-128, a subnormal) the FP32 quotient v / norm
+    takes the product's place.  A site that is all zero gets norm 0, codes 0.
     Input is complex64 (already rounded to FP32).
     Returns (codes float16 [..., V, 24] as (re, im) pairs, norms float32 [..., V]).
     """
@@ -311,7 +314,9 @@ def fp16n_encode(psi_f32: np.ndarray):
     re = np.stack([v.real, v.imag], axis=-1).reshape(lead + (24,)).astype(np.float32)
     norm = np.max(np.abs(re), axis=-1).astype(np.float32)
     safe = np.where(norm > 0, norm, np.float32(1)).astype(np.float32)
-    q = (re / safe[..., None]).astype(np.float32)
+    with np.errstate(over="ignore", invalid="ignore"):
+        inv = (np.float32(1) / safe).astype(np.float32)
+        q = np.where(np.isinf(inv)[..., None], re / safe[..., None], re * inv[..., None]).astype(np.float32)
     q = np.where(norm[..., None] > 0, q, np.float32(0))
     return q.astype(np.float16), norm
 

@@ -219,25 +219,43 @@ template <> struct Spinor<P16> {
             for (int k = 0; k < 4; ++k) o[4 * j + k] = {n * (float)v[2 * k], n * (float)v[2 * k + 1]};
         }
     }
-    // Quantise: norm = max |re|,|im| over the site; code = half(v / norm), the
-    // FP32 quotient rounded to nearest even.  Returns the stored values in o.
+    // Quantise: norm = max |re|,|im| over the site, inv = 1 / norm (FP32, one
+    // division per site); the scaled value q = v inv is the FP32 product, or
+    // the FP32 quotient v / norm where 1 / norm overflows (norm < 2^-128);
+    // code = half(q), rounded to nearest even.  Returns the stored values in o.
     template <bool NT = false>
     __device__ static __forceinline__ void store(const FieldPtr &f, int r, int s, cx<R> o[12]) {
         float n = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) n = fmaxf(n, fmaxf(fabsf(o[k].re), fabsf(o[k].im)));
+        const float inv = n > 0.f ? 1.f / n : 0.f;
+        float q[24];
+        if (inv < INFINITY) {   // also n == 0 (inv 0: the codes are 0)
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                q[2 * k] = n > 0.f ? o[k].re * inv : 0.f;
+                q[2 * k + 1] = n > 0.f ? o[k].im * inv : 0.f;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                q[2 * k] = o[k].re / n;
+                q[2 * k + 1] = o[k].im / n;
+            }
+        }
         const size_t pb = (size_t)f.V * 16;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             half8v v;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                float a = n > 0.f ? o[4 * j + k].re / n : 0.f;
-                float b = n > 0.f ? o[4 * j + k].im / n : 0.f;
-                v[2 * k] = (h16)a;
-                v[2 * k + 1] = (h16)b;
-                o[4 * j + k] = {n * (float)v[2 * k], n * (float)v[2 * k + 1]};
+            for (int k = 0; k < 8; ++k) {
+                // the FP32 value is final before the conversion (no fused
+                // multiply-and-round-to-half)
+                asm volatile("" : "+v"(q[8 * j + k]));
+                v[k] = (h16)q[8 * j + k];
             }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) o[4 * j + k] = {n * (float)v[2 * k], n * (float)v[2 * k + 1]};
             st<NT>(at<half8v>(f.p, (size_t)(r * 3 + j) * pb, (uint32_t)s * 16u), v);
         }
         st<NT>(at<float>(f.p, norm_plane(f, r), (uint32_t)s * 4u), n);

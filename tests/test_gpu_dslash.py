@@ -111,6 +111,24 @@ def test_pack_unpack_bit_exact():
     V = wdgen.volume(dims)
     U, psi = field_set(dims, 0.5, 3, 3, 4)
     psi[1, 0, 0, 0, 0] = 0.0          # an all-zero site
+    # a site of norm 3 whose values v give a product v * float32(1/3) that
+    # rounds to a different half directly than through FP32 (the encoding
+    # rounds to FP32 first, then to half)
+    rng = np.random.default_rng(41)
+    inv3 = np.float32(1) / np.float32(3)
+    cand = rng.uniform(-3, 3, 2_000_000).astype(np.float32)
+    direct = (cand.astype(np.float64) * np.float64(inv3)).astype(np.float16)
+    twice = (cand * inv3).astype(np.float32).astype(np.float16)
+    tricky = cand[direct.view(np.uint16) != twice.view(np.uint16)][:23]
+    assert len(tricky) == 23
+    site = np.concatenate([[np.float32(3)], tricky]).astype(np.float64)
+    psi[2, 1, 0, 0, 0] = (site[0::2] + 1j * site[1::2]).reshape(4, 3)
+    # a site whose norm is an FP32 subnormal with an overflowing reciprocal
+    # (codes from the quotient), and one just above that range
+    psi[2, 2, 0, 0, 0] = 0.0
+    psi[2, 2, 0, 0, 0, 0, 0] = -2.0 ** -140 + 1j * 3 * 2.0 ** -143
+    psi[2, 2, 0, 0, 0, 1, 2] = 2.0 ** -141 - 1j * 2.0 ** -145
+    psi[2, 3, 0, 0, 0] = psi[2, 1, 0, 0, 0] * 2.0 ** -128
     g = wd.Gauge(dev(U), dims)
     say("pack f64/f32/f16n")
     # FP64: exact round trip

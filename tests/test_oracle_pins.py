@@ -147,14 +147,33 @@ def test_fp16n_encoding():
     c, n = oracle.fp16n_encode(z)
     assert n[0, 0] == 0 and not np.any(c[0, 0])
     assert n[0, 1] == 0.5 and c[0, 1, 14] == 1.0 and c[0, 1, 15] == 0.5
-    # ties round to even: 1 + 2^-11 sits halfway between 1 and 1 + 2^-10
+    # ties round to even: with norm 2 the scaled values are exact in FP32, and
+    # 0.5 + 2^-12 sits halfway between 0.5 and 0.5 + 2^-11 (even: 0.5), 0.5 +
+    # 3 2^-12 halfway between 0.5 + 2^-11 and 0.5 + 2^-10 (even: the latter)
     t = np.zeros((1, 1, 4, 3), dtype=np.complex64)
-    t[0, 0, 0, 0] = 2.0
-    t[0, 0, 0, 1] = 2.0 * (1 + 2.0 ** -11)  # becomes the norm
-    t[0, 0, 0, 2] = 1.0 + 2.0 ** -11
+    t[0, 0, 0, 0] = 2.0                                   # the norm
+    t[0, 0, 0, 1] = (1.0 + 2.0 ** -11) + 1j * (1.0 + 3 * 2.0 ** -11)
+    t[0, 0, 0, 2] = -0.75 - 1j * 2.0 ** -20                # -2^-21: a half subnormal
     c, n = oracle.fp16n_encode(t)
-    q = np.float32(1.0 + 2.0 ** -11) / np.float32(2.0 * (1 + 2.0 ** -11))
-    assert c[0, 0, 4] == np.float16(q)
+    assert n[0, 0] == 2.0
+    assert c[0, 0, 2] == 0.5 and c[0, 0, 3] == 0.5 + 2.0 ** -10
+    assert c[0, 0, 4] == -0.375 and c[0, 0, 5] == -2.0 ** -21
+    # a norm that is not a power of two: every code is within one half-ulp of
+    # half (+1 FP32 rounding) of the exact quotient, and the site's largest
+    # component is coded 1 exactly
+    u = np.zeros((1, 1, 4, 3), dtype=np.complex64)
+    u[0, 0, 0, 0] = 3.0
+    u[0, 0, 1, 1] = 1.0 - 2.0j
+    c, n = oracle.fp16n_encode(u)
+    assert n[0, 0] == 3.0 and c[0, 0, 0] == 1.0
+    assert abs(float(c[0, 0, 8]) - 1 / 3) <= 2.0 ** -13 and abs(float(c[0, 0, 9]) + 2 / 3) <= 2.0 ** -12
+    # a subnormal norm whose reciprocal overflows FP32: codes from the quotient,
+    # exact here (-1, 0.5, 0), no infinities and no NaN
+    w = np.zeros((1, 1, 4, 3), dtype=np.complex64)
+    w[0, 0, 0, 0] = -np.float32(2.0 ** -140) + 1j * np.float32(2.0 ** -141)
+    c, n = oracle.fp16n_encode(w)
+    assert n[0, 0] == np.float32(2.0 ** -140)
+    assert c[0, 0, 0] == -1.0 and c[0, 0, 1] == 0.5 and np.all(c[0, 0, 2:] == 0)
 
 
 @pytest.mark.parametrize("dims", [(2, 2, 2, 2), (2, 2, 4, 4), (4, 4, 4, 4)])
