@@ -107,7 +107,7 @@ def main():
     dU = torch.from_numpy(U).to(dev)
     dsrc = torch.from_numpy(src).to(dev)
     # links: the complete copies plus a two-row (reconstruct-12) FP32 copy, which
-    # the FP32 operator and phases A and B of the FP32-inner CG read
+    # the FP32 operator and the stencils of every FP32-inner solver read
     g = wd.Gauge(dU, dims, -1, recon12=True)
     sol = torch.zeros_like(dsrc)
 
