@@ -31,8 +31,10 @@
  *   WD_F16N  16-byte [rhs][3][V] codes, then float [rhs][V] norms, in one buffer:
  *            chunk j = 8 halves = components 4j..4j+3 as (re,im) pairs; value =
  *            norm * code; norm = max |real or imaginary part| over the site's 24
- *            numbers (FP32), code = half(v / norm) (FP32 quotient, then
- *            round-to-nearest-even to half); an all-zero site has norm 0.
+ *            numbers (FP32), code = half(v * inv) with inv = 1 / norm rounded to
+ *            FP32 (the FP32 product, then round-to-nearest-even to half; the
+ *            FP32 quotient v / norm where 1 / norm overflows, norm < 2^-128);
+ *            an all-zero site has norm 0.
  *
  * Memory ownership: every pointer argument named *_dev is device memory owned by
  * the caller (for example a PyTorch tensor); the library never frees it.  A
