@@ -111,20 +111,21 @@ __global__ __launch_bounds__(256) void k_norm(const Prob *__restrict__ probs, in
 }
 
 // Even-odd preconditioning (eo_core.h)
-template <int P, int NR, bool DAG, bool R12 = false>
+// XY: half-plane blocks (see eo_tile), hop order 5, one rhs per thread
+template <int P, int NR, bool DAG, bool R12 = false, bool XY = false>
 __global__ __launch_bounds__(256) void k_eo_hop1(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(DAG ? KEA1 : KEB1)
-    eo_hop1_tile<P, NR, DAG, true, R12>(pr, t_);
+    eo_hop1_tile<P, NR, DAG, true, R12, XY>(pr, t_);
 }
-template <int P, int NR, bool R12 = false>
+template <int P, int NR, bool R12 = false, bool XY = false>
 __global__ __launch_bounds__(256) void k_eo_phaseA(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KA)
-    eo_phaseA_tile<P, NR, true, R12>(pr, t_);
+    eo_phaseA_tile<P, NR, true, R12, XY>(pr, t_);
 }
-template <int P, int NR, bool R12 = false>
+template <int P, int NR, bool R12 = false, bool XY = false>
 __global__ __launch_bounds__(256) void k_eo_phaseB(const Prob *__restrict__ probs, int nprob, int remap) {
     WD_KERNEL_PROLOGUE(KB)
-    eo_phaseB_tile<P, NR, R12>(pr, t_);
+    eo_phaseB_tile<P, NR, R12, XY>(pr, t_);
 }
 template <int NR>
 __global__ __launch_bounds__(256) void k_eo_ru2a(const Prob *__restrict__ probs, int nprob, int remap) {
@@ -497,6 +498,19 @@ static void launch_finish_after(int kind, const LaunchSet &ls, hipStream_t st, c
     launch_finish(kind == KB && fa ? (KB | FIN_AB) : kind, st, d, nprob);
 }
 
+// the half-plane blocked hops of phases A and B (one rhs per thread; FP32 on
+// the reconstruct-12 links where the gauge has them)
+template <int P, bool R12>
+static void launch_eo_xy(int kind, const KindShape &k, hipStream_t st, const Prob *d, int n) {
+    const dim3 gr(k.grid), bl(k.block);
+    const size_t lds = k.lds;   // the half-plane's spinors
+    switch (kind) {
+    case KEA1: hipLaunchKernelGGL((k_eo_hop1<P, 1, true, R12, true>), gr, bl, lds, st, d, n, k.remap); break;
+    case KEB1: hipLaunchKernelGGL((k_eo_hop1<P, 1, false, R12, true>), gr, bl, lds, st, d, n, k.remap); break;
+    case KA: hipLaunchKernelGGL((k_eo_phaseA<P, 1, R12, true>), gr, bl, lds, st, d, n, k.remap); break;
+    case KB: hipLaunchKernelGGL((k_eo_phaseB<P, 1, R12, true>), gr, bl, lds, st, d, n, k.remap); break;
+    }
+}
 // the FP32 half-lattice hops of phases A and B on the reconstruct-12 links
 static void launch_eo_r12(int kind, const KindShape &k, hipStream_t st, const Prob *d, int n) {
     const dim3 gr(k.grid), bl(k.block);
@@ -525,6 +539,11 @@ template <int P>
 static void launch_eo(int kind, const KindShape &k, hipStream_t st, const Prob *d, int n) {
     const dim3 gr(k.grid), bl(k.block);
     const bool two = k.nr >= 2;
+    if (k.xy && (kind == KEA1 || kind == KEB1 || kind == KA || kind == KB)) {
+        if (P == P32 && k.r12) launch_eo_xy<P, P == P32>(kind, k, st, d, n);
+        else launch_eo_xy<P, false>(kind, k, st, d, n);
+        return;
+    }
     if (P == P32 && k.r12 && (kind == KEA1 || kind == KEB1 || kind == KA || kind == KB)) {
         launch_eo_r12(kind, k, st, d, n);
         return;
@@ -778,12 +797,26 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
                 ks.ordered = 5;
                 ks.r12 = pr.U12 != nullptr;
             }
+            // even-odd: the phases' half-lattice hops on half-plane blocks (the
+            // Lx Ly / 2 sites of one parity on an xy-plane, 64..256 of them),
+            // one rhs per thread, hop order 5
+            if (pr.eo && (k == KA || k == KB || k == KEA1 || k == KEB1)) {
+                const int nh = np / 2;
+                ks.xy = st[k]->xylds && nh >= 64 && nh <= 256 ? 1 : 0;
+                ks.order = 0;
+                if (ks.xy) {
+                    ks.block = (nh + 63) & ~63;
+                    ks.nr = 1;
+                    ks.ordered = 5;
+                    ks.lds = nh * (inner == WD_F64 ? 192 : 96);   // the half-plane in LDS
+                }
+            }
             // hop order 5 exists for plane blocks with one rhs per thread
             if (ks.ordered == 5 && !(ks.xy == 1 && ks.nr == 1)) ks.ordered = 3;
             // several z-adjacent planes per block (FP32 / FP16 storage, hop order 5);
             // the block is rounded up to whole wavefronts for the block sums
             ks.planes = 1;
-            if ((k == KA || k == KB) && ks.xy == 1 && ks.nr == 1 && ks.ordered == 5 && !ks.nt) {
+            if ((k == KA || k == KB) && ks.xy == 1 && ks.nr == 1 && ks.ordered == 5 && !ks.nt && !pr.eo) {
                 const int kp = xy_planes(*st[k], geo, inner, 1);
                 if (kp > 1) {
                     ks.planes = kp;

@@ -31,32 +31,53 @@ __device__ __forceinline__ int eo_site(const Geom &g, int k, int par) {
     return 2 * k + ((c[1] + c[2] + c[3] + par) & 1);
 }
 
-// tile t of an even-odd kind: site block and rhs group; k = half index or vf
+// tile t of an even-odd kind: site block and rhs group; k = half index or vf.
+// XY: a site block is the Lx Ly / 2 sites of one parity on an xy-plane, whose
+// half indices are consecutive (so are the other parity's on that plane: the
+// x and y neighbours of the block's sites).
+template <bool XY = false>
 __device__ __forceinline__ void eo_tile(const Prob &pr, int K, int t, int &sb, int &grp, int &k) {
     sb = t / pr.ng[K];
     grp = t - sb * pr.ng[K];
-    const int L = sb * (int)blockDim.x + (int)threadIdx.x;
-    k = L < pr.vf ? L : pr.vf;
+    const int rows = XY ? pr.g.S[2] >> 1 : (int)blockDim.x;
+    const int L = sb * rows + (int)threadIdx.x;
+    k = ((int)threadIdx.x < rows && L < pr.vf) ? L : pr.vf;
+}
+
+// XY: stage the half-plane of the hop's input field (the other parity's sites
+// on the block's xy-plane) in LDS; every thread of the block calls it.
+template <int P, int NR, bool XY>
+__device__ __forceinline__ void eo_stage(const Prob &pr, const FieldPtr &in, int rhs0, unsigned act, int k,
+                                         typename LdsSpinor<P>::word *xy) {
+    if constexpr (XY) stage_plane<P, NR>(in, rhs0, act, k, pr.vf, xy, pr.g.S[2] >> 1);
 }
 
 // First half hop, onto the odd sites: tmp_o = H_oe v_e (H^dagger with DAG).
 // v: p for phase A (DAG), q for phase B.  QR: phase A hops r, as it forms the
 // direction as q = Dhat^dagger r + beta q (see phaseA_tile).  R12 (here and in
 // the second halves of phases A and B): links from the reconstruct-12 copy.
-template <int P, int NR, bool DAG, bool QR = false, bool R12 = false>
+// XY (here and there): half-plane blocks, the x and y neighbours from LDS, hop
+// order 5 (z and t first); one rhs per thread.
+template <int P, int NR, bool DAG, bool QR = false, bool R12 = false, bool XY = false>
 __device__ __forceinline__ void eo_hop1_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
+    typedef typename LdsSpinor<P>::word W;
+    extern __shared__ uint4 eo_lds[];   // XY: the half-plane, sized at launch
+    W *xy = (W *)eo_lds;
     constexpr int K = DAG ? KEA1 : KEB1;
     int sb, grp, k;
-    eo_tile(pr, K, t, sb, grp, k);
+    eo_tile<XY>(pr, K, t, sb, grp, k);
     const int rhs0 = grp * NR;
     const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
-    if (!act || k >= pr.vf) return;
+    if (!act) return;   // uniform over the block
+    FieldPtr fin{DAG ? (QR ? pr.r : pr.p) : pr.q, pr.vf, pr.nrhs}, fo{pr.tmp, pr.vf, pr.nrhs};
+    eo_stage<P, NR, XY>(pr, fin, rhs0, act, k, xy);
+    if (k >= pr.vf) return;
     const Geom g = pr.g;
     const int s = eo_site(g, k, 1);
-    FieldPtr fin{DAG ? (QR ? pr.r : pr.p) : pr.q, pr.vf, pr.nrhs}, fo{pr.tmp, pr.vf, pr.nrhs};
     cx<R> acc[NR][12];
-    hopping<P, DAG, NR, 1, false, true, false, R12>(g, s, R12 ? pr.U12 : pr.U_lo, fin, rhs0, act, acc);
+    hopping<P, DAG, NR, XY ? 5 : 1, XY, true, false, R12>(g, s, R12 ? pr.U12 : pr.U_lo, fin, rhs0, act, acc,
+                                                          nullptr, xy, k - (int)threadIdx.x, g.S[2] >> 1);
 #pragma unroll
     for (int j = 0; j < NR; ++j)
         if (act >> j & 1) Spinor<P>::store(fo, rhs0 + j, k, acc[j]);
@@ -64,22 +85,28 @@ __device__ __forceinline__ void eo_hop1_tile(const Prob &pr, int t) {
 
 // Phase A, second half: q_e = A p_e - c H^dagger_eo tmp_o, partial |q|^2.
 // QR: with r in place of p, plus beta times the old q_e (not after a restart).
-template <int P, int NR, bool QR = false, bool R12 = false>
+template <int P, int NR, bool QR = false, bool R12 = false, bool XY = false>
 __device__ __forceinline__ void eo_phaseA_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
+    typedef typename LdsSpinor<P>::word W;
+    extern __shared__ uint4 eo_lds[];   // XY: the half-plane, sized at launch
+    W *xy = (W *)eo_lds;
     int sb, grp, k;
-    eo_tile(pr, KA, t, sb, grp, k);
+    eo_tile<XY>(pr, KA, t, sb, grp, k);
     const int rhs0 = grp * NR;
     const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
     double part[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) part[j] = 0.0;
+    FieldPtr ft{pr.tmp, pr.vf, pr.nrhs};
+    if (act) eo_stage<P, NR, XY>(pr, ft, rhs0, act, k, xy);
     if (act && k < pr.vf) {
         const Geom g = pr.g;
         const int s = eo_site(g, k, 0);
-        FieldPtr ft{pr.tmp, pr.vf, pr.nrhs}, fp{QR ? pr.r : pr.p, pr.vf, pr.nrhs}, fq{pr.q, pr.vf, pr.nrhs};
+        FieldPtr fp{QR ? pr.r : pr.p, pr.vf, pr.nrhs}, fq{pr.q, pr.vf, pr.nrhs};
         cx<R> acc[NR][12];
-        hopping<P, true, NR, 1, false, true, false, R12>(g, s, R12 ? pr.U12 : pr.U_lo, ft, rhs0, act, acc);
+        hopping<P, true, NR, XY ? 5 : 1, XY, true, false, R12>(g, s, R12 ? pr.U12 : pr.U_lo, ft, rhs0, act, acc,
+                                                               nullptr, xy, k - (int)threadIdx.x, g.S[2] >> 1);
         const R a = (R)pr.diag, c = (R)pr.eo_c;
 #pragma unroll
         for (int j = 0; j < NR; ++j) {
@@ -117,25 +144,30 @@ __device__ __forceinline__ void eo_phaseA_tile(const Prob &pr, int t) {
 
 // Phase B, second half: t_e = A q_e - c H_eo tmp_o; r -= alpha t; x_lo += alpha q;
 // partial |r|^2
-template <int P, int NR, bool R12 = false>
+template <int P, int NR, bool R12 = false, bool XY = false>
 __device__ __forceinline__ void eo_phaseB_tile(const Prob &pr, int t) {
     typedef typename real_of<P>::type R;
     constexpr int XP = XPrec<P>::value;
     typedef typename real_of<XP>::type RX;
+    typedef typename LdsSpinor<P>::word W;
+    extern __shared__ uint4 eo_lds[];   // XY: the half-plane, sized at launch
+    W *xy = (W *)eo_lds;
     int sb, grp, k;
-    eo_tile(pr, KB, t, sb, grp, k);
+    eo_tile<XY>(pr, KB, t, sb, grp, k);
     const int rhs0 = grp * NR;
     const unsigned act = rhs_mask<NR>(pr, rhs0, ST_ACTIVE);
     double part[NR];
 #pragma unroll
     for (int j = 0; j < NR; ++j) part[j] = 0.0;
+    FieldPtr ft{pr.tmp, pr.vf, pr.nrhs};
+    if (act) eo_stage<P, NR, XY>(pr, ft, rhs0, act, k, xy);
     if (act && k < pr.vf) {
         const Geom g = pr.g;
         const int s = eo_site(g, k, 0);
-        FieldPtr ft{pr.tmp, pr.vf, pr.nrhs}, fq{pr.q, pr.vf, pr.nrhs}, fr{pr.r, pr.vf, pr.nrhs},
-            fx{pr.x_lo, pr.vf, pr.nrhs};
+        FieldPtr fq{pr.q, pr.vf, pr.nrhs}, fr{pr.r, pr.vf, pr.nrhs}, fx{pr.x_lo, pr.vf, pr.nrhs};
         cx<R> acc[NR][12];
-        hopping<P, false, NR, 1, false, true, false, R12>(g, s, R12 ? pr.U12 : pr.U_lo, ft, rhs0, act, acc);
+        hopping<P, false, NR, XY ? 5 : 1, XY, true, false, R12>(g, s, R12 ? pr.U12 : pr.U_lo, ft, rhs0, act, acc,
+                                                                nullptr, xy, k - (int)threadIdx.x, g.S[2] >> 1);
         const R a = (R)pr.diag, c = (R)pr.eo_c;
 #pragma unroll
         for (int j = 0; j < NR; ++j) {

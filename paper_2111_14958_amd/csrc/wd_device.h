@@ -482,7 +482,8 @@ template <> struct LdsSpinor<P64> {
 // XYLDS: the neighbours in x and y are read from the block's LDS copy of its
 // xy-plane (`xy`, plane starting at site `plane0`, np sites) instead of memory.
 // HALF: `in` holds only the sites of the other parity, site n at index n / 2
-// (even-odd preconditioning; needs an even Lx).
+// (even-odd preconditioning; needs an even Lx); with XYLDS, plane0 and np
+// count half indices (the block's half-plane).
 // R12: U is a reconstruct-12 copy (two rows per link, FP32/FP16).
 // ZIN (with XYLDS; a block of several z-adjacent xy-planes, whose sites are
 // consecutive, all staged in `xy`): a z neighbour that lies in the block's
@@ -575,7 +576,7 @@ __device__ __forceinline__ void hopping(const Geom &g, int s, const void *U, con
         for (int j = 0; j < NR; ++j) {
             if (act >> j & 1) {
                 cx<R> p[12], h[6], w[6];
-                if constexpr (XYLDS && MU < 2) LdsSpinor<P>::get(xy, np, j, nb - plane0, p);
+                if constexpr (XYLDS && MU < 2) LdsSpinor<P>::get(xy, np, j, (HALF ? nb >> 1 : nb) - plane0, p);
                 else if constexpr (ZM && MU == 2) LdsSpinor<P>::get(zn, np, j, s - plane0, p);
                 else if constexpr (ZIN && MU == 2) {
                     const int li = nb - plane0;   // in the block's planes: only one wave can diverge

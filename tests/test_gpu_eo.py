@@ -123,3 +123,34 @@ def test_initial_guess_zero_source_periodic_and_errors():
     eo_src = dev(wdgen.gaussian_source(do, 1, 24))
     _, _, rc = wd.cg_solve_batch(go, m0, eo_src, params=_params(wd.F32), raise_on_error=False)
     assert rc == wd.WD_EINVAL
+
+
+@pytest.mark.parametrize("inner", [wd.F64, wd.F32, wd.F16N], ids=["f64", "f32", "f16n"])
+@pytest.mark.parametrize("dims", [(14, 14, 4, 4), (16, 8, 4, 6), (12, 12, 2, 6)], ids=["14x14", "16x8", "12x12"])
+def test_half_plane_blocks(inner, dims):
+    """The phases' half-lattice hops on half-plane blocks (the Lx Ly / 2 sites
+    of one parity on an xy-plane, 98, 64 and 72 here: x and y neighbours from
+    LDS, hop order 5; FP32 on the reconstruct-12 links) against site blocks
+    (hop order 1, complete links): both solutions pass the oracle's residual
+    check and agree within kappa(D) (2 tol); in FP64 without reliable updates
+    both iterate the same recurrence, so the iteration counts agree to
+    rounding."""
+    m0 = 0.1
+    U = wdgen.gauge_field(dims, 0.5, 1301)
+    eta = wdgen.mixed_sources(dims, 3, 2, 1302)
+    nrhs = eta.shape[0]
+    sols, iters = {}, {}
+    for xy in (1, 0):
+        say("eo half-plane blocks", dims, inner, xy)
+        g = wd.Gauge(dev(U), dims, recon12=bool(xy) and inner == wd.F32)
+        for fam, dag in ((wd.FAMILY_CG_A, True), (wd.FAMILY_CG_B, False)):
+            wd.shape_set(g, inner, nrhs, dag, fam, 256, 1, 1, 5 if xy else 1, 1, 0, 0, xy)
+        x, reps, rc = wd.cg_solve_batch(g, m0, dev(eta), params=_params(inner))
+        assert rc == wd.WD_OK, (xy, reps)
+        sols[xy] = host(x)
+        iters[xy] = [r["iters"] for r in reps]
+        _check_solution(U, eta, sols[xy], dims, m0)
+    for i in range(nrhs):
+        assert rel(sols[1][i], sols[0][i]) <= kappa(m0) * 2 * TOL, i
+        if inner == wd.F64:
+            assert abs(iters[1][i] - iters[0][i]) <= 2, (iters, i)
