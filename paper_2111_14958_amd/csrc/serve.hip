@@ -120,21 +120,34 @@ static void server_shapes(int inner, int &blk, int &nr_ab) {
     nr_ab = inner == WD_F64 ? 1 : 2;
 }
 
+// Phases A and B of an FP32 or FP64 request without even-odd preconditioning
+// whose xy-planes hold 128..256 sites run on plane blocks (one plane per
+// 256-thread block, x and y neighbours from LDS, hop order 5, one rhs per
+// thread); every other kernel, and every other request, on site blocks.  The
+// choice depends on the request alone, so its results do not depend on the mix.
+static bool server_xy(int inner, int eo, const int dims[4]) {
+    const int np = dims[0] * dims[1];
+    return !eo && inner != WD_F16N && np >= 128 && np <= 256;
+}
+static bool prob_xy(const Prob &pr) { return (pr.sorder[KA] >> 17) & 1; }
+
 // tiles of every kernel kind for one request (vectors of vf sites)
-static void prob_tiles(Prob &pr, int inner, int64_t vf, int nrhs) {
+static void prob_tiles(Prob &pr, int inner, int64_t vf, int nrhs, bool xy) {
     int blk, nr;
     server_shapes(inner, blk, nr);
     for (int k = 0; k < NKIND; ++k) {
-        const int knr = (k == KA || k == KB || k == KEA1 || k == KEB1) ? nr : 1;
-        pr.nsb[k] = (int)((vf + blk - 1) / blk);
+        const bool plane = xy && (k == KA || k == KB);
+        const int knr = plane ? 1 : (k == KA || k == KB || k == KEA1 || k == KEB1) ? nr : 1;
+        pr.nsb[k] = plane ? (int)(vf / pr.g.S[2]) : (int)((vf + blk - 1) / blk);
         pr.ng[k] = (k == KC || k == KR1 || k == KN) ? nrhs : (nrhs + knr - 1) / knr;
         pr.nt[k] = pr.nsb[k] * pr.ng[k];
         pr.t0[k] = 0;
+        pr.sorder[k] = plane ? 1 << 17 : 0;   // plane-blocked tiles, lexicographic planes
     }
 }
 
 // launch shapes of the server's kernels, with the grid of every kind
-static LaunchSet server_launch(int inner, int eo, const int grid[NKIND]) {
+static LaunchSet server_launch(int inner, int eo, int xy, const int grid[NKIND]) {
     int blk, nr;
     server_shapes(inner, blk, nr);
     LaunchSet ls;
@@ -148,11 +161,17 @@ static LaunchSet server_launch(int inner, int eo, const int grid[NKIND]) {
         ls.k[k].nr = (k == KA || k == KB || k == KEA1 || k == KEB1) ? nr : 1;
         ls.k[k].remap = stencil ? 1 : 0;
         ls.k[k].grid = grid[k];
+        if (xy && (k == KA || k == KB)) {
+            ls.k[k].xy = 1;
+            ls.k[k].nr = 1;
+            ls.k[k].ordered = 5;
+            ls.k[k].order = 1 << 17;
+        }
     }
     return ls;
 }
 
-static LaunchSet single_launch(const Prob &pr, int inner) { return server_launch(inner, pr.eo, pr.nt); }
+static LaunchSet single_launch(const Prob &pr, int inner) { return server_launch(inner, pr.eo, prob_xy(pr), pr.nt); }
 
 }  // namespace wd
 
@@ -170,10 +189,11 @@ struct wd_server {
     std::thread th;
     hipStream_t st = nullptr;
     wd_serve_stats stats{};
-    // per (inner precision, even-odd) group: max_slots Prob records
-    size_t table_off[6] = {0, 0, 0, 0, 0, 0};
-    size_t table_bytes = 0;             // arena bytes the six tables occupy
-    std::vector<wd::Prob> table[6];     // host staging of the tables (alive until the step syncs)
+    // per (inner precision, even-odd, plane-blocked phases) group: max_slots Prob records
+    static constexpr int NGROUP = 12;
+    size_t table_off[NGROUP] = {};
+    size_t table_bytes = 0;             // arena bytes the tables occupy
+    std::vector<wd::Prob> table[NGROUP];   // host staging of the tables (alive until the step syncs)
     int chunk = 25;
 };
 
@@ -205,7 +225,7 @@ static int init_slot(wd_server *s, Slot &sl) {
     fill_prob(sl.prob, &g, rq.m0, rq.nrhs, rq.params, w, L);
     const int eo = sl.prob.eo;
     const int64_t vf = sl.prob.vf;
-    prob_tiles(sl.prob, inner, vf, rq.nrhs);
+    prob_tiles(sl.prob, inner, vf, rq.nrhs, server_xy(inner, eo, rq.dims));
     init_scalars(sl.sc, rq.nrhs);
     WD_HIP(hipMemcpyAsync(w + L.prob, &sl.prob, sizeof(Prob), hipMemcpyHostToDevice, st));
     WD_HIP(hipMemcpyAsync(w + L.scal, sl.sc.data(), sizeof(Scal) * rq.nrhs, hipMemcpyHostToDevice, st));
@@ -236,10 +256,12 @@ static int init_slot(wd_server *s, Slot &sl) {
 }
 
 // One step: `chunk` iterations plus a reliable update for every resident
-// request of one group (inner precision, even-odd or not), as grouped launches.
+// request of one group (inner precision, even-odd or not, plane-blocked phases
+// or not: gkey = (inner 2 + eo) 2 + xy), as grouped launches.
+static int group_key(const Slot &sl) { return (sl.req.params.inner * 2 + sl.prob.eo) * 2 + (prob_xy(sl.prob) ? 1 : 0); }
 static int step_group(wd_server *s, int gkey, const std::vector<Slot *> &grp) {
     if (grp.empty()) return WD_OK;
-    const int inner = gkey >> 1, eo = gkey & 1;
+    const int inner = gkey >> 2, eo = (gkey >> 1) & 1, xy = gkey & 1;
     std::vector<Prob> &table = s->table[gkey];
     table.clear();
     int tot[NKIND] = {};
@@ -251,7 +273,7 @@ static int step_group(wd_server *s, int gkey, const std::vector<Slot *> &grp) {
         }
         table.push_back(p);
     }
-    const LaunchSet ls = server_launch(inner, eo, tot);
+    const LaunchSet ls = server_launch(inner, eo, xy, tot);
     Prob *dt = (Prob *)arena_ptr(s, s->table_off[gkey]);
     const int n = (int)table.size();
     WD_HIP(hipMemcpyAsync(dt, table.data(), sizeof(Prob) * n, hipMemcpyHostToDevice, s->st));
@@ -368,9 +390,9 @@ static void scheduler(wd_server *s) {
         }
         if (rc) { fail_all(s, rc); continue; }
         // one step over every resident request
-        std::vector<Slot *> grp[6];
-        for (Slot &sl : s->active) grp[sl.req.params.inner * 2 + sl.prob.eo].push_back(&sl);
-        for (int p = 0; p < 6 && !rc; ++p) rc = step_group(s, p, grp[p]);
+        std::vector<Slot *> grp[wd_server::NGROUP];
+        for (Slot &sl : s->active) grp[group_key(sl)].push_back(&sl);
+        for (int p = 0; p < wd_server::NGROUP && !rc; ++p) rc = step_group(s, p, grp[p]);
         if (!rc && hipStreamSynchronize(s->st) != hipSuccess) rc = WD_EHIP;
         for (Slot &sl : s->active) {
             if (rc) break;
@@ -471,7 +493,7 @@ int wd_serve_create(const wd_serve_config *cfg, wd_server **out) {
     s->chunk = cfg->chunk > 0 ? cfg->chunk : 25;
     s->arena.init(cfg->arena_bytes);
     const size_t tb = al256s(sizeof(Prob) * cfg->max_slots);
-    for (int p = 0; p < 6; ++p) {
+    for (int p = 0; p < wd_server::NGROUP; ++p) {
         if (!s->arena.alloc(tb, &s->table_off[p])) {
             delete s;
             return fail(WD_ETOOBIG, "arena too small for the request tables");
