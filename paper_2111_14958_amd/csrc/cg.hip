@@ -9,8 +9,10 @@
 //   chunk  K x [A, B], then R1 (x64 += x_lo), R2, summary   (one graph; with a
 //          z-marching phase A, which reads p: K x [A, B, C], then R1, R2, C)
 // and replays the chunk graph until no right-hand side is active, reading back
-// one counter per replay.  BiCGSTAB (bicgstab_core.h) uses the same driver with
-// the chunk K x [S1, S2, S3, S4, S5], then R1, R2, summary.
+// the summary (active count, abort flag, estimated iterations left) after each
+// replay; with the library's chunk length a replay is cut to that estimate.
+// BiCGSTAB (bicgstab_core.h) uses the same driver with the chunk
+// K x [S1, S2, S3, S4, S5], then R1, R2, summary.
 #include <stdlib.h>
 #include <string.h>
 
@@ -534,13 +536,14 @@ static void launch_eo_r12(int kind, const KindShape &k, hipStream_t st, const Pr
         break;
     }
 }
-// even-odd kernels of the stencil kinds (1 or 2 rhs per thread)
+// even-odd kernels of the stencil kinds (site blocks: 1 or 2 rhs per thread;
+// half-plane blocks: launch_eo_xy)
 template <int P>
 static void launch_eo(int kind, const KindShape &k, hipStream_t st, const Prob *d, int n) {
     const dim3 gr(k.grid), bl(k.block);
     const bool two = k.nr >= 2;
     if (k.xy && (kind == KEA1 || kind == KEB1 || kind == KA || kind == KB)) {
-        if (P == P32 && k.r12) launch_eo_xy<P, P == P32>(kind, k, st, d, n);
+        if (P == P32 && k.r12) launch_eo_xy<P, P == P32>(kind, k, st, d, n);   // R12: FP32 only
         else launch_eo_xy<P, false>(kind, k, st, d, n);
         return;
     }
@@ -752,11 +755,12 @@ void plan_shapes(const wd_gauge *g, int nrhs, int inner, LaunchSet &ls, Prob &pr
             ks.ordered = (k == KA || k == KB) && (st[k]->ordered == 3 || st[k]->ordered == 5) ? st[k]->ordered : 1;
             const int strip = (st[k]->strip > 0 && st[k]->strip < g->dims[2]) ? st[k]->strip : 0;
             ks.order = strip | (st[k]->gmajor ? 1 << 16 : 0) | (st[k]->fpass << 24);
-            // plane-blocked phases A and B: one xy-plane of 64..256 sites per
-            // block (the partial-sum buffer holds one entry per 64 sites)
+            // plane-blocked phases A and B, reliable update and BiCGSTAB
+            // stencils: one xy-plane of 64..256 sites per block (the
+            // partial-sum buffer holds one entry per 64 sites)
             ks.xy = (k == KA || k == KB || k == KR2 || k == KS2 || k == KS4) && st[k]->xylds && np >= 64 &&
                     np <= 256 && !pr.eo;
-            if (pr.eo) {   // the half-lattice kernels: site blocks, lexicographic order
+            if (pr.eo) {   // the half-lattice kernels: lexicographic order (half-plane blocks below)
                 ks.order = 0;
                 if (ks.nr > 2) ks.nr = 2;
             }
