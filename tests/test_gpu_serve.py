@@ -37,14 +37,17 @@ def _requests():
 def _big_requests():
     """The serving workload's largest volumes beside small ones: 14^4 and
     16^3 x 32 with 12 right-hand sides at m0 0.02 (the hardest conditioning the
-    stream draws), one of them even-odd preconditioned, and three small requests."""
+    stream draws), one of them even-odd preconditioned, and three smaller
+    requests, the 12^4 one in FP64.  The 14^4 and 12^4 requests run their
+    phases on plane blocks, the others on site blocks."""
     out = []
     specs = [((14, 14, 14, 14), 12, 0.02, 0), ((16, 16, 16, 32), 12, 0.02, 1),
-             ((4, 4, 4, 4), 3, 0.2, 0), ((8, 8, 8, 8), 5, 0.07, 1), ((12, 12, 12, 12), 1, 0.11, 0)]
+             ((4, 4, 4, 4), 3, 0.2, 0), ((8, 8, 8, 8), 5, 0.07, 1), ((12, 12, 12, 12), 2, 0.11, 0)]
     for i, (dims, nrhs, m0, eo) in enumerate(specs):
         U = wdgen.gauge_field(dims, 0.5, 11_000 + i)
         src = wdgen.gaussian_source(dims, nrhs, 61_000 + i)
-        out.append(dict(dims=dims, nrhs=nrhs, m0=m0, U=U, src=src, inner=wd.F32, eo=eo))
+        inner = wd.F64 if i == 4 else wd.F32
+        out.append(dict(dims=dims, nrhs=nrhs, m0=m0, U=U, src=src, inner=inner, eo=eo))
     return out
 
 
@@ -105,7 +108,7 @@ def test_serve_mix_at_the_largest_volumes():
         assert np.all(res <= TOL * 1.0000001), (r["dims"], res)
         for e, o in zip(rep, res):
             assert abs(e["true_rel_res"] - o) <= 1e-3 * TOL + 1e-6 * o
-    for i in (0, 1):
+    for i in (0, 1, 4):
         say("serve big alone", reqs[i]["dims"])
         xa, repa, _ = _run([reqs[i]], 2 << 30, chunk=25)
         assert np.array_equal(xa[0], xs[i]), reqs[i]["dims"]
